@@ -1,0 +1,376 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself:
+published test vectors, closed forms, brute-force sums without FFTs, exact
+algebraic identities of the rPS derivation (Sec. 3.2), special cases and
+invariants.  All CPU; no GPU code is involved."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import rps_inputs as ri
+from oracle import basis, brute, conventional, grid, isdf, rng, rps
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- generator
+def test_philox_known_answers():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        out = rng.philox4x32_10(*v[:6])
+        assert [int(o) for o in out] == v[6:]
+
+
+def test_sketch_normal_statistics():
+    z = rng.sketch_normal(400, 50, seed=12345, stream=3)
+    assert abs(z.mean()) < 0.02 and abs(z.std() - 1.0) < 0.02
+    z2 = rng.sketch_normal(400, 50, seed=12345, stream=4)
+    assert abs(np.corrcoef(z.ravel(), z2.ravel())[0, 1]) < 0.02
+
+
+# ---------------------------------------------------------------- Coulomb on the grid
+@pytest.mark.parametrize("skew", [False, True])
+@pytest.mark.parametrize("mesh", [(6, 6, 6), (5, 6, 7)])
+def test_poisson_equals_direct_g_sum(skew, mesh):
+    """FFT Poisson solve == dense matrix from explicit cos(G.(R-R')) sums."""
+    lat = np.eye(3) * 5.0
+    if skew:
+        lat = np.array([[5.0, 0.0, 0.0], [1.3, 4.6, 0.0], [0.4, -0.9, 5.5]])
+    Vd = brute.dense_coulomb(lat, mesh)
+    f = np.random.default_rng(1).standard_normal((3, int(np.prod(mesh))))
+    got = grid.poisson(f, lat, mesh)
+    np.testing.assert_allclose(got, f @ Vd.T, rtol=0, atol=1e-12 * np.abs(got).max())
+    # symmetric positive semi-definite, null vector = constant (G = 0 removed)
+    np.testing.assert_allclose(Vd, Vd.T, atol=1e-12)
+    ev = np.linalg.eigvalsh(Vd)
+    assert ev.min() > -1e-10
+    assert abs(np.ones(Vd.shape[0]) @ Vd @ np.ones(Vd.shape[0])) < 1e-9
+
+
+@pytest.mark.parametrize("a,b", [(0.8, 1.1), (0.5, 0.5)])
+def test_grid_coulomb_matches_analytic_lattice_sum(a, b):
+    """dV sum rho_A Vc rho_B for periodized s Gaussians == the reciprocal
+    lattice sum of their analytic transforms (Eq. 4), G = 0 removed.  Pins dV,
+    1/Omega, 4 pi / G^2, the G = 0 rule, the FFT convention and the s
+    normalisation together."""
+    L = 7.0
+    lat = np.eye(3) * L
+    mesh = (40, 40, 40)
+    A = np.array([1.0, 2.0, 3.0])
+    B = np.array([4.5, 0.7, 5.9])
+    w = ri.Workload("t", lat, np.array(mesh), np.stack([A, B]), np.array([0, 1]),
+                    np.array([0, 0]), np.array([a, b]), 1, 1, 0)
+    Phi = basis.eval_basis(w)
+    dV = grid.dvol(lat, mesh)
+    got = dV * Phi[:, 0] @ grid.poisson(Phi[:, 1], lat, mesh)
+    ref = brute.analytic_s_coulomb(lat, A, a, B, b)
+    assert abs(got - ref) < 1e-11 * max(1.0, abs(ref))
+
+
+# ---------------------------------------------------------------- basis functions
+def _one_shell_workload(l, a, L=10.0, mesh=64, center=(3.1, 4.7, 5.3)):
+    return ri.Workload("t", np.eye(3) * L, np.array([mesh] * 3), np.array([center]),
+                       np.array([0]), np.array([l]), np.array([a]), 1, 1, 0)
+
+
+@pytest.mark.parametrize("l,a", [(0, 1.3), (1, 0.9), (2, 1.1), (2, 0.6)])
+def test_shell_components_orthonormal(l, a):
+    """Tight shell in a large cell: the grid overlap of its components is the
+    identity (free-space normalisation, mutually orthogonal components)."""
+    w = _one_shell_workload(l, a)
+    Phi = basis.eval_basis(w)
+    S = basis.overlap(Phi, grid.dvol(w.lattice, w.mesh))
+    np.testing.assert_allclose(S, np.eye(2 * l + 1), atol=1e-10)
+
+
+def test_d_shell_sum_of_squares_is_spherical():
+    """For correctly normalised real spherical d functions sum_m d_m(r)^2
+    depends only on |r| (addition theorem)."""
+    d = np.random.default_rng(3).standard_normal((50, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    v = basis.shell_values(2, 0.7, 1.3 * d)
+    s = (v * v).sum(axis=1)
+    np.testing.assert_allclose(s, s[0], rtol=1e-13)
+
+
+def test_basis_is_periodic_and_sums_images():
+    lat = np.array([[6.0, 0, 0], [0.8, 5.5, 0], [0.3, 0.2, 6.2]])
+    w = ri.Workload("t", lat, np.array([8, 8, 8]), np.array([[0.2, 0.1, 5.9]]),
+                    np.array([0, 0, 0]), np.array([0, 1, 2]), np.array([0.12, 0.3, 0.25]), 1, 1, 0)
+    p = np.random.default_rng(0).uniform(0, 6, size=(20, 3))
+    v0 = basis.eval_basis(w, p)
+    for k in range(3):
+        np.testing.assert_allclose(basis.eval_basis(w, p + lat[k]), v0, atol=1e-12, rtol=1e-12)
+    # brute force over a wide block of images for the s shell
+    A = w.atoms[0]
+    acc = np.zeros(len(p))
+    for i in range(-12, 13):
+        for j in range(-12, 13):
+            for k in range(-12, 13):
+                T = i * lat[0] + j * lat[1] + k * lat[2]
+                r2 = ((p - A - T) ** 2).sum(1)
+                acc += (2 * 0.12 / math.pi) ** 0.75 * np.exp(-0.12 * r2)
+    np.testing.assert_allclose(v0[:, 0], acc, rtol=1e-13, atol=1e-16)
+
+
+def test_voronoi_brute_force():
+    lat = np.array([[5.0, 0, 0], [1.1, 4.8, 0], [0.2, 0.4, 5.1]])
+    atoms = np.array([[0.1, 0.2, 0.3], [2.5, 2.4, 2.6], [4.0, 1.0, 4.5]])
+    w = ri.Workload("t", lat, np.array([7, 6, 5]), atoms, np.arange(3), np.zeros(3, int),
+                    np.ones(3), 1, 1, 0)
+    own = basis.voronoi(w)
+    pts = grid.grid_points(lat, w.mesh)
+    best = np.full(len(pts), np.inf)
+    ref = np.zeros(len(pts), int)
+    for I, A in enumerate(atoms):
+        for i in range(-3, 4):
+            for j in range(-3, 4):
+                for k in range(-3, 4):
+                    T = i * lat[0] + j * lat[1] + k * lat[2]
+                    d2 = ((pts - A - T) ** 2).sum(1)
+                    upd = d2 < best - 1e-12
+                    best[upd] = d2[upd]
+                    ref[upd] = I
+    assert np.array_equal(own, ref)
+
+
+# ---------------------------------------------------------------- conventional exchange
+def test_conventional_exchange_closed_form():
+    """Two s orbitals far from their images: E = -[(AA|AA) + (BB|BB) + 2 (AB|BA)]
+    with every pair density a Gaussian (product theorem) whose Coulomb energy is
+    the analytic lattice sum."""
+    L, a, b = 10.0, 1.2, 1.6
+    lat = np.eye(3) * L
+    A = np.array([3.0, 3.5, 4.0])
+    B = np.array([5.0, 4.6, 4.9])
+    w = ri.Workload("t", lat, np.array([64] * 3), np.stack([A, B]), np.array([0, 1]),
+                    np.array([0, 0]), np.array([a, b]), 2, 1, 0)
+    Phi = basis.eval_basis(w)
+    K, E = conventional.exchange_occ(Phi, np.eye(2), lat, w.mesh)
+
+    def nrm(x):
+        return (2 * x / math.pi) ** 0.75
+
+    def self_energy(x, X):      # (rho|rho) for rho = N_x^2 exp(-2 x |r-X|^2)
+        c = nrm(x) ** 2 / nrm(2 * x)
+        return c * c * brute.analytic_s_coulomb(lat, X, 2 * x, X, 2 * x)
+    p = a + b
+    P = (a * A + b * B) / p
+    cab = nrm(a) * nrm(b) * math.exp(-a * b / p * np.sum((A - B) ** 2)) / nrm(p)
+    cross = cab * cab * brute.analytic_s_coulomb(lat, P, p, P, p)
+    ref = -(self_energy(a, A) + self_energy(b, B) + 2 * cross)
+    assert abs(E - ref) < 1e-10 * abs(ref)
+    assert abs(E + np.trace(K)) < 1e-12 * abs(E)   # C = I: E = -tr(K)
+
+
+def test_conventional_matches_dense_and_full():
+    w = ri.tiny_s_cell(5, 6, 4.0, 2, 8, lmax=1)
+    Phi = basis.eval_basis(w)
+    dV = grid.dvol(w.lattice, w.mesh)
+    C = ri.lowdin(ri.random_coefficients(w), basis.overlap(Phi, dV))
+    K, E = conventional.exchange_occ(Phi, C, w.lattice, w.mesh)
+    Vd = brute.dense_coulomb(w.lattice, w.mesh)
+    U = Phi @ C
+    Kref = np.zeros_like(K)
+    Eref = 0.0
+    for j in range(U.shape[1]):
+        for i in range(U.shape[1]):
+            Vij = Vd @ (U[:, i] * U[:, j])
+            Kref[:, j] += dV * Phi.T @ (U[:, i] * Vij)
+            Eref -= dV * (U[:, i] * U[:, j]) @ Vij
+    np.testing.assert_allclose(K, Kref, atol=1e-13)
+    assert abs(E - Eref) < 1e-13
+    Kf = conventional.exchange_full(Phi, C, w.lattice, w.mesh)
+    np.testing.assert_allclose(Kf @ C, K, atol=1e-13)
+    np.testing.assert_allclose(Kf, Kf.T, atol=1e-13)
+    assert np.linalg.eigvalsh(Kf).min() > -1e-12      # exchange operator is PSD
+    assert E < 0
+
+
+# ---------------------------------------------------------------- ISDF + rPS
+@pytest.fixture(scope="module")
+def tiny():
+    w = ri.tiny_s_cell(6, 8, 4.0, 2, 8, lmax=1)
+    Phi = basis.eval_basis(w)
+    dV = grid.dvol(w.lattice, w.mesh)
+    C = ri.lowdin(ri.random_coefficients(w), basis.overlap(Phi, dV))
+    Kc, Ec = conventional.exchange_occ(Phi, C, w.lattice, w.mesh)
+    return w, Phi, dV, C, Kc, Ec
+
+
+def _delta(rho, pts, chi):
+    return rho - rho[..., pts] @ chi
+
+
+@pytest.mark.parametrize("naux", [10, 18, 30])
+def test_rps_error_identities(tiny, naux):
+    """Sec. 3.2: rPS keeps three of the four terms of the exact expansion and
+    drops the fit-error term.  Hence, with delta_ab = rho_ab - sum_g
+    rho_ab(R_g) chi_g computed independently:
+      E_rPS - E_conv         = + dV sum_ij <delta_ij, Vc delta_ij>  (>= 0)
+      K_rPS(mu,j) - K_conv   = - dV sum_i <delta_{mu i}, Vc delta_ij>
+    A dropped line, a wrong sign or a transposed operand breaks these."""
+    w, Phi, dV, C, Kc, Ec = tiny
+    st = isdf.setup(w.with_naux(naux), Phi, mode="global")
+    pts, chi = st["points"], st["chi"]
+    K, E, Etr = rps.build_occ(Phi, pts, st["V"], st["W"], C, dV)
+    U = Phi @ C
+    n = U.shape[1]
+    dij = np.stack([_delta(U[:, i] * U[:, j], pts, chi) for i in range(n) for j in range(n)])
+    eref = dV * np.sum(dij * grid.poisson(dij, w.lattice, w.mesh))
+    assert abs((E - Ec) - eref) < 1e-13 * max(1, abs(Ec))
+    assert E - Ec >= -1e-14
+    dK = np.zeros_like(K)
+    for i in range(n):
+        dmu = _delta((Phi * U[:, i][:, None]).T, pts, chi)           # (N, N_g)
+        for j in range(n):
+            vij = grid.poisson(_delta(U[:, i] * U[:, j], pts, chi), w.lattice, w.mesh)
+            dK[:, j] -= dV * dmu @ vij
+    np.testing.assert_allclose(K - Kc, dK, atol=1e-13)
+    assert abs(E - Etr) < 1e-13
+
+
+def test_rps_exact_with_all_points(tiny):
+    """N_chi = N_g: chi is the identity and rPS reproduces exact exchange."""
+    w, Phi, dV, C, Kc, Ec = tiny
+    pts = np.random.default_rng(5).permutation(w.ngrid)
+    st = isdf.setup(w.with_naux(w.ngrid), Phi, points=pts)
+    K, E, _ = rps.build_occ(Phi, pts, st["V"], st["W"], C, dV)
+    np.testing.assert_allclose(K, Kc, atol=1e-13)
+    assert abs(E - Ec) < 1e-13
+
+
+def test_rps_structure_and_invariants(tiny):
+    w, Phi, dV, C, Kc, Ec = tiny
+    st = isdf.setup(w.with_naux(18), Phi, mode="global")
+    pts = st["points"]
+    K, E, Etr, parts = rps.build_occ(Phi, pts, st["V"], st["W"], C, dV, return_parts=True)
+    CK = C.T @ K
+    np.testing.assert_allclose(CK, CK.T, atol=1e-14)                   # symmetric integrals
+    np.testing.assert_allclose(C.T @ parts["K1"], (C.T @ parts["K2"]).T, atol=1e-14)
+    Kf = rps.build_full(Phi, pts, st["V"], st["W"], C, dV)
+    np.testing.assert_allclose(Kf, Kf.T, atol=1e-14)
+    np.testing.assert_allclose(Kf @ C, K, atol=1e-14)
+    assert E < 0 and abs(E - Etr) < 1e-13
+    Q, _ = np.linalg.qr(np.random.default_rng(2).standard_normal((C.shape[1],) * 2))
+    K2, E2, _ = rps.build_occ(Phi, pts, st["V"], st["W"], C @ Q, dV)
+    assert abs(E2 - E) < 1e-13
+    np.testing.assert_allclose(K2, K @ Q, atol=1e-13)
+    np.testing.assert_allclose(st["W"], st["W"].T, atol=0)
+    assert np.linalg.eigvalsh(st["W"]).min() > -1e-10 * np.abs(st["W"]).max()
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    w = ri.tiny_cell()
+    Phi = basis.eval_basis(w)
+    dV = grid.dvol(w.lattice, w.mesh)
+    C = ri.lowdin(ri.random_coefficients(w), basis.overlap(Phi, dV))
+    Kc, Ec = conventional.exchange_occ(Phi, C, w.lattice, w.mesh)
+    return w, Phi, dV, C, Kc, Ec, basis.voronoi(w)
+
+
+@pytest.mark.parametrize("c", [5, 6])
+def test_ps_and_thc_errors_are_first_order(cfg1, c):
+    """Sec. 3.2: PS (line 1) and THC (line 3) carry O(eps) errors, rPS O(eps^2):
+    once the fit is good the rPS error is far below both."""
+    w, Phi, dV, C, Kc, Ec, own = cfg1
+    st = isdf.setup(w.with_naux(c * w.nbas), Phi, owner=own)
+    args = (Phi, st["points"], st["V"], st["W"], C, dV)
+    _, E, _ = rps.build_occ(*args)
+    _, Eps = rps.ps_occ(*args)
+    _, Ethc = rps.thc_occ(*args)
+    err = abs(E - Ec)
+    assert abs(Eps - Ec) > 10 * err and abs(Ethc - Ec) > 10 * err
+
+
+def test_fit_interpolates_and_solves_normal_equations(tiny):
+    w, Phi, dV, C, Kc, Ec = tiny
+    st = isdf.setup(w.with_naux(12), Phi, mode="global")
+    pts, chi = st["points"], st["chi"]
+    np.testing.assert_allclose(chi[:, pts], np.eye(len(pts)), atol=1e-8)
+    X = isdf.fitting_metric(Phi[pts])
+    XgR = (Phi[pts] @ Phi.T) ** 2
+    assert np.abs(X @ chi - XgR).max() < 1e-10 * np.abs(XgR).max()
+
+
+def test_randomized_qrcp_equals_full_qrcp_when_sketch_is_square():
+    """With p = N the sketch matrices are square orthogonal, the sketch is an
+    orthogonal row transform of the full pair matrix, and the pivots agree."""
+    w = ri.tiny_s_cell(4, 6, 4.0, 2, 8)
+    Phi = basis.eval_basis(w)
+    full = isdf.qrcp_full(Phi, 8)
+    sk = isdf.randomized_qrcp(Phi, 8, seed=77, streams=(0, 1))
+    assert isdf.sketch_size(8, 4) == 4
+    assert np.array_equal(full, sk)
+
+
+def test_qrcp_pivots_are_greedy_max_residual():
+    """QRCP pivot k = column of largest norm after projecting out pivots < k."""
+    w = ri.tiny_s_cell(5, 6, 4.0, 2, 8, lmax=1)
+    Phi = basis.eval_basis(w)
+    N = Phi.shape[1]
+    M = (Phi[:, :, None] * Phi[:, None, :]).reshape(Phi.shape[0], N * N).T
+    piv = isdf.qrcp_full(Phi, 10)
+    chosen = []
+    for k in range(10):
+        if chosen:
+            Q, _ = np.linalg.qr(M[:, chosen])
+            R = M - Q @ (Q.T @ M)
+        else:
+            R = M
+        nr = np.linalg.norm(R, axis=0)
+        nr[chosen] = -1
+        chosen.append(int(np.argmax(nr)))
+    assert list(piv) == chosen
+
+
+def test_voronoi_isdf_quality_config1(cfg1):
+    """Config-1 cell: the rPS energy error is non-negative and falls roughly
+    exponentially with c = N_chi/N (Sec. 5.2, 5.3); the global randomized ISDF
+    gives an error of the same size as v-ISDF (Sec. 5.1, Table 3)."""
+    w, Phi, dV, C, Kc, Ec, own = cfg1
+    errs = []
+    for c in (2, 3, 4, 5, 6):
+        st = isdf.setup(w.with_naux(c * w.nbas), Phi, owner=own)
+        _, E, _ = rps.build_occ(Phi, st["points"], st["V"], st["W"], C, dV)
+        errs.append(E - Ec)
+    assert all(e >= -1e-12 for e in errs)
+    assert all(errs[i + 1] < errs[i] / 3 for i in range(len(errs) - 1))
+    assert errs[-1] < 1e-3 * errs[0]
+    stg = isdf.setup(w, Phi, mode="global")
+    _, Eg, _ = rps.build_occ(Phi, stg["points"], stg["V"], stg["W"], C, dV)
+    assert 0 <= Eg - Ec < 10 * errs[2]
+
+
+# ---------------------------------------------------------------- inputs
+def test_workload_recipes():
+    w1 = ri.tiny_cell()
+    assert (w1.nbas, w1.nocc, w1.naux, w1.ngrid) == (40, 8, 160, 24 ** 3)
+    w2 = ri.diamond_cell(6.0)
+    assert (w2.nbas, w2.nocc, w2.naux, w2.ngrid, w2.natom) == (104, 16, 624, 48 ** 3, 8)
+    assert [ri.diamond_cell(c).naux for c in (4, 6, 8, 10)] == [416, 624, 832, 1040]
+    w3 = ri.diamond_2x2x2()
+    assert (w3.nbas, w3.nocc, w3.naux, w3.ngrid) == (832, 128, 4992, 72 ** 3)
+    w4 = ri.diamond_3x3x3()
+    assert (w4.nbas, w4.nocc, w4.naux, w4.ngrid) == (2808, 432, 12000, 108 ** 3)
+    assert np.array_equal(ri.diamond_cell().atoms, ri.diamond_cell().atoms)
+    b = ri.batch_cells()
+    assert len(b) == 64 and all(32 <= m <= 72 for x in b for m in x.mesh)
+    assert all(ri.smooth_235(int(m)) == int(m) for x in b for m in x.mesh)
+    assert all(x.naux == 6 * x.nbas and x.nocc == 2 * x.natom for x in b)
+
+
+def test_lowdin_orthonormal():
+    rg = np.random.default_rng(0)
+    X = rg.standard_normal((30, 30))
+    S = X @ X.T + 30 * np.eye(30)
+    C = ri.lowdin(rg.standard_normal((30, 7)), S)
+    np.testing.assert_allclose(C.T @ S @ C, np.eye(7), atol=1e-12)
+    C2 = ri.perturbed(C, S, 1, cid=3)
+    np.testing.assert_allclose(C2.T @ S @ C2, np.eye(7), atol=1e-12)
+    assert 1e-4 < np.abs(C2 - C).max() < 0.2
