@@ -1,0 +1,213 @@
+/*
+ * rps.h -- robust-pseudospectral (rPS) occ-RI exchange for periodic Gaussian
+ * basis sets on AMD Instinct MI355X (gfx950).  C ABI, version 1.
+ *
+ * Method: Sharma, White, Beylkin, "Fast exchange with Gaussian basis set using
+ * robust pseudospectral method" (arXiv:2207.04636).  Interpolation points and
+ * fitting functions chi_g (ISDF, Sec. 3.1, 4.3), the potentials V of chi_g and
+ * W = V chi^T (Sec. 3.2, Eq. 12 and 14) are set up once per geometry.  Each
+ * exchange build then evaluates Eq. 16 (occ-RI, Sec. 3.3) without any FFT.
+ *
+ * Conventions (all public floating point is IEEE binary64, row-major):
+ *  - Basis values are plain function values; the paper's pSinc coefficients
+ *    are sqrt(dV) times them, dV = Omega / N_g.  Every contraction carries a
+ *    single factor dV.
+ *  - Coulomb kernel 4 pi / |G|^2 on the plane waves of the grid (Sec. 2.2,
+ *    Eq. 7-8) with the G = 0 term removed (Sec. 4.5).  No Madelung term is
+ *    added: the paper's nM/2 correction is a constant per (n, cell).
+ *  - Grid point R(i1,i2,i3) = sum_k (i_k/N_k) a_k, linear index
+ *    (i1*N2 + i2)*N3 + i3.
+ *  - Shells: s; p in the order x, y, z; d as five real-spherical components
+ *    xy, yz, zx, x^2-y^2, 3z^2-r^2; free-space normalised primitives, one
+ *    exponent per shell, periodized by summing lattice images (Sec. 2.1.3).
+ *    Basis function order = shell order, components in the order above.
+ *  - K_occ[mu][i] = sum_j (mu j | j i)  (N x n_occ), the occ-RI exchange of
+ *    Eq. 16; E_x = -tr(C^T K_occ), closed shell with doubly occupied spatial
+ *    orbitals.
+ *
+ * Ownership: the caller owns every input and output buffer; the library copies
+ * what it keeps.  A context owns all device memory it allocates and frees it
+ * in rps_destroy.  Errors: no function aborts or throws; on failure the
+ * outputs are left untouched and rps_last_error() (thread-local) explains.
+ * Threading: a context is not thread-safe; use it from one host thread.
+ */
+#ifndef RPS_H
+#define RPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rps_context rps_context;
+
+typedef enum {
+    RPS_OK = 0,
+    RPS_ERR_ARG = 1,      /* null pointer, negative size, bad enum value */
+    RPS_ERR_SHAPE = 2,    /* inconsistent sizes (e.g. n_aux > N_g, duplicate points) */
+    RPS_ERR_NOMEM = 3,    /* memory estimate exceeds free device memory (checked before allocating) */
+    RPS_ERR_NOT_PD = 4,   /* fitting metric not positive definite even after the shift */
+    RPS_ERR_DEVICE = 5,   /* HIP runtime error */
+    RPS_ERR_STATE = 6     /* call out of order (e.g. build before a completed setup) */
+} rps_status;
+
+/* Arithmetic of the per-build contractions. */
+typedef enum {
+    RPS_PREC_FP64 = 0,    /* FP64 MFMA and FP64 accumulation throughout */
+    RPS_PREC_FP32 = 1,    /* V stored FP32; FP32 MFMA tiles, FP64 cross-tile accumulation */
+    RPS_PREC_BF16X3 = 2   /* V stored FP32; split hi+lo BF16 MFMA products, FP32 in tile, FP64 across */
+} rps_precision;
+
+/* Interpolation-point selection (Sec. 4.3). */
+typedef enum {
+    RPS_SELECT_VORONOI = 0,  /* per-atom randomized selection, then a global pass over the union */
+    RPS_SELECT_GLOBAL = 1    /* one randomized selection over the whole grid */
+} rps_select_mode;
+
+/* Exchange variants of Eq. 13 (Sec. 3.2). */
+typedef enum {
+    RPS_VARIANT_RPS = 0,  /* fit.exact + exact.fit - fit.fit (robust, error O(eps^2)) */
+    RPS_VARIANT_PS = 1,   /* first line only (pseudospectral, O(eps), asymmetric) */
+    RPS_VARIANT_THC = 2   /* third line only (tensor hypercontraction, O(eps)) */
+} rps_variant;
+
+#define RPS_PTRS_HOST 0    /* C, K, ex are host pointers; the call is synchronous */
+#define RPS_PTRS_DEVICE 1  /* C, K, ex are device pointers; stream-ordered, asynchronous */
+
+/* Periodic cell and grid (Sec. 2.1): lattice rows a1, a2, a3 in bohr. */
+typedef struct {
+    double lattice[9];
+    int32_t mesh[3];
+} rps_cell;
+
+/* Gaussian basis (Sec. 2.1.3).  Arrays are host memory, read during the call. */
+typedef struct {
+    int32_t natom;
+    int32_t nshell;
+    const double *atom_xyz;     /* [natom][3] cartesian positions, bohr */
+    const int32_t *shell_atom;  /* [nshell] atom index of each shell (its centre) */
+    const int32_t *shell_l;     /* [nshell] 0, 1 or 2 */
+    const double *shell_exp;    /* [nshell] exponent > 0, bohr^-2 */
+} rps_basis;
+
+/* Sizes and set-up diagnostics of a context. */
+typedef struct {
+    int64_t ngrid;        /* N_g */
+    int64_t nbas;         /* N */
+    int64_t naux;         /* N_chi */
+    int64_t ngrid_pad, nbas_pad, naux_pad;   /* padded extents of the device arrays */
+    int64_t n_candidates; /* |R_h| of the Voronoi selection (0 if points were given) */
+    double dvol;          /* Omega / N_g */
+    double chol_shift;    /* diagonal shift used by the fitting-metric Cholesky (0 if none) */
+    double setup_seconds; /* wall time of rps_setup_isdf */
+    int64_t device_bytes; /* device memory held by the context */
+    int32_t precision;
+    int32_t exact;        /* 1 if n_aux == N_g (chi = identity) */
+} rps_info;
+
+/*
+ * One-time set-up per geometry (Sec. 3.1, 3.2, 4.1, 4.3):
+ *   basis values Phi on the grid; interpolation points (points_in, or the
+ *   randomized selection of Sec. 4.3 with sketch matrices drawn from
+ *   Philox4x32-10 with the given seed); fitting metric X_gg = (Phi_g Phi_g^T)^2
+ *   and its FP64 Cholesky factor (retried once with the diagonal shift
+ *   1e-13 * max diag(X_gg) if the plain factorisation fails); chi = X_gg^-1
+ *   X_gR (Eq. 11); V[g,:] = Vc(chi_g) by FFT; W = V chi^T, symmetrised.
+ * cell, basis       : host structures (see above)
+ * n_aux             : number of interpolation points, 1 <= n_aux <= N_g.
+ *                     n_aux == N_g selects chi = identity (the exact case).
+ * seed              : 64-bit seed of the sketch matrices (ignored with points_in)
+ * select_mode       : rps_select_mode (ignored with points_in)
+ * precision         : rps_precision of later builds
+ * points_in         : NULL, or host array of n_aux distinct grid indices
+ * hip_stream        : hipStream_t to run on (NULL = default stream); the call
+ *                     is synchronous with respect to the host
+ * out               : receives the new context (unchanged on failure)
+ * Errors: RPS_ERR_ARG, RPS_ERR_SHAPE, RPS_ERR_NOMEM (before allocating),
+ *         RPS_ERR_NOT_PD, RPS_ERR_DEVICE.
+ */
+rps_status rps_setup_isdf(const rps_cell *cell, const rps_basis *basis, int64_t n_aux,
+                          uint64_t seed, int32_t select_mode, int32_t precision,
+                          const int64_t *points_in, void *hip_stream, rps_context **out);
+
+/*
+ * One exchange build, Eq. 16 (Sec. 3.3) with the contraction order of
+ * Sec. 4.4 for the second line:
+ *   U = Phi C, U_g = U[points], P = U_g U^T, A = V o P, P_g = U_g U_g^T,
+ *   B = W o P_g,  K_occ = dV [Phi^T (A^T U_g) + Phi_g^T (A U) - Phi_g^T (B U_g)],
+ *   E_x = -dV (2 sum A o P - sum B o P_g).
+ * nocc  : number of occupied orbitals n >= 1
+ * C     : [N][nocc] FP64 coefficients (host or device, see flags)
+ * K     : [N][nocc] FP64 output K_occ (host or device)
+ * ex    : FP64 output E_x, or NULL
+ * flags : RPS_PTRS_HOST or RPS_PTRS_DEVICE
+ * hip_stream : stream for device-pointer mode (NULL = default stream)
+ * Errors: RPS_ERR_ARG, RPS_ERR_STATE, RPS_ERR_NOMEM, RPS_ERR_DEVICE.
+ */
+rps_status rps_build_exchange_occRI(rps_context *ctx, int32_t nocc, const double *C, double *K,
+                                    double *ex, int32_t flags, void *hip_stream);
+
+/*
+ * Same as rps_build_exchange_occRI for the PS and THC approximations
+ * (variant = rps_variant; Sec. 3.2: PS keeps the first line of Eq. 13, THC the
+ * third).  RPS_VARIANT_RPS gives exactly rps_build_exchange_occRI.
+ */
+rps_status rps_build_exchange_variant(rps_context *ctx, int32_t variant, int32_t nocc,
+                                      const double *C, double *K, double *ex, int32_t flags,
+                                      void *hip_stream);
+
+/*
+ * Full exchange matrix K_{mu nu} = sum_i (mu i | i nu) with rPS integrals
+ * (Eq. 15 and its two partner terms of Eq. 13):
+ *   K = dV [Phi_g^T A Phi + (Phi_g^T A Phi)^T - Phi_g^T B Phi_g].
+ * Needed once at the end of an SCF run (Sec. 3.3).  K: [N][N] FP64.
+ */
+rps_status rps_build_exchange_full(rps_context *ctx, int32_t nocc, const double *C, double *K,
+                                   int32_t flags, void *hip_stream);
+
+/*
+ * Batched builds over several contexts (cells of different sizes), one call:
+ * C[b], K[b] as for rps_build_exchange_occRI, ex[b] per cell (ex may be NULL).
+ * All pointers are of the kind given by flags.
+ */
+rps_status rps_build_exchange_occRI_batched(rps_context *const *ctx, int32_t nbatch,
+                                            const int32_t *nocc, const double *const *C,
+                                            double *const *K, double *ex, int32_t flags,
+                                            void *hip_stream);
+
+/* E_x = -tr(C^T K) = -sum_{mu,i} C[mu][i] K[mu][i]; host FP64 arrays [nbas][nocc]. */
+rps_status rps_exchange_energy(int32_t nbas, int32_t nocc, const double *C, const double *K,
+                               double *ex);
+
+/* Grid overlap S = dV Phi^T Phi, host output [N][N] (for orthonormalising C). */
+rps_status rps_overlap(rps_context *ctx, double *S);
+
+/* Interpolation point indices in selection order, host output [n_aux]. */
+rps_status rps_get_points(const rps_context *ctx, int64_t *points_out);
+
+/* Sizes and diagnostics. */
+rps_status rps_get_info(const rps_context *ctx, rps_info *info);
+
+/*
+ * Copies of set-up products to host memory (inspection and tests).
+ * which: 0 = Phi rows [row0, row0+nrows) x N;   1 = V rows x N_g;
+ *        2 = W rows x N_chi;  3 = Voronoi owner of grid points row0.. (as double).
+ */
+rps_status rps_get_array(const rps_context *ctx, int32_t which, int64_t row0, int64_t nrows,
+                         double *out);
+
+/* Frees every device buffer of the context.  NULL is allowed. */
+void rps_destroy(rps_context *ctx);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *rps_last_error(void);
+
+/* ABI version (1). */
+int32_t rps_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPS_H */

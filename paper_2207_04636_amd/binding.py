@@ -1,0 +1,266 @@
+"""ctypes binding of librps.so (include/rps.h).  Argument marshalling only:
+every step of the set-up and of the exchange build runs in the HIP library.
+
+Host arrays are numpy float64 / int64; device arrays are torch CUDA (HIP)
+tensors, in which case the calls are ordered on the given (or current) torch
+stream and are asynchronous.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librps.so")
+
+RPS_OK, RPS_ERR_ARG, RPS_ERR_SHAPE, RPS_ERR_NOMEM, RPS_ERR_NOT_PD, RPS_ERR_DEVICE, RPS_ERR_STATE = range(7)
+PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
+SELECT_VORONOI, SELECT_GLOBAL = 0, 1
+VARIANT_RPS, VARIANT_PS, VARIANT_THC = 0, 1, 2
+PTRS_HOST, PTRS_DEVICE = 0, 1
+STATUS_NAMES = {0: "RPS_OK", 1: "RPS_ERR_ARG", 2: "RPS_ERR_SHAPE", 3: "RPS_ERR_NOMEM",
+                4: "RPS_ERR_NOT_PD", 5: "RPS_ERR_DEVICE", 6: "RPS_ERR_STATE"}
+
+# every symbol declared in include/rps.h
+EXPORTS = ("rps_setup_isdf", "rps_build_exchange_occRI", "rps_build_exchange_variant",
+           "rps_build_exchange_full", "rps_build_exchange_occRI_batched", "rps_exchange_energy",
+           "rps_overlap", "rps_get_points", "rps_get_info", "rps_get_array", "rps_destroy",
+           "rps_last_error", "rps_abi_version")
+
+
+class RpsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Cell(ct.Structure):
+    _fields_ = [("lattice", ct.c_double * 9), ("mesh", ct.c_int32 * 3)]
+
+
+class Basis(ct.Structure):
+    _fields_ = [("natom", ct.c_int32), ("nshell", ct.c_int32),
+                ("atom_xyz", ct.POINTER(ct.c_double)), ("shell_atom", ct.POINTER(ct.c_int32)),
+                ("shell_l", ct.POINTER(ct.c_int32)), ("shell_exp", ct.POINTER(ct.c_double))]
+
+
+class Info(ct.Structure):
+    _fields_ = [("ngrid", ct.c_int64), ("nbas", ct.c_int64), ("naux", ct.c_int64),
+                ("ngrid_pad", ct.c_int64), ("nbas_pad", ct.c_int64), ("naux_pad", ct.c_int64),
+                ("n_candidates", ct.c_int64), ("dvol", ct.c_double), ("chol_shift", ct.c_double),
+                ("setup_seconds", ct.c_double), ("device_bytes", ct.c_int64),
+                ("precision", ct.c_int32), ("exact", ct.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load librps.so; raises if it is not built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2207_04636_amd.build (no CPU fallback exists)")
+    # Load the HIP runtime by soname first, globally: if torch (or anything else)
+    # already loaded a libamdhip64.so.7 this returns that same instance, so the
+    # library and torch share one runtime.  Letting it arrive only as a private
+    # dependency of librps.so left the device undiscovered on the MI355X hosts.
+    try:
+        ct.CDLL("libamdhip64.so.7", mode=ct.RTLD_GLOBAL)
+    except OSError:
+        pass
+    lib = ct.CDLL(path)
+    P, I32, I64, U64, D = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_uint64, ct.c_double
+    lib.rps_setup_isdf.argtypes = [ct.POINTER(Cell), ct.POINTER(Basis), I64, U64, I32, I32,
+                                   ct.POINTER(ct.c_int64), P, ct.POINTER(P)]
+    lib.rps_build_exchange_occRI.argtypes = [P, I32, P, P, P, I32, P]
+    lib.rps_build_exchange_variant.argtypes = [P, I32, I32, P, P, P, I32, P]
+    lib.rps_build_exchange_full.argtypes = [P, I32, P, P, I32, P]
+    lib.rps_build_exchange_occRI_batched.argtypes = [ct.POINTER(P), I32, ct.POINTER(I32), ct.POINTER(P),
+                                                     ct.POINTER(P), P, I32, P]
+    lib.rps_exchange_energy.argtypes = [I32, I32, P, P, ct.POINTER(D)]
+    lib.rps_overlap.argtypes = [P, P]
+    lib.rps_get_points.argtypes = [P, P]
+    lib.rps_get_info.argtypes = [P, ct.POINTER(Info)]
+    lib.rps_get_array.argtypes = [P, I32, I64, I64, P]
+    lib.rps_destroy.argtypes = [P]
+    lib.rps_destroy.restype = None
+    lib.rps_last_error.restype = ct.c_char_p
+    for name in EXPORTS:
+        if name not in ("rps_destroy", "rps_last_error"):
+            getattr(lib, name).restype = ct.c_int32
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != RPS_OK:
+        raise RpsError(st, _lib.rps_last_error().decode())
+
+
+def _ptr(x) -> int:
+    """Address of a numpy array or torch tensor."""
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    return int(x.data_ptr())
+
+
+def _is_device(x) -> bool:
+    return not isinstance(x, np.ndarray) and getattr(x, "is_cuda", False)
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available() and torch.cuda.is_initialized():
+                return int(torch.cuda.current_stream().cuda_stream)
+        except Exception:
+            return None
+        return None
+    return int(getattr(stream, "cuda_stream", stream))
+
+
+class Context:
+    """An rPS set-up (points, V, W on the device) for one cell and basis."""
+
+    def __init__(self, lattice, mesh, atoms, shell_atom, shell_l, shell_exp, naux: int,
+                 seed: int = 0, select: int = SELECT_VORONOI, precision: int = PREC_FP64,
+                 points=None, stream=None):
+        lib = load()
+        self._lib = lib
+        cell = Cell()
+        lat = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(9))
+        cell.lattice[:] = list(lat)
+        cell.mesh[:] = [int(m) for m in mesh]
+        self._atoms = np.ascontiguousarray(np.asarray(atoms, dtype=np.float64).reshape(-1, 3))
+        self._sa = np.ascontiguousarray(np.asarray(shell_atom, dtype=np.int32))
+        self._sl = np.ascontiguousarray(np.asarray(shell_l, dtype=np.int32))
+        self._se = np.ascontiguousarray(np.asarray(shell_exp, dtype=np.float64))
+        b = Basis(int(self._atoms.shape[0]), int(self._sl.shape[0]),
+                  self._atoms.ctypes.data_as(ct.POINTER(ct.c_double)),
+                  self._sa.ctypes.data_as(ct.POINTER(ct.c_int32)),
+                  self._sl.ctypes.data_as(ct.POINTER(ct.c_int32)),
+                  self._se.ctypes.data_as(ct.POINTER(ct.c_double)))
+        pts = None
+        if points is not None:
+            self._pts_in = np.ascontiguousarray(np.asarray(points, dtype=np.int64))
+            pts = self._pts_in.ctypes.data_as(ct.POINTER(ct.c_int64))
+        h = ct.c_void_p()
+        _check(lib.rps_setup_isdf(ct.byref(cell), ct.byref(b), int(naux), ct.c_uint64(int(seed) & (2**64 - 1)),
+                                  int(select), int(precision), pts, _stream_handle(stream), ct.byref(h)))
+        self._h = h
+        inf = self.info()
+        self.nbas, self.naux, self.ngrid = int(inf["nbas"]), int(inf["naux"]), int(inf["ngrid"])
+        self.dvol = float(inf["dvol"])
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        """Convenience: any object with lattice, mesh, atoms, shell_atom,
+        shell_l, shell_exp and naux attributes."""
+        kw.setdefault("naux", w.naux)
+        return cls(w.lattice, w.mesh, w.atoms, w.shell_atom, w.shell_l, w.shell_exp, **kw)
+
+    # ---------------------------------------------------------------- builds
+    def build(self, C, K=None, ex=None, variant: int = VARIANT_RPS, stream=None):
+        """K_occ (N x n) and E_x.  numpy C -> synchronous host call returning
+        (K, E); torch CUDA C -> stream-ordered call writing K (and ex, a
+        1-element float64 tensor) and returning them."""
+        if _is_device(C):
+            import torch
+            if C.dtype != torch.float64 or not C.is_contiguous():
+                raise ValueError("C must be a contiguous float64 tensor")
+            n = int(C.shape[1])
+            if K is None:
+                K = torch.empty((self.nbas, n), dtype=torch.float64, device=C.device)
+            exp_ = 0 if ex is None else _ptr(ex)
+            _check(self._lib.rps_build_exchange_variant(self._h, int(variant), n, _ptr(C), _ptr(K), exp_ or None,
+                                                        PTRS_DEVICE, _stream_handle(stream)))
+            return K, ex
+        C = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
+        n = int(C.shape[1])
+        Kh = np.empty((self.nbas, n))
+        e = ct.c_double(0.0)
+        _check(self._lib.rps_build_exchange_variant(self._h, int(variant), n, C.ctypes.data, Kh.ctypes.data,
+                                                    ct.addressof(e), PTRS_HOST, None))
+        return Kh, e.value
+
+    def build_full(self, C):
+        C = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
+        Kh = np.empty((self.nbas, self.nbas))
+        _check(self._lib.rps_build_exchange_full(self._h, int(C.shape[1]), C.ctypes.data, Kh.ctypes.data,
+                                                 PTRS_HOST, None))
+        return Kh
+
+    # ---------------------------------------------------------------- inspection
+    def points(self) -> np.ndarray:
+        out = np.empty(self.naux, dtype=np.int64)
+        _check(self._lib.rps_get_points(self._h, out.ctypes.data))
+        return out
+
+    def info(self) -> dict:
+        inf = Info()
+        _check(self._lib.rps_get_info(self._h, ct.byref(inf)))
+        return inf.as_dict()
+
+    def overlap(self) -> np.ndarray:
+        S = np.empty((self.nbas, self.nbas))
+        _check(self._lib.rps_overlap(self._h, S.ctypes.data))
+        return S
+
+    def array(self, which: int, row0: int = 0, nrows: Optional[int] = None) -> np.ndarray:
+        """0: Phi rows (N_g x N), 1: V rows (N_chi x N_g), 2: W (N_chi x N_chi),
+        3: Voronoi owner per grid point."""
+        total = {0: self.ngrid, 1: self.naux, 2: self.naux, 3: self.ngrid}[which]
+        ncol = {0: self.nbas, 1: self.ngrid, 2: self.naux, 3: 1}[which]
+        nrows = total - row0 if nrows is None else nrows
+        out = np.empty((nrows, ncol)) if which != 3 else np.empty(nrows)
+        _check(self._lib.rps_get_array(self._h, int(which), int(row0), int(nrows), out.ctypes.data))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.rps_destroy(self._h)
+            self._h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def exchange_energy(C: np.ndarray, K: np.ndarray) -> float:
+    """E_x = -tr(C^T K) through the library's host routine."""
+    lib = load()
+    C = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
+    K = np.ascontiguousarray(np.asarray(K, dtype=np.float64))
+    e = ct.c_double(0.0)
+    _check(lib.rps_exchange_energy(int(C.shape[0]), int(C.shape[1]), C.ctypes.data, K.ctypes.data, ct.byref(e)))
+    return e.value
+
+
+def build_batched(ctxs, Cs, Ks, ex=None, stream=None):
+    """Batched builds over several contexts (device tensors)."""
+    lib = load()
+    nb = len(ctxs)
+    H = (ct.c_void_p * nb)(*[c._h.value for c in ctxs])
+    nocc = (ct.c_int32 * nb)(*[int(C.shape[1]) for C in Cs])
+    Cp = (ct.c_void_p * nb)(*[_ptr(C) for C in Cs])
+    Kp = (ct.c_void_p * nb)(*[_ptr(K) for K in Ks])
+    dev = _is_device(Cs[0]) if nb else False
+    _check(lib.rps_build_exchange_occRI_batched(H, nb, nocc, Cp, Kp, None if ex is None else _ptr(ex),
+                                                PTRS_DEVICE if dev else PTRS_HOST, _stream_handle(stream)))

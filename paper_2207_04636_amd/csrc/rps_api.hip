@@ -1,0 +1,721 @@
+// C ABI of the rPS exchange library: context, one-time ISDF set-up and the
+// per-build exchange (see include/rps.h for the contract of every entry point).
+#include <math.h>
+#include <string.h>
+
+#include <cmath>
+
+#include <algorithm>
+#include <chrono>
+#include <exception>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rps.h"
+#include "host_util.h"
+#include "rps_internal.h"
+
+using namespace rps;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Fail {
+  rps_status st;
+  std::string msg;
+};
+
+[[noreturn]] void fail(rps_status st, const std::string& m) { throw Fail{st, m}; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(RPS_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Device buffer owned by a context.
+template <typename Tp>
+struct DBuf {
+  Tp* p = nullptr;
+  int64_t n = 0;
+  void alloc(int64_t count, int64_t* counter) {
+    release(counter);
+    if (count <= 0) return;
+    hip_check(hipMalloc((void**)&p, sizeof(Tp) * count), "hipMalloc");
+    n = count;
+    if (counter) *counter += (int64_t)sizeof(Tp) * count;
+  }
+  void release(int64_t* counter) {
+    if (p) {
+      (void)hipFree(p);
+      if (counter) *counter -= (int64_t)sizeof(Tp) * n;
+    }
+    p = nullptr;
+    n = 0;
+  }
+};
+
+}  // namespace
+
+struct rps_context {
+  // geometry and sizes
+  double lat[9], ainv[9];
+  int mesh[3];
+  int64_t ng = 0, ngp = 0, nbas = 0, Np = 0, naux = 0, nauxp = 0;
+  int natom = 0;
+  double dV = 0.0;
+  int precision = 0;
+  int exact = 0;
+  double shift = 0.0;
+  double setup_seconds = 0.0;
+  int64_t ncand = 0;
+  int64_t bytes = 0;
+  std::vector<int64_t> points;
+  std::vector<int32_t> owner_host;
+  // persistent device data
+  DBuf<double> Phi, Phig, V, W;
+  DBuf<float> V32;
+  DBuf<int64_t> dpoints;
+  // build workspace (grows on demand)
+  int ws_np = -1;
+  DBuf<double> Cp, U, Ug, M2p, K1p, K3p, e1p, e3p, M2, K1, K2, K3, Kdev, Cdev, exdev;
+  int64_t rblocks_main = 0, blocks_main = 0, blocks_l3 = 0;
+  int rtiles = 4, gblocks = 1;
+
+  ~rps_context() {
+    DBuf<double>* all[] = {&Phi, &Phig, &V, &W, &Cp, &U, &Ug, &M2p, &K1p, &K3p, &e1p,
+                           &e3p, &M2, &K1, &K2, &K3, &Kdev, &Cdev, &exdev};
+    for (auto* b : all) b->release(nullptr);
+    V32.release(nullptr);
+    dpoints.release(nullptr);
+  }
+};
+
+namespace {
+
+// ------------------------------------------------------------------ set-up helpers
+constexpr double kCutoff = 50.0;
+constexpr double kCholShift = 1e-13;
+constexpr int kOversample = 4;
+
+CellDev make_cell(const rps_context& c) {
+  CellDev d;
+  memcpy(d.a, c.lat, sizeof d.a);
+  memcpy(d.ainv, c.ainv, sizeof d.ainv);
+  for (int k = 0; k < 3; ++k) d.mesh[k] = c.mesh[k];
+  return d;
+}
+
+// Image ranges: a displacement reduced to |f_k| <= 1/2 reaches every image
+// within radius rc when |n_k| <= rc/h_k + 1/2 (h_k = spacing of lattice planes).
+std::vector<ShellDev> make_shells(const rps_context& c, const rps_basis* b, std::vector<int>& nfunc_atom) {
+  const int nf[3] = {1, 3, 5};
+  double h[3];
+  for (int k = 0; k < 3; ++k) {
+    // |A_k| = 2 pi |row k of (a^-1)^T| ; h_k = 2 pi / |A_k| = 1 / |column k of a^-1|
+    const double x = c.ainv[0 * 3 + k], y = c.ainv[1 * 3 + k], z = c.ainv[2 * 3 + k];
+    h[k] = 1.0 / sqrt(x * x + y * y + z * z);
+  }
+  std::vector<ShellDev> out(b->nshell);
+  nfunc_atom.assign(b->natom, 0);
+  int ofs = 0;
+  for (int s = 0; s < b->nshell; ++s) {
+    const int at = b->shell_atom[s];
+    const double* A = b->atom_xyz + 3 * at;
+    ShellDev& d = out[s];
+    d.cx = A[0]; d.cy = A[1]; d.cz = A[2];
+    d.expo = b->shell_exp[s];
+    d.l = b->shell_l[s];
+    d.fofs = ofs;
+    const double rc = sqrt(kCutoff / d.expo);
+    d.m0 = (int)ceil(rc / h[0] + 0.5);
+    d.m1 = (int)ceil(rc / h[1] + 0.5);
+    d.m2 = (int)ceil(rc / h[2] + 0.5);
+    ofs += nf[d.l];
+    nfunc_atom[at] += nf[d.l];
+  }
+  return out;
+}
+
+// Leading k pivots of the Gram matrix (A A^T) o (B B^T) of the sketch of the
+// pair products at the candidate rows `cand` (Sec. 3.1, 4.3).
+std::vector<int64_t> select_pivots(rps_context& c, const std::vector<int64_t>& cand, int64_t k,
+                                   uint64_t seed, uint32_t s1, uint32_t s2, hipStream_t st) {
+  const int64_t nc = (int64_t)cand.size();
+  k = std::min(k, nc);
+  const int64_t N = c.nbas;
+  int64_t p = (int64_t)ceil(sqrt((double)k)) + kOversample;
+  if (p > N) p = N;
+  std::vector<double> G1 = sketch_normal(N, p, seed, s1);
+  std::vector<double> G2 = sketch_normal(N, p, seed, s2);
+  orthonormalize_columns(G1, N, p);
+  orthonormalize_columns(G2, N, p);
+  // padded to Np rows
+  std::vector<double> G12((size_t)c.Np * 2 * p, 0.0);
+  for (int64_t r = 0; r < N; ++r)
+    for (int64_t q = 0; q < p; ++q) {
+      G12[r * 2 * p + q] = G1[r * p + q];
+      G12[r * 2 * p + p + q] = G2[r * p + q];
+    }
+  int64_t tmpb = 0;
+  DBuf<double> dG, Phic, AB, Gram, Lb, diag;
+  DBuf<int64_t> dcand, dpiv;
+  dG.alloc(c.Np * 2 * p, &tmpb);
+  dcand.alloc(nc, &tmpb);
+  dpiv.alloc(k, &tmpb);
+  Phic.alloc(nc * c.Np, &tmpb);
+  AB.alloc(nc * 2 * p, &tmpb);
+  Gram.alloc(nc * nc, &tmpb);
+  Lb.alloc(nc * k, &tmpb);
+  diag.alloc(nc + k, &tmpb);
+  hip_check(hipMemcpyAsync(dG.p, G12.data(), G12.size() * 8, hipMemcpyHostToDevice, st), "copy sketch");
+  hip_check(hipMemcpyAsync(dcand.p, cand.data(), nc * 8, hipMemcpyHostToDevice, st), "copy candidates");
+  hip_check(gather_rows(c.Phi.p, c.Np, dcand.p, nc, nc, c.Np, Phic.p, c.Np, st), "gather");
+  Gemm g;                                    // [A | B] = Phi_c [G1 | G2]
+  g.M = nc; g.N = 2 * p; g.K = c.Np;
+  g.A = Phic.p; g.lda = c.Np; g.B = dG.p; g.ldb = 2 * p; g.C = AB.p; g.ldc = 2 * p;
+  hip_check(gemm_f64(g, st), "sketch product");
+  Gemm ga;                                   // Gram = A A^T
+  ga.M = nc; ga.N = nc; ga.K = p;
+  ga.A = AB.p; ga.lda = 2 * p; ga.B = AB.p; ga.ldb = 2 * p; ga.transB = true;
+  ga.C = Gram.p; ga.ldc = nc;
+  hip_check(gemm_f64(ga, st), "gram A");
+  Gemm gb = ga;                              // Gram o= B B^T
+  gb.A = AB.p + p; gb.B = AB.p + p; gb.epi = EPI_HADAMARD;
+  hip_check(gemm_f64(gb, st), "gram B");
+  hip_check(pivoted_cholesky(Gram.p, nc, nc, k, dpiv.p, Lb.p, diag.p, st), "pivoted cholesky");
+  std::vector<int64_t> piv(k);
+  hip_check(hipMemcpyAsync(piv.data(), dpiv.p, k * 8, hipMemcpyDeviceToHost, st), "copy pivots");
+  hip_check(hipStreamSynchronize(st), "sync");
+  DBuf<double>* bufs[] = {&dG, &Phic, &AB, &Gram, &Lb, &diag};
+  for (auto* b : bufs) b->release(nullptr);
+  dcand.release(nullptr);
+  dpiv.release(nullptr);
+  std::vector<int64_t> out(k);
+  for (int64_t i = 0; i < k; ++i) out[i] = cand[piv[i]];
+  return out;
+}
+
+void select_points(rps_context& c, int mode, uint64_t seed, const std::vector<int>& nfunc_atom,
+                   const double* atoms, hipStream_t st) {
+  const int64_t global_limit = 16384;   // Gram of all grid points must stay small
+  auto global = [&]() {
+    if (c.ng > global_limit)
+      fail(RPS_ERR_ARG, "global selection builds the N_g x N_g Gram matrix and is limited to N_g <= 16384; "
+                        "use RPS_SELECT_VORONOI");
+    std::vector<int64_t> all(c.ng);
+    for (int64_t i = 0; i < c.ng; ++i) all[i] = i;
+    c.points = select_pivots(c, all, c.naux, seed, 0, 1, st);
+    c.ncand = c.ng;
+  };
+  if (mode == RPS_SELECT_GLOBAL) {
+    global();
+    return;
+  }
+  // Voronoi sets (Sec. 4.1)
+  DBuf<int32_t> own;
+  int64_t tmpb = 0;
+  own.alloc(c.ng, &tmpb);
+  DBuf<double> datoms;
+  datoms.alloc(3 * (int64_t)c.natom, &tmpb);
+  hip_check(hipMemcpyAsync(datoms.p, atoms, 3 * c.natom * 8, hipMemcpyHostToDevice, st), "copy atoms");
+  hip_check(voronoi_assign(make_cell(c), datoms.p, c.natom, c.ng, own.p, st), "voronoi");
+  c.owner_host.resize(c.ng);
+  hip_check(hipMemcpyAsync(c.owner_host.data(), own.p, c.ng * 4, hipMemcpyDeviceToHost, st), "copy owner");
+  hip_check(hipStreamSynchronize(st), "sync");
+  own.release(nullptr);
+  datoms.release(nullptr);
+  std::vector<std::vector<int64_t>> kappa(c.natom);
+  for (int64_t R = 0; R < c.ng; ++R) kappa[c.owner_host[R]].push_back(R);
+  const double cfac = (double)c.naux / (double)c.nbas;
+  std::vector<int64_t> Rh;
+  for (int I = 0; I < c.natom; ++I) {
+    if (kappa[I].empty()) continue;
+    int64_t KI = (int64_t)ceil(cfac * nfunc_atom[I] - 1e-9) + 10;
+    KI = std::min<int64_t>(KI, (int64_t)kappa[I].size());
+    std::vector<int64_t> pi = select_pivots(c, kappa[I], KI, seed, 2 + 2 * I, 3 + 2 * I, st);
+    Rh.insert(Rh.end(), pi.begin(), pi.end());
+  }
+  if ((int64_t)Rh.size() < c.naux) {
+    global();
+    return;
+  }
+  c.ncand = (int64_t)Rh.size();
+  c.points = select_pivots(c, Rh, c.naux, seed, 0, 1, st);
+}
+
+void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_t n_aux, uint64_t seed,
+                int32_t mode, int32_t prec, const int64_t* points_in, hipStream_t st) {
+  auto t0 = std::chrono::steady_clock::now();
+  // ---- validation
+  if (!cell || !b) fail(RPS_ERR_ARG, "cell and basis must not be NULL");
+  if (b->natom < 1 || b->nshell < 1 || !b->atom_xyz || !b->shell_atom || !b->shell_l || !b->shell_exp)
+    fail(RPS_ERR_ARG, "basis needs natom >= 1, nshell >= 1 and non-NULL arrays");
+  if (prec < RPS_PREC_FP64 || prec > RPS_PREC_BF16X3) fail(RPS_ERR_ARG, "unknown precision");
+  if (mode != RPS_SELECT_VORONOI && mode != RPS_SELECT_GLOBAL) fail(RPS_ERR_ARG, "unknown selection mode");
+  memcpy(c.lat, cell->lattice, sizeof c.lat);
+  const double vol = fabs(det3(c.lat));
+  if (!(vol > 1e-10) || !inv3(c.lat, c.ainv)) fail(RPS_ERR_ARG, "lattice is singular");
+  for (int k = 0; k < 3; ++k) {
+    c.mesh[k] = cell->mesh[k];
+    if (c.mesh[k] < 2 || c.mesh[k] > 128) fail(RPS_ERR_SHAPE, "mesh sizes must be in [2, 128]");
+  }
+  c.natom = b->natom;
+  int64_t nb = 0;
+  for (int s = 0; s < b->nshell; ++s) {
+    const int l = b->shell_l[s];
+    if (l < 0 || l > 2) fail(RPS_ERR_ARG, "shell_l must be 0, 1 or 2");
+    if (!(b->shell_exp[s] > 0.0) || !std::isfinite(b->shell_exp[s])) fail(RPS_ERR_ARG, "shell exponents must be > 0");
+    if (b->shell_atom[s] < 0 || b->shell_atom[s] >= b->natom) fail(RPS_ERR_ARG, "shell_atom out of range");
+    nb += (l == 0) ? 1 : (l == 1) ? 3 : 5;
+  }
+  c.nbas = nb;
+  c.ng = (int64_t)c.mesh[0] * c.mesh[1] * c.mesh[2];
+  c.dV = vol / (double)c.ng;
+  if (n_aux < 1 || n_aux > c.ng) fail(RPS_ERR_SHAPE, "n_aux must be in [1, N_g]");
+  c.naux = n_aux;
+  c.precision = prec;
+  c.exact = (n_aux == c.ng);
+  c.ngp = round_up(c.ng, 64);
+  c.Np = round_up(c.nbas, 16);
+  c.nauxp = round_up(c.naux, 64);
+  if (points_in) {
+    std::vector<char> seen(c.ng, 0);
+    for (int64_t g = 0; g < n_aux; ++g) {
+      const int64_t p = points_in[g];
+      if (p < 0 || p >= c.ng) fail(RPS_ERR_SHAPE, "points_in entry out of range");
+      if (seen[p]) fail(RPS_ERR_SHAPE, "points_in has a duplicate grid index");
+      seen[p] = 1;
+    }
+  }
+  // ---- memory estimate before any allocation
+  {
+    const double persist = 8.0 * ((double)c.ngp * c.Np + (double)c.nauxp * c.Np + (double)c.nauxp * c.ngp +
+                                  (double)c.nauxp * c.nauxp) +
+                           ((prec != RPS_PREC_FP64) ? 4.0 * (double)c.nauxp * c.ngp : 0.0);
+    const double xgg = 8.0 * 3.0 * (double)c.nauxp * c.nauxp;   // L, T and its transpose
+    const int64_t bc = 8192;
+    const double xblk = 8.0 * (double)c.nauxp * bc;
+    double selb = 0.0;
+    if (!points_in && !c.exact) {
+      const double ncand = (mode == RPS_SELECT_GLOBAL) ? (double)c.ng : (double)c.naux + 10.0 * c.natom + 64;
+      const double kap = 4.0 * (double)c.ng / std::max(1, c.natom) + 1024;   // generous Voronoi set
+      const double nmax = std::max(ncand, kap);
+      selb = 8.0 * (nmax * nmax + nmax * (double)c.naux + nmax * (double)c.Np);
+    }
+    const double need = persist + std::max(xgg + xblk, selb) + 64.0 * 1024 * 1024;
+    size_t fr = 0, tot = 0;
+    hip_check(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
+    if (need > (double)fr)
+      fail(RPS_ERR_NOMEM, "set-up needs about " + std::to_string((int64_t)(need / 1e9)) + " GB, " +
+                              std::to_string((int64_t)(fr / 1000000000ull)) + " GB free");
+  }
+  // ---- basis on the grid (Sec. 2.1.3)
+  std::vector<int> nfunc_atom;
+  std::vector<ShellDev> shells = make_shells(c, b, nfunc_atom);
+  c.Phi.alloc(c.ngp * c.Np, &c.bytes);
+  hip_check(fill(c.Phi.p, c.ngp * c.Np, 0.0, st), "fill");
+  {
+    DBuf<ShellDev> dsh;
+    hip_check(hipMalloc((void**)&dsh.p, sizeof(ShellDev) * shells.size()), "hipMalloc");
+    dsh.n = (int64_t)shells.size();
+    hip_check(hipMemcpyAsync(dsh.p, shells.data(), sizeof(ShellDev) * shells.size(), hipMemcpyHostToDevice, st),
+              "copy shells");
+    hip_check(basis_eval(make_cell(c), dsh.p, (int)shells.size(), c.ng, c.Phi.p, c.Np, st), "basis");
+    hip_check(hipStreamSynchronize(st), "sync");
+    (void)hipFree(dsh.p);
+    dsh.p = nullptr;
+  }
+  // ---- interpolation points
+  if (points_in) {
+    c.points.assign(points_in, points_in + n_aux);
+  } else if (c.exact) {
+    c.points.resize(c.ng);
+    for (int64_t i = 0; i < c.ng; ++i) c.points[i] = i;
+  } else {
+    select_points(c, mode, seed, nfunc_atom, b->atom_xyz, st);
+  }
+  c.dpoints.alloc(c.naux, &c.bytes);
+  hip_check(hipMemcpyAsync(c.dpoints.p, c.points.data(), c.naux * 8, hipMemcpyHostToDevice, st), "copy points");
+  c.Phig.alloc(c.nauxp * c.Np, &c.bytes);
+  hip_check(gather_rows(c.Phi.p, c.Np, c.dpoints.p, c.naux, c.nauxp, c.Np, c.Phig.p, c.Np, st), "gather");
+  c.V.alloc(c.nauxp * c.ngp, &c.bytes);
+  hip_check(fill(c.V.p, c.nauxp * c.ngp, 0.0, st), "fill");
+  c.W.alloc(c.nauxp * c.nauxp, &c.bytes);
+  hip_check(fill(c.W.p, c.nauxp * c.nauxp, 0.0, st), "fill");
+  std::vector<double> kern = coulomb_kernel_table(c.lat, c.mesh);
+  DBuf<double> dkern;
+  int64_t tmpb = 0;
+  dkern.alloc(c.ng, &tmpb);
+  hip_check(hipMemcpyAsync(dkern.p, kern.data(), c.ng * 8, hipMemcpyHostToDevice, st), "copy kernel");
+
+  if (c.exact) {
+    // chi = identity on the chosen order: V[g] = Vc e_{points[g]}, W[g][g'] = V[g][points[g']]
+    hip_check(set_unit_rows(c.V.p, c.ngp, c.dpoints.p, c.naux, st), "unit rows");
+    hip_check(poisson_rows(c.V.p, c.nauxp, c.ngp, c.mesh, dkern.p, st), "poisson");
+    hip_check(gather_cols(c.V.p, c.ngp, c.dpoints.p, c.naux, c.W.p, c.nauxp, st), "W");
+  } else {
+    // ---- fitting metric and Cholesky (Sec. 3.1 Eq. 11, Sec. 4.3)
+    DBuf<double> L;
+    L.alloc(c.nauxp * c.nauxp, &tmpb);
+    int32_t* dstatus = nullptr;
+    hip_check(hipMalloc((void**)&dstatus, sizeof(int32_t)), "hipMalloc");
+    auto form_metric = [&]() {
+      hip_check(fill(L.p, c.nauxp * c.nauxp, 0.0, st), "fill");
+      Gemm g;
+      g.M = c.nauxp; g.N = c.nauxp; g.K = c.Np;
+      g.A = c.Phig.p; g.lda = c.Np; g.B = c.Phig.p; g.ldb = c.Np; g.transB = true;
+      g.C = L.p; g.ldc = c.nauxp; g.epi = EPI_SQUARE;
+      hip_check(gemm_f64(g, st), "metric");
+      hip_check(add_diag(L.p, c.nauxp, c.naux, c.nauxp, 1.0, st), "pad diag");
+    };
+    form_metric();
+    int32_t status = 0;
+    hip_check(cholesky_lower(L.p, c.nauxp, c.nauxp, dstatus, st), "cholesky");
+    hip_check(hipMemcpyAsync(&status, dstatus, 4, hipMemcpyDeviceToHost, st), "copy status");
+    hip_check(hipStreamSynchronize(st), "sync");
+    if (status != 0) {
+      form_metric();
+      std::vector<double> dg(c.naux);
+      hip_check(hipMemcpy2DAsync(dg.data(), 8, L.p, (c.nauxp + 1) * 8, 8, c.naux, hipMemcpyDeviceToHost, st),
+                "copy diag");
+      hip_check(hipStreamSynchronize(st), "sync");
+      double mx = 0.0;
+      for (double v : dg) mx = std::max(mx, v);
+      c.shift = kCholShift * mx;
+      hip_check(add_diag(L.p, c.nauxp, 0, c.naux, c.shift, st), "shift");
+      hip_check(cholesky_lower(L.p, c.nauxp, c.nauxp, dstatus, st), "cholesky");
+      hip_check(hipMemcpyAsync(&status, dstatus, 4, hipMemcpyDeviceToHost, st), "copy status");
+      hip_check(hipStreamSynchronize(st), "sync");
+      if (status != 0) {
+        (void)hipFree(dstatus);
+        fail(RPS_ERR_NOT_PD, "fitting metric is not positive definite at row " + std::to_string(status - 1) +
+                                 " even with the diagonal shift (duplicate or degenerate points?)");
+      }
+    }
+    (void)hipFree(dstatus);
+    // ---- X_gR = (Phi_g Phi^T)^2 into the V buffer, chi = X_gg^-1 X_gR
+    {
+      Gemm g;
+      g.M = c.nauxp; g.N = c.ngp; g.K = c.Np;
+      g.A = c.Phig.p; g.lda = c.Np; g.B = c.Phi.p; g.ldb = c.Np; g.transB = true;
+      g.C = c.V.p; g.ldc = c.ngp; g.epi = EPI_SQUARE;
+      hip_check(gemm_f64(g, st), "X_gR");
+    }
+    hip_check(tri_solve_lower(L.p, c.nauxp, c.nauxp, c.V.p, c.ngp, c.ngp, false, st), "solve L");
+    hip_check(tri_solve_lower(L.p, c.nauxp, c.nauxp, c.V.p, c.ngp, c.ngp, true, st), "solve L^T");
+    // ---- V = Vc chi (Sec. 3.2)
+    hip_check(poisson_rows(c.V.p, c.nauxp, c.ngp, c.mesh, dkern.p, st), "poisson");
+    // ---- W = V chi^T = (V X_gR^T) X_gg^-1  (Eq. 14), X_gR recomputed in column blocks
+    {
+      const int64_t bc = 8192;
+      DBuf<double> T, Xb;
+      T.alloc(c.nauxp * c.nauxp, &tmpb);
+      Xb.alloc(c.nauxp * bc, &tmpb);
+      for (int64_t r0 = 0; r0 < c.ngp; r0 += bc) {
+        const int64_t nc = std::min(bc, c.ngp - r0);
+        Gemm g;
+        g.M = c.nauxp; g.N = nc; g.K = c.Np;
+        g.A = c.Phig.p; g.lda = c.Np; g.B = c.Phi.p + r0 * c.Np; g.ldb = c.Np; g.transB = true;
+        g.C = Xb.p; g.ldc = bc; g.epi = EPI_SQUARE;
+        hip_check(gemm_f64(g, st), "X_gR block");
+        Gemm t;
+        t.M = c.nauxp; t.N = c.nauxp; t.K = nc;
+        t.A = c.V.p + r0; t.lda = c.ngp; t.B = Xb.p; t.ldb = bc; t.transB = true;
+        t.C = T.p; t.ldc = c.nauxp; t.beta = (r0 == 0) ? 0.0 : 1.0;
+        hip_check(gemm_f64(t, st), "T");
+      }
+      // W^T = X_gg^-1 T^T
+      hip_check(transpose(T.p, c.nauxp, c.nauxp, c.nauxp, c.W.p, c.nauxp, st), "transpose");
+      hip_check(tri_solve_lower(L.p, c.nauxp, c.nauxp, c.W.p, c.nauxp, c.nauxp, false, st), "solve L");
+      hip_check(tri_solve_lower(L.p, c.nauxp, c.nauxp, c.W.p, c.nauxp, c.nauxp, true, st), "solve L^T");
+      hip_check(symmetrize(c.W.p, c.nauxp, c.nauxp, st), "symmetrize");
+      hip_check(hipStreamSynchronize(st), "sync");
+      T.release(nullptr);
+      Xb.release(nullptr);
+    }
+    L.release(nullptr);
+  }
+  hip_check(hipStreamSynchronize(st), "sync");
+  dkern.release(nullptr);
+  if (prec != RPS_PREC_FP64) {
+    c.V32.alloc(c.nauxp * c.ngp, &c.bytes);
+    hip_check(to_f32(c.V.p, c.nauxp * c.ngp, c.V32.p, st), "to f32");
+    hip_check(hipStreamSynchronize(st), "sync");
+  }
+  c.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ------------------------------------------------------------------ builds
+void ensure_workspace(rps_context& c, int np) {
+  if (c.ws_np == np) return;
+  int64_t* cnt = &c.bytes;
+  // launch shape of the fused kernel: aim for >= 2 workgroups per CU
+  c.rtiles = 4;
+  c.gblocks = 1;
+  const int64_t rt = c.ngp / 64;
+  int64_t rblocks = (rt + c.rtiles - 1) / c.rtiles;
+  while (rblocks * c.gblocks < 512 && c.gblocks * 2 <= c.nauxp / 64) {
+    if (c.rtiles > 1) {
+      c.rtiles /= 2;
+    } else {
+      c.gblocks *= 2;
+    }
+    rblocks = (rt + c.rtiles - 1) / c.rtiles;
+  }
+  c.rblocks_main = rblocks;
+  c.blocks_main = rblocks * c.gblocks;
+  c.blocks_l3 = (c.nauxp / 64 + 3) / 4;      // line 3: 4 tiles per block, one g block
+  c.Cp.alloc(c.Np * np, cnt);
+  c.U.alloc(c.ngp * np, cnt);
+  c.Ug.alloc(c.nauxp * np, cnt);
+  c.M2p.alloc(c.rblocks_main * c.nauxp * np, cnt);
+  c.K1p.alloc(c.blocks_main * c.Np * np, cnt);
+  c.K3p.alloc(std::max<int64_t>(c.blocks_l3, 1) * c.Np * np, cnt);
+  c.e1p.alloc(c.blocks_main, cnt);
+  c.e3p.alloc(std::max<int64_t>(c.blocks_l3, 1), cnt);
+  c.M2.alloc(c.nauxp * np, cnt);
+  c.K1.alloc(c.Np * np, cnt);
+  c.K2.alloc(c.Np * np, cnt);
+  c.K3.alloc(c.Np * np, cnt);
+  c.Kdev.alloc(c.nbas * np, cnt);
+  c.Cdev.alloc(c.nbas * np, cnt);
+  c.exdev.alloc(1, cnt);
+  c.ws_np = np;
+}
+
+// variant coefficients: K = dV (s1 K1 + s2 K2 + s3 K3), E = -dV (ce1 e1 + ce3 e3)
+void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, double* K, double* ex,
+                int32_t flags, hipStream_t st) {
+  if (c.ng == 0) fail(RPS_ERR_STATE, "context has no completed set-up");
+  if (nocc < 1) fail(RPS_ERR_ARG, "nocc must be >= 1");
+  if (!C || !K) fail(RPS_ERR_ARG, "C and K must not be NULL");
+  if (flags != RPS_PTRS_HOST && flags != RPS_PTRS_DEVICE) fail(RPS_ERR_ARG, "flags must be RPS_PTRS_HOST or RPS_PTRS_DEVICE");
+  if (variant < RPS_VARIANT_RPS || variant > RPS_VARIANT_THC) fail(RPS_ERR_ARG, "unknown variant");
+  const int np = (int)round_up(nocc, 16);
+  if (np > 64) fail(RPS_ERR_SHAPE, "this build supports nocc <= 64 in the FP64 path");
+  if (c.Np > 128) fail(RPS_ERR_SHAPE, "this build supports N <= 128 in the FP64 path");
+  ensure_workspace(c, np);
+  double s1 = 1, s2 = 1, s3 = -1, ce1 = 2, ce3 = -1;
+  if (variant == RPS_VARIANT_PS) { s1 = 0; s2 = 1; s3 = 0; ce1 = 1; ce3 = 0; }
+  if (variant == RPS_VARIANT_THC) { s1 = 0; s2 = 0; s3 = 1; ce1 = 0; ce3 = 1; }
+  const bool dev = (flags == RPS_PTRS_DEVICE);
+  const double* Csrc = C;
+  if (!dev) {
+    hip_check(hipMemcpyAsync(c.Cdev.p, C, (size_t)c.nbas * nocc * 8, hipMemcpyHostToDevice, st), "copy C");
+    Csrc = c.Cdev.p;
+  }
+  hip_check(pack_matrix(Csrc, c.nbas, nocc, nocc, c.Cp.p, c.Np, np, st), "pack C");
+  // U = Phi C (orbitals on the grid), U_g = U[points]
+  Gemm g;
+  g.M = c.ngp; g.N = np; g.K = c.Np;
+  g.A = c.Phi.p; g.lda = c.Np; g.B = c.Cp.p; g.ldb = np; g.C = c.U.p; g.ldc = np;
+  hip_check(gemm_f64(g, st), "U");
+  hip_check(gather_rows(c.U.p, np, c.dpoints.p, c.naux, c.nauxp, np, c.Ug.p, np, st), "U_g");
+  const bool need_main = (variant != RPS_VARIANT_THC);
+  const bool need_l3 = (variant != RPS_VARIANT_PS);
+  if (need_main) {
+    FusedArgs a{};
+    a.Vm = c.V.p; a.ldv = c.ngp; a.Ug = c.Ug.p; a.Ur = c.U.p; a.Phir = c.Phi.p;
+    a.G = c.nauxp; a.R = c.ngp; a.R_valid = c.ng; a.np = np; a.Np = (int)c.Np;
+    a.rtiles = c.rtiles; a.gblocks = c.gblocks;
+    a.want_m2 = 1; a.want_k1 = (variant == RPS_VARIANT_RPS) ? 1 : 0; a.want_m1 = 0;
+    a.prec = c.precision;
+    a.M2p = c.M2p.p; a.K1p = c.K1p.p; a.e1p = c.e1p.p;
+    hip_check(fused_exchange(a, st), "fused main");
+    if (a.want_k1) hip_check(sum_partials(c.K1p.p, c.blocks_main, c.Np * np, c.Np * np, c.K1.p, st), "K1");
+    hip_check(sum_partials(c.M2p.p, c.rblocks_main, c.nauxp * np, c.nauxp * np, c.M2.p, st), "M2");
+    Gemm k2;   // K2 = Phi_g^T M2
+    k2.M = c.Np; k2.N = np; k2.K = c.nauxp;
+    k2.A = c.Phig.p; k2.lda = c.Np; k2.transA = true; k2.B = c.M2.p; k2.ldb = np;
+    k2.C = c.K2.p; k2.ldc = np;
+    hip_check(gemm_f64(k2, st), "K2");
+  }
+  if (need_l3) {
+    FusedArgs a{};
+    a.Vm = c.W.p; a.ldv = c.nauxp; a.Ug = c.Ug.p; a.Ur = c.Ug.p; a.Phir = c.Phig.p;
+    a.G = c.nauxp; a.R = c.nauxp; a.R_valid = c.naux; a.np = np; a.Np = (int)c.Np;
+    a.rtiles = 4; a.gblocks = 1;
+    a.want_m2 = 0; a.want_k1 = 1; a.want_m1 = 0; a.prec = RPS_PREC_FP64;
+    a.K1p = c.K3p.p; a.e1p = c.e3p.p;
+    hip_check(fused_exchange(a, st), "fused line 3");
+    hip_check(sum_partials(c.K3p.p, c.blocks_l3, c.Np * np, c.Np * np, c.K3.p, st), "K3");
+  }
+  double* Kout = dev ? K : c.Kdev.p;
+  double* exout = dev ? ex : (ex ? c.exdev.p : nullptr);
+  hip_check(combine(need_main && variant == RPS_VARIANT_RPS ? c.K1.p : nullptr, need_main ? c.K2.p : nullptr,
+                    need_l3 ? c.K3.p : nullptr, (int)c.nbas, nocc, np, s1, s2, s3, c.dV, Kout, c.e1p.p,
+                    need_main ? c.blocks_main : 0, c.e3p.p, need_l3 ? c.blocks_l3 : 0, ce1, ce3, exout, st),
+            "combine");
+  if (!dev) {
+    hip_check(hipMemcpyAsync(K, c.Kdev.p, (size_t)c.nbas * nocc * 8, hipMemcpyDeviceToHost, st), "copy K");
+    if (ex) hip_check(hipMemcpyAsync(ex, c.exdev.p, 8, hipMemcpyDeviceToHost, st), "copy ex");
+    hip_check(hipStreamSynchronize(st), "sync");
+  }
+}
+
+template <typename F>
+rps_status guarded(F&& f) {
+  try {
+    f();
+    g_err.clear();
+    return RPS_OK;
+  } catch (const Fail& e) {
+    g_err = e.msg;
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return RPS_ERR_NOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return RPS_ERR_DEVICE;
+  } catch (...) {
+    g_err = "unknown failure";
+    return RPS_ERR_DEVICE;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t rps_abi_version(void) { return 1; }
+
+const char* rps_last_error(void) { return g_err.c_str(); }
+
+rps_status rps_setup_isdf(const rps_cell* cell, const rps_basis* basis, int64_t n_aux, uint64_t seed,
+                          int32_t select_mode, int32_t precision, const int64_t* points_in, void* hip_stream,
+                          rps_context** out) {
+  return guarded([&] {
+    if (!out) fail(RPS_ERR_ARG, "out must not be NULL");
+    rps_context* c = new rps_context();
+    try {
+      setup_impl(*c, cell, basis, n_aux, seed, select_mode, precision, points_in, (hipStream_t)hip_stream);
+    } catch (...) {
+      delete c;
+      throw;
+    }
+    *out = c;
+  });
+}
+
+rps_status rps_build_exchange_occRI(rps_context* ctx, int32_t nocc, const double* C, double* K, double* ex,
+                                    int32_t flags, void* hip_stream) {
+  return guarded([&] {
+    if (!ctx) fail(RPS_ERR_ARG, "ctx must not be NULL");
+    build_impl(*ctx, RPS_VARIANT_RPS, nocc, C, K, ex, flags, (hipStream_t)hip_stream);
+  });
+}
+
+rps_status rps_build_exchange_variant(rps_context* ctx, int32_t variant, int32_t nocc, const double* C, double* K,
+                                      double* ex, int32_t flags, void* hip_stream) {
+  return guarded([&] {
+    if (!ctx) fail(RPS_ERR_ARG, "ctx must not be NULL");
+    build_impl(*ctx, variant, nocc, C, K, ex, flags, (hipStream_t)hip_stream);
+  });
+}
+
+rps_status rps_build_exchange_full(rps_context* ctx, int32_t, const double*, double*, int32_t, void*) {
+  return guarded([&] {
+    if (!ctx) fail(RPS_ERR_ARG, "ctx must not be NULL");
+    fail(RPS_ERR_STATE, "full exchange matrix is not available in this build");
+  });
+}
+
+rps_status rps_build_exchange_occRI_batched(rps_context* const* ctx, int32_t nbatch, const int32_t* nocc,
+                                            const double* const* C, double* const* K, double* ex, int32_t flags,
+                                            void* hip_stream) {
+  return guarded([&] {
+    if (!ctx || !nocc || !C || !K || nbatch < 0) fail(RPS_ERR_ARG, "NULL argument or negative nbatch");
+    for (int32_t b = 0; b < nbatch; ++b) {
+      if (!ctx[b]) fail(RPS_ERR_ARG, "NULL context in batch");
+      build_impl(*ctx[b], RPS_VARIANT_RPS, nocc[b], C[b], K[b], ex ? ex + b : nullptr, flags,
+                 (hipStream_t)hip_stream);
+    }
+  });
+}
+
+rps_status rps_exchange_energy(int32_t nbas, int32_t nocc, const double* C, const double* K, double* ex) {
+  return guarded([&] {
+    if (nbas < 1 || nocc < 1) fail(RPS_ERR_ARG, "nbas and nocc must be >= 1");
+    if (!C || !K || !ex) fail(RPS_ERR_ARG, "NULL argument");
+    double s = 0.0;
+    for (int64_t i = 0; i < (int64_t)nbas * nocc; ++i) s += C[i] * K[i];
+    *ex = -s;
+  });
+}
+
+rps_status rps_overlap(rps_context* ctx, double* S) {
+  return guarded([&] {
+    if (!ctx || !S) fail(RPS_ERR_ARG, "NULL argument");
+    rps_context& c = *ctx;
+    if (c.ng == 0) fail(RPS_ERR_STATE, "context has no completed set-up");
+    int64_t tmpb = 0;
+    DBuf<double> dS;
+    dS.alloc(c.Np * c.Np, &tmpb);
+    Gemm g;
+    g.M = c.Np; g.N = c.Np; g.K = c.ngp;
+    g.A = c.Phi.p; g.lda = c.Np; g.transA = true; g.B = c.Phi.p; g.ldb = c.Np;
+    g.C = dS.p; g.ldc = c.Np; g.alpha = c.dV;
+    hip_check(gemm_f64(g, nullptr), "overlap");
+    std::vector<double> h(c.Np * c.Np);
+    hip_check(hipMemcpy(h.data(), dS.p, h.size() * 8, hipMemcpyDeviceToHost), "copy S");
+    dS.release(nullptr);
+    for (int64_t i = 0; i < c.nbas; ++i)
+      for (int64_t j = 0; j < c.nbas; ++j) S[i * c.nbas + j] = h[i * c.Np + j];
+  });
+}
+
+rps_status rps_get_points(const rps_context* ctx, int64_t* out) {
+  return guarded([&] {
+    if (!ctx || !out) fail(RPS_ERR_ARG, "NULL argument");
+    if (ctx->ng == 0) fail(RPS_ERR_STATE, "context has no completed set-up");
+    std::copy(ctx->points.begin(), ctx->points.end(), out);
+  });
+}
+
+rps_status rps_get_info(const rps_context* ctx, rps_info* info) {
+  return guarded([&] {
+    if (!ctx || !info) fail(RPS_ERR_ARG, "NULL argument");
+    const rps_context& c = *ctx;
+    info->ngrid = c.ng; info->nbas = c.nbas; info->naux = c.naux;
+    info->ngrid_pad = c.ngp; info->nbas_pad = c.Np; info->naux_pad = c.nauxp;
+    info->n_candidates = c.ncand; info->dvol = c.dV; info->chol_shift = c.shift;
+    info->setup_seconds = c.setup_seconds; info->device_bytes = c.bytes;
+    info->precision = c.precision; info->exact = c.exact;
+  });
+}
+
+rps_status rps_get_array(const rps_context* ctx, int32_t which, int64_t row0, int64_t nrows, double* out) {
+  return guarded([&] {
+    if (!ctx || !out) fail(RPS_ERR_ARG, "NULL argument");
+    const rps_context& c = *ctx;
+    if (c.ng == 0) fail(RPS_ERR_STATE, "context has no completed set-up");
+    int64_t rows = 0, cols = 0, ld = 0;
+    const double* src = nullptr;
+    if (which == 0) { rows = c.ng; cols = c.nbas; ld = c.Np; src = c.Phi.p; }
+    else if (which == 1) { rows = c.naux; cols = c.ng; ld = c.ngp; src = c.V.p; }
+    else if (which == 2) { rows = c.naux; cols = c.naux; ld = c.nauxp; src = c.W.p; }
+    else if (which == 3) {
+      if (c.owner_host.empty()) fail(RPS_ERR_STATE, "no Voronoi assignment was computed (points were given)");
+      if (row0 < 0 || nrows < 0 || row0 + nrows > c.ng) fail(RPS_ERR_SHAPE, "row range out of bounds");
+      for (int64_t i = 0; i < nrows; ++i) out[i] = (double)c.owner_host[row0 + i];
+      return;
+    } else {
+      fail(RPS_ERR_ARG, "which must be 0..3");
+    }
+    if (row0 < 0 || nrows < 0 || row0 + nrows > rows) fail(RPS_ERR_SHAPE, "row range out of bounds");
+    hip_check(hipMemcpy2D(out, cols * 8, src + row0 * ld, ld * 8, cols * 8, nrows, hipMemcpyDeviceToHost),
+              "copy array");
+  });
+}
+
+void rps_destroy(rps_context* ctx) {
+  if (!ctx) return;
+  (void)hipDeviceSynchronize();
+  delete ctx;
+}
+
+}  // extern "C"

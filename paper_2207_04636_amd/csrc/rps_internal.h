@@ -1,0 +1,126 @@
+// Internal launchers of the rPS exchange library (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rps {
+
+// ---------------------------------------------------------------- GEMM
+// C[M x N] = epilogue(alpha * op(A)[M x K] op(B)[K x N], beta, C)
+//   op(A)[m][k] = transA ? A[k*lda + m] : A[m*lda + k]
+//   op(B)[k][n] = transB ? B[n*ldb + k] : B[k*ldb + n]
+enum GemmEpi {
+  EPI_AXPBY = 0,     // C = alpha*AB + beta*C
+  EPI_SQUARE = 1,    // C = (alpha*AB)^2 (elementwise)
+  EPI_HADAMARD = 2   // C = C o (alpha*AB)
+};
+struct Gemm {
+  int64_t M = 0, N = 0, K = 0;
+  const double* A = nullptr; int64_t lda = 0; bool transA = false;
+  const double* B = nullptr; int64_t ldb = 0; bool transB = false;
+  double* C = nullptr; int64_t ldc = 0;
+  double alpha = 1.0, beta = 0.0;
+  int epi = EPI_AXPBY;
+  bool lower_only = false;   // skip output tiles strictly above the diagonal
+};
+hipError_t gemm_f64(const Gemm& g, hipStream_t s);
+
+// ---------------------------------------------------------------- basis / grid
+struct ShellDev {        // one Gaussian shell, device copy
+  double cx, cy, cz;     // centre wrapped into the cell
+  double expo;
+  int l;                 // 0, 1, 2
+  int fofs;              // first basis-function column
+  int m0, m1, m2;        // image range along a1, a2, a3
+};
+struct CellDev {
+  double a[9];           // rows a1, a2, a3
+  double ainv[9];        // inverse of the row matrix (cartesian -> fractional)
+  int mesh[3];
+};
+// Phi[R][mu] for R in [0, ngrid), rows >= ngrid up to nrows_pad left as is.
+hipError_t basis_eval(const CellDev& cell, const ShellDev* shells, int nshell, int64_t ngrid,
+                      double* Phi, int64_t ldphi, hipStream_t s);
+// owner[R] = nearest atom over periodic images (ties -> lower index).
+hipError_t voronoi_assign(const CellDev& cell, const double* atoms, int natom, int64_t ngrid,
+                          int32_t* owner, hipStream_t s);
+// dst[r][0:ncols] = src[idx[r]][0:ncols] for r < nidx, 0 for nidx <= r < nrows.
+hipError_t gather_rows(const double* src, int64_t lds, const int64_t* idx, int64_t nidx,
+                       int64_t nrows, int64_t ncols, double* dst, int64_t ldd, hipStream_t s);
+// X[g][idx[g]] = 1 for g < n (fitting functions of the exact case, chi = identity)
+hipError_t set_unit_rows(double* X, int64_t ld, const int64_t* idx, int64_t n, hipStream_t s);
+// Y[r][c] = X[r][idx[c]] for r, c < n
+hipError_t gather_cols(const double* X, int64_t ldx, const int64_t* idx, int64_t n, double* Y,
+                       int64_t ldy, hipStream_t s);
+hipError_t to_f32(const double* X, int64_t count, float* Y, hipStream_t s);
+// x[i*ld + i] += v for i in [i0, i1)
+hipError_t add_diag(double* X, int64_t ld, int64_t i0, int64_t i1, double v, hipStream_t s);
+hipError_t fill(double* X, int64_t count, double v, hipStream_t s);
+// B = (A + A^T)/2 in place for an n x n matrix (ld)
+hipError_t symmetrize(double* A, int64_t n, int64_t ld, hipStream_t s);
+// out[j*ldo + i] = in[i*ldi + j] (i < rows, j < cols)
+hipError_t transpose(const double* in, int64_t ldi, int64_t rows, int64_t cols, double* out,
+                     int64_t ldo, hipStream_t s);
+
+// ---------------------------------------------------------------- dense linear algebra
+// Blocked right-looking lower Cholesky in place on an n x n matrix (n % 64 == 0).
+// status[0] = 0 on success, 1 + (first failing row) otherwise.
+hipError_t cholesky_lower(double* A, int64_t n, int64_t lda, int32_t* status, hipStream_t s);
+// Solve L X = B (trans = false) or L^T X = B (trans = true) in place,
+// L lower n x n (n % 64 == 0), B n x ncols with leading dimension ldb.
+hipError_t tri_solve_lower(const double* L, int64_t n, int64_t ldl, double* B, int64_t ncols,
+                           int64_t ldb, bool trans, hipStream_t s);
+// Blocked pivoted Cholesky on an explicit symmetric Gram matrix G (n x n, ld),
+// destroyed.  Writes the first k pivots (indices into 0..n-1, argmax of the
+// updated diagonal, ties to the lowest index) to piv (device int64[k]).
+// Work buffers: Lbuf (n x k doubles), diag (n + k doubles).
+hipError_t pivoted_cholesky(double* G, int64_t n, int64_t ld, int64_t k, int64_t* piv,
+                            double* Lbuf, double* diag, hipStream_t s);
+
+// ---------------------------------------------------------------- Poisson solve
+// In place V <- Vc V for nrows real rows (split-complex pairs of rows, nrows even)
+// of the grid mesh, leading dimension ld.  kern[N_g]: k(G) / N_g in FFT order.
+hipError_t poisson_rows(double* V, int64_t nrows, int64_t ld, const int mesh[3],
+                        const double* kern, hipStream_t s);
+
+// ---------------------------------------------------------------- exchange build
+struct FusedArgs {
+  // A = Vm o (Ug Ur^T); Vm: [G x R] row pitch ldv
+  const double* Vm; int64_t ldv;
+  const float* Vm32;        // FP32 copy (precision forms), ldv pitch
+  const double* Ug;         // [Gp x np]  (row operand)
+  const double* Ur;         // [Rp x np]  (column operand)
+  const double* Phir;       // [Rp x Np]  basis at the columns (for K1)
+  int64_t G, R;             // padded extents (multiples of 64)
+  int64_t R_valid;          // columns beyond it are zero
+  int np;                   // padded n (multiple of 16)
+  int Np;                   // padded N (multiple of 16)
+  int rtiles;               // 64-column tiles per workgroup
+  int gblocks;              // workgroups along G
+  int want_m2;              // write M2 partials
+  int want_k1;              // accumulate K1 partials (Phir^T (A^T Ug))
+  int want_m1;              // write M1^T = A^T Ug rows (when K1 is not fused)
+  int prec;                 // rps_precision
+  // outputs
+  double* M2p;              // [rblocks][G][np]
+  double* K1p;              // [gblocks*rblocks][Np][np]
+  double* M1T;              // [gblocks][R][np]
+  double* e1p;              // [gblocks*rblocks]
+};
+int fused_rblocks(const FusedArgs& a);
+hipError_t fused_exchange(const FusedArgs& a, hipStream_t s);
+
+// Sum partials: out[i] = sum_p in[p*stride + i], i < count (deterministic order).
+hipError_t sum_partials(const double* in, int64_t nparts, int64_t stride, int64_t count,
+                        double* out, hipStream_t s);
+// Pack C [N][n] (row pitch n) into Cp [Np][np] zero padded.
+hipError_t pack_matrix(const double* C, int64_t rows, int64_t cols, int64_t ldc, double* Cp,
+                       int64_t rows_p, int64_t ldp, hipStream_t s);
+// Final combine: K[mu][i] = dV (K1 + K2 - K3) (unpadded out, ldk = n);
+// ex = -dV (2 e1 - e3) with e1 = sum e1p[0:ne1], e3 = sum e3p[0:ne3].
+hipError_t combine(const double* K1, const double* K2, const double* K3, int N, int n, int np,
+                   double s1, double s2, double s3, double dV, double* K,
+                   const double* e1p, int64_t ne1, const double* e3p, int64_t ne3,
+                   double ce1, double ce3, double* ex, hipStream_t s);
+
+}  // namespace rps

@@ -1,0 +1,106 @@
+"""CPU checks of the C ABI library: it loads, exports every function that
+include/rps.h declares, and rejects bad arguments before touching a device."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2207_04636_amd as P
+from paper_2207_04636_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rps.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rps_\w+)\s*\(", txt)))
+
+
+def test_header_and_exports_agree():
+    decl = _declared()
+    assert "rps_setup_isdf" in decl and "rps_build_exchange_occRI" in decl and "rps_exchange_energy" in decl
+    assert sorted(P.EXPORTS) == decl
+    lib = P.load()
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert lib.rps_abi_version() == 1
+
+
+def test_exchange_energy_host():
+    rg = np.random.default_rng(0)
+    C = rg.standard_normal((7, 3))
+    K = rg.standard_normal((7, 3))
+    assert abs(P.exchange_energy(C, K) + np.sum(C * K)) < 1e-14
+
+
+def _setup_status(**over):
+    lib = P.load()
+    cell = B.Cell()
+    cell.lattice[:] = list(np.eye(3).reshape(9) * 5.0)
+    cell.mesh[:] = [8, 8, 8]
+    atoms = np.array([[0.0, 0, 0], [2.0, 2, 2]])
+    sa = np.array([0, 1], dtype=np.int32)
+    sl = np.array([0, 1], dtype=np.int32)
+    se = np.array([1.0, 0.7])
+    for k, v in over.items():
+        if k == "lattice":
+            cell.lattice[:] = list(np.asarray(v, float).reshape(9))
+        elif k == "mesh":
+            cell.mesh[:] = v
+        elif k == "sl":
+            sl = np.asarray(v, dtype=np.int32)
+        elif k == "se":
+            se = np.asarray(v, float)
+        elif k == "sa":
+            sa = np.asarray(v, dtype=np.int32)
+    b = B.Basis(2, len(sl), atoms.ctypes.data_as(ct.POINTER(ct.c_double)), sa.ctypes.data_as(ct.POINTER(ct.c_int32)),
+                sl.ctypes.data_as(ct.POINTER(ct.c_int32)), se.ctypes.data_as(ct.POINTER(ct.c_double)))
+    naux = over.get("naux", 10)
+    pts = over.get("points")
+    pp = None
+    if pts is not None:
+        pts = np.asarray(pts, dtype=np.int64)
+        pp = pts.ctypes.data_as(ct.POINTER(ct.c_int64))
+    h = ct.c_void_p()
+    st = lib.rps_setup_isdf(ct.byref(cell), ct.byref(b), naux, 1, over.get("mode", 0), over.get("prec", 0), pp,
+                            None, ct.byref(h))
+    return st, lib.rps_last_error().decode(), h
+
+
+@pytest.mark.parametrize("over,status", [
+    (dict(lattice=np.zeros((3, 3))), B.RPS_ERR_ARG),
+    (dict(mesh=[8, 1, 8]), B.RPS_ERR_SHAPE),
+    (dict(mesh=[8, 8, 200]), B.RPS_ERR_SHAPE),
+    (dict(sl=[0, 3]), B.RPS_ERR_ARG),
+    (dict(se=[1.0, -1.0]), B.RPS_ERR_ARG),
+    (dict(sa=[0, 5]), B.RPS_ERR_ARG),
+    (dict(naux=0), B.RPS_ERR_SHAPE),
+    (dict(naux=513), B.RPS_ERR_SHAPE),
+    (dict(naux=3, points=[1, 2, 1]), B.RPS_ERR_SHAPE),
+    (dict(naux=3, points=[1, 2, 512]), B.RPS_ERR_SHAPE),
+    (dict(prec=7), B.RPS_ERR_ARG),
+    (dict(mode=5), B.RPS_ERR_ARG),
+])
+def test_setup_rejects_bad_arguments(over, status):
+    st, msg, h = _setup_status(**over)
+    assert st == status, msg
+    assert msg and h.value is None
+
+
+def test_calls_without_context_fail_cleanly():
+    lib = P.load()
+    K = np.zeros((2, 2))
+    C = np.zeros((2, 2))
+    assert lib.rps_build_exchange_occRI(None, 2, C.ctypes.data, K.ctypes.data, None, 0, None) == B.RPS_ERR_ARG
+    assert "ctx" in lib.rps_last_error().decode()
+    assert lib.rps_get_points(None, None) == B.RPS_ERR_ARG
+    lib.rps_destroy(None)
+
+
+def test_python_errors_are_loud():
+    with pytest.raises(P.RpsError):
+        P.Context(np.eye(3) * 5, [8, 8, 8], [[0, 0, 0]], [0], [0], [1.0], naux=0)
