@@ -197,6 +197,18 @@ rps_status rps_get_info(const rps_context *ctx, rps_info *info);
 rps_status rps_get_array(const rps_context *ctx, int32_t which, int64_t row0, int64_t nrows,
                          double *out);
 
+/*
+ * Kernel timing for measurement.  With enable = 1 every later build records
+ * HIP events on its stream around the V-streaming kernel (Eq. 16, lines 1-2),
+ * around the fit-fit kernel (line 3) and around the whole build.
+ * rps_get_profile synchronises the stream of the last build, writes
+ *   out[0] = builds timed, out[1] = total ms in the V-streaming kernel,
+ *   out[2] = total ms in the fit-fit kernel, out[3] = total ms of whole builds,
+ * and clears the record.  At most 65536 builds are recorded between reads.
+ */
+rps_status rps_set_profiling(rps_context *ctx, int32_t enable);
+rps_status rps_get_profile(rps_context *ctx, double *out);
+
 /* Frees every device buffer of the context.  NULL is allowed. */
 void rps_destroy(rps_context *ctx);
 

@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "RPS_OK", 1: "RPS_ERR_ARG", 2: "RPS_ERR_SHAPE", 3: "RPS_ERR_N
 EXPORTS = ("rps_setup_isdf", "rps_build_exchange_occRI", "rps_build_exchange_variant",
            "rps_build_exchange_full", "rps_build_exchange_occRI_batched", "rps_exchange_energy",
            "rps_overlap", "rps_get_points", "rps_get_info", "rps_get_array", "rps_destroy",
-           "rps_last_error", "rps_abi_version")
+           "rps_last_error", "rps_abi_version", "rps_set_profiling", "rps_get_profile")
 
 
 class RpsError(RuntimeError):
@@ -90,6 +90,8 @@ def load(path: str = LIB_PATH):
     lib.rps_get_points.argtypes = [P, P]
     lib.rps_get_info.argtypes = [P, ct.POINTER(Info)]
     lib.rps_get_array.argtypes = [P, I32, I64, I64, P]
+    lib.rps_set_profiling.argtypes = [P, I32]
+    lib.rps_get_profile.argtypes = [P, P]
     lib.rps_destroy.argtypes = [P]
     lib.rps_destroy.restype = None
     lib.rps_last_error.restype = ct.c_char_p
@@ -224,6 +226,15 @@ class Context:
         out = np.empty((nrows, ncol)) if which != 3 else np.empty(nrows)
         _check(self._lib.rps_get_array(self._h, int(which), int(row0), int(nrows), out.ctypes.data))
         return out
+
+    def set_profiling(self, enable: bool = True):
+        _check(self._lib.rps_set_profiling(self._h, 1 if enable else 0))
+
+    def profile(self) -> dict:
+        """Kernel timings recorded since the last read (see rps_get_profile)."""
+        out = np.zeros(4)
+        _check(self._lib.rps_get_profile(self._h, out.ctypes.data))
+        return dict(builds=int(out[0]), fused_ms=float(out[1]), line3_ms=float(out[2]), build_ms=float(out[3]))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -22,51 +22,70 @@
 // B = W o P_g; the same kernel computes it with M2 disabled.
 #include <math.h>
 
+#include <algorithm>
+
 #include "mfma.h"
 #include "rps_internal.h"
 
 namespace rps {
 namespace {
 
-constexpr int T = 64;        // tile edge
-constexpr int LDA = T + 1;   // LDS pitch of the A tile (doubles)
+constexpr int T = 64;        // R tile width; g rows are processed in 16-row subtiles
+constexpr int SLAB = T + 1;  // LDS pitch of a wave's A slab (doubles)
 
-template <int NI, int RT, int MT>
-__global__ __launch_bounds__(256) void fused_f64_kernel(FusedArgs a) {
-  constexpr int NP = 16 * NI;          // padded n
-  constexpr int LDU = NP + 1;          // LDS pitch of the U tiles
-  __shared__ double sA[T][LDA];
-  __shared__ double sUg[T][LDU];       // U_g rows of the current g tile
-  __shared__ double sUr[T][LDU];       // U rows of the current R tile
-  __shared__ double sRed[4][64];
+// Dynamic LDS layout of the fused kernel (doubles):
+//   slabs [NW][16][SLAB]   each wave's A = V o P for its 16 rows (wave-private)
+//   sU    [T][NP+1]        U rows of the current R tile
+//   sM2   [BG][NP]         M2 rows of this workgroup's g block (row owner = one wave)
+template <int NW, int NI>
+__host__ __device__ constexpr int64_t fused_lds_doubles(int64_t bg) {
+  return (int64_t)NW * 16 * SLAB + (int64_t)T * (16 * NI + 1) + bg * 16 * NI;
+}
+
+template <int NW, int NI, int MT>
+__global__ __launch_bounds__(NW * 64) void fused_f64_kernel(FusedArgs a) {
+  constexpr int NP = 16 * NI;
+  constexpr int LDU = NP + 1;
+  extern __shared__ double smem[];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
 
-  const int64_t gtiles = a.G / T;
-  const int64_t gper = (gtiles + a.gblocks - 1) / a.gblocks;
+  // g block of this workgroup
+  const int64_t gsub_total = a.G / 16;
+  const int64_t gper = ((a.G / T + a.gblocks - 1) / a.gblocks) * (T / 16);   // subtiles per g block
   const int gb = blockIdx.x % a.gblocks;
   const int rb = blockIdx.x / a.gblocks;
-  const int64_t gt0 = gb * gper;
-  const int64_t gt1 = (gt0 + gper < gtiles) ? gt0 + gper : gtiles;
+  const int64_t gs0 = gb * gper;
+  const int64_t gs1 = (gs0 + gper < gsub_total) ? gs0 + gper : gsub_total;
+  const int64_t bg = gper * 16;                            // rows of sM2
+  // R tiles of this workgroup
   const int64_t rtiles_valid = (a.R_valid + T - 1) / T;
-  const int64_t rt0 = (int64_t)rb * RT;
-  const int64_t rt1 = (rt0 + RT < rtiles_valid) ? rt0 + RT : rtiles_valid;
-  const int nrt = (int)(rt1 - rt0);
-  const int64_t ntile = (gt1 > gt0 && nrt > 0) ? (gt1 - gt0) * nrt : 0;
+  const int64_t rt0 = (int64_t)rb * a.rtiles;
+  const int64_t rt1 = (rt0 + a.rtiles < rtiles_valid) ? rt0 + a.rtiles : rtiles_valid;
 
-  d4_t m1[RT][NI];
-#pragma unroll
-  for (int r = 0; r < RT; ++r)
-#pragma unroll
-    for (int j = 0; j < NI; ++j) m1[r][j] = zero_d4();
-  d4_t m2[NI];
-  double e1 = 0.0;
+  double* slab = smem + (int64_t)w * 16 * SLAB;
+  double* sU = smem + (int64_t)NW * 16 * SLAB;
+  double* sM2 = sU + (int64_t)T * LDU;
+  double* red = smem;                                      // reuses the slabs between phases
 
-  // V fragment of tile t: lane holds V[g0 + 16w + 4r + lq][R0 + 16c + l16]
+  // this wave's subtiles: gs0 + w, gs0 + w + NW, ...
+  const int64_t nmy = (gs1 - gs0 > w) ? (gs1 - gs0 - w + NW - 1) / NW : 0;
+  const int64_t nstep = nmy * (rt1 > rt0 ? rt1 - rt0 : 0);
+
+  if (a.want_m2)
+    for (int64_t e = tid; e < bg * NP; e += NW * 64) sM2[e] = 0.0;
+
+  // V fragment of step t: lane holds V[g0 + 4r + lq][R0 + 16c + l16]
   double vnext[4][4];
+  auto step_coords = [&](int64_t t, int64_t& g0, int64_t& R0) {
+    const int64_t ri = t / nmy, si = t % nmy;
+    R0 = (rt0 + ri) * T;
+    g0 = (gs0 + w + si * NW) * 16;
+  };
   auto load_v = [&](int64_t t) {
-    const int64_t g0 = (gt0 + t / nrt) * T, R0 = (rt0 + t % nrt) * T;
-    const double* base = a.Vm + (g0 + 16 * w + lq) * a.ldv + R0 + l16;
+    int64_t g0, R0;
+    step_coords(t, g0, R0);
+    const double* base = a.Vm + (g0 + lq) * a.ldv + R0 + l16;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const double* row = base + (int64_t)(4 * r) * a.ldv;
@@ -74,155 +93,252 @@ __global__ __launch_bounds__(256) void fused_f64_kernel(FusedArgs a) {
       for (int c = 0; c < 4; ++c) vnext[r][c] = row[16 * c];
     }
   };
-  // stage 64 rows x NP of a U matrix into LDS (rows contiguous, NP doubles each)
-  auto stage = [&](double (*dst)[LDU], const double* src) {
-#pragma unroll
-    for (int e = tid; e < T * NP; e += 256) dst[e / NP][e % NP] = src[e];
-  };
-  if (ntile > 0) load_v(0);
+  if (nstep > 0) load_v(0);
 
-  for (int64_t gt = gt0; gt < gt1 && nrt > 0; ++gt) {
-    const int64_t g0 = gt * T;
+  double e1 = 0.0;
+  // K1 output tiles owned by this wave: m = w, w + NW, ...  (MTW of them)
+  constexpr int MTW = (MT + NW - 1) / NW > 0 ? (MT + NW - 1) / NW : 1;
+  d4_t k1[MTW][NI];
 #pragma unroll
-    for (int j = 0; j < NI; ++j) m2[j] = zero_d4();
-    stage(sUg, a.Ug + g0 * NP);
+  for (int mm = 0; mm < MTW; ++mm)
 #pragma unroll
-    for (int rl = 0; rl < RT; ++rl) {
-      if (rl >= nrt) break;
-      const int64_t t = (gt - gt0) * nrt + rl;
-      const int64_t R0 = (rt0 + rl) * T;
-      stage(sUr, a.Ur + R0 * NP);
+    for (int j = 0; j < NI; ++j) k1[mm][j] = zero_d4();
+  const int mt = a.Np / 16;
+
+  int64_t t = 0;
+  for (int64_t rt = rt0; rt < rt1; ++rt) {
+    const int64_t R0 = rt * T;
+    __syncthreads();
+    for (int e = tid; e < T * NP; e += NW * 64) sU[(e / NP) * LDU + (e % NP)] = a.Ur[R0 * NP + e];
+    __syncthreads();
+    d4_t m1[4][NI];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int j = 0; j < NI; ++j) m1[c][j] = zero_d4();
+
+    for (int64_t si = 0; si < nmy; ++si, ++t) {
+      const int64_t g0 = (gs0 + w + si * NW) * 16;
       double v[4][4];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c) v[r][c] = vnext[r][c];
-      if (t + 1 < ntile) load_v(t + 1);
-      __syncthreads();
+      if (t + 1 < nstep) load_v(t + 1);
+      // U_g operands of these 16 rows: A operand of P, B operand of M1
+      const double* ug = a.Ug + g0 * NP;
+      double ugA[NI * 4], ugB[4][NI];
+#pragma unroll
+      for (int kk = 0; kk < NI * 4; ++kk) ugA[kk] = ug[l16 * NP + 4 * kk + lq];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < NI; ++j) ugB[r][j] = ug[(4 * r + lq) * NP + 16 * j + l16];
 
-      // P for rows g0+16w.. and the 4 column subtiles: D[g][R] += U_g[g][k] U^T[k][R]
+      // P[g][R] = sum_k U_g[g][k] U[R][k]
       d4_t p[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) p[c] = zero_d4();
 #pragma unroll
-      for (int kk = 0; kk < NI * 4; ++kk) {
-        const double x = sUg[16 * w + l16][4 * kk + lq];
+      for (int kk = 0; kk < NI * 4; ++kk)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) p[c] = mfma_f64(x, sUr[16 * c + l16][4 * kk + lq], p[c]);
-      }
-      // A = V o P, energy, stage A
+        for (int c = 0; c < 4; ++c) p[c] = mfma_f64(ugA[kk], sU[(16 * c + l16) * LDU + 4 * kk + lq], p[c]);
+      // A = V o P; energy; M1^T from the registers (reg r is the k-slice g = 4r + lq)
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
+      for (int c = 0; c < 4; ++c) {
+        d4_t av;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const double av = v[r][c] * p[c][r];
-          e1 += av * p[c][r];
-          sA[16 * w + 4 * r + lq][16 * c + l16] = av;
+          av[r] = v[r][c] * p[c][r];
+          e1 += av[r] * p[c][r];
+          slab[(4 * r + lq) * SLAB + 16 * c + l16] = av[r];
         }
-      __syncthreads();
-
-      // M1^T for column subtile w: D[R][i] += sum_g A^T[R][g] U_g[g][i]
 #pragma unroll
-      for (int kk = 0; kk < 16; ++kk) {
-        const double x = sA[4 * kk + lq][16 * w + l16];
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int j = 0; j < NI; ++j) m1[rl][j] = mfma_f64(x, sUg[4 * kk + lq][16 * j + l16], m1[rl][j]);
+          for (int j = 0; j < NI; ++j) m1[c][j] = mfma_f64(av[r], ugB[r][j], m1[c][j]);
       }
-      // M2 for row subtile w: D[g][i] += sum_R A[g][R] U[R][i]
+      __builtin_amdgcn_wave_barrier();
+      if (a.want_m2) {
+        // M2[g][i] = sum_R A[g][R] U[R][i]: A operand from the wave's own slab
+        d4_t m2[NI];
 #pragma unroll
-      for (int kk = 0; kk < 16; ++kk) {
-        const double x = sA[16 * w + l16][4 * kk + lq];
+        for (int j = 0; j < NI; ++j) m2[j] = zero_d4();
 #pragma unroll
-        for (int j = 0; j < NI; ++j) m2[j] = mfma_f64(x, sUr[4 * kk + lq][16 * j + l16], m2[j]);
+        for (int kk = 0; kk < 16; ++kk) {
+          const double x = slab[l16 * SLAB + 4 * kk + lq];
+#pragma unroll
+          for (int j = 0; j < NI; ++j) m2[j] = mfma_f64(x, sU[(4 * kk + lq) * LDU + 16 * j + l16], m2[j]);
+        }
+        double* acc = sM2 + (g0 - gs0 * 16) * NP + l16;
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[(4 * r + lq) * NP + 16 * j] += m2[j][r];
       }
-      __syncthreads();
+      __builtin_amdgcn_wave_barrier();
     }
-    if (a.want_m2) {
-      double* out = a.M2p + ((int64_t)rb * a.G + g0 + 16 * w) * NP + l16;
+
+    // M1^T of this R tile summed over the waves (fixed order) into LDS, then
+    // K1 += Phi[R tile]^T M1^T with each wave owning whole K1 output tiles.
+    if (MT > 0 || a.want_m1) {
+      double* m1s = sU;                       // the U tile is not needed until the next R tile
 #pragma unroll
-      for (int j = 0; j < NI; ++j)
+      for (int j = 0; j < NI; ++j) {
+        __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 4; ++r) out[(int64_t)(4 * r + lq) * NP + 16 * j] = m2[j][r];
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) red[(w * 64 + 16 * c + 4 * r + lq) * 16 + l16] = m1[c][j][r];
+        __syncthreads();
+        if (w < 4) {
+          const int q = w;   // R subtile
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double s = 0.0;
+            for (int ww = 0; ww < NW; ++ww) s += red[(ww * 64 + 16 * q + 4 * r + lq) * 16 + l16];
+            m1s[(16 * q + 4 * r + lq) * 16 + l16] = s;
+            if (a.want_m1) a.M1T[((int64_t)gb * a.R + R0 + 16 * q + 4 * r + lq) * NP + 16 * j + l16] = s;
+          }
+        }
+        __syncthreads();
+        if (MT > 0 && a.want_k1) {
+          // slice (q, r) <-> R = R0 + 16q + 4r + lq
+#pragma unroll
+          for (int mm = 0; mm < MTW; ++mm) {
+            const int m = w + mm * NW;
+            if (m < mt) {
+              const double* ph = a.Phir + (R0 + lq) * a.Np + 16 * m + l16;
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                  k1[mm][j] = mfma_f64(ph[(int64_t)(16 * q + 4 * r) * a.Np], m1s[(16 * q + 4 * r + lq) * 16 + l16],
+                                       k1[mm][j]);
+            }
+          }
+        }
+      }
     }
   }
 
   const int wg = blockIdx.x;
-  // M1^T rows of this workgroup (when K1 is not fused): lane holds
-  // M1^T[R0 + 16w + 4r + lq][16j + l16]
-  if (a.want_m1) {
-#pragma unroll
-    for (int rl = 0; rl < RT; ++rl) {
-      if (rl >= nrt) break;
-      const int64_t R0 = (rt0 + rl) * T;
-      double* out = a.M1T + ((int64_t)gb * a.R + R0 + 16 * w) * NP + l16;
-#pragma unroll
-      for (int j = 0; j < NI; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) out[(int64_t)(4 * r + lq) * NP + 16 * j] = m1[rl][j][r];
-    }
-  }
+  __syncthreads();
   if (MT > 0 && a.want_k1) {
-    // K1[mu][i] += sum_R Phi[R][mu] M1^T[R][i]; the M1 fragment registers are
-    // already the B operand (reg r <-> k = 4r + lq of this wave's 16 rows).
-    d4_t k1[MT > 0 ? MT : 1][NI];
-#pragma unroll
-    for (int m = 0; m < MT; ++m)
-#pragma unroll
-      for (int j = 0; j < NI; ++j) k1[m][j] = zero_d4();
-    const int mt = a.Np / 16;
-#pragma unroll
-    for (int rl = 0; rl < RT; ++rl) {
-      if (rl >= nrt) break;
-      const int64_t R0 = (rt0 + rl) * T;
-      const double* ph = a.Phir + (R0 + 16 * w + lq) * a.Np + l16;
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int m = 0; m < MT; ++m) {
-          if (m < mt) {
-            const double x = ph[(int64_t)(4 * r) * a.Np + 16 * m];
-#pragma unroll
-            for (int j = 0; j < NI; ++j) {
-              d4_t one = m1[rl][j];
-              k1[m][j] = mfma_f64(x, one[r], k1[m][j]);
-            }
-          }
-        }
-    }
-    // reduce over the 4 waves through LDS, one (m, j) fragment at a time
     double* out = a.K1p + (int64_t)wg * a.Np * NP;
 #pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      if (m >= mt) break;
+    for (int mm = 0; mm < MTW; ++mm) {
+      const int m = w + mm * NW;
+      if (m < mt)
 #pragma unroll
-      for (int j = 0; j < NI; ++j) {
+        for (int j = 0; j < NI; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          sRed[w][lane] = k1[m][j][r];
-          __syncthreads();
-          if (w == 0) {
-            const double s = sRed[0][lane] + sRed[1][lane] + sRed[2][lane] + sRed[3][lane];
-            out[(int64_t)(16 * m + 4 * r + lq) * NP + 16 * j + l16] = s;
-          }
-          __syncthreads();
-        }
-      }
+          for (int r = 0; r < 4; ++r) out[(int64_t)(16 * m + 4 * r + lq) * NP + 16 * j + l16] = k1[mm][j][r];
     }
   }
-  // energy partial
+  if (a.want_m2) {
+    double* out = a.M2p + ((int64_t)rb * a.G + gs0 * 16) * NP;
+    const int64_t rows = (gs1 - gs0) * 16;
+    for (int64_t e = tid; e < rows * NP; e += NW * 64) out[e] = sM2[e];
+  }
+  // energy partial: waves in fixed order
   const double es = wave_sum(e1);
-  if (lane == 0) sRed[w][0] = es;
   __syncthreads();
-  if (tid == 0) a.e1p[wg] = ((sRed[0][0] + sRed[1][0]) + sRed[2][0]) + sRed[3][0];
+  if (lane == 0) red[w] = es;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int ww = 0; ww < NW; ++ww) s += red[ww];
+    a.e1p[wg] = s;
+  }
 }
 
-__global__ void sum_partials_kernel(const double* __restrict__ in, int64_t nparts, int64_t stride,
-                                    int64_t count, double* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
+// U = Phi C for a tall Phi [R x Np] and C [Np x NP]: each wave computes 16
+// rows per step on the FP64 matrix cores, C staged once in LDS.
+template <int NI>
+__global__ __launch_bounds__(256) void tall_gemm_kernel(const double* __restrict__ Phi, int64_t R, int Np,
+                                                       const double* __restrict__ C, double* __restrict__ U) {
+  constexpr int NP = 16 * NI;
+  extern __shared__ double sC[];     // [Np][NP]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, lq = lane >> 4;
+  for (int e = tid; e < Np * NP; e += 256) sC[e] = C[e];
+  __syncthreads();
+  const int64_t nsub = R / 16;
+  for (int64_t s = (int64_t)blockIdx.x * 4 + w; s < nsub; s += (int64_t)gridDim.x * 4) {
+    const double* ph = Phi + (s * 16 + l16) * Np + lq;
+    d4_t acc[NI];
+#pragma unroll
+    for (int j = 0; j < NI; ++j) acc[j] = zero_d4();
+    for (int kk = 0; kk < Np / 4; ++kk) {
+      const double x = ph[4 * kk];
+#pragma unroll
+      for (int j = 0; j < NI; ++j) acc[j] = mfma_f64(x, sC[(4 * kk + lq) * NP + 16 * j + l16], acc[j]);
+    }
+    double* out = U + (s * 16 + lq) * NP + l16;
+#pragma unroll
+    for (int j = 0; j < NI; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[(int64_t)(4 * r) * NP + 16 * j] = acc[j][r];
+  }
+}
+
+// Deterministic sum over partials: block = 64 outputs x 4 partial lanes.
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ in, int64_t nparts,
+                                                             int64_t stride, int64_t count,
+                                                             double* __restrict__ out) {
+  __shared__ double red[4][64];
+  const int x = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + x;
   double s = 0.0;
-  for (int64_t p = 0; p < nparts; ++p) s += in[p * stride + i];
-  out[i] = s;
+  if (i < count)
+    for (int64_t p = q; p < nparts; p += 4) s += in[p * stride + i];
+  red[q][x] = s;
+  __syncthreads();
+  if (q == 0 && i < count) out[i] = ((red[0][x] + red[1][x]) + red[2][x]) + red[3][x];
+}
+
+// K2 = Phi_g^T M2 and the final combination; block b < nmu_blocks handles 16
+// rows mu; the last block sums the energy partials with a fixed tree.
+__global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ Phig, const double* __restrict__ M2,
+                                                      int64_t G, const double* __restrict__ K1,
+                                                      const double* __restrict__ K3, int N, int n, int np, int Np,
+                                                      double s1, double s2, double s3, double dV,
+                                                      double* __restrict__ K, const double* __restrict__ e1p,
+                                                      int64_t ne1, const double* __restrict__ e3p, int64_t ne3,
+                                                      double ce1, double ce3, double* __restrict__ ex) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  const int nmu_blocks = (Np + 15) / 16;
+  if ((int)blockIdx.x < nmu_blocks) {
+    const int per = 256 / np;                 // rows mu per pass
+    for (int mu0 = blockIdx.x * 16; mu0 < blockIdx.x * 16 + 16; mu0 += per) {
+      const int mu = mu0 + tid / np, i = tid % np;
+      if (tid / np < per && mu < blockIdx.x * 16 + 16 && mu < N && i < n) {
+        double k2 = 0.0;
+        if (M2) {
+          for (int64_t g = 0; g < G; ++g) k2 += Phig[g * Np + mu] * M2[g * np + i];
+        }
+        const int64_t q = (int64_t)mu * np + i;
+        double v = s2 * k2;
+        if (K1) v += s1 * K1[q];
+        if (K3) v += s3 * K3[q];
+        K[(int64_t)mu * n + i] = dV * v;
+      }
+    }
+    return;
+  }
+  if (!ex) return;
+  double sa = 0.0, sb = 0.0;
+  for (int64_t p = tid; p < ne1; p += 256) sa += e1p[p];
+  for (int64_t p = tid; p < ne3; p += 256) sb += e3p[p];
+  red[tid] = ce1 * sa + ce3 * sb;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) *ex = -dV * red[0];
 }
 
 __global__ void pack_kernel(const double* __restrict__ C, int64_t rows, int64_t cols, int64_t ldc,
@@ -233,54 +349,33 @@ __global__ void pack_kernel(const double* __restrict__ C, int64_t rows, int64_t 
   Cp[t] = (r < rows && c < cols) ? C[r * ldc + c] : 0.0;
 }
 
-__global__ __launch_bounds__(256) void combine_kernel(const double* K1, const double* K2, const double* K3,
-                                                     int N, int n, int np, double s1, double s2, double s3,
-                                                     double dV, double* K, const double* e1p, int64_t ne1,
-                                                     const double* e3p, int64_t ne3, double ce1, double ce3,
-                                                     double* ex) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < (int64_t)N * n) {
-    const int64_t mu = t / n, i = t % n;
-    const int64_t q = mu * np + i;
-    double v = 0.0;
-    if (K1) v += s1 * K1[q];
-    if (K2) v += s2 * K2[q];
-    if (K3) v += s3 * K3[q];
-    K[t] = dV * v;
-  }
-  if (ex && t == 0) {
-    double e1 = 0.0, e3 = 0.0;
-    for (int64_t p = 0; p < ne1; ++p) e1 += e1p[p];
-    for (int64_t p = 0; p < ne3; ++p) e3 += e3p[p];
-    *ex = -dV * (ce1 * e1 + ce3 * e3);
-  }
-}
-
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-template <int NI, int RT>
-hipError_t launch_fused_mt(const FusedArgs& a, int blocks, hipStream_t s) {
-  const int mt = a.want_k1 ? a.Np / 16 : 0;
-  if (mt == 0) {
-    hipLaunchKernelGGL((fused_f64_kernel<NI, RT, 0>), dim3(blocks), dim3(256), 0, s, a);
-  } else if (mt <= 4) {
-    hipLaunchKernelGGL((fused_f64_kernel<NI, RT, 4>), dim3(blocks), dim3(256), 0, s, a);
-  } else if (mt <= 8) {
-    hipLaunchKernelGGL((fused_f64_kernel<NI, RT, 8>), dim3(blocks), dim3(256), 0, s, a);
-  } else {
-    return hipErrorInvalidValue;
-  }
+template <int NW, int NI, int MT>
+hipError_t launch_fused3(const FusedArgs& a, int blocks, hipStream_t s) {
+  const int64_t gper = ((a.G / T + a.gblocks - 1) / a.gblocks) * (T / 16);
+  const int64_t lds = fused_lds_doubles<NW, NI>(a.want_m2 ? gper * 16 : 0) * 8;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  auto k = fused_f64_kernel<NW, NI, MT>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(NW * 64), (size_t)lds, s, a);
   return hipGetLastError();
 }
 
+template <int NW, int NI>
+hipError_t launch_fused2(const FusedArgs& a, int blocks, hipStream_t s) {
+  const int mt = a.want_k1 ? a.Np / 16 : 0;
+  if (mt == 0) return launch_fused3<NW, NI, 0>(a, blocks, s);
+  if (mt <= 4) return launch_fused3<NW, NI, 4>(a, blocks, s);
+  if (mt <= 8) return launch_fused3<NW, NI, 8>(a, blocks, s);
+  return hipErrorInvalidValue;
+}
+
 template <int NI>
-hipError_t launch_fused_rt(const FusedArgs& a, int blocks, hipStream_t s) {
-  switch (a.rtiles) {
-    case 1: return launch_fused_mt<NI, 1>(a, blocks, s);
-    case 2: return launch_fused_mt<NI, 2>(a, blocks, s);
-    case 4: return launch_fused_mt<NI, 4>(a, blocks, s);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_fused1(const FusedArgs& a, int blocks, hipStream_t s) {
+  if (a.nwaves == 8) return launch_fused2<8, NI>(a, blocks, s);
+  return launch_fused2<4, NI>(a, blocks, s);
 }
 
 }  // namespace
@@ -290,16 +385,24 @@ int fused_rblocks(const FusedArgs& a) {
   return (int)((rt + a.rtiles - 1) / a.rtiles);
 }
 
+int64_t fused_lds_bytes(const FusedArgs& a) {
+  const int64_t gper = ((a.G / T + a.gblocks - 1) / a.gblocks) * (T / 16);
+  const int64_t bg = a.want_m2 ? gper * 16 : 0;
+  const int64_t per = (int64_t)(a.nwaves == 8 ? 8 : 4) * 16 * SLAB + (int64_t)T * (a.np + 1) + bg * a.np;
+  return per * 8;
+}
+
 hipError_t fused_exchange(const FusedArgs& a, hipStream_t s) {
   if (a.G % T != 0 || a.R % T != 0 || a.np % 16 != 0 || a.Np % 16 != 0) return hipErrorInvalidValue;
   if (a.want_k1 && a.Np / 16 > 8) return hipErrorInvalidValue;
+  if (a.rtiles < 1 || a.gblocks < 1) return hipErrorInvalidValue;
   const int blocks = fused_rblocks(a) * a.gblocks;
   if (blocks <= 0) return hipSuccess;
   switch (a.np / 16) {
-    case 1: return launch_fused_rt<1>(a, blocks, s);
-    case 2: return launch_fused_rt<2>(a, blocks, s);
-    case 3: return launch_fused_rt<3>(a, blocks, s);
-    case 4: return launch_fused_rt<4>(a, blocks, s);
+    case 1: return launch_fused1<1>(a, blocks, s);
+    case 2: return launch_fused1<2>(a, blocks, s);
+    case 3: return launch_fused1<3>(a, blocks, s);
+    case 4: return launch_fused1<4>(a, blocks, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -307,8 +410,33 @@ hipError_t fused_exchange(const FusedArgs& a, hipStream_t s) {
 hipError_t sum_partials(const double* in, int64_t nparts, int64_t stride, int64_t count,
                         double* out, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sum_partials_kernel, dim3(nblk(count, 256)), dim3(256), 0, s, in, nparts, stride,
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(nblk(count, 64)), dim3(256), 0, s, in, nparts, stride,
                      count, out);
+  return hipGetLastError();
+}
+
+hipError_t tall_gemm(const double* Phi, int64_t R, int Np, const double* C, int np, double* U, hipStream_t s) {
+  if (R % 16 != 0 || Np % 4 != 0 || np % 16 != 0) return hipErrorInvalidValue;
+  const int64_t nsub = R / 16;
+  const unsigned blocks = (unsigned)std::min<int64_t>((nsub + 3) / 4, 2048);
+  const size_t lds = (size_t)Np * np * 8;
+  switch (np / 16) {
+    case 1: hipLaunchKernelGGL(tall_gemm_kernel<1>, dim3(blocks), dim3(256), lds, s, Phi, R, Np, C, U); break;
+    case 2: hipLaunchKernelGGL(tall_gemm_kernel<2>, dim3(blocks), dim3(256), lds, s, Phi, R, Np, C, U); break;
+    case 3: hipLaunchKernelGGL(tall_gemm_kernel<3>, dim3(blocks), dim3(256), lds, s, Phi, R, Np, C, U); break;
+    case 4: hipLaunchKernelGGL(tall_gemm_kernel<4>, dim3(blocks), dim3(256), lds, s, Phi, R, Np, C, U); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t finalize(const double* Phig, const double* M2, int64_t G, const double* K1, const double* K3, int N,
+                    int n, int np, int Np, double s1, double s2, double s3, double dV, double* K,
+                    const double* e1p, int64_t ne1, const double* e3p, int64_t ne3, double ce1, double ce3,
+                    double* ex, hipStream_t s) {
+  const int nb = (Np + 15) / 16 + 1;
+  hipLaunchKernelGGL(finalize_kernel, dim3(nb), dim3(256), 0, s, Phig, M2, G, K1, K3, N, n, np, Np, s1, s2, s3,
+                     dV, K, e1p, ne1, e3p, ne3, ce1, ce3, ex);
   return hipGetLastError();
 }
 
@@ -316,16 +444,6 @@ hipError_t pack_matrix(const double* C, int64_t rows, int64_t cols, int64_t ldc,
                        int64_t rows_p, int64_t ldp, hipStream_t s) {
   hipLaunchKernelGGL(pack_kernel, dim3(nblk(rows_p * ldp, 256)), dim3(256), 0, s, C, rows, cols, ldc,
                      Cp, rows_p, ldp);
-  return hipGetLastError();
-}
-
-hipError_t combine(const double* K1, const double* K2, const double* K3, int N, int n, int np,
-                   double s1, double s2, double s3, double dV, double* K,
-                   const double* e1p, int64_t ne1, const double* e3p, int64_t ne3,
-                   double ce1, double ce3, double* ex, hipStream_t s) {
-  const int64_t cnt = (int64_t)N * n;
-  hipLaunchKernelGGL(combine_kernel, dim3(nblk(cnt > 0 ? cnt : 1, 256)), dim3(256), 0, s, K1, K2, K3, N,
-                     n, np, s1, s2, s3, dV, K, e1p, ne1, e3p, ne3, ce1, ce3, ex);
   return hipGetLastError();
 }
 

@@ -1,6 +1,8 @@
 // C ABI of the rPS exchange library: context, one-time ISDF set-up and the
 // per-build exchange (see include/rps.h for the contract of every entry point).
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <cmath>
@@ -80,16 +82,22 @@ struct rps_context {
   DBuf<int64_t> dpoints;
   // build workspace (grows on demand)
   int ws_np = -1;
-  DBuf<double> Cp, U, Ug, M2p, K1p, K3p, e1p, e3p, M2, K1, K2, K3, Kdev, Cdev, exdev;
+  DBuf<double> Cp, U, Ug, M2p, K1p, K3p, e1p, e3p, M2, K1, K3, Kdev, Cdev, exdev;
   int64_t rblocks_main = 0, blocks_main = 0, blocks_l3 = 0;
-  int rtiles = 4, gblocks = 1;
+  int rtiles = 4, gblocks = 1, nwaves = 4;
+  // profiling: event triples (build start, main start, main end, l3 start, l3 end, build end)
+  int profiling = 0;
+  std::vector<hipEvent_t> ev_pool;
+  int64_t ev_used = 0;
+  hipStream_t last_stream = nullptr;
 
   ~rps_context() {
     DBuf<double>* all[] = {&Phi, &Phig, &V, &W, &Cp, &U, &Ug, &M2p, &K1p, &K3p, &e1p,
-                           &e3p, &M2, &K1, &K2, &K3, &Kdev, &Cdev, &exdev};
+                           &e3p, &M2, &K1, &K3, &Kdev, &Cdev, &exdev};
     for (auto* b : all) b->release(nullptr);
     V32.release(nullptr);
     dpoints.release(nullptr);
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
   }
 };
 
@@ -449,25 +457,68 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
 }
 
 // ------------------------------------------------------------------ builds
+constexpr int kEvPerBuild = 6;
+constexpr int64_t kMaxProfiled = 65536;
+
+hipEvent_t prof_event(rps_context& c, int slot) {
+  const int64_t i = c.ev_used * kEvPerBuild + slot;
+  while ((int64_t)c.ev_pool.size() <= i) {
+    hipEvent_t e;
+    hip_check(hipEventCreate(&e), "hipEventCreate");
+    c.ev_pool.push_back(e);
+  }
+  return c.ev_pool[i];
+}
+
+void prof_mark(rps_context& c, int slot, hipStream_t st) {
+  if (!c.profiling || c.ev_used >= kMaxProfiled) return;
+  hip_check(hipEventRecord(prof_event(c, slot), st), "hipEventRecord");
+}
+
+// Launch shape of the fused V-streaming kernel for n padded to np:
+// one workgroup per CU (8 waves when np == 16, else 4), all g rows of a
+// workgroup kept in LDS (M2 accumulators) unless they do not fit, then
+// g blocks; R tiles split so that the workgroups cover the CUs once.
+void choose_shape(rps_context& c, int np, FusedArgs& a) {
+  a.nwaves = (np == 16) ? 8 : 4;
+  a.np = np;
+  a.G = c.nauxp;
+  a.want_m2 = 1;
+  const int64_t lds_cap = 160 * 1024;
+  const int64_t gt = c.nauxp / 64;
+  a.gblocks = 1;
+  a.rtiles = 1;
+  while (true) {
+    if (fused_lds_bytes(a) <= lds_cap || a.gblocks >= gt) break;
+    ++a.gblocks;
+  }
+  const int64_t rt = c.ngp / 64;
+  const int64_t target = std::max<int64_t>(1, 256 / a.gblocks);
+  a.rtiles = (int)std::max<int64_t>(1, (rt + target - 1) / target);
+  // launch-shape override for tuning sweeps: RPS_FUSED_SHAPE="rtiles,gblocks"
+  if (const char* ov = getenv("RPS_FUSED_SHAPE")) {
+    int x = 0, y = 0;
+    if (sscanf(ov, "%d,%d", &x, &y) == 2 && x >= 1 && y >= 1 && y <= gt) {
+      FusedArgs t = a;
+      t.rtiles = x;
+      t.gblocks = y;
+      if (fused_lds_bytes(t) <= lds_cap) { a.rtiles = x; a.gblocks = y; }
+    }
+  }
+}
+
 void ensure_workspace(rps_context& c, int np) {
   if (c.ws_np == np) return;
   int64_t* cnt = &c.bytes;
-  // launch shape of the fused kernel: aim for >= 2 workgroups per CU
-  c.rtiles = 4;
-  c.gblocks = 1;
-  const int64_t rt = c.ngp / 64;
-  int64_t rblocks = (rt + c.rtiles - 1) / c.rtiles;
-  while (rblocks * c.gblocks < 512 && c.gblocks * 2 <= c.nauxp / 64) {
-    if (c.rtiles > 1) {
-      c.rtiles /= 2;
-    } else {
-      c.gblocks *= 2;
-    }
-    rblocks = (rt + c.rtiles - 1) / c.rtiles;
-  }
-  c.rblocks_main = rblocks;
-  c.blocks_main = rblocks * c.gblocks;
-  c.blocks_l3 = (c.nauxp / 64 + 3) / 4;      // line 3: 4 tiles per block, one g block
+  FusedArgs a{};
+  a.R_valid = c.ng;
+  choose_shape(c, np, a);
+  c.rtiles = a.rtiles;
+  c.gblocks = a.gblocks;
+  c.nwaves = a.nwaves;
+  c.rblocks_main = fused_rblocks(a);
+  c.blocks_main = c.rblocks_main * c.gblocks;
+  c.blocks_l3 = (c.nauxp / 64) * ((c.naux + 63) / 64);   // one 64 x 64 tile of W per workgroup
   c.Cp.alloc(c.Np * np, cnt);
   c.U.alloc(c.ngp * np, cnt);
   c.Ug.alloc(c.nauxp * np, cnt);
@@ -478,10 +529,9 @@ void ensure_workspace(rps_context& c, int np) {
   c.e3p.alloc(std::max<int64_t>(c.blocks_l3, 1), cnt);
   c.M2.alloc(c.nauxp * np, cnt);
   c.K1.alloc(c.Np * np, cnt);
-  c.K2.alloc(c.Np * np, cnt);
   c.K3.alloc(c.Np * np, cnt);
-  c.Kdev.alloc(c.nbas * np, cnt);
   c.Cdev.alloc(c.nbas * np, cnt);
+  c.Kdev.alloc(c.nbas * np, cnt);
   c.exdev.alloc(1, cnt);
   c.ws_np = np;
 }
@@ -502,6 +552,8 @@ void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, doub
   if (variant == RPS_VARIANT_PS) { s1 = 0; s2 = 1; s3 = 0; ce1 = 1; ce3 = 0; }
   if (variant == RPS_VARIANT_THC) { s1 = 0; s2 = 0; s3 = 1; ce1 = 0; ce3 = 1; }
   const bool dev = (flags == RPS_PTRS_DEVICE);
+  c.last_stream = st;
+  prof_mark(c, 0, st);
   const double* Csrc = C;
   if (!dev) {
     hip_check(hipMemcpyAsync(c.Cdev.p, C, (size_t)c.nbas * nocc * 8, hipMemcpyHostToDevice, st), "copy C");
@@ -509,10 +561,7 @@ void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, doub
   }
   hip_check(pack_matrix(Csrc, c.nbas, nocc, nocc, c.Cp.p, c.Np, np, st), "pack C");
   // U = Phi C (orbitals on the grid), U_g = U[points]
-  Gemm g;
-  g.M = c.ngp; g.N = np; g.K = c.Np;
-  g.A = c.Phi.p; g.lda = c.Np; g.B = c.Cp.p; g.ldb = np; g.C = c.U.p; g.ldc = np;
-  hip_check(gemm_f64(g, st), "U");
+  hip_check(tall_gemm(c.Phi.p, c.ngp, (int)c.Np, c.Cp.p, np, c.U.p, st), "U");
   hip_check(gather_rows(c.U.p, np, c.dpoints.p, c.naux, c.nauxp, np, c.Ug.p, np, st), "U_g");
   const bool need_main = (variant != RPS_VARIANT_THC);
   const bool need_l3 = (variant != RPS_VARIANT_PS);
@@ -520,35 +569,41 @@ void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, doub
     FusedArgs a{};
     a.Vm = c.V.p; a.ldv = c.ngp; a.Ug = c.Ug.p; a.Ur = c.U.p; a.Phir = c.Phi.p;
     a.G = c.nauxp; a.R = c.ngp; a.R_valid = c.ng; a.np = np; a.Np = (int)c.Np;
-    a.rtiles = c.rtiles; a.gblocks = c.gblocks;
+    a.rtiles = c.rtiles; a.gblocks = c.gblocks; a.nwaves = c.nwaves;
     a.want_m2 = 1; a.want_k1 = (variant == RPS_VARIANT_RPS) ? 1 : 0; a.want_m1 = 0;
     a.prec = c.precision;
     a.M2p = c.M2p.p; a.K1p = c.K1p.p; a.e1p = c.e1p.p;
+    prof_mark(c, 1, st);
     hip_check(fused_exchange(a, st), "fused main");
+    prof_mark(c, 2, st);
     if (a.want_k1) hip_check(sum_partials(c.K1p.p, c.blocks_main, c.Np * np, c.Np * np, c.K1.p, st), "K1");
     hip_check(sum_partials(c.M2p.p, c.rblocks_main, c.nauxp * np, c.nauxp * np, c.M2.p, st), "M2");
-    Gemm k2;   // K2 = Phi_g^T M2
-    k2.M = c.Np; k2.N = np; k2.K = c.nauxp;
-    k2.A = c.Phig.p; k2.lda = c.Np; k2.transA = true; k2.B = c.M2.p; k2.ldb = np;
-    k2.C = c.K2.p; k2.ldc = np;
-    hip_check(gemm_f64(k2, st), "K2");
   }
   if (need_l3) {
     FusedArgs a{};
     a.Vm = c.W.p; a.ldv = c.nauxp; a.Ug = c.Ug.p; a.Ur = c.Ug.p; a.Phir = c.Phig.p;
     a.G = c.nauxp; a.R = c.nauxp; a.R_valid = c.naux; a.np = np; a.Np = (int)c.Np;
-    a.rtiles = 4; a.gblocks = 1;
+    a.rtiles = 1; a.gblocks = (int)(c.nauxp / 64); a.nwaves = 4;
     a.want_m2 = 0; a.want_k1 = 1; a.want_m1 = 0; a.prec = RPS_PREC_FP64;
     a.K1p = c.K3p.p; a.e1p = c.e3p.p;
+    prof_mark(c, 3, st);
     hip_check(fused_exchange(a, st), "fused line 3");
+    prof_mark(c, 4, st);
     hip_check(sum_partials(c.K3p.p, c.blocks_l3, c.Np * np, c.Np * np, c.K3.p, st), "K3");
   }
   double* Kout = dev ? K : c.Kdev.p;
   double* exout = dev ? ex : (ex ? c.exdev.p : nullptr);
-  hip_check(combine(need_main && variant == RPS_VARIANT_RPS ? c.K1.p : nullptr, need_main ? c.K2.p : nullptr,
-                    need_l3 ? c.K3.p : nullptr, (int)c.nbas, nocc, np, s1, s2, s3, c.dV, Kout, c.e1p.p,
-                    need_main ? c.blocks_main : 0, c.e3p.p, need_l3 ? c.blocks_l3 : 0, ce1, ce3, exout, st),
-            "combine");
+  hip_check(finalize(c.Phig.p, need_main ? c.M2.p : nullptr, c.nauxp,
+                     (need_main && variant == RPS_VARIANT_RPS) ? c.K1.p : nullptr, need_l3 ? c.K3.p : nullptr,
+                     (int)c.nbas, nocc, np, (int)c.Np, s1, s2, s3, c.dV, Kout, c.e1p.p,
+                     need_main ? c.blocks_main : 0, c.e3p.p, need_l3 ? c.blocks_l3 : 0, ce1, ce3, exout, st),
+            "finalize");
+  prof_mark(c, 5, st);
+  if (c.profiling && c.ev_used < kMaxProfiled) {
+    if (!need_main) { prof_mark(c, 1, st); prof_mark(c, 2, st); }
+    if (!need_l3) { prof_mark(c, 3, st); prof_mark(c, 4, st); }
+    ++c.ev_used;
+  }
   if (!dev) {
     hip_check(hipMemcpyAsync(K, c.Kdev.p, (size_t)c.nbas * nocc * 8, hipMemcpyDeviceToHost, st), "copy K");
     if (ex) hip_check(hipMemcpyAsync(ex, c.exdev.p, 8, hipMemcpyDeviceToHost, st), "copy ex");
@@ -709,6 +764,40 @@ rps_status rps_get_array(const rps_context* ctx, int32_t which, int64_t row0, in
     if (row0 < 0 || nrows < 0 || row0 + nrows > rows) fail(RPS_ERR_SHAPE, "row range out of bounds");
     hip_check(hipMemcpy2D(out, cols * 8, src + row0 * ld, ld * 8, cols * 8, nrows, hipMemcpyDeviceToHost),
               "copy array");
+  });
+}
+
+rps_status rps_set_profiling(rps_context* ctx, int32_t enable) {
+  return guarded([&] {
+    if (!ctx) fail(RPS_ERR_ARG, "ctx must not be NULL");
+    ctx->profiling = enable ? 1 : 0;
+    ctx->ev_used = 0;
+  });
+}
+
+rps_status rps_get_profile(rps_context* ctx, double* out) {
+  return guarded([&] {
+    if (!ctx || !out) fail(RPS_ERR_ARG, "NULL argument");
+    rps_context& c = *ctx;
+    double tot[3] = {0.0, 0.0, 0.0};
+    if (c.ev_used > 0) {
+      hip_check(hipStreamSynchronize(c.last_stream), "sync");
+      for (int64_t b = 0; b < c.ev_used; ++b) {
+        hipEvent_t* e = &c.ev_pool[b * kEvPerBuild];
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, e[1], e[2]), "elapsed");
+        tot[0] += ms;
+        hip_check(hipEventElapsedTime(&ms, e[3], e[4]), "elapsed");
+        tot[1] += ms;
+        hip_check(hipEventElapsedTime(&ms, e[0], e[5]), "elapsed");
+        tot[2] += ms;
+      }
+    }
+    out[0] = (double)c.ev_used;
+    out[1] = tot[0];
+    out[2] = tot[1];
+    out[3] = tot[2];
+    c.ev_used = 0;
   });
 }
 

@@ -97,6 +97,7 @@ struct FusedArgs {
   int Np;                   // padded N (multiple of 16)
   int rtiles;               // 64-column tiles per workgroup
   int gblocks;              // workgroups along G
+  int nwaves;               // waves per workgroup (4 or 8)
   int want_m2;              // write M2 partials
   int want_k1;              // accumulate K1 partials (Phir^T (A^T Ug))
   int want_m1;              // write M1^T = A^T Ug rows (when K1 is not fused)
@@ -108,7 +109,16 @@ struct FusedArgs {
   double* e1p;              // [gblocks*rblocks]
 };
 int fused_rblocks(const FusedArgs& a);
+int64_t fused_lds_bytes(const FusedArgs& a);
 hipError_t fused_exchange(const FusedArgs& a, hipStream_t s);
+// U [R x np] = Phi [R x Np] C [Np x np]  (R % 16 == 0, np % 16 == 0, np <= 64)
+hipError_t tall_gemm(const double* Phi, int64_t R, int Np, const double* C, int np, double* U, hipStream_t s);
+// K[mu][i] = dV (s1 K1 + s2 Phi_g^T M2 + s3 K3) for mu < N, i < n (M2, K1, K3 may be NULL);
+// ex = -dV (ce1 sum e1p + ce3 sum e3p) (ex may be NULL).
+hipError_t finalize(const double* Phig, const double* M2, int64_t G, const double* K1, const double* K3, int N,
+                    int n, int np, int Np, double s1, double s2, double s3, double dV, double* K,
+                    const double* e1p, int64_t ne1, const double* e3p, int64_t ne3, double ce1, double ce3,
+                    double* ex, hipStream_t s);
 
 // Sum partials: out[i] = sum_p in[p*stride + i], i < count (deterministic order).
 hipError_t sum_partials(const double* in, int64_t nparts, int64_t stride, int64_t count,
@@ -116,11 +126,4 @@ hipError_t sum_partials(const double* in, int64_t nparts, int64_t stride, int64_
 // Pack C [N][n] (row pitch n) into Cp [Np][np] zero padded.
 hipError_t pack_matrix(const double* C, int64_t rows, int64_t cols, int64_t ldc, double* Cp,
                        int64_t rows_p, int64_t ldp, hipStream_t s);
-// Final combine: K[mu][i] = dV (K1 + K2 - K3) (unpadded out, ldk = n);
-// ex = -dV (2 e1 - e3) with e1 = sum e1p[0:ne1], e3 = sum e3p[0:ne3].
-hipError_t combine(const double* K1, const double* K2, const double* K3, int N, int n, int np,
-                   double s1, double s2, double s3, double dV, double* K,
-                   const double* e1p, int64_t ne1, const double* e3p, int64_t ne3,
-                   double ce1, double ce3, double* ex, hipStream_t s);
-
 }  // namespace rps
