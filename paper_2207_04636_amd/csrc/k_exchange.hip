@@ -253,29 +253,66 @@ __global__ __launch_bounds__(NW * 64) void fused_f64_kernel(FusedArgs a) {
   }
 }
 
-// U = Phi C for a tall Phi [R x Np] and C [Np x NP]: each wave computes 16
-// rows per step on the FP64 matrix cores, C staged once in LDS.
-template <int NI>
-__global__ __launch_bounds__(256) void tall_gemm_kernel(const double* __restrict__ Phi, int64_t R, int Np,
-                                                       const double* __restrict__ C, double* __restrict__ U) {
+// Orbitals on the grid and at the points: U = Phi C and U_g = Phi_g C.
+// Row subtiles 16 at a time on the FP64 matrix cores; rows [0, R) come from
+// Phi, rows [R, R + G) from Phi_g.  C [N x n] (row pitch n) is read once into
+// LDS as the zero-padded [Np x NP] operand.  Each wave loads its 16 x Np block
+// of basis values up front (MT = Np/16 <= 8) so that the loads overlap.
+template <int NI, int MT>
+__global__ __launch_bounds__(256) void orbitals_kernel(const double* __restrict__ Phi, int64_t R,
+                                                      const double* __restrict__ Phig, int64_t G, int Np,
+                                                      const double* __restrict__ C, int N, int n,
+                                                      double* __restrict__ U, double* __restrict__ Ug) {
   constexpr int NP = 16 * NI;
-  extern __shared__ double sC[];     // [Np][NP]
+  constexpr int PB = 16 * (MT * 16 + 1);      // one wave's staged block, padded rows
+  extern __shared__ double lds[];
+  double* sC = lds;                            // [Np][NP]
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
-  for (int e = tid; e < Np * NP; e += 256) sC[e] = C[e];
+  double* sB = lds + Np * NP + w * PB;         // this wave's 16 x Np block, pitch Np + 1
+  const int ldb = MT * 16 + 1;
+  for (int e = tid; e < Np * NP; e += 256) {
+    const int r = e / NP, c = e % NP;
+    sC[e] = (r < N && c < n) ? C[(int64_t)r * n + c] : 0.0;
+  }
   __syncthreads();
-  const int64_t nsub = R / 16;
-  for (int64_t s = (int64_t)blockIdx.x * 4 + w; s < nsub; s += (int64_t)gridDim.x * 4) {
-    const double* ph = Phi + (s * 16 + l16) * Np + lq;
+  const int64_t nsub = (R + G) / 16;
+  const int nvec = 16 * Np / 2;                // 16-byte pieces of a 16-row block
+  for (int64_t sidx = (int64_t)blockIdx.x * 4 + w; sidx < nsub; sidx += (int64_t)gridDim.x * 4) {
+    const int64_t row0 = sidx * 16;
+    const double* src = (row0 < R) ? Phi + row0 * Np : Phig + (row0 - R) * Np;
+    double* dst = (row0 < R) ? U + row0 * NP : Ug + (row0 - R) * NP;
+    // the 16 rows are contiguous in memory: 16*Np doubles
+    const double2* src2 = reinterpret_cast<const double2*>(src);
+    double2 buf[(16 * MT * 16 / 2 + 63) / 64];
+#pragma unroll
+    for (int q = 0; q < (16 * MT * 16 / 2 + 63) / 64; ++q) {
+      const int v = q * 64 + lane;
+      if (v < nvec) buf[q] = src2[v];
+    }
+#pragma unroll
+    for (int q = 0; q < (16 * MT * 16 / 2 + 63) / 64; ++q) {
+      const int v = q * 64 + lane;
+      if (v < nvec) {
+        const int e = 2 * v, r = e / Np, c = e % Np;
+        sB[r * ldb + c] = buf[q].x;
+        sB[r * ldb + c + 1] = buf[q].y;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
     d4_t acc[NI];
 #pragma unroll
     for (int j = 0; j < NI; ++j) acc[j] = zero_d4();
-    for (int kk = 0; kk < Np / 4; ++kk) {
-      const double x = ph[4 * kk];
 #pragma unroll
-      for (int j = 0; j < NI; ++j) acc[j] = mfma_f64(x, sC[(4 * kk + lq) * NP + 16 * j + l16], acc[j]);
+    for (int kk = 0; kk < MT * 4; ++kk) {
+      if (4 * kk < Np) {
+        const double x = sB[l16 * ldb + 4 * kk + lq];
+#pragma unroll
+        for (int j = 0; j < NI; ++j) acc[j] = mfma_f64(x, sC[(4 * kk + lq) * NP + 16 * j + l16], acc[j]);
+      }
     }
-    double* out = U + (s * 16 + lq) * NP + l16;
+    __builtin_amdgcn_wave_barrier();
+    double* out = dst + lq * NP + l16;
 #pragma unroll
     for (int j = 0; j < NI; ++j)
 #pragma unroll
@@ -283,70 +320,114 @@ __global__ __launch_bounds__(256) void tall_gemm_kernel(const double* __restrict
   }
 }
 
-// Deterministic sum over partials: block = 64 outputs x 4 partial lanes.
-__global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ in, int64_t nparts,
-                                                             int64_t stride, int64_t count,
-                                                             double* __restrict__ out) {
+// Deterministic sums over partials for up to three segments in one launch:
+// out_s[i] = sum_p in_s[p * count_s + i].  A block owns 64 outputs of one
+// segment; its 4 partial lanes take p = q, q + 4, ... with 8 loads in flight,
+// and are combined in a fixed order.
+struct ReduceSeg {
+  const double* in;
+  int64_t nparts, count;
+  double* out;
+  int64_t block0;     // first block of this segment
+};
+struct ReduceArgs {
+  ReduceSeg seg[3];
+  int nseg;
+};
+
+__global__ __launch_bounds__(256) void reduce_partials_kernel(ReduceArgs ra) {
   __shared__ double red[4][64];
+  int si = 0;
+  for (int k = 1; k < ra.nseg; ++k)
+    if ((int64_t)blockIdx.x >= ra.seg[k].block0) si = k;
+  const ReduceSeg sg = ra.seg[si];
   const int x = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const int64_t i = (int64_t)blockIdx.x * 64 + x;
+  const int64_t i = ((int64_t)blockIdx.x - sg.block0) * 64 + x;
   double s = 0.0;
-  if (i < count)
-    for (int64_t p = q; p < nparts; p += 4) s += in[p * stride + i];
+  if (i < sg.count) {
+    int64_t p = q;
+    for (; p + 28 < sg.nparts; p += 32) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = sg.in[(p + 4 * u) * sg.count + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; p < sg.nparts; p += 4) s += sg.in[p * sg.count + i];
+  }
   red[q][x] = s;
   __syncthreads();
-  if (q == 0 && i < count) out[i] = ((red[0][x] + red[1][x]) + red[2][x]) + red[3][x];
+  if (q == 0 && i < sg.count) sg.out[i] = ((red[0][x] + red[1][x]) + red[2][x]) + red[3][x];
 }
 
-// K2 = Phi_g^T M2 and the final combination; block b < nmu_blocks handles 16
-// rows mu; the last block sums the energy partials with a fixed tree.
-__global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ Phig, const double* __restrict__ M2,
+// Final step of a build.  Workgroup (m, j) owns the 16 x 16 output tile
+// K[16m.., 16j..]: it forms K2 = Phi_g^T M2 for the tile on the matrix cores
+// with the inner dimension split over the 8 waves (fixed-order reduction) and
+// writes K = dV (s1 K1 + s2 K2 + s3 K3) for mu < N, i < n.  The last workgroup
+// sums the energy partials with a fixed tree.
+__global__ __launch_bounds__(512) void finalize_kernel(const double* __restrict__ Phig, const double* __restrict__ M2,
                                                       int64_t G, const double* __restrict__ K1,
-                                                      const double* __restrict__ K3, int N, int n, int np, int Np,
-                                                      double s1, double s2, double s3, double dV,
+                                                      const double* __restrict__ K3, int N, int n,
+                                                      int np, int Np, double s1, double s2, double s3, double dV,
                                                       double* __restrict__ K, const double* __restrict__ e1p,
                                                       int64_t ne1, const double* __restrict__ e3p, int64_t ne3,
                                                       double ce1, double ce3, double* __restrict__ ex) {
-  __shared__ double red[256];
-  const int tid = threadIdx.x;
-  const int nmu_blocks = (Np + 15) / 16;
-  if ((int)blockIdx.x < nmu_blocks) {
-    const int per = 256 / np;                 // rows mu per pass
-    for (int mu0 = blockIdx.x * 16; mu0 < blockIdx.x * 16 + 16; mu0 += per) {
-      const int mu = mu0 + tid / np, i = tid % np;
-      if (tid / np < per && mu < blockIdx.x * 16 + 16 && mu < N && i < n) {
-        double k2 = 0.0;
-        if (M2) {
-          for (int64_t g = 0; g < G; ++g) k2 += Phig[g * Np + mu] * M2[g * np + i];
-        }
-        const int64_t q = (int64_t)mu * np + i;
-        double v = s2 * k2;
-        if (K1) v += s1 * K1[q];
-        if (K3) v += s3 * K3[q];
-        K[(int64_t)mu * n + i] = dV * v;
-      }
+  __shared__ double red[8][64][4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int ntile = (Np / 16) * (np / 16);
+  if ((int)blockIdx.x == ntile) {
+    if (!ex) return;
+    double sa = 0.0, sb = 0.0;
+    for (int64_t p = tid; p < ne1; p += 512) sa += e1p[p];
+    for (int64_t p = tid; p < ne3; p += 512) sb += e3p[p];
+    double* r1 = &red[0][0][0];
+    r1[tid] = ce1 * sa + ce3 * sb;
+    __syncthreads();
+    for (int off = 256; off > 0; off >>= 1) {
+      if (tid < off) r1[tid] += r1[tid + off];
+      __syncthreads();
     }
+    if (tid == 0) *ex = -dV * r1[0];
     return;
   }
-  if (!ex) return;
-  double sa = 0.0, sb = 0.0;
-  for (int64_t p = tid; p < ne1; p += 256) sa += e1p[p];
-  for (int64_t p = tid; p < ne3; p += 256) sb += e3p[p];
-  red[tid] = ce1 * sa + ce3 * sb;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (tid < off) red[tid] += red[tid + off];
-    __syncthreads();
+  const int m = blockIdx.x / (np / 16), j = blockIdx.x % (np / 16);
+  d4_t acc = zero_d4();
+  if (M2) {
+    const int64_t nsl = G / 4;
+    int64_t sl = w;
+    for (; sl + 56 < nsl; sl += 64) {
+      double a[8], b[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t g = 4 * (sl + 8 * u) + lq;
+        a[u] = Phig[g * Np + 16 * m + l16];
+        b[u] = M2[g * np + 16 * j + l16];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = mfma_f64(a[u], b[u], acc);
+    }
+    for (; sl < nsl; sl += 8) {
+      const int64_t g = 4 * sl + lq;
+      acc = mfma_f64(Phig[g * Np + 16 * m + l16], M2[g * np + 16 * j + l16], acc);
+    }
   }
-  if (tid == 0) *ex = -dV * red[0];
-}
-
-__global__ void pack_kernel(const double* __restrict__ C, int64_t rows, int64_t cols, int64_t ldc,
-                            double* __restrict__ Cp, int64_t rows_p, int64_t ldp) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= rows_p * ldp) return;
-  const int64_t r = t / ldp, c = t % ldp;
-  Cp[t] = (r < rows && c < cols) ? C[r * ldc + c] : 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[w][lane][r] = acc[r];
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double s = 0.0;
+      for (int ww = 0; ww < 8; ++ww) s += red[ww][lane][r];
+      const int mu = 16 * m + 4 * r + lq, i = 16 * j + l16;
+      const int64_t q = (int64_t)mu * np + i;
+      double v = s2 * s;
+      if (K1) v += s1 * K1[q];
+      if (K3) v += s3 * K3[q];
+      if (mu < N && i < n) K[(int64_t)mu * n + i] = dV * v;
+    }
+  }
 }
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -407,43 +488,61 @@ hipError_t fused_exchange(const FusedArgs& a, hipStream_t s) {
   }
 }
 
-hipError_t sum_partials(const double* in, int64_t nparts, int64_t stride, int64_t count,
-                        double* out, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3(nblk(count, 64)), dim3(256), 0, s, in, nparts, stride,
-                     count, out);
+hipError_t sum_partials3(const double* in0, int64_t n0, int64_t c0, double* o0, const double* in1, int64_t n1,
+                         int64_t c1, double* o1, const double* in2, int64_t n2, int64_t c2, double* o2,
+                         hipStream_t s) {
+  ReduceArgs ra{};
+  int64_t blocks = 0;
+  const double* ins[3] = {in0, in1, in2};
+  const int64_t ns[3] = {n0, n1, n2}, cs[3] = {c0, c1, c2};
+  double* outs[3] = {o0, o1, o2};
+  for (int k = 0; k < 3; ++k) {
+    if (!ins[k] || ns[k] <= 0 || cs[k] <= 0) continue;
+    ReduceSeg& g = ra.seg[ra.nseg++];
+    g.in = ins[k]; g.nparts = ns[k]; g.count = cs[k]; g.out = outs[k]; g.block0 = blocks;
+    blocks += (cs[k] + 63) / 64;
+  }
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)blocks), dim3(256), 0, s, ra);
   return hipGetLastError();
 }
 
-hipError_t tall_gemm(const double* Phi, int64_t R, int Np, const double* C, int np, double* U, hipStream_t s) {
-  if (R % 16 != 0 || Np % 4 != 0 || np % 16 != 0) return hipErrorInvalidValue;
-  const int64_t nsub = R / 16;
-  const unsigned blocks = (unsigned)std::min<int64_t>((nsub + 3) / 4, 2048);
-  const size_t lds = (size_t)Np * np * 8;
+hipError_t orbitals(const double* Phi, int64_t R, const double* Phig, int64_t G, int Np, const double* C,
+                    int N, int n, int np, double* U, double* Ug, hipStream_t s) {
+  if (R % 16 != 0 || G % 16 != 0 || Np % 16 != 0 || np % 16 != 0 || Np > 128) return hipErrorInvalidValue;
+  const int64_t nsub = (R + G) / 16;
+  const unsigned blocks = (unsigned)std::min<int64_t>((nsub + 3) / 4, 4096);
+  const int mt = Np / 16;
+  const int mtc = (mt <= 2) ? 2 : (mt <= 4) ? 4 : 8;
+  const size_t lds = (size_t)Np * np * 8 + (size_t)4 * 16 * (mtc * 16 + 1) * 8;
+#define RPS_ORB(NI_, MT_)                                                                                   \
+  do {                                                                                                       \
+    hipError_t e_ = hipFuncSetAttribute((const void*)orbitals_kernel<NI_, MT_>,                              \
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);               \
+    if (e_ != hipSuccess) return e_;                                                                         \
+    hipLaunchKernelGGL((orbitals_kernel<NI_, MT_>), dim3(blocks), dim3(256), lds, s, Phi, R, Phig, G, Np, C, \
+                       N, n, U, Ug);                                                                         \
+  } while (0)
+#define RPS_ORB_NI(NI_) \
+  do { if (mt <= 2) RPS_ORB(NI_, 2); else if (mt <= 4) RPS_ORB(NI_, 4); else RPS_ORB(NI_, 8); } while (0)
   switch (np / 16) {
-    case 1: hipLaunchKernelGGL(tall_gemm_kernel<1>, dim3(blocks), dim3(256), lds, s, Phi, R, Np, C, U); break;
-    case 2: hipLaunchKernelGGL(tall_gemm_kernel<2>, dim3(blocks), dim3(256), lds, s, Phi, R, Np, C, U); break;
-    case 3: hipLaunchKernelGGL(tall_gemm_kernel<3>, dim3(blocks), dim3(256), lds, s, Phi, R, Np, C, U); break;
-    case 4: hipLaunchKernelGGL(tall_gemm_kernel<4>, dim3(blocks), dim3(256), lds, s, Phi, R, Np, C, U); break;
+    case 1: RPS_ORB_NI(1); break;
+    case 2: RPS_ORB_NI(2); break;
+    case 3: RPS_ORB_NI(3); break;
+    case 4: RPS_ORB_NI(4); break;
     default: return hipErrorInvalidValue;
   }
+#undef RPS_ORB_NI
+#undef RPS_ORB
   return hipGetLastError();
 }
 
 hipError_t finalize(const double* Phig, const double* M2, int64_t G, const double* K1, const double* K3, int N,
-                    int n, int np, int Np, double s1, double s2, double s3, double dV, double* K,
-                    const double* e1p, int64_t ne1, const double* e3p, int64_t ne3, double ce1, double ce3,
-                    double* ex, hipStream_t s) {
-  const int nb = (Np + 15) / 16 + 1;
-  hipLaunchKernelGGL(finalize_kernel, dim3(nb), dim3(256), 0, s, Phig, M2, G, K1, K3, N, n, np, Np, s1, s2, s3,
-                     dV, K, e1p, ne1, e3p, ne3, ce1, ce3, ex);
-  return hipGetLastError();
-}
-
-hipError_t pack_matrix(const double* C, int64_t rows, int64_t cols, int64_t ldc, double* Cp,
-                       int64_t rows_p, int64_t ldp, hipStream_t s) {
-  hipLaunchKernelGGL(pack_kernel, dim3(nblk(rows_p * ldp, 256)), dim3(256), 0, s, C, rows, cols, ldc,
-                     Cp, rows_p, ldp);
+                    int n, int np, int Np, double s1, double s2, double s3, double dV, double* K, const double* e1p,
+                    int64_t ne1, const double* e3p, int64_t ne3, double ce1, double ce3, double* ex, hipStream_t s) {
+  const int ntile = (Np / 16) * (np / 16);
+  hipLaunchKernelGGL(finalize_kernel, dim3(ntile + 1), dim3(512), 0, s, Phig, M2, G, K1, K3, N, n, np, Np, s1, s2,
+                     s3, dV, K, e1p, ne1, e3p, ne3, ce1, ce3, ex);
   return hipGetLastError();
 }
 

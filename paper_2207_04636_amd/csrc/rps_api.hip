@@ -82,7 +82,7 @@ struct rps_context {
   DBuf<int64_t> dpoints;
   // build workspace (grows on demand)
   int ws_np = -1;
-  DBuf<double> Cp, U, Ug, M2p, K1p, K3p, e1p, e3p, M2, K1, K3, Kdev, Cdev, exdev;
+  DBuf<double> U, Ug, M2p, K1p, K3p, e1p, e3p, M2, K1, K3, Kdev, Cdev, exdev;
   int64_t rblocks_main = 0, blocks_main = 0, blocks_l3 = 0;
   int rtiles = 4, gblocks = 1, nwaves = 4;
   // profiling: event triples (build start, main start, main end, l3 start, l3 end, build end)
@@ -92,7 +92,7 @@ struct rps_context {
   hipStream_t last_stream = nullptr;
 
   ~rps_context() {
-    DBuf<double>* all[] = {&Phi, &Phig, &V, &W, &Cp, &U, &Ug, &M2p, &K1p, &K3p, &e1p,
+    DBuf<double>* all[] = {&Phi, &Phig, &V, &W, &U, &Ug, &M2p, &K1p, &K3p, &e1p,
                            &e3p, &M2, &K1, &K3, &Kdev, &Cdev, &exdev};
     for (auto* b : all) b->release(nullptr);
     V32.release(nullptr);
@@ -519,7 +519,6 @@ void ensure_workspace(rps_context& c, int np) {
   c.rblocks_main = fused_rblocks(a);
   c.blocks_main = c.rblocks_main * c.gblocks;
   c.blocks_l3 = (c.nauxp / 64) * ((c.naux + 63) / 64);   // one 64 x 64 tile of W per workgroup
-  c.Cp.alloc(c.Np * np, cnt);
   c.U.alloc(c.ngp * np, cnt);
   c.Ug.alloc(c.nauxp * np, cnt);
   c.M2p.alloc(c.rblocks_main * c.nauxp * np, cnt);
@@ -559,10 +558,9 @@ void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, doub
     hip_check(hipMemcpyAsync(c.Cdev.p, C, (size_t)c.nbas * nocc * 8, hipMemcpyHostToDevice, st), "copy C");
     Csrc = c.Cdev.p;
   }
-  hip_check(pack_matrix(Csrc, c.nbas, nocc, nocc, c.Cp.p, c.Np, np, st), "pack C");
-  // U = Phi C (orbitals on the grid), U_g = U[points]
-  hip_check(tall_gemm(c.Phi.p, c.ngp, (int)c.Np, c.Cp.p, np, c.U.p, st), "U");
-  hip_check(gather_rows(c.U.p, np, c.dpoints.p, c.naux, c.nauxp, np, c.Ug.p, np, st), "U_g");
+  // U = Phi C (orbitals on the grid) and U_g = Phi_g C (at the points)
+  hip_check(orbitals(c.Phi.p, c.ngp, c.Phig.p, c.nauxp, (int)c.Np, Csrc, (int)c.nbas, nocc, np, c.U.p, c.Ug.p, st),
+            "orbitals");
   const bool need_main = (variant != RPS_VARIANT_THC);
   const bool need_l3 = (variant != RPS_VARIANT_PS);
   if (need_main) {
@@ -576,8 +574,6 @@ void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, doub
     prof_mark(c, 1, st);
     hip_check(fused_exchange(a, st), "fused main");
     prof_mark(c, 2, st);
-    if (a.want_k1) hip_check(sum_partials(c.K1p.p, c.blocks_main, c.Np * np, c.Np * np, c.K1.p, st), "K1");
-    hip_check(sum_partials(c.M2p.p, c.rblocks_main, c.nauxp * np, c.nauxp * np, c.M2.p, st), "M2");
   }
   if (need_l3) {
     FusedArgs a{};
@@ -589,14 +585,18 @@ void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, doub
     prof_mark(c, 3, st);
     hip_check(fused_exchange(a, st), "fused line 3");
     prof_mark(c, 4, st);
-    hip_check(sum_partials(c.K3p.p, c.blocks_l3, c.Np * np, c.Np * np, c.K3.p, st), "K3");
   }
   double* Kout = dev ? K : c.Kdev.p;
   double* exout = dev ? ex : (ex ? c.exdev.p : nullptr);
-  hip_check(finalize(c.Phig.p, need_main ? c.M2.p : nullptr, c.nauxp,
-                     (need_main && variant == RPS_VARIANT_RPS) ? c.K1.p : nullptr, need_l3 ? c.K3.p : nullptr,
-                     (int)c.nbas, nocc, np, (int)c.Np, s1, s2, s3, c.dV, Kout, c.e1p.p,
-                     need_main ? c.blocks_main : 0, c.e3p.p, need_l3 ? c.blocks_l3 : 0, ce1, ce3, exout, st),
+  const bool k1 = need_main && variant == RPS_VARIANT_RPS;
+  hip_check(sum_partials3(k1 ? c.K1p.p : nullptr, c.blocks_main, c.Np * np, c.K1.p,
+                          need_main ? c.M2p.p : nullptr, c.rblocks_main, c.nauxp * np, c.M2.p,
+                          need_l3 ? c.K3p.p : nullptr, c.blocks_l3, c.Np * np, c.K3.p, st),
+            "partial sums");
+  hip_check(finalize(c.Phig.p, need_main ? c.M2.p : nullptr, c.nauxp, k1 ? c.K1.p : nullptr,
+                     need_l3 ? c.K3.p : nullptr, (int)c.nbas, nocc, np, (int)c.Np, s1, s2, s3, c.dV, Kout,
+                     c.e1p.p, need_main ? c.blocks_main : 0, c.e3p.p, need_l3 ? c.blocks_l3 : 0, ce1, ce3, exout,
+                     st),
             "finalize");
   prof_mark(c, 5, st);
   if (c.profiling && c.ev_used < kMaxProfiled) {

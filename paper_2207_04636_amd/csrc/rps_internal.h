@@ -111,19 +111,19 @@ struct FusedArgs {
 int fused_rblocks(const FusedArgs& a);
 int64_t fused_lds_bytes(const FusedArgs& a);
 hipError_t fused_exchange(const FusedArgs& a, hipStream_t s);
-// U [R x np] = Phi [R x Np] C [Np x np]  (R % 16 == 0, np % 16 == 0, np <= 64)
-hipError_t tall_gemm(const double* Phi, int64_t R, int Np, const double* C, int np, double* U, hipStream_t s);
-// K[mu][i] = dV (s1 K1 + s2 Phi_g^T M2 + s3 K3) for mu < N, i < n (M2, K1, K3 may be NULL);
-// ex = -dV (ce1 sum e1p + ce3 sum e3p) (ex may be NULL).
+// U [R x np] = Phi [R x Np] C and U_g [G x np] = Phi_g [G x Np] C, with C [N x n]
+// (row pitch n) zero padded to [Np x np] (R, G % 16 == 0, np <= 64, Np <= 128).
+hipError_t orbitals(const double* Phi, int64_t R, const double* Phig, int64_t G, int Np, const double* C,
+                    int N, int n, int np, double* U, double* Ug, hipStream_t s);
+// Up to three partial sums in one launch: out_k[i] = sum_p in_k[p*count_k + i]
+// (fixed order); a segment with a NULL input is skipped.
+hipError_t sum_partials3(const double* in0, int64_t n0, int64_t c0, double* o0, const double* in1, int64_t n1,
+                         int64_t c1, double* o1, const double* in2, int64_t n2, int64_t c2, double* o2,
+                         hipStream_t s);
+// K[mu][i] = dV (s1 K1 + s2 Phi_g^T M2 + s3 K3) for mu < N, i < n ([Np][np] arrays,
+// any may be NULL); ex = -dV (ce1 sum e1p + ce3 sum e3p) if ex is not NULL.
 hipError_t finalize(const double* Phig, const double* M2, int64_t G, const double* K1, const double* K3, int N,
-                    int n, int np, int Np, double s1, double s2, double s3, double dV, double* K,
-                    const double* e1p, int64_t ne1, const double* e3p, int64_t ne3, double ce1, double ce3,
-                    double* ex, hipStream_t s);
+                    int n, int np, int Np, double s1, double s2, double s3, double dV, double* K, const double* e1p,
+                    int64_t ne1, const double* e3p, int64_t ne3, double ce1, double ce3, double* ex, hipStream_t s);
 
-// Sum partials: out[i] = sum_p in[p*stride + i], i < count (deterministic order).
-hipError_t sum_partials(const double* in, int64_t nparts, int64_t stride, int64_t count,
-                        double* out, hipStream_t s);
-// Pack C [N][n] (row pitch n) into Cp [Np][np] zero padded.
-hipError_t pack_matrix(const double* C, int64_t rows, int64_t cols, int64_t ldc, double* Cp,
-                       int64_t rows_p, int64_t ldp, hipStream_t s);
 }  // namespace rps
