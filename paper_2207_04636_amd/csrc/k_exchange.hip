@@ -82,6 +82,8 @@ __global__ __launch_bounds__(NW * 64) void fused_f64_kernel(FusedArgs a) {
     R0 = (rt0 + ri) * T;
     g0 = (gs0 + w + si * NW) * 16;
   };
+  // U_g operands of step t: A operand of P, B operand of M1
+  double ugAn[NI * 4], ugBn[4][NI];
   auto load_v = [&](int64_t t) {
     int64_t g0, R0;
     step_coords(t, g0, R0);
@@ -92,6 +94,13 @@ __global__ __launch_bounds__(NW * 64) void fused_f64_kernel(FusedArgs a) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) vnext[r][c] = row[16 * c];
     }
+    const double* ug = a.Ug + g0 * NP;
+#pragma unroll
+    for (int kk = 0; kk < NI * 4; ++kk) ugAn[kk] = ug[l16 * NP + 4 * kk + lq];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int j = 0; j < NI; ++j) ugBn[r][j] = ug[(4 * r + lq) * NP + 16 * j + l16];
   };
   if (nstep > 0) load_v(0);
 
@@ -124,16 +133,14 @@ __global__ __launch_bounds__(NW * 64) void fused_f64_kernel(FusedArgs a) {
       for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c) v[r][c] = vnext[r][c];
-      if (t + 1 < nstep) load_v(t + 1);
-      // U_g operands of these 16 rows: A operand of P, B operand of M1
-      const double* ug = a.Ug + g0 * NP;
       double ugA[NI * 4], ugB[4][NI];
 #pragma unroll
-      for (int kk = 0; kk < NI * 4; ++kk) ugA[kk] = ug[l16 * NP + 4 * kk + lq];
+      for (int kk = 0; kk < NI * 4; ++kk) ugA[kk] = ugAn[kk];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int j = 0; j < NI; ++j) ugB[r][j] = ug[(4 * r + lq) * NP + 16 * j + l16];
+        for (int j = 0; j < NI; ++j) ugB[r][j] = ugBn[r][j];
+      if (t + 1 < nstep) load_v(t + 1);
 
       // P[g][R] = sum_k U_g[g][k] U[R][k]
       d4_t p[4];
@@ -253,6 +260,244 @@ __global__ __launch_bounds__(NW * 64) void fused_f64_kernel(FusedArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// n <= 16 variant on v_mfma_f64_4x4x4_f64 (4 blocks).  On gfx950 this
+// instruction sustains nearly the FP64 peak while the 16x16x4 form does not.
+// With lane l, q = l / 16, c4 = l % 4, b = (l / 4) % 4 (the block):
+//   A_b[c4][q], B_b[q][c4] -> D_b[q][c4].
+// Two views of one instruction are used:
+//   shared A (4 x 16 output): A[l%4][l/16], B[l/16][l%16] -> D[l/16][l%16]
+//   shared B (16 x 4 output): A[l%16][l/16], B[l/16][l%4] -> D[4b + l/16][l%4]
+// P = U_g U^T uses the first (rows g, columns R, k = orbital): its fragment
+// P[g0 + 4 gq + l/16][R0 + 16c + l%16] is the same as the 16x16 layout, so the
+// V fragment and the wave's A slab are unchanged.  M1^T = A^T U_g uses the
+// second with A^T taken straight from those registers (k = 4 rows of g).  M2 =
+// A U uses the second with A read transposed from the wave's slab.
+// Orbital operands are read from a permuted copy [row][i % 4][i / 4] so that
+// the four k slices a lane needs are contiguous.
+__device__ __forceinline__ double mfma4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int NW, int MT, int M2MODE>
+__global__ __launch_bounds__(NW * 64) void fused_m4_kernel(FusedArgs a) {
+  constexpr int NP = 16;
+  constexpr int LDP = 18;               // pitch of the permuted U tile rows (doubles, 16-byte aligned)
+  extern __shared__ double smem[];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, lq = lane >> 4, c4 = lane & 3, bq = (lane >> 2) & 3;
+
+  const int64_t gsub_total = a.G / 16;
+  const int64_t gper = ((a.G / T + a.gblocks - 1) / a.gblocks) * (T / 16);
+  const int gb = blockIdx.x % a.gblocks;
+  const int rb = blockIdx.x / a.gblocks;
+  const int64_t gs0 = gb * gper;
+  const int64_t gs1 = (gs0 + gper < gsub_total) ? gs0 + gper : gsub_total;
+  const int64_t bg = gper * 16;
+  const int64_t rtiles_valid = (a.R_valid + T - 1) / T;
+  const int64_t rt0 = (int64_t)rb * a.rtiles;
+  const int64_t rt1 = (rt0 + a.rtiles < rtiles_valid) ? rt0 + a.rtiles : rtiles_valid;
+
+  double* slab = smem + (int64_t)w * 16 * SLAB;
+  double* sU = smem + (int64_t)NW * 16 * SLAB;          // [T][LDP] permuted: [R][j4*4 + ich]
+  double* sM2 = sU + (int64_t)T * LDP;                   // [bg][NP]
+  double* red = smem;
+
+  const int64_t nmy = (gs1 - gs0 > w) ? (gs1 - gs0 - w + NW - 1) / NW : 0;
+  const int64_t nstep = nmy * (rt1 > rt0 ? rt1 - rt0 : 0);
+  if (a.want_m2)
+    for (int64_t e = tid; e < bg * NP; e += NW * 64) sM2[e] = 0.0;
+
+  double vnext[4][4];
+  auto load_v = [&](int64_t t) {
+    const int64_t ri = t / nmy, si = t % nmy;
+    const int64_t R0 = (rt0 + ri) * T, g0 = (gs0 + w + si * NW) * 16;
+    const double* base = a.Vm + (g0 + lq) * a.ldv + R0 + l16;
+#pragma unroll
+    for (int gq = 0; gq < 4; ++gq) {
+      const double* row = base + (int64_t)(4 * gq) * a.ldv;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) vnext[gq][c] = row[16 * c];
+    }
+  };
+  if (nstep > 0) load_v(0);
+
+  double e1 = 0.0;
+  constexpr int MTW = (MT + NW - 1) / NW > 0 ? (MT + NW - 1) / NW : 1;
+  d4_t k1[MTW];
+#pragma unroll
+  for (int mm = 0; mm < MTW; ++mm) k1[mm] = zero_d4();
+  const int mt = a.Np / 16;
+
+  int64_t t = 0;
+  for (int64_t rt = rt0; rt < rt1; ++rt) {
+    const int64_t R0 = rt * T;
+    __syncthreads();
+    // U tile, permuted: sU[R][(i % 4) * 4 + i / 4] = U[R0 + R][i]
+    for (int e = tid; e < T * NP; e += NW * 64) {
+      const int r = e / NP, i = e % NP;
+      sU[r * LDP + (i & 3) * 4 + (i >> 2)] = a.Ur[(R0 + r) * NP + i];
+    }
+    __syncthreads();
+    double m1[4][4];                       // [c][ich]: M1^T[R0 + 16c + 4bq + lq][4 ich + c4]
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) m1[c][k] = 0.0;
+
+    for (int64_t si = 0; si < nmy; ++si, ++t) {
+      const int64_t g0 = (gs0 + w + si * NW) * 16;
+      double v[4][4];
+#pragma unroll
+      for (int gq = 0; gq < 4; ++gq)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[gq][c] = vnext[gq][c];
+      if (t + 1 < nstep) load_v(t + 1);
+      const double* ugp = a.Ugp + g0 * NP;   // permuted U_g rows of this subtile
+      double pA[4][4];                      // P A operand: U_g[g0 + 4gq + c4][4kk + lq] = ugp[.. + lq*4 + kk]
+      double mB[4][4];                      // M1 B operand: U_g[g0 + 4gq + lq][4ich + c4] = ugp[.. + c4*4 + ich]
+#pragma unroll
+      for (int gq = 0; gq < 4; ++gq) {
+        const double2* x = reinterpret_cast<const double2*>(ugp + (4 * gq + c4) * NP + lq * 4);
+        const double2 x0 = x[0], x1 = x[1];
+        pA[gq][0] = x0.x; pA[gq][1] = x0.y; pA[gq][2] = x1.x; pA[gq][3] = x1.y;
+        const double2* y = reinterpret_cast<const double2*>(ugp + (4 * gq + lq) * NP + c4 * 4);
+        const double2 y0 = y[0], y1 = y[1];
+        mB[gq][0] = y0.x; mB[gq][1] = y0.y; mB[gq][2] = y1.x; mB[gq][3] = y1.y;
+      }
+      // P[g0 + 4gq + lq][R0 + 16c + l16] = sum_k U_g[g][k] U[R][k]  (shared-A view)
+      double p[4][4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double2* u = reinterpret_cast<const double2*>(sU + (16 * c + l16) * LDP + lq * 4);
+        const double2 u0 = u[0], u1 = u[1];
+        const double ub[4] = {u0.x, u0.y, u1.x, u1.y};     // U[R][4kk + lq]
+#pragma unroll
+        for (int gq = 0; gq < 4; ++gq) {
+          double acc = 0.0;
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) acc = mfma4(pA[gq][kk], ub[kk], acc);
+          p[gq][c] = acc;
+        }
+      }
+      // A = V o P, energy, slab; M1^T[R][i] += sum_g A^T[R][g] U_g[g][i]  (shared-B view)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+#pragma unroll
+        for (int gq = 0; gq < 4; ++gq) {
+          const double av = v[gq][c] * p[gq][c];
+          e1 += av * p[gq][c];
+          slab[(4 * gq + lq) * SLAB + 16 * c + l16] = av;
+#pragma unroll
+          for (int ich = 0; ich < 4; ++ich) m1[c][ich] = mfma4(av, mB[gq][ich], m1[c][ich]);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (a.want_m2) {
+        if (M2MODE == 0) {
+          // M2[g0 + 4bq + lq][4 ich + c4] += sum_R A[g][R] U[R][i]  (shared-B view, A^T from the slab);
+          // four partial chains per output (R slices s % 4) for independent MFMAs
+          double m2[4][4];
+#pragma unroll
+          for (int ich = 0; ich < 4; ++ich)
+#pragma unroll
+            for (int h = 0; h < 4; ++h) m2[ich][h] = 0.0;
+#pragma unroll
+          for (int s = 0; s < 16; ++s) {
+            const double x = slab[l16 * SLAB + 4 * s + lq];
+            const double2* u = reinterpret_cast<const double2*>(sU + (4 * s + lq) * LDP + c4 * 4);
+            const double2 u0 = u[0], u1 = u[1];
+            m2[0][s & 3] = mfma4(x, u0.x, m2[0][s & 3]);
+            m2[1][s & 3] = mfma4(x, u0.y, m2[1][s & 3]);
+            m2[2][s & 3] = mfma4(x, u1.x, m2[2][s & 3]);
+            m2[3][s & 3] = mfma4(x, u1.y, m2[3][s & 3]);
+          }
+          double* acc = sM2 + (g0 - gs0 * 16 + 4 * bq + lq) * NP + c4;
+#pragma unroll
+          for (int ich = 0; ich < 4; ++ich)
+            acc[4 * ich] += (m2[ich][0] + m2[ich][1]) + (m2[ich][2] + m2[ich][3]);
+        } else {
+          // 16x16x4 form: D[g][i] += A[g][R] U[R][i], A from the slab, U (unpermuted index) from the tile
+          d4_t m2 = zero_d4();
+#pragma unroll
+          for (int s = 0; s < 16; ++s) {
+            const double x = slab[l16 * SLAB + 4 * s + lq];
+            m2 = mfma_f64(x, sU[(4 * s + lq) * LDP + (l16 & 3) * 4 + (l16 >> 2)], m2);
+          }
+          double* acc = sM2 + (g0 - gs0 * 16 + lq) * NP + l16;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[4 * r * NP] += m2[r];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+
+    if (MT > 0 || a.want_m1) {
+      double* m1s = sU;
+      __syncthreads();
+      // wave w's partial M1^T -> red[w][R][i]
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int ich = 0; ich < 4; ++ich)
+          red[(w * 64 + 16 * c + 4 * bq + lq) * 16 + 4 * ich + c4] = m1[c][ich];
+      __syncthreads();
+      if (w < 4) {
+        const int q = w;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double s = 0.0;
+          for (int ww = 0; ww < NW; ++ww) s += red[(ww * 64 + 16 * q + 4 * r + lq) * 16 + l16];
+          m1s[(16 * q + 4 * r + lq) * 16 + l16] = s;
+          if (a.want_m1) a.M1T[((int64_t)gb * a.R + R0 + 16 * q + 4 * r + lq) * NP + l16] = s;
+        }
+      }
+      __syncthreads();
+      if (MT > 0 && a.want_k1) {
+#pragma unroll
+        for (int mm = 0; mm < MTW; ++mm) {
+          const int m = w + mm * NW;
+          if (m < mt) {
+            const double* ph = a.Phir + (R0 + lq) * a.Np + 16 * m + l16;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                k1[mm] = mfma_f64(ph[(int64_t)(16 * q + 4 * r) * a.Np], m1s[(16 * q + 4 * r + lq) * 16 + l16], k1[mm]);
+          }
+        }
+      }
+    }
+  }
+
+  const int wg = blockIdx.x;
+  __syncthreads();
+  if (MT > 0 && a.want_k1) {
+    double* out = a.K1p + (int64_t)wg * a.Np * NP;
+#pragma unroll
+    for (int mm = 0; mm < MTW; ++mm) {
+      const int m = w + mm * NW;
+      if (m < mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[(int64_t)(16 * m + 4 * r + lq) * NP + l16] = k1[mm][r];
+    }
+  }
+  if (a.want_m2) {
+    double* out = a.M2p + ((int64_t)rb * a.G + gs0 * 16) * NP;
+    const int64_t rows = (gs1 - gs0) * 16;
+    for (int64_t e = tid; e < rows * NP; e += NW * 64) out[e] = sM2[e];
+  }
+  const double es = wave_sum(e1);
+  __syncthreads();
+  if (lane == 0) red[w] = es;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int ww = 0; ww < NW; ++ww) s += red[ww];
+    a.e1p[wg] = s;
+  }
+}
+
 // Orbitals on the grid and at the points: U = Phi C and U_g = Phi_g C.
 // Row subtiles 16 at a time on the FP64 matrix cores; rows [0, R) come from
 // Phi, rows [R, R + G) from Phi_g.  C [N x n] (row pitch n) is read once into
@@ -262,7 +507,8 @@ template <int NI, int MT>
 __global__ __launch_bounds__(256) void orbitals_kernel(const double* __restrict__ Phi, int64_t R,
                                                       const double* __restrict__ Phig, int64_t G, int Np,
                                                       const double* __restrict__ C, int N, int n,
-                                                      double* __restrict__ U, double* __restrict__ Ug) {
+                                                      double* __restrict__ U, double* __restrict__ Ug,
+                                                      double* __restrict__ Ugp) {
   constexpr int NP = 16 * NI;
   constexpr int PB = 16 * (MT * 16 + 1);      // one wave's staged block, padded rows
   extern __shared__ double lds[];
@@ -317,6 +563,12 @@ __global__ __launch_bounds__(256) void orbitals_kernel(const double* __restrict_
     for (int j = 0; j < NI; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) out[(int64_t)(4 * r) * NP + 16 * j] = acc[j][r];
+    if (NI == 1 && Ugp && row0 >= R) {
+      // permuted copy [g][i % 4][i / 4] of U_g for the n <= 16 exchange kernel
+      double* op = Ugp + (row0 - R + lq) * 16 + (l16 & 3) * 4 + (l16 >> 2);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) op[(int64_t)(4 * r) * 16] = acc[0][r];
+    }
   }
 }
 
@@ -430,6 +682,32 @@ __global__ __launch_bounds__(512) void finalize_kernel(const double* __restrict_
   }
 }
 
+// Zero-padded copy Cp [rows_p x ldp] of C [rows x cols] (row pitch ldc).
+__global__ void pack_kernel(const double* __restrict__ C, int64_t rows, int64_t cols, int64_t ldc,
+                            double* __restrict__ Cp, int64_t rows_p, int64_t ldp) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows_p * ldp) return;
+  const int64_t r = t / ldp, c = t % ldp;
+  Cp[t] = (r < rows && c < cols) ? C[r * ldc + c] : 0.0;
+}
+
+// Partial dot products: out[b] = sum of x[i] y[i] over the block's range (tree).
+__global__ __launch_bounds__(256) void dot_partials_kernel(const double* __restrict__ x, const double* __restrict__ y,
+                                                          int64_t n, int64_t per, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int64_t b0 = (int64_t)blockIdx.x * per;
+  const int64_t b1 = (b0 + per < n) ? b0 + per : n;
+  double s = 0.0;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) s += x[i] * y[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <int NW, int NI, int MT>
@@ -453,8 +731,37 @@ hipError_t launch_fused2(const FusedArgs& a, int blocks, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+template <int NW, int MT, int M2MODE>
+hipError_t launch_m4(const FusedArgs& a, int blocks, hipStream_t s) {
+  const int64_t gper = ((a.G / T + a.gblocks - 1) / a.gblocks) * (T / 16);
+  const int64_t lds = ((int64_t)NW * 16 * SLAB + (int64_t)T * 18 + (a.want_m2 ? gper * 16 : 0) * 16) * 8;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  auto k = fused_m4_kernel<NW, MT, M2MODE>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(NW * 64), (size_t)lds, s, a);
+  return hipGetLastError();
+}
+
+template <int NW, int M2MODE>
+hipError_t launch_m4_mt(const FusedArgs& a, int blocks, hipStream_t s) {
+  const int mt = a.want_k1 ? a.Np / 16 : 0;
+  if (mt == 0) return launch_m4<NW, 0, M2MODE>(a, blocks, s);
+  if (mt <= 4) return launch_m4<NW, 4, M2MODE>(a, blocks, s);
+  if (mt <= 8) return launch_m4<NW, 8, M2MODE>(a, blocks, s);
+  return hipErrorInvalidValue;
+}
+
 template <int NI>
 hipError_t launch_fused1(const FusedArgs& a, int blocks, hipStream_t s) {
+  if (NI == 1 && a.use_m4 && a.Ugp) {
+    if (a.use_m4 == 2) {
+      if (a.nwaves == 8) return launch_m4_mt<8, 1>(a, blocks, s);
+      return launch_m4_mt<4, 1>(a, blocks, s);
+    }
+    if (a.nwaves == 8) return launch_m4_mt<8, 0>(a, blocks, s);
+    return launch_m4_mt<4, 0>(a, blocks, s);
+  }
   if (a.nwaves == 8) return launch_fused2<8, NI>(a, blocks, s);
   return launch_fused2<4, NI>(a, blocks, s);
 }
@@ -469,7 +776,7 @@ int fused_rblocks(const FusedArgs& a) {
 int64_t fused_lds_bytes(const FusedArgs& a) {
   const int64_t gper = ((a.G / T + a.gblocks - 1) / a.gblocks) * (T / 16);
   const int64_t bg = a.want_m2 ? gper * 16 : 0;
-  const int64_t per = (int64_t)(a.nwaves == 8 ? 8 : 4) * 16 * SLAB + (int64_t)T * (a.np + 1) + bg * a.np;
+  const int64_t per = (int64_t)(a.nwaves == 8 ? 8 : 4) * 16 * SLAB + (int64_t)T * (a.np + 2) + bg * a.np;
   return per * 8;
 }
 
@@ -508,7 +815,7 @@ hipError_t sum_partials3(const double* in0, int64_t n0, int64_t c0, double* o0, 
 }
 
 hipError_t orbitals(const double* Phi, int64_t R, const double* Phig, int64_t G, int Np, const double* C,
-                    int N, int n, int np, double* U, double* Ug, hipStream_t s) {
+                    int N, int n, int np, double* U, double* Ug, double* Ugp, hipStream_t s) {
   if (R % 16 != 0 || G % 16 != 0 || Np % 16 != 0 || np % 16 != 0 || Np > 128) return hipErrorInvalidValue;
   const int64_t nsub = (R + G) / 16;
   const unsigned blocks = (unsigned)std::min<int64_t>((nsub + 3) / 4, 4096);
@@ -521,7 +828,7 @@ hipError_t orbitals(const double* Phi, int64_t R, const double* Phig, int64_t G,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);               \
     if (e_ != hipSuccess) return e_;                                                                         \
     hipLaunchKernelGGL((orbitals_kernel<NI_, MT_>), dim3(blocks), dim3(256), lds, s, Phi, R, Phig, G, Np, C, \
-                       N, n, U, Ug);                                                                         \
+                       N, n, U, Ug, Ugp);                                                                    \
   } while (0)
 #define RPS_ORB_NI(NI_) \
   do { if (mt <= 2) RPS_ORB(NI_, 2); else if (mt <= 4) RPS_ORB(NI_, 4); else RPS_ORB(NI_, 8); } while (0)
@@ -544,6 +851,22 @@ hipError_t finalize(const double* Phig, const double* M2, int64_t G, const doubl
   hipLaunchKernelGGL(finalize_kernel, dim3(ntile + 1), dim3(512), 0, s, Phig, M2, G, K1, K3, N, n, np, Np, s1, s2,
                      s3, dV, K, e1p, ne1, e3p, ne3, ce1, ce3, ex);
   return hipGetLastError();
+}
+
+hipError_t pack_matrix(const double* C, int64_t rows, int64_t cols, int64_t ldc, double* Cp, int64_t rows_p,
+                       int64_t ldp, hipStream_t s) {
+  hipLaunchKernelGGL(pack_kernel, dim3(nblk(rows_p * ldp, 256)), dim3(256), 0, s, C, rows, cols, ldc, Cp, rows_p,
+                     ldp);
+  return hipGetLastError();
+}
+
+int dot_partials(const double* x, const double* y, int64_t n, double* out, int max_parts, hipStream_t s) {
+  int64_t parts = (n + 16383) / 16384;
+  if (parts > max_parts) parts = max_parts;
+  if (parts < 1) parts = 1;
+  const int64_t per = (n + parts - 1) / parts;
+  hipLaunchKernelGGL(dot_partials_kernel, dim3((unsigned)parts), dim3(256), 0, s, x, y, n, per, out);
+  return (hipGetLastError() == hipSuccess) ? (int)parts : -1;
 }
 
 }  // namespace rps

@@ -82,7 +82,12 @@ struct rps_context {
   DBuf<int64_t> dpoints;
   // build workspace (grows on demand)
   int ws_np = -1;
-  DBuf<double> U, Ug, M2p, K1p, K3p, e1p, e3p, M2, K1, K3, Kdev, Cdev, exdev;
+  DBuf<double> U, Ug, Ugp, M2p, K1p, K3p, e1p, e3p, M2, K1, K3, Kdev, Cdev, exdev;
+  int use_m4 = 1;
+  // general path workspace
+  int gws_np = -1;
+  int64_t gchunk = 0;
+  DBuf<double> gCp, gU, gUg, gA, gM2, gM1T, gK1, gK3, gY, gwork, ge;
   int64_t rblocks_main = 0, blocks_main = 0, blocks_l3 = 0;
   int rtiles = 4, gblocks = 1, nwaves = 4;
   // profiling: event triples (build start, main start, main end, l3 start, l3 end, build end)
@@ -92,9 +97,11 @@ struct rps_context {
   hipStream_t last_stream = nullptr;
 
   ~rps_context() {
-    DBuf<double>* all[] = {&Phi, &Phig, &V, &W, &U, &Ug, &M2p, &K1p, &K3p, &e1p,
+    DBuf<double>* all[] = {&Phi, &Phig, &V, &W, &U, &Ug, &Ugp, &M2p, &K1p, &K3p, &e1p,
                            &e3p, &M2, &K1, &K3, &Kdev, &Cdev, &exdev};
     for (auto* b : all) b->release(nullptr);
+    DBuf<double>* gen[] = {&gCp, &gU, &gUg, &gA, &gM2, &gM1T, &gK1, &gK3, &gY, &gwork, &ge};
+    for (auto* b : gen) b->release(nullptr);
     V32.release(nullptr);
     dpoints.release(nullptr);
     for (auto e : ev_pool) (void)hipEventDestroy(e);
@@ -516,11 +523,14 @@ void ensure_workspace(rps_context& c, int np) {
   c.rtiles = a.rtiles;
   c.gblocks = a.gblocks;
   c.nwaves = a.nwaves;
+  if (const char* m = getenv("RPS_FP64_MFMA"))
+    c.use_m4 = (strcmp(m, "16x16x4") == 0) ? 0 : (strcmp(m, "hybrid") == 0) ? 2 : 1;
   c.rblocks_main = fused_rblocks(a);
   c.blocks_main = c.rblocks_main * c.gblocks;
   c.blocks_l3 = (c.nauxp / 64) * ((c.naux + 63) / 64);   // one 64 x 64 tile of W per workgroup
   c.U.alloc(c.ngp * np, cnt);
   c.Ug.alloc(c.nauxp * np, cnt);
+  c.Ugp.alloc(c.nauxp * np, cnt);
   c.M2p.alloc(c.rblocks_main * c.nauxp * np, cnt);
   c.K1p.alloc(c.blocks_main * c.Np * np, cnt);
   c.K3p.alloc(std::max<int64_t>(c.blocks_l3, 1) * c.Np * np, cnt);
@@ -535,6 +545,120 @@ void ensure_workspace(rps_context& c, int np) {
   c.ws_np = np;
 }
 
+// ------------------------------------------------------------------ general path
+// Any N and n.  For chunks of Gc interpolation points (rows of V):
+//   A_c = V_c o (U_g[c] U^T)              (product whose epilogue multiplies by V)
+//   M2[c] = A_c U                          (long inner dimension, split over workgroups)
+//   M1^T += A_c^T U_g[c]
+// then K1 = Phi^T M1^T, K2 = Phi_g^T M2, B = W o (U_g U_g^T), Y = B U_g,
+// K3 = Phi_g^T Y, e1 = tr(U_g^T M2), e3 = tr(U_g^T Y)  (Eq. 16).
+constexpr int64_t kSplitWork = 64ll << 20;   // doubles of split-K partials (512 MB)
+constexpr int kEnergyParts = 256;
+
+void ensure_general(rps_context& c, int np) {
+  if (c.gws_np == np) return;
+  int64_t* cnt = &c.bytes;
+  const int64_t budget = 2000000000ll / 8;     // A chunk: about 2 GB
+  int64_t gc = std::max<int64_t>(64, budget / c.ngp / 64 * 64);
+  gc = std::min(gc, c.nauxp);
+  c.gchunk = gc;
+  c.gCp.alloc(c.Np * np, cnt);
+  c.gU.alloc(c.ngp * np, cnt);
+  c.gUg.alloc(c.nauxp * np, cnt);
+  c.gA.alloc(std::max(gc * c.ngp, c.nauxp * c.nauxp), cnt);
+  c.gM2.alloc(c.nauxp * np, cnt);
+  c.gM1T.alloc(c.ngp * np, cnt);
+  c.gK1.alloc(c.Np * np, cnt);
+  c.gK3.alloc(c.Np * np, cnt);
+  c.gY.alloc(c.nauxp * np, cnt);
+  c.gwork.alloc(kSplitWork, cnt);
+  c.ge.alloc(2 * kEnergyParts, cnt);
+  c.Cdev.alloc(c.nbas * np, cnt);
+  c.Kdev.alloc(c.nbas * np, cnt);
+  c.exdev.alloc(1, cnt);
+  c.gws_np = np;
+}
+
+void gemm_run(Gemm g, rps_context& c, hipStream_t st, const char* what, bool allow_split) {
+  if (allow_split && g.epi == EPI_AXPBY) {
+    g.splitk = gemm_splitk_for(g.M, g.N, g.K, kSplitWork);
+    g.work = c.gwork.p;
+  }
+  hip_check(gemm_f64(g, st), what);
+}
+
+void build_general(rps_context& c, int variant, int nocc, const double* Csrc, double* Kout, double* exout,
+                   hipStream_t st, double s1, double s2, double s3, double ce1, double ce3) {
+  const int np = (int)round_up(nocc, 16);
+  ensure_general(c, np);
+  hip_check(pack_matrix(Csrc, c.nbas, nocc, nocc, c.gCp.p, c.Np, np, st), "pack C");
+  {
+    Gemm g;   // U = Phi C
+    g.M = c.ngp; g.N = np; g.K = c.Np;
+    g.A = c.Phi.p; g.lda = c.Np; g.B = c.gCp.p; g.ldb = np; g.C = c.gU.p; g.ldc = np;
+    gemm_run(g, c, st, "U", false);
+  }
+  hip_check(gather_rows(c.gU.p, np, c.dpoints.p, c.naux, c.nauxp, np, c.gUg.p, np, st), "U_g");
+  const bool need_main = (variant != RPS_VARIANT_THC);
+  const bool need_l3 = (variant != RPS_VARIANT_PS);
+  const bool k1 = need_main && variant == RPS_VARIANT_RPS;
+  int ne1 = 0, ne3 = 0;
+  if (need_main) {
+    prof_mark(c, 1, st);
+    for (int64_t g0 = 0; g0 < c.nauxp; g0 += c.gchunk) {
+      const int64_t gc = std::min(c.gchunk, c.nauxp - g0);
+      Gemm a;   // A_c = V_c o (U_g[c] U^T)
+      a.M = gc; a.N = c.ngp; a.K = np;
+      a.A = c.gUg.p + g0 * np; a.lda = np; a.B = c.gU.p; a.ldb = np; a.transB = true;
+      a.C = c.gA.p; a.ldc = c.ngp; a.epi = EPI_HADAMARD_SRC; a.D = c.V.p + g0 * c.ngp; a.ldd = c.ngp;
+      gemm_run(a, c, st, "A chunk", false);
+      Gemm m2;  // M2[c] = A_c U
+      m2.M = gc; m2.N = np; m2.K = c.ngp;
+      m2.A = c.gA.p; m2.lda = c.ngp; m2.B = c.gU.p; m2.ldb = np; m2.C = c.gM2.p + g0 * np; m2.ldc = np;
+      gemm_run(m2, c, st, "M2", true);
+      if (k1) {
+        Gemm m1;  // M1^T += A_c^T U_g[c]
+        m1.M = c.ngp; m1.N = np; m1.K = gc;
+        m1.A = c.gA.p; m1.lda = c.ngp; m1.transA = true; m1.B = c.gUg.p + g0 * np; m1.ldb = np;
+        m1.C = c.gM1T.p; m1.ldc = np; m1.beta = (g0 == 0) ? 0.0 : 1.0;
+        gemm_run(m1, c, st, "M1", false);
+      }
+    }
+    prof_mark(c, 2, st);
+    if (k1) {
+      Gemm g;   // K1 = Phi^T M1^T
+      g.M = c.Np; g.N = np; g.K = c.ngp;
+      g.A = c.Phi.p; g.lda = c.Np; g.transA = true; g.B = c.gM1T.p; g.ldb = np; g.C = c.gK1.p; g.ldc = np;
+      gemm_run(g, c, st, "K1", true);
+    }
+    ne1 = dot_partials(c.gUg.p, c.gM2.p, c.nauxp * np, c.ge.p, kEnergyParts, st);
+    if (ne1 < 0) fail(RPS_ERR_DEVICE, "energy partials");
+  }
+  if (need_l3) {
+    prof_mark(c, 3, st);
+    Gemm b;     // B = W o (U_g U_g^T)
+    b.M = c.nauxp; b.N = c.nauxp; b.K = np;
+    b.A = c.gUg.p; b.lda = np; b.B = c.gUg.p; b.ldb = np; b.transB = true;
+    b.C = c.gA.p; b.ldc = c.nauxp; b.epi = EPI_HADAMARD_SRC; b.D = c.W.p; b.ldd = c.nauxp;
+    gemm_run(b, c, st, "B", false);
+    Gemm y;     // Y = B U_g
+    y.M = c.nauxp; y.N = np; y.K = c.nauxp;
+    y.A = c.gA.p; y.lda = c.nauxp; y.B = c.gUg.p; y.ldb = np; y.C = c.gY.p; y.ldc = np;
+    gemm_run(y, c, st, "Y", true);
+    Gemm k3;    // K3 = Phi_g^T Y
+    k3.M = c.Np; k3.N = np; k3.K = c.nauxp;
+    k3.A = c.Phig.p; k3.lda = c.Np; k3.transA = true; k3.B = c.gY.p; k3.ldb = np; k3.C = c.gK3.p; k3.ldc = np;
+    gemm_run(k3, c, st, "K3", true);
+    ne3 = dot_partials(c.gUg.p, c.gY.p, c.nauxp * np, c.ge.p + kEnergyParts, kEnergyParts, st);
+    if (ne3 < 0) fail(RPS_ERR_DEVICE, "energy partials");
+    prof_mark(c, 4, st);
+  }
+  hip_check(finalize(c.Phig.p, need_main ? c.gM2.p : nullptr, c.nauxp, k1 ? c.gK1.p : nullptr,
+                     need_l3 ? c.gK3.p : nullptr, (int)c.nbas, nocc, np, (int)c.Np, s1, s2, s3, c.dV, Kout,
+                     c.ge.p, ne1, c.ge.p + kEnergyParts, ne3, ce1, ce3, exout, st),
+            "finalize");
+}
+
 // variant coefficients: K = dV (s1 K1 + s2 K2 + s3 K3), E = -dV (ce1 e1 + ce3 e3)
 void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, double* K, double* ex,
                 int32_t flags, hipStream_t st) {
@@ -544,22 +668,41 @@ void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, doub
   if (flags != RPS_PTRS_HOST && flags != RPS_PTRS_DEVICE) fail(RPS_ERR_ARG, "flags must be RPS_PTRS_HOST or RPS_PTRS_DEVICE");
   if (variant < RPS_VARIANT_RPS || variant > RPS_VARIANT_THC) fail(RPS_ERR_ARG, "unknown variant");
   const int np = (int)round_up(nocc, 16);
-  if (np > 64) fail(RPS_ERR_SHAPE, "this build supports nocc <= 64 in the FP64 path");
-  if (c.Np > 128) fail(RPS_ERR_SHAPE, "this build supports N <= 128 in the FP64 path");
-  ensure_workspace(c, np);
+  bool general = (np > 64) || (c.Np > 128);
+  if (const char* bp = getenv("RPS_BUILD_PATH")) general = general || (strcmp(bp, "general") == 0);
   double s1 = 1, s2 = 1, s3 = -1, ce1 = 2, ce3 = -1;
   if (variant == RPS_VARIANT_PS) { s1 = 0; s2 = 1; s3 = 0; ce1 = 1; ce3 = 0; }
   if (variant == RPS_VARIANT_THC) { s1 = 0; s2 = 0; s3 = 1; ce1 = 0; ce3 = 1; }
   const bool dev = (flags == RPS_PTRS_DEVICE);
   c.last_stream = st;
+  if (general) ensure_general(c, np); else ensure_workspace(c, np);
   prof_mark(c, 0, st);
   const double* Csrc = C;
   if (!dev) {
     hip_check(hipMemcpyAsync(c.Cdev.p, C, (size_t)c.nbas * nocc * 8, hipMemcpyHostToDevice, st), "copy C");
     Csrc = c.Cdev.p;
   }
+  if (general) {
+    double* Kout = dev ? K : c.Kdev.p;
+    double* exout = dev ? ex : (ex ? c.exdev.p : nullptr);
+    build_general(c, variant, nocc, Csrc, Kout, exout, st, s1, s2, s3, ce1, ce3);
+    prof_mark(c, 5, st);
+    if (c.profiling && c.ev_used < kMaxProfiled) {
+      if (variant == RPS_VARIANT_THC) { prof_mark(c, 1, st); prof_mark(c, 2, st); }
+      if (variant == RPS_VARIANT_PS) { prof_mark(c, 3, st); prof_mark(c, 4, st); }
+      ++c.ev_used;
+    }
+    if (!dev) {
+      hip_check(hipMemcpyAsync(K, c.Kdev.p, (size_t)c.nbas * nocc * 8, hipMemcpyDeviceToHost, st), "copy K");
+      if (ex) hip_check(hipMemcpyAsync(ex, c.exdev.p, 8, hipMemcpyDeviceToHost, st), "copy ex");
+      hip_check(hipStreamSynchronize(st), "sync");
+    }
+    return;
+  }
   // U = Phi C (orbitals on the grid) and U_g = Phi_g C (at the points)
-  hip_check(orbitals(c.Phi.p, c.ngp, c.Phig.p, c.nauxp, (int)c.Np, Csrc, (int)c.nbas, nocc, np, c.U.p, c.Ug.p, st),
+  const bool m4 = (np == 16) && c.use_m4;
+  hip_check(orbitals(c.Phi.p, c.ngp, c.Phig.p, c.nauxp, (int)c.Np, Csrc, (int)c.nbas, nocc, np, c.U.p, c.Ug.p,
+                     m4 ? c.Ugp.p : nullptr, st),
             "orbitals");
   const bool need_main = (variant != RPS_VARIANT_THC);
   const bool need_l3 = (variant != RPS_VARIANT_PS);
@@ -570,6 +713,7 @@ void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, doub
     a.rtiles = c.rtiles; a.gblocks = c.gblocks; a.nwaves = c.nwaves;
     a.want_m2 = 1; a.want_k1 = (variant == RPS_VARIANT_RPS) ? 1 : 0; a.want_m1 = 0;
     a.prec = c.precision;
+    a.Ugp = m4 ? c.Ugp.p : nullptr; a.use_m4 = m4 ? c.use_m4 : 0;
     a.M2p = c.M2p.p; a.K1p = c.K1p.p; a.e1p = c.e1p.p;
     prof_mark(c, 1, st);
     hip_check(fused_exchange(a, st), "fused main");
@@ -581,6 +725,7 @@ void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, doub
     a.G = c.nauxp; a.R = c.nauxp; a.R_valid = c.naux; a.np = np; a.Np = (int)c.Np;
     a.rtiles = 1; a.gblocks = (int)(c.nauxp / 64); a.nwaves = 4;
     a.want_m2 = 0; a.want_k1 = 1; a.want_m1 = 0; a.prec = RPS_PREC_FP64;
+    a.Ugp = m4 ? c.Ugp.p : nullptr; a.use_m4 = m4 ? c.use_m4 : 0;
     a.K1p = c.K3p.p; a.e1p = c.e3p.p;
     prof_mark(c, 3, st);
     hip_check(fused_exchange(a, st), "fused line 3");

@@ -12,7 +12,8 @@ namespace rps {
 enum GemmEpi {
   EPI_AXPBY = 0,     // C = alpha*AB + beta*C
   EPI_SQUARE = 1,    // C = (alpha*AB)^2 (elementwise)
-  EPI_HADAMARD = 2   // C = C o (alpha*AB)
+  EPI_HADAMARD = 2,  // C = C o (alpha*AB)
+  EPI_HADAMARD_SRC = 3   // C = D o (alpha*AB), D a separate matrix (ldd)
 };
 struct Gemm {
   int64_t M = 0, N = 0, K = 0;
@@ -22,8 +23,13 @@ struct Gemm {
   double alpha = 1.0, beta = 0.0;
   int epi = EPI_AXPBY;
   bool lower_only = false;   // skip output tiles strictly above the diagonal
+  const double* D = nullptr; int64_t ldd = 0;   // EPI_HADAMARD_SRC operand
+  int splitk = 1;            // > 1: K split over workgroups, partials in work (EPI_AXPBY only)
+  double* work = nullptr;    // splitk * M * N doubles
 };
 hipError_t gemm_f64(const Gemm& g, hipStream_t s);
+// Split count giving enough workgroups for a long-K product within work_cap doubles.
+int gemm_splitk_for(int64_t M, int64_t N, int64_t K, int64_t work_cap_doubles);
 
 // ---------------------------------------------------------------- basis / grid
 struct ShellDev {        // one Gaussian shell, device copy
@@ -89,6 +95,8 @@ struct FusedArgs {
   const double* Vm; int64_t ldv;
   const float* Vm32;        // FP32 copy (precision forms), ldv pitch
   const double* Ug;         // [Gp x np]  (row operand)
+  const double* Ugp;        // permuted copy [Gp][i % 4][i / 4] (np == 16 only), or NULL
+  int use_m4;               // use the 4x4x4 FP64 MFMA form (np == 16)
   const double* Ur;         // [Rp x np]  (column operand)
   const double* Phir;       // [Rp x Np]  basis at the columns (for K1)
   int64_t G, R;             // padded extents (multiples of 64)
@@ -113,8 +121,14 @@ int64_t fused_lds_bytes(const FusedArgs& a);
 hipError_t fused_exchange(const FusedArgs& a, hipStream_t s);
 // U [R x np] = Phi [R x Np] C and U_g [G x np] = Phi_g [G x Np] C, with C [N x n]
 // (row pitch n) zero padded to [Np x np] (R, G % 16 == 0, np <= 64, Np <= 128).
+// Ugp (may be NULL; np == 16 only): permuted copy [g][i % 4][i / 4] of U_g.
 hipError_t orbitals(const double* Phi, int64_t R, const double* Phig, int64_t G, int Np, const double* C,
-                    int N, int n, int np, double* U, double* Ug, hipStream_t s);
+                    int N, int n, int np, double* U, double* Ug, double* Ugp, hipStream_t s);
+// Cp [rows_p x ldp] = C [rows x cols] zero padded.
+hipError_t pack_matrix(const double* C, int64_t rows, int64_t cols, int64_t ldc, double* Cp, int64_t rows_p,
+                       int64_t ldp, hipStream_t s);
+// out[0..parts) = partial sums of x . y (fixed order); returns parts (<= max_parts), -1 on error.
+int dot_partials(const double* x, const double* y, int64_t n, double* out, int max_parts, hipStream_t s);
 // Up to three partial sums in one launch: out_k[i] = sum_p in_k[p*count_k + i]
 // (fixed order); a segment with a NULL input is skipped.
 hipError_t sum_partials3(const double* in0, int64_t n0, int64_t c0, double* o0, const double* in1, int64_t n1,
