@@ -67,6 +67,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--c", type=float, default=6.0, help="N_aux / N (4, 6, 8 or 10)")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+                    help="fp64: FP64 V and products; fp32: V stored FP32, FP32 in-tile products, FP64 across tiles")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -81,7 +83,8 @@ def main():
 
     w = ri.diamond_cell(args.c)
     t0 = time.perf_counter()
-    ctx = P.Context.from_workload(w, seed=w.sketch_seed())
+    prec = P.PREC_FP64 if args.precision == "fp64" else P.PREC_FP32
+    ctx = P.Context.from_workload(w, seed=w.sketch_seed(), precision=prec)
     setup_s = time.perf_counter() - t0
     info = ctx.info()
     S = ctx.overlap()

@@ -498,6 +498,192 @@ __global__ __launch_bounds__(NW * 64) void fused_m4_kernel(FusedArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Precision form, n <= 16: V stored in FP32, the in-tile products on the FP32
+// matrix cores (v_mfma_f32_16x16x4_f32) with FP32 accumulation inside a tile,
+// FP64 accumulation across tiles (M2 in the LDS accumulators, M1 when the waves'
+// partials are combined, K1 and the energy in FP64).  Same structure as the
+// FP64 kernel; the FP32 fragment layout has rows 4*(l/16) + r, so the V
+// fragment and the k-slices of the M1 product follow that layout.
+template <int NW, int MT>
+__global__ __launch_bounds__(NW * 64) void fused_f32_kernel(FusedArgs a) {
+  constexpr int NP = 16;
+  constexpr int LDU = NP + 1;
+  constexpr int SL = T + 1;                // FP32 slab pitch (floats)
+  extern __shared__ double smem[];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, lq = lane >> 4;
+
+  const int64_t gsub_total = a.G / 16;
+  const int64_t gper = ((a.G / T + a.gblocks - 1) / a.gblocks) * (T / 16);
+  const int gb = blockIdx.x % a.gblocks;
+  const int rb = blockIdx.x / a.gblocks;
+  const int64_t gs0 = gb * gper;
+  const int64_t gs1 = (gs0 + gper < gsub_total) ? gs0 + gper : gsub_total;
+  const int64_t bg = gper * 16;
+  const int64_t rtiles_valid = (a.R_valid + T - 1) / T;
+  const int64_t rt0 = (int64_t)rb * a.rtiles;
+  const int64_t rt1 = (rt0 + a.rtiles < rtiles_valid) ? rt0 + a.rtiles : rtiles_valid;
+
+  // layout (doubles): slabs NW*16*SLAB (holds the FP32 slabs and the reduction area),
+  // sU [T][LDU] (FP32 copy in the first half), sM2 [bg][NP] FP64
+  float* slab = reinterpret_cast<float*>(smem + (int64_t)w * 16 * SLAB);
+  double* red = smem;
+  float* sU = reinterpret_cast<float*>(smem + (int64_t)NW * 16 * SLAB);
+  double* m1s = smem + (int64_t)NW * 16 * SLAB;          // reuses the sU area between R tiles
+  double* sM2 = smem + (int64_t)NW * 16 * SLAB + (int64_t)T * LDU;
+
+  const int64_t nmy = (gs1 - gs0 > w) ? (gs1 - gs0 - w + NW - 1) / NW : 0;
+  const int64_t nstep = nmy * (rt1 > rt0 ? rt1 - rt0 : 0);
+  if (a.want_m2)
+    for (int64_t e = tid; e < bg * NP; e += NW * 64) sM2[e] = 0.0;
+
+  // V fragment: lane holds V[g0 + 4lq + r][R0 + 16c + l16]; U_g operands of the step
+  float vnext[4][4], ugAn[4], ugBn[4];
+  auto load_v = [&](int64_t t) {
+    const int64_t ri = t / nmy, si = t % nmy;
+    const int64_t R0 = (rt0 + ri) * T, g0 = (gs0 + w + si * NW) * 16;
+    const float* base = a.Vm32 + (g0 + 4 * lq) * a.ldv + R0 + l16;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float* row = base + (int64_t)r * a.ldv;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) vnext[r][c] = row[16 * c];
+    }
+    const double* ug = a.Ug + g0 * NP;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) ugAn[kk] = (float)ug[l16 * NP + 4 * kk + lq];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ugBn[r] = (float)ug[(4 * lq + r) * NP + l16];
+  };
+  if (nstep > 0) load_v(0);
+
+  double e1 = 0.0;
+  constexpr int MTW = (MT + NW - 1) / NW > 0 ? (MT + NW - 1) / NW : 1;
+  d4_t k1[MTW];
+#pragma unroll
+  for (int mm = 0; mm < MTW; ++mm) k1[mm] = zero_d4();
+  const int mt = a.Np / 16;
+
+  int64_t t = 0;
+  for (int64_t rt = rt0; rt < rt1; ++rt) {
+    const int64_t R0 = rt * T;
+    __syncthreads();
+    for (int e = tid; e < T * NP; e += NW * 64) sU[(e / NP) * LDU + (e % NP)] = (float)a.Ur[R0 * NP + e];
+    __syncthreads();
+    f4_t m1[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) m1[c] = zero_f4();
+
+    for (int64_t si = 0; si < nmy; ++si, ++t) {
+      const int64_t g0 = (gs0 + w + si * NW) * 16;
+      float v[4][4], ugA[4], ugB[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        ugA[r] = ugAn[r];
+        ugB[r] = ugBn[r];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[r][c] = vnext[r][c];
+      }
+      if (t + 1 < nstep) load_v(t + 1);
+      // P[g0 + 4lq + r][R0 + 16c + l16]
+      f4_t p[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) p[c] = zero_f4();
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) p[c] = mfma_f32(ugA[kk], sU[(16 * c + l16) * LDU + 4 * kk + lq], p[c]);
+      // A = V o P; energy in FP64; slab; M1^T from the registers (slice r <-> g = 4lq + r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        f4_t av;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          av[r] = v[r][c] * p[c][r];
+          e1 += (double)av[r] * (double)p[c][r];
+          slab[(4 * lq + r) * SL + 16 * c + l16] = av[r];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) m1[c] = mfma_f32(av[r], ugB[r], m1[c]);
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (a.want_m2) {
+        f4_t m2 = zero_f4();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk)
+          m2 = mfma_f32(slab[l16 * SL + 4 * kk + lq], sU[(4 * kk + lq) * LDU + l16], m2);
+        double* acc = sM2 + (g0 - gs0 * 16 + 4 * lq) * NP + l16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r * NP] += (double)m2[r];
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+
+    if (MT > 0 || a.want_m1) {
+      __syncthreads();
+      // wave w's partial M1^T[R0 + 16c + 4lq + r][l16] -> red (FP64)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[(w * 64 + 16 * c + 4 * lq + r) * 16 + l16] = (double)m1[c][r];
+      __syncthreads();
+      if (w < 4) {
+        const int q = w;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double s = 0.0;
+          for (int ww = 0; ww < NW; ++ww) s += red[(ww * 64 + 16 * q + 4 * r + lq) * 16 + l16];
+          m1s[(16 * q + 4 * r + lq) * 16 + l16] = s;
+          if (a.want_m1) a.M1T[((int64_t)gb * a.R + R0 + 16 * q + 4 * r + lq) * NP + l16] = s;
+        }
+      }
+      __syncthreads();
+      if (MT > 0 && a.want_k1) {
+#pragma unroll
+        for (int mm = 0; mm < MTW; ++mm) {
+          const int m = w + mm * NW;
+          if (m < mt) {
+            const double* ph = a.Phir + (R0 + lq) * a.Np + 16 * m + l16;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                k1[mm] = mfma_f64(ph[(int64_t)(16 * q + 4 * r) * a.Np], m1s[(16 * q + 4 * r + lq) * 16 + l16], k1[mm]);
+          }
+        }
+      }
+    }
+  }
+
+  const int wg = blockIdx.x;
+  __syncthreads();
+  if (MT > 0 && a.want_k1) {
+    double* out = a.K1p + (int64_t)wg * a.Np * NP;
+#pragma unroll
+    for (int mm = 0; mm < MTW; ++mm) {
+      const int m = w + mm * NW;
+      if (m < mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[(int64_t)(16 * m + 4 * r + lq) * NP + l16] = k1[mm][r];
+    }
+  }
+  if (a.want_m2) {
+    double* out = a.M2p + ((int64_t)rb * a.G + gs0 * 16) * NP;
+    const int64_t rows = (gs1 - gs0) * 16;
+    for (int64_t e = tid; e < rows * NP; e += NW * 64) out[e] = sM2[e];
+  }
+  const double es = wave_sum(e1);
+  __syncthreads();
+  if (lane == 0) red[w] = es;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int ww = 0; ww < NW; ++ww) s += red[ww];
+    a.e1p[wg] = s;
+  }
+}
+
 // Orbitals on the grid and at the points: U = Phi C and U_g = Phi_g C.
 // Row subtiles 16 at a time on the FP64 matrix cores; rows [0, R) come from
 // Phi, rows [R, R + G) from Phi_g.  C [N x n] (row pitch n) is read once into
@@ -752,8 +938,33 @@ hipError_t launch_m4_mt(const FusedArgs& a, int blocks, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+template <int NW, int MT>
+hipError_t launch_f32(const FusedArgs& a, int blocks, hipStream_t s) {
+  const int64_t gper = ((a.G / T + a.gblocks - 1) / a.gblocks) * (T / 16);
+  const int64_t lds = ((int64_t)NW * 16 * SLAB + (int64_t)T * 17 + (a.want_m2 ? gper * 16 : 0) * 16) * 8;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  auto k = fused_f32_kernel<NW, MT>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(NW * 64), (size_t)lds, s, a);
+  return hipGetLastError();
+}
+
+template <int NW>
+hipError_t launch_f32_mt(const FusedArgs& a, int blocks, hipStream_t s) {
+  const int mt = a.want_k1 ? a.Np / 16 : 0;
+  if (mt == 0) return launch_f32<NW, 0>(a, blocks, s);
+  if (mt <= 4) return launch_f32<NW, 4>(a, blocks, s);
+  if (mt <= 8) return launch_f32<NW, 8>(a, blocks, s);
+  return hipErrorInvalidValue;
+}
+
 template <int NI>
 hipError_t launch_fused1(const FusedArgs& a, int blocks, hipStream_t s) {
+  if (NI == 1 && a.prec != 0 && a.Vm32) {
+    if (a.nwaves == 8) return launch_f32_mt<8>(a, blocks, s);
+    return launch_f32_mt<4>(a, blocks, s);
+  }
   if (NI == 1 && a.use_m4 && a.Ugp) {
     if (a.use_m4 == 2) {
       if (a.nwaves == 8) return launch_m4_mt<8, 1>(a, blocks, s);

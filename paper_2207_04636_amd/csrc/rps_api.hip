@@ -111,6 +111,18 @@ struct rps_context {
 namespace {
 
 // ------------------------------------------------------------------ set-up helpers
+// Stage timing on stderr when RPS_VERBOSE is set (large set-ups run for minutes).
+struct StageLog {
+  bool on = getenv("RPS_VERBOSE") != nullptr;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  void operator()(const char* what, hipStream_t st) {
+    if (!on) return;
+    (void)hipStreamSynchronize(st);
+    const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fprintf(stderr, "[rps setup %8.2f s] %s\n", t, what);
+    fflush(stderr);
+  }
+};
 constexpr double kCutoff = 50.0;
 constexpr double kCholShift = 1e-13;
 constexpr int kOversample = 4;
@@ -264,6 +276,7 @@ void select_points(rps_context& c, int mode, uint64_t seed, const std::vector<in
 void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_t n_aux, uint64_t seed,
                 int32_t mode, int32_t prec, const int64_t* points_in, hipStream_t st) {
   auto t0 = std::chrono::steady_clock::now();
+  StageLog stage;
   // ---- validation
   if (!cell || !b) fail(RPS_ERR_ARG, "cell and basis must not be NULL");
   if (b->natom < 1 || b->nshell < 1 || !b->atom_xyz || !b->shell_atom || !b->shell_l || !b->shell_exp)
@@ -343,6 +356,7 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
     (void)hipFree(dsh.p);
     dsh.p = nullptr;
   }
+  stage("basis on the grid", st);
   // ---- interpolation points
   if (points_in) {
     c.points.assign(points_in, points_in + n_aux);
@@ -352,6 +366,7 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
   } else {
     select_points(c, mode, seed, nfunc_atom, b->atom_xyz, st);
   }
+  stage("interpolation points", st);
   c.dpoints.alloc(c.naux, &c.bytes);
   hip_check(hipMemcpyAsync(c.dpoints.p, c.points.data(), c.naux * 8, hipMemcpyHostToDevice, st), "copy points");
   c.Phig.alloc(c.nauxp * c.Np, &c.bytes);
@@ -411,18 +426,32 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
       }
     }
     (void)hipFree(dstatus);
-    // ---- X_gR = (Phi_g Phi^T)^2 into the V buffer, chi = X_gg^-1 X_gR
+    stage("fitting metric and Cholesky", st);
+    // ---- chi = X_gg^-1 X_gR in column panels: X_gR = (Phi_g Phi^T)^2 for the panel,
+    //      two triangular solves on the panel (its working set stays on chip), copy into V
     {
-      Gemm g;
-      g.M = c.nauxp; g.N = c.ngp; g.K = c.Np;
-      g.A = c.Phig.p; g.lda = c.Np; g.B = c.Phi.p; g.ldb = c.Np; g.transB = true;
-      g.C = c.V.p; g.ldc = c.ngp; g.epi = EPI_SQUARE;
-      hip_check(gemm_f64(g, st), "X_gR");
+      const int64_t pw = 8192;
+      DBuf<double> Xp;
+      Xp.alloc(c.nauxp * pw, &tmpb);
+      for (int64_t r0 = 0; r0 < c.ngp; r0 += pw) {
+        const int64_t nc = std::min(pw, c.ngp - r0);
+        Gemm g;
+        g.M = c.nauxp; g.N = nc; g.K = c.Np;
+        g.A = c.Phig.p; g.lda = c.Np; g.B = c.Phi.p + r0 * c.Np; g.ldb = c.Np; g.transB = true;
+        g.C = Xp.p; g.ldc = pw; g.epi = EPI_SQUARE;
+        hip_check(gemm_f64(g, st), "X_gR panel");
+        hip_check(tri_solve_lower(L.p, c.nauxp, c.nauxp, Xp.p, nc, pw, false, st), "solve L");
+        hip_check(tri_solve_lower(L.p, c.nauxp, c.nauxp, Xp.p, nc, pw, true, st), "solve L^T");
+        hip_check(hipMemcpy2DAsync(c.V.p + r0, c.ngp * 8, Xp.p, pw * 8, nc * 8, c.nauxp, hipMemcpyDeviceToDevice, st),
+                  "panel copy");
+      }
+      hip_check(hipStreamSynchronize(st), "sync");
+      Xp.release(nullptr);
     }
-    hip_check(tri_solve_lower(L.p, c.nauxp, c.nauxp, c.V.p, c.ngp, c.ngp, false, st), "solve L");
-    hip_check(tri_solve_lower(L.p, c.nauxp, c.nauxp, c.V.p, c.ngp, c.ngp, true, st), "solve L^T");
+    stage("fitting functions chi", st);
     // ---- V = Vc chi (Sec. 3.2)
     hip_check(poisson_rows(c.V.p, c.nauxp, c.ngp, c.mesh, dkern.p, st), "poisson");
+    stage("potentials V", st);
     // ---- W = V chi^T = (V X_gR^T) X_gg^-1  (Eq. 14), X_gR recomputed in column blocks
     {
       const int64_t bc = 8192;
@@ -452,6 +481,7 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
       Xb.release(nullptr);
     }
     L.release(nullptr);
+    stage("W", st);
   }
   hip_check(hipStreamSynchronize(st), "sync");
   dkern.release(nullptr);
@@ -713,6 +743,7 @@ void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, doub
     a.rtiles = c.rtiles; a.gblocks = c.gblocks; a.nwaves = c.nwaves;
     a.want_m2 = 1; a.want_k1 = (variant == RPS_VARIANT_RPS) ? 1 : 0; a.want_m1 = 0;
     a.prec = c.precision;
+    a.Vm32 = (c.precision != RPS_PREC_FP64) ? c.V32.p : nullptr;
     a.Ugp = m4 ? c.Ugp.p : nullptr; a.use_m4 = m4 ? c.use_m4 : 0;
     a.M2p = c.M2p.p; a.K1p = c.K1p.p; a.e1p = c.e1p.p;
     prof_mark(c, 1, st);

@@ -202,3 +202,32 @@ def test_config2_selection_and_convergence(lib):
         assert -1e-9 < err < 3 * ref + 1e-7
         errs.append(err)
     assert errs[1] < errs[0] / 10
+
+
+# ------------------------------------------------------------------ precision form
+@pytest.mark.parametrize("c", [4, 6, 10])
+def test_precision_fp32_config2(lib, c):
+    """V stored in FP32, in-tile products on the FP32 matrix cores, FP64 across
+    tiles: |dE_x| < 1e-6 Ha against the FP64 oracle (same points); the K error
+    is reported and bounded."""
+    _say(f"case: config-2 FP32 precision form c={c}")
+    g = np.load(os.path.join(GOLDEN, f"diamond1x1x1_c{c}.npz"))
+    w = ri.diamond_cell(float(c))
+    with _ctx(lib, w, points=g["points"], precision=lib.PREC_FP32) as ctx:
+        K, E = ctx.build(g["C"])
+        assert ctx.info()["precision"] == lib.PREC_FP32
+    dk = _kerr(K, g["K"])
+    _say(f"  FP32 form: dE={E - float(g['E']):.3e}  max|dK|/max|K|={dk:.3e}")
+    assert abs(E - float(g["E"])) < 1e-6
+    assert dk < 1e-4
+
+
+def test_precision_fp32_config1(lib, cfg1):
+    _say("case: config-1 FP32 precision form")
+    w, st, C, dV, Phi = cfg1["w"], cfg1["st"], cfg1["C"], cfg1["dV"], cfg1["Phi"]
+    Kref, Eref, _ = rps.build_occ(Phi, st["points"], st["V"], st["W"], C, dV)
+    with _ctx(lib, w, points=st["points"], precision=lib.PREC_FP32) as ctx:
+        K, E = ctx.build(C)
+    _say(f"  FP32 form: dE={E - Eref:.3e}  max|dK|/max|K|={_kerr(K, Kref):.3e}")
+    assert abs(E - Eref) < 1e-6
+    assert _kerr(K, Kref) < 1e-4
