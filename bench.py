@@ -8,13 +8,17 @@ before the timed region and is reported separately.  Inputs (C) are resident
 in device memory when the timed region starts.
 
 Default workload: the 8-atom diamond-like cell (L = 6.74 bohr, 48^3 grid,
-N = 104, n_occ = 16) with N_aux = 6N = 624, FP64 path.  --c selects another
-N_aux/N of the convergence sweep (4, 6, 8, 10).
+N = 104, n_occ = 16) with N_aux = 6N = 624.  The timed path (`value`) is the
+mixed-precision form; the FP64 path is timed beside it on the same points and
+coefficients, and the energy difference between the two is reported against
+the 1e-6 Ha bar.  --precision fp64 times the FP64 path alone.  --c selects
+another N_aux/N of the convergence sweep (4, 6, 8, 10).
 
 Prints one JSON line.  The roofline block refers to the fused V-streaming
-kernel, timed with HIP events recorded by the library on its own stream; its
-algorithmic work per launch is 6 n N_aux N_g flops (P = U_g U^T, M1 = A^T U_g,
-M2 = A U, each 2 n N_aux N_g) on 8 N_aux N_g bytes of V.
+kernel of the timed path, timed with HIP events recorded by the library on
+its own stream; its algorithmic work per launch is 6 n N_aux N_g flops
+(P = U_g U^T, M1 = A^T U_g, M2 = A U, each 2 n N_aux N_g) on s_V N_aux N_g
+bytes of V (s_V = 4 mixed, 8 FP64).
 """
 from __future__ import annotations
 
@@ -28,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix = vector)
+PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 matrix
 PEAK_HBM_GBS = 8000.0
 
 
@@ -61,90 +66,157 @@ def cpu_baseline(w, nrep: int = 3):
                       f"on seeded arrays, after one warm-up; {dt:.3f} s per build"}
 
 
+def _time_path(P, w, prec, points, C, steps, warmup):
+    """Set up one context (given points), then time `steps` builds after
+    `warmup` untimed ones, C and the outputs resident in device memory."""
+    import torch
+    t0 = time.perf_counter()
+    ctx = P.Context.from_workload(w, points=points, precision=prec)
+    setup_s = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    Cd = torch.from_numpy(C).to(dev)
+    K = torch.empty((w.nbas, w.nocc), dtype=torch.float64, device=dev)
+    ex = torch.zeros(1, dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        ctx.build(Cd, K, ex)
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.build(Cd, K, ex)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = ctx.profile()
+    ctx.set_profiling(False)
+    nb = max(prof["builds"], 1)
+    res = {"builds_per_s": steps / dt, "ms_per_step": dt / steps * 1e3,
+           "fused_s": prof["fused_ms"] / nb * 1e-3, "line3_s": prof["line3_ms"] / nb * 1e-3,
+           "build_us_events": prof["build_ms"] / nb * 1e3, "setup_s": setup_s,
+           "setup_s_library": float(ctx.info()["setup_seconds"]),
+           "E_x": float(ex.item()), "K": K.cpu().numpy()}
+    ctx.close()
+    return res
+
+
+def _traffic(kernel_tag):
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    counter summary, or None when the kernel source changed since the counters
+    were taken (the summary records the source hash)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_tag}.txt")
+    src = os.path.join(ROOT, "paper_2207_04636_amd", "csrc", "k_exchange.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("k_exchange.hip sha256") != sha or "traffic bytes per launch" not in fields:
+        return None
+    return float(fields["traffic bytes per launch"])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--c", type=float, default=6.0, help="N_aux / N (4, 6, 8 or 10)")
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
-                    help="fp64: FP64 V and products; fp32: V stored FP32, FP32 in-tile products, FP64 across tiles")
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32",
+                    help="fp32 (default): the mixed form (V stored FP32, FP32 in-tile products, FP64 across "
+                         "tiles), timed next to the FP64 path on the same points and C; fp64: the FP64 path only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (three times) and exit: the reference "
+                         "kernel that scales the HBM byte counters of a profiler run")
     args = ap.parse_args()
+    if args.copy_calibration > 0:
+        import torch
+        nel = args.copy_calibration // 8
+        x = torch.ones(nel, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nel * 8, "copy_bytes_written": nel * 8, "launches": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the exchange build of one cell "
               f"is not sharded here.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
-    import torch
     import paper_2207_04636_amd as P
     import rps_inputs as ri
 
     w = ri.diamond_cell(args.c)
+    # interpolation points and the orthonormal occupied coefficients, shared by both paths
     t0 = time.perf_counter()
-    prec = P.PREC_FP64 if args.precision == "fp64" else P.PREC_FP32
-    ctx = P.Context.from_workload(w, seed=w.sketch_seed(), precision=prec)
-    setup_s = time.perf_counter() - t0
-    info = ctx.info()
-    S = ctx.overlap()
+    with P.Context.from_workload(w, seed=w.sketch_seed()) as sel:
+        points = sel.points()
+        S = sel.overlap()
+    select_s = time.perf_counter() - t0
     C = ri.lowdin(ri.random_coefficients(w), S)
-    dev = torch.device("cuda:0")
-    Cd = torch.from_numpy(C).to(dev)
-    K = torch.empty((w.nbas, w.nocc), dtype=torch.float64, device=dev)
-    ex = torch.zeros(1, dtype=torch.float64, device=dev)
 
-    for _ in range(args.warmup):
-        ctx.build(Cd, K, ex)
-    torch.cuda.synchronize()
-    ctx.set_profiling(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.build(Cd, K, ex)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = ctx.profile()
-    ctx.set_profiling(False)
-    Ex = float(ex.item())
+    mixed = args.precision == "fp32"
+    ref = _time_path(P, w, P.PREC_FP64, points, C, args.steps, args.warmup)
+    run = _time_path(P, w, P.PREC_FP32, points, C, args.steps, args.warmup) if mixed else ref
 
     n, naux, ng, N = w.nocc, w.naux, w.ngrid, w.nbas
-    fused_s = prof["fused_ms"] / max(prof["builds"], 1) * 1e-3
-    line3_s = prof["line3_ms"] / max(prof["builds"], 1) * 1e-3
     flops = 6.0 * n * naux * ng
-    vbytes = 8.0 * naux * ng
+    vbytes = (4.0 if mixed else 8.0) * naux * ng
+    fused_s = run["fused_s"]
     achieved = flops / fused_s / 1e12
+    peak = PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS
+    tag = ("fused_f32" if mixed else "fused_f64") + f"_diamond1x1x1_c{args.c:g}"
+    traffic = _traffic(tag)
     out = {
         "metric": "exchange builds/s (K_occ + E_x)",
-        "value": round(args.steps / dt, 2),
+        "value": round(run["builds_per_s"], 2),
         "unit": "builds/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt / args.steps * 1e3, 5),
+        "ms_per_step": round(run["ms_per_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if mixed else "f64",
         "data": "synthetic (seeded diamond-like cell, random S-orthonormal occupied coefficients)",
-        "config": {"workload": f"diamond 1x1x1 L=6.74 bohr, 48^3 grid, N={N}, n_occ={n}, "
-                               f"N_aux={naux} (c={args.c:g}), FP64 rPS occ-RI", "global_batch": 1,
-                   "parallelism": "single GPU"},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
-                     "kernel": "fused V-streaming kernel (Eq. 16 lines 1-2)",
+        "config": {"workload": f"diamond 1x1x1 L=6.74 bohr, 48^3 grid, N={N}, n_occ={n}, N_aux={naux} "
+                               f"(c={args.c:g}), rPS occ-RI, "
+                               + ("mixed: V FP32, FP32 MFMA in-tile products, FP64 across tiles and in K"
+                                  if mixed else "FP64"),
+                   "global_batch": 1, "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "kernel": ("fused_f32_kernel" if mixed else "fused_f64_kernel")
+                               + " (Eq. 16 lines 1-2 streaming V)",
                      "kernel_avg_us": round(fused_s * 1e6, 3),
+                     "algorithmic_flops_per_launch": flops,
+                     "algorithmic_V_bytes_per_launch": vbytes,
                      "hbm_view_GBs": round(vbytes / fused_s / 1e9, 1),
                      "hbm_view_frac": round(vbytes / fused_s / 1e9 / PEAK_HBM_GBS, 4)},
-        "line3_avg_us": round(line3_s * 1e6, 3),
-        "build_avg_us_events": round(prof["build_ms"] / max(prof["builds"], 1) * 1e3, 3),
-        "setup_s": round(setup_s, 3),
-        "setup_s_library": round(float(info["setup_seconds"]), 3),
-        "E_x": Ex,
+        "line3_avg_us": round(run["line3_s"] * 1e6, 3),
+        "build_avg_us_events": round(run["build_us_events"], 3),
+        "setup_s": round(select_s + run["setup_s"], 3),
+        "E_x": run["E_x"],
     }
+    if mixed:
+        dK = float(np.abs(run["K"] - ref["K"]).max() / np.abs(ref["K"]).max())
+        out["fp64_path"] = {"builds_per_s": round(ref["builds_per_s"], 2),
+                            "ms_per_step": round(ref["ms_per_step"], 5),
+                            "fused_f64_kernel_avg_us": round(ref["fused_s"] * 1e6, 3),
+                            "E_x": ref["E_x"]}
+        out["mixed_vs_fp64"] = {"speedup": round(run["builds_per_s"] / ref["builds_per_s"], 4),
+                                "dE_x": run["E_x"] - ref["E_x"], "max_dK_over_max_K": dK,
+                                "dE_x_bar": 1e-6, "within_bar": abs(run["E_x"] - ref["E_x"]) < 1e-6}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 

@@ -83,7 +83,7 @@ struct rps_context {
   // build workspace (grows on demand)
   int ws_np = -1;
   DBuf<double> U, Ug, Ugp, M2p, K1p, K3p, e1p, e3p, M2, K1, K3, Kdev, Cdev, exdev;
-  int use_m4 = 1;
+  int use_m4 = 0;   // 16x16x4 FP64 kernel by default (faster on gfx950); RPS_FP64_MFMA=m4|hybrid selects the 4x4x4 one
   // general path workspace
   int gws_np = -1;
   int64_t gchunk = 0;
