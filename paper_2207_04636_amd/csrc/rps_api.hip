@@ -87,7 +87,7 @@ struct rps_context {
   // general path workspace
   int gws_np = -1;
   int64_t gchunk = 0;
-  DBuf<double> gCp, gU, gUg, gA, gM2, gM1T, gK1, gK3, gY, gwork, ge;
+  DBuf<double> gCp, gU, gUg, gA, gSp, gM2, gM1T, gK1, gK3, gY, gwork, ge;
   int64_t rblocks_main = 0, blocks_main = 0, blocks_l3 = 0;
   int rtiles = 4, gblocks = 1, nwaves = 4;
   // profiling: event triples (build start, main start, main end, l3 start, l3 end, build end)
@@ -100,7 +100,7 @@ struct rps_context {
     DBuf<double>* all[] = {&Phi, &Phig, &V, &W, &U, &Ug, &Ugp, &M2p, &K1p, &K3p, &e1p,
                            &e3p, &M2, &K1, &K3, &Kdev, &Cdev, &exdev};
     for (auto* b : all) b->release(nullptr);
-    DBuf<double>* gen[] = {&gCp, &gU, &gUg, &gA, &gM2, &gM1T, &gK1, &gK3, &gY, &gwork, &ge};
+    DBuf<double>* gen[] = {&gCp, &gU, &gUg, &gA, &gSp, &gM2, &gM1T, &gK1, &gK3, &gY, &gwork, &ge};
     for (auto* b : gen) b->release(nullptr);
     V32.release(nullptr);
     dpoints.release(nullptr);
@@ -584,6 +584,9 @@ void ensure_workspace(rps_context& c, int np) {
 // K3 = Phi_g^T Y, e1 = tr(U_g^T M2), e3 = tr(U_g^T Y)  (Eq. 16).
 constexpr int64_t kSplitWork = 64ll << 20;   // doubles of split-K partials (512 MB)
 constexpr int kEnergyParts = 256;
+constexpr int kStreamMaxNp = 128;             // largest padded n of the streaming form
+constexpr int64_t kStreamPartRows = 65536;    // rows of split partials (nsplit * nx <= 512 * 128)
+constexpr int kStreamBlocks = 512;            // workgroups aimed at per streaming launch
 
 void ensure_general(rps_context& c, int np) {
   if (c.gws_np == np) return;
@@ -595,7 +598,13 @@ void ensure_general(rps_context& c, int np) {
   c.gCp.alloc(c.Np * np, cnt);
   c.gU.alloc(c.ngp * np, cnt);
   c.gUg.alloc(c.nauxp * np, cnt);
-  c.gA.alloc(std::max(gc * c.ngp, c.nauxp * c.nauxp), cnt);
+  if (np > kStreamMaxNp || getenv("RPS_GENERAL_GEMM")) {
+    c.gSp.release(cnt);
+    c.gA.alloc(std::max(gc * c.ngp, c.nauxp * c.nauxp), cnt);
+  } else {
+    c.gA.release(cnt);
+    c.gSp.alloc(kStreamPartRows * np, cnt);    // split partials of the streaming form
+  }
   c.gM2.alloc(c.nauxp * np, cnt);
   c.gM1T.alloc(c.ngp * np, cnt);
   c.gK1.alloc(c.Np * np, cnt);
@@ -633,7 +642,56 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
   const bool need_l3 = (variant != RPS_VARIANT_PS);
   const bool k1 = need_main && variant == RPS_VARIANT_RPS;
   int ne1 = 0, ne3 = 0;
-  if (need_main) {
+  const bool stream = c.gSp.p != nullptr && np <= kStreamMaxNp;
+  if (stream) {
+    // streaming form: O never materialises A = V o P (see k_stream.hip)
+    const bool f32 = c.precision != RPS_PREC_FP64;
+    if (need_main) {
+      prof_mark(c, 1, st);
+      StreamArgs m2;   // M2 = (V o P) U, x = interpolation points
+      m2.V = c.V.p; m2.V32 = c.V32.p; m2.ldv = c.ngp; m2.trans = 0;
+      m2.X = c.gUg.p; m2.ldx = np; m2.Y = c.gU.p; m2.ldy = np;
+      m2.nx = c.nauxp; m2.ny = c.ngp; m2.np = np; m2.out = c.gSp.p;
+      const int sp = stream_splits(m2.nx, m2.ny, kStreamBlocks);
+      hip_check(stream_product(m2, f32, sp, st), "stream M2");
+      hip_check(sum_partials3(c.gSp.p, sp, c.nauxp * np, c.gM2.p, nullptr, 0, 0, nullptr, nullptr, 0, 0, nullptr, st),
+                "M2 partials");
+      if (k1) {
+        StreamArgs m1;  // M1^T = (V o P)^T U_g, x = grid points
+        m1.V = c.V.p; m1.V32 = c.V32.p; m1.ldv = c.ngp; m1.trans = 1;
+        m1.X = c.gU.p; m1.ldx = np; m1.Y = c.gUg.p; m1.ldy = np;
+        m1.nx = c.ngp; m1.ny = c.nauxp; m1.np = np; m1.out = c.gM1T.p;
+        hip_check(stream_product(m1, f32, 1, st), "stream M1");
+      }
+      prof_mark(c, 2, st);
+      if (k1) {
+        Gemm g;   // K1 = Phi^T M1^T
+        g.M = c.Np; g.N = np; g.K = c.ngp;
+        g.A = c.Phi.p; g.lda = c.Np; g.transA = true; g.B = c.gM1T.p; g.ldb = np; g.C = c.gK1.p; g.ldc = np;
+        gemm_run(g, c, st, "K1", true);
+      }
+      ne1 = dot_partials(c.gUg.p, c.gM2.p, c.nauxp * np, c.ge.p, kEnergyParts, st);
+      if (ne1 < 0) fail(RPS_ERR_DEVICE, "energy partials");
+    }
+    if (need_l3) {
+      prof_mark(c, 3, st);
+      StreamArgs l3;   // Y = (W o P_g) U_g, FP64
+      l3.V = c.W.p; l3.ldv = c.nauxp; l3.trans = 0;
+      l3.X = c.gUg.p; l3.ldx = np; l3.Y = c.gUg.p; l3.ldy = np;
+      l3.nx = c.nauxp; l3.ny = c.nauxp; l3.np = np; l3.out = c.gSp.p;
+      const int sp = stream_splits(l3.nx, l3.ny, kStreamBlocks);
+      hip_check(stream_product(l3, false, sp, st), "stream line 3");
+      hip_check(sum_partials3(c.gSp.p, sp, c.nauxp * np, c.gY.p, nullptr, 0, 0, nullptr, nullptr, 0, 0, nullptr, st),
+                "line-3 partials");
+      Gemm k3;    // K3 = Phi_g^T Y
+      k3.M = c.Np; k3.N = np; k3.K = c.nauxp;
+      k3.A = c.Phig.p; k3.lda = c.Np; k3.transA = true; k3.B = c.gY.p; k3.ldb = np; k3.C = c.gK3.p; k3.ldc = np;
+      gemm_run(k3, c, st, "K3", true);
+      ne3 = dot_partials(c.gUg.p, c.gY.p, c.nauxp * np, c.ge.p + kEnergyParts, kEnergyParts, st);
+      if (ne3 < 0) fail(RPS_ERR_DEVICE, "energy partials");
+      prof_mark(c, 4, st);
+    }
+  } else if (need_main) {
     prof_mark(c, 1, st);
     for (int64_t g0 = 0; g0 < c.nauxp; g0 += c.gchunk) {
       const int64_t gc = std::min(c.gchunk, c.nauxp - g0);
@@ -664,7 +722,7 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
     ne1 = dot_partials(c.gUg.p, c.gM2.p, c.nauxp * np, c.ge.p, kEnergyParts, st);
     if (ne1 < 0) fail(RPS_ERR_DEVICE, "energy partials");
   }
-  if (need_l3) {
+  if (need_l3 && !stream) {
     prof_mark(c, 3, st);
     Gemm b;     // B = W o (U_g U_g^T)
     b.M = c.nauxp; b.N = c.nauxp; b.K = np;

@@ -140,4 +140,26 @@ hipError_t finalize(const double* Phig, const double* M2, int64_t G, const doubl
                     int n, int np, int Np, double s1, double s2, double s3, double dV, double* K, const double* e1p,
                     int64_t ne1, const double* e3p, int64_t ne3, double ce1, double ce3, double* ex, hipStream_t s);
 
+// ---------------------------------------------------------------- streaming form (general sizes)
+// O[x][c] = sum_y S[x][y] (sum_d X[x][d] Y[y][d]) Y[y][c], S = V (or W) stored
+// row-major [rows][cols] with pitch ldv; trans = 0: x indexes rows of S,
+// trans = 1: x indexes columns.  X [nx][ldx], Y [ny][np] (ldy == np), np a
+// multiple of 16 up to 128, nx % 16 == 0, ny % 32 == 0.  The y range is split
+// over nsplit workgroup columns; out holds nsplit partials [nsplit][nx][np].
+struct StreamArgs {
+  const double* V = nullptr;
+  const float* V32 = nullptr;
+  int64_t ldv = 0;
+  int trans = 0;
+  const double* X = nullptr; int64_t ldx = 0;
+  const double* Y = nullptr; int64_t ldy = 0;
+  int64_t nx = 0, ny = 0;
+  int64_t ysplit = 0;       // set by stream_product
+  int np = 0;
+  double* out = nullptr;
+};
+// Split count along y giving about target_blocks workgroups.
+int stream_splits(int64_t nx, int64_t ny, int target_blocks);
+hipError_t stream_product(const StreamArgs& a, bool fp32, int nsplit, hipStream_t s);
+
 }  // namespace rps
