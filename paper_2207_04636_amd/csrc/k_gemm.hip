@@ -99,6 +99,142 @@ __global__ __launch_bounds__(256) void gemm_kernel(Gemm g) {
       }
 }
 
+// Large tiles: 4 waves in 2 x 2, each wave (16*TM) x (16*TN) of C, BK = 16,
+// operands prefetched into registers while the matrix cores work on the
+// current LDS buffer (two buffers, one barrier per K step).
+template <int TM, int TN, bool TA, bool TB>
+__global__ __launch_bounds__(256, 2) void gemm_big_kernel(Gemm g) {
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  constexpr int PA = BM * BK / 256, PB = BN * BK / 256;
+  constexpr int LA = BM + 1, LB = BN + 1;
+  __shared__ double As[2][BK * LA];
+  __shared__ double Bs[2][BK * LB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+  if (g.lower_only && n0 > m0 + BM - 1) return;
+
+  int64_t kbeg = 0, kend = g.K;
+  if (g.splitk > 1) {
+    const int64_t per = ((g.K + g.splitk - 1) / g.splitk + BK - 1) / BK * BK;
+    kbeg = (int64_t)blockIdx.z * per;
+    kend = (kbeg + per < g.K) ? kbeg + per : g.K;
+  }
+  const int64_t nk = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
+
+  // Element e = tid + 256 i of a tile maps to consecutive addresses across
+  // consecutive threads for either storage order of each operand.  Addresses
+  // are a uniform tile base plus 32-bit per-lane offsets (a tile spans less
+  // than 2^31 elements for every leading dimension used here).
+  const bool interior = (m0 + BM <= g.M) && (n0 + BN <= g.N);
+  const int lda = (int)g.lda, ldb = (int)g.ldb;
+  double ra[PA], rb[PB];
+  auto load = [&](int64_t k0) {
+    const bool full = interior && (k0 + BK <= kend);
+    const int64_t kc = (k0 < kend) ? k0 : kbeg;   // keeps the base in bounds past the last step
+    const double* ba = g.A + (TA ? kc * g.lda + m0 : m0 * g.lda + kc);
+    const double* bb = g.B + (TB ? n0 * g.ldb + kc : kc * g.ldb + n0);
+    if (full) {     // uniform: whole tile inside, straight-line loads
+#pragma unroll
+      for (int i = 0; i < PA; ++i) {
+        const int e = tid + 256 * i;
+        const int m = TA ? e % BM : e / BK, k = TA ? e / BM : e % BK;
+        ra[i] = ba[TA ? k * lda + m : m * lda + k];
+      }
+#pragma unroll
+      for (int i = 0; i < PB; ++i) {
+        const int e = tid + 256 * i;
+        const int n = TB ? e / BK : e % BN, k = TB ? e % BK : e / BN;
+        rb[i] = bb[TB ? n * ldb + k : k * ldb + n];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < PA; ++i) {
+        const int e = tid + 256 * i;
+        const int m = TA ? e % BM : e / BK, k = TA ? e / BM : e % BK;
+        ra[i] = (m0 + m < g.M && k0 + k < kend) ? ba[TA ? k * lda + m : m * lda + k] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < PB; ++i) {
+        const int e = tid + 256 * i;
+        const int n = TB ? e / BK : e % BN, k = TB ? e % BK : e / BN;
+        rb[i] = (n0 + n < g.N && k0 + k < kend) ? bb[TB ? n * ldb + k : k * ldb + n] : 0.0;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < PA; ++i) {
+      const int e = tid + 256 * i;
+      const int m = TA ? e % BM : e / BK, k = TA ? e / BM : e % BK;
+      As[buf][k * LA + m] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < PB; ++i) {
+      const int e = tid + 256 * i;
+      const int n = TB ? e / BK : e % BN, k = TB ? e % BK : e / BN;
+      Bs[buf][k * LB + n] = rb[i];
+    }
+  };
+
+  d4_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = zero_d4();
+
+  if (nk > 0) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  // The loop body is one basic block (the prefetch past the last step reads
+  // in-bounds addresses and is discarded), which keeps the accumulators in
+  // the matrix-core registers across iterations.
+  for (int64_t t = 0; t < nk; ++t) {
+    load(kbeg + (t + 1) * BK);
+    const double* as = As[t & 1] + lq * LA + wm * 16 * TM + l16;
+    const double* bs = Bs[t & 1] + lq * LB + wn * 16 * TN + l16;
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      double a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = as[4 * kk * LA + 16 * i];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[j] = bs[4 * kk * LB + 16 * j];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = mfma_f64(a[i], b[j], acc[i][j]);
+    }
+    store((t + 1) & 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = m0 + wm * 16 * TM + i * 16 + d64_row(lane, r);
+        const int64_t gn = n0 + wn * 16 * TN + j * 16 + l16;
+        if (gm < g.M && gn < g.N) {
+          const double v = g.alpha * acc[i][j][r];
+          if (g.splitk > 1) {
+            g.work[((int64_t)blockIdx.z * g.M + gm) * g.N + gn] = v;
+            continue;
+          }
+          double* c = g.C + gm * g.ldc + gn;
+          if (g.epi == EPI_SQUARE) *c = v * v;
+          else if (g.epi == EPI_HADAMARD) *c = *c * v;
+          else if (g.epi == EPI_HADAMARD_SRC) *c = g.D[gm * g.ldd + gn] * v;
+          else *c = (g.beta == 0.0) ? v : v + g.beta * *c;
+        }
+      }
+}
+
 // C = alpha * sum_z work[z] + beta * C (fixed order over z)
 __global__ void splitk_reduce_kernel(const double* __restrict__ work, int splitk, int64_t M, int64_t N,
                                      double* __restrict__ C, int64_t ldc, double beta) {
@@ -109,6 +245,20 @@ __global__ void splitk_reduce_kernel(const double* __restrict__ work, int splitk
   const int64_t m = t / N, n = t % N;
   double* c = C + m * ldc + n;
   *c = (beta == 0.0) ? s : s + beta * *c;
+}
+
+template <int TM, int TN>
+void launch_big(const Gemm& g, dim3 grid, hipStream_t s) {
+  if (!g.transA && !g.transB) hipLaunchKernelGGL((gemm_big_kernel<TM, TN, false, false>), grid, dim3(256), 0, s, g);
+  else if (g.transA && !g.transB) hipLaunchKernelGGL((gemm_big_kernel<TM, TN, true, false>), grid, dim3(256), 0, s, g);
+  else if (!g.transA && g.transB) hipLaunchKernelGGL((gemm_big_kernel<TM, TN, false, true>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((gemm_big_kernel<TM, TN, true, true>), grid, dim3(256), 0, s, g);
+}
+
+// Output tile width: 16 for skinny products, 64 when N <= 64, else 128 (all 128 rows high).
+int gemm_tile_n(int64_t M, int64_t N) {
+  (void)M;
+  return (N <= 16) ? 16 : (N <= 64) ? 64 : 128;
 }
 
 }  // namespace
@@ -122,12 +272,16 @@ hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
   }
   if (g.splitk > 1 && (!g.work || g.epi != EPI_AXPBY)) return hipErrorInvalidValue;
   if (g.splitk < 1) g.splitk = 1;
-  if (g.N <= 16) {
+  const int bn = gemm_tile_n(g.M, g.N);
+  if (bn == 16) {
     dim3 grid((unsigned)((g.N + 15) / 16), (unsigned)((g.M + 127) / 128), (unsigned)g.splitk);
     hipLaunchKernelGGL((gemm_kernel<4, 2, 1>), grid, dim3(256), 0, s, g);
+  } else if (bn == 64) {
+    dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 127) / 128), (unsigned)g.splitk);
+    launch_big<4, 2>(g, grid, s);
   } else {
-    dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), (unsigned)g.splitk);
-    hipLaunchKernelGGL((gemm_kernel<2, 2, 2>), grid, dim3(256), 0, s, g);
+    dim3 grid((unsigned)((g.N + 127) / 128), (unsigned)((g.M + 127) / 128), (unsigned)g.splitk);
+    launch_big<4, 4>(g, grid, s);
   }
   if (g.splitk > 1) {
     const int64_t cnt = g.M * g.N;
@@ -139,7 +293,8 @@ hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
 
 int gemm_splitk_for(int64_t M, int64_t N, int64_t K, int64_t work_cap_doubles) {
   // aim for >= 512 workgroups, at least 256 K per split, bounded by the workspace
-  const int64_t tiles = (N <= 16) ? ((M + 127) / 128) * ((N + 15) / 16) : ((M + 63) / 64) * ((N + 63) / 64);
+  const int bn = gemm_tile_n(M, N);
+  const int64_t tiles = ((M + 127) / 128) * ((N + bn - 1) / bn);
   int64_t z = 1;
   while (tiles * z < 512 && K / (z * 2) >= 256 && (z * 2) * M * N <= work_cap_doubles) z *= 2;
   return (int)z;
