@@ -167,14 +167,58 @@ rps_status rps_build_exchange_full(rps_context *ctx, int32_t nocc, const double 
                                    int32_t flags, void *hip_stream);
 
 /*
- * Batched builds over several contexts (cells of different sizes), one call:
- * C[b], K[b] as for rps_build_exchange_occRI, ex[b] per cell (ex may be NULL).
- * All pointers are of the kind given by flags.
+ * Batched builds over several contexts (cells of different sizes), one call,
+ * issued one after another on hip_stream: C[b], K[b] as for
+ * rps_build_exchange_occRI, ex[b] per cell (ex may be NULL).  All pointers are
+ * of the kind given by flags.  The graph-captured form is rps_batch_create.
  */
 rps_status rps_build_exchange_occRI_batched(rps_context *const *ctx, int32_t nbatch,
                                             const int32_t *nocc, const double *const *C,
                                             double *const *K, double *ex, int32_t flags,
                                             void *hip_stream);
+
+/*
+ * Autotuner.  Times the launch parameters that matter for this context's
+ * build path on the given device-pointer inputs (the work-group target of the
+ * streaming passes, or the R tiles per work-group and g blocks of the fused
+ * kernel), keeps the fastest in the context for every later build, and writes
+ * its mean build time in ms to best_ms (may be NULL).  Results of later builds
+ * stay deterministic; they may differ from untuned builds in the last bits
+ * (another summation order).  C, K: device [N][nocc]; ex device or NULL.
+ * The call synchronises hip_stream.
+ * Errors: RPS_ERR_ARG, RPS_ERR_STATE, RPS_ERR_NOMEM, RPS_ERR_DEVICE.
+ */
+rps_status rps_autotune(rps_context *ctx, int32_t nocc, const double *C, double *K, double *ex,
+                        void *hip_stream, double *best_ms);
+
+/*
+ * Batching form: the builds of many independent cells (contexts of any sizes)
+ * captured once into one HIP graph and replayed with one launch.  Cells are
+ * ordered by work (n N_aux N_g, largest first) and dealt to parallel graph
+ * branches by least accumulated work.  rps_batch_create takes device pointers
+ * only (C[b], K[b] as for rps_build_exchange_occRI; ex: device array [nbatch]
+ * or NULL); they are baked into the graph, so every rps_batch_run reads the
+ * current contents of C[b] and overwrites K[b] and ex[b].  flags:
+ *   RPS_BATCH_AUTOTUNE     run rps_autotune on every context first;
+ *   RPS_BATCH_BRANCHES(k)  use k parallel branches (1..15) instead of timing
+ *                          1, 2 and 4 and keeping the fastest.
+ * A context may appear once per batch and must not be used by other builds
+ * while a replay of the batch runs (the builds share its workspace).
+ * Destroy the batch before any of its contexts.
+ * rps_batch_info: nbranch, and seconds[3] = {create (tuning + capture),
+ * last capture, mean replay measured at creation}.
+ * Errors: RPS_ERR_ARG, RPS_ERR_STATE, RPS_ERR_NOMEM, RPS_ERR_DEVICE.
+ */
+typedef struct rps_batch rps_batch;
+#define RPS_BATCH_AUTOTUNE 1
+#define RPS_BATCH_FIXED_BRANCHES_MASK 0xF00
+#define RPS_BATCH_BRANCHES(k) (((k) & 15) << 8)
+rps_status rps_batch_create(rps_context *const *ctx, int32_t nbatch, const int32_t *nocc,
+                            const double *const *C, double *const *K, double *ex, int32_t flags,
+                            void *hip_stream, rps_batch **out);
+rps_status rps_batch_run(rps_batch *batch, void *hip_stream);
+rps_status rps_batch_info(const rps_batch *batch, int32_t *nbranch, double *seconds);
+void rps_batch_destroy(rps_batch *batch);
 
 /* E_x = -tr(C^T K) = -sum_{mu,i} C[mu][i] K[mu][i]; host FP64 arrays [nbas][nocc]. */
 rps_status rps_exchange_energy(int32_t nbas, int32_t nocc, const double *C, const double *K,
@@ -199,7 +243,7 @@ rps_status rps_get_array(const rps_context *ctx, int32_t which, int64_t row0, in
 
 /*
  * Kernel timing for measurement.  With enable = 1 every later build records
- * HIP events on its stream around the V-streaming kernel (Eq. 16, lines 1-2),
+ * HIP events on its stream around the V-streaming kernel(s) (Eq. 16, lines 1-2),
  * around the fit-fit kernel (line 3) and around the whole build.
  * rps_get_profile synchronises the stream of the last build, writes
  *   out[0] = builds timed, out[1] = total ms in the V-streaming kernel,

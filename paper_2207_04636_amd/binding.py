@@ -28,7 +28,13 @@ STATUS_NAMES = {0: "RPS_OK", 1: "RPS_ERR_ARG", 2: "RPS_ERR_SHAPE", 3: "RPS_ERR_N
 EXPORTS = ("rps_setup_isdf", "rps_build_exchange_occRI", "rps_build_exchange_variant",
            "rps_build_exchange_full", "rps_build_exchange_occRI_batched", "rps_exchange_energy",
            "rps_overlap", "rps_get_points", "rps_get_info", "rps_get_array", "rps_destroy",
-           "rps_last_error", "rps_abi_version", "rps_set_profiling", "rps_get_profile")
+           "rps_last_error", "rps_abi_version", "rps_set_profiling", "rps_get_profile", "rps_autotune",
+           "rps_batch_create", "rps_batch_run", "rps_batch_info", "rps_batch_destroy")
+BATCH_AUTOTUNE = 1
+
+
+def BATCH_BRANCHES(k: int) -> int:
+    return (int(k) & 15) << 8
 
 
 class RpsError(RuntimeError):
@@ -92,11 +98,18 @@ def load(path: str = LIB_PATH):
     lib.rps_get_array.argtypes = [P, I32, I64, I64, P]
     lib.rps_set_profiling.argtypes = [P, I32]
     lib.rps_get_profile.argtypes = [P, P]
+    lib.rps_autotune.argtypes = [P, I32, P, P, P, P, ct.POINTER(D)]
+    lib.rps_batch_create.argtypes = [ct.POINTER(P), I32, ct.POINTER(I32), ct.POINTER(P), ct.POINTER(P), P, I32, P,
+                                     ct.POINTER(P)]
+    lib.rps_batch_run.argtypes = [P, P]
+    lib.rps_batch_info.argtypes = [P, ct.POINTER(I32), P]
+    lib.rps_batch_destroy.argtypes = [P]
+    lib.rps_batch_destroy.restype = None
     lib.rps_destroy.argtypes = [P]
     lib.rps_destroy.restype = None
     lib.rps_last_error.restype = ct.c_char_p
     for name in EXPORTS:
-        if name not in ("rps_destroy", "rps_last_error"):
+        if name not in ("rps_destroy", "rps_last_error", "rps_batch_destroy"):
             getattr(lib, name).restype = ct.c_int32
     _lib = lib
     return lib
@@ -227,6 +240,14 @@ class Context:
         _check(self._lib.rps_get_array(self._h, int(which), int(row0), int(nrows), out.ctypes.data))
         return out
 
+    def autotune(self, C, K, ex=None, stream=None) -> float:
+        """Tune this context's launch parameters on device tensors C, K (and ex);
+        returns the best mean build time in ms (see rps_autotune)."""
+        best = ct.c_double(0.0)
+        _check(self._lib.rps_autotune(self._h, int(C.shape[1]), _ptr(C), _ptr(K), None if ex is None else _ptr(ex),
+                                      _stream_handle(stream), ct.byref(best)))
+        return best.value
+
     def set_profiling(self, enable: bool = True):
         _check(self._lib.rps_set_profiling(self._h, 1 if enable else 0))
 
@@ -275,3 +296,52 @@ def build_batched(ctxs, Cs, Ks, ex=None, stream=None):
     dev = _is_device(Cs[0]) if nb else False
     _check(lib.rps_build_exchange_occRI_batched(H, nb, nocc, Cp, Kp, None if ex is None else _ptr(ex),
                                                 PTRS_DEVICE if dev else PTRS_HOST, _stream_handle(stream)))
+
+
+class Batch:
+    """Batching form: the builds of many contexts captured into one HIP graph
+    (rps_batch_create); run() replays it with one launch.  Cs, Ks are device
+    tensors (their addresses are baked into the graph), ex a device float64
+    tensor of len(ctxs) elements or None."""
+
+    def __init__(self, ctxs, Cs, Ks, ex=None, autotune: bool = True, branches: int = 0, stream=None):
+        lib = load()
+        self._lib = lib
+        self._keep = (list(ctxs), list(Cs), list(Ks), ex)
+        nb = len(ctxs)
+        H = (ct.c_void_p * nb)(*[c._h.value for c in ctxs])
+        nocc = (ct.c_int32 * nb)(*[int(C.shape[1]) for C in Cs])
+        Cp = (ct.c_void_p * nb)(*[_ptr(C) for C in Cs])
+        Kp = (ct.c_void_p * nb)(*[_ptr(K) for K in Ks])
+        flags = (BATCH_AUTOTUNE if autotune else 0) | (BATCH_BRANCHES(branches) if branches else 0)
+        h = ct.c_void_p()
+        _check(lib.rps_batch_create(H, nb, nocc, Cp, Kp, None if ex is None else _ptr(ex), flags,
+                                    _stream_handle(stream), ct.byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        _check(self._lib.rps_batch_run(self._h, _stream_handle(stream)))
+
+    def info(self) -> dict:
+        nbr = ct.c_int32(0)
+        sec = np.zeros(3)
+        _check(self._lib.rps_batch_info(self._h, ct.byref(nbr), sec.ctypes.data))
+        return dict(branches=int(nbr.value), create_s=float(sec[0]), capture_s=float(sec[1]),
+                    replay_ms=float(sec[2]) * 1e3)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.rps_batch_destroy(self._h)
+            self._h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(Gemm g) {
           double* c = g.C + gm * g.ldc + gn;
           if (g.epi == EPI_SQUARE) *c = v * v;
           else if (g.epi == EPI_HADAMARD) *c = *c * v;
-          else if (g.epi == EPI_HADAMARD_SRC) *c = g.D[gm * g.ldd + gn] * v;
+          else if (g.epi == EPI_HADAMARD_SRC) *c = (g.D ? g.D[gm * g.ldd + gn] : (double)g.D32[gm * g.ldd + gn]) * v;
           else *c = (g.beta == 0.0) ? v : v + g.beta * *c;
         }
       }
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(Gemm g) {
           double* c = g.C + gm * g.ldc + gn;
           if (g.epi == EPI_SQUARE) *c = v * v;
           else if (g.epi == EPI_HADAMARD) *c = *c * v;
-          else if (g.epi == EPI_HADAMARD_SRC) *c = g.D[gm * g.ldd + gn] * v;
+          else if (g.epi == EPI_HADAMARD_SRC) *c = (g.D ? g.D[gm * g.ldd + gn] : (double)g.D32[gm * g.ldd + gn]) * v;
           else *c = (g.beta == 0.0) ? v : v + g.beta * *c;
         }
       }
@@ -271,6 +271,7 @@ hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
     if (g.epi == EPI_AXPBY && g.beta == 1.0) return hipSuccess;
   }
   if (g.splitk > 1 && (!g.work || g.epi != EPI_AXPBY)) return hipErrorInvalidValue;
+  if (g.epi == EPI_HADAMARD_SRC && !g.D && !g.D32) return hipErrorInvalidValue;
   if (g.splitk < 1) g.splitk = 1;
   const int bn = gemm_tile_n(g.M, g.N);
   if (bn == 16) {

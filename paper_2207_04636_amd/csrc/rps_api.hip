@@ -12,6 +12,7 @@
 #include <exception>
 #include <new>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "../../include/rps.h"
@@ -90,6 +91,10 @@ struct rps_context {
   DBuf<double> gCp, gU, gUg, gA, gSp, gM2, gM1T, gK1, gK3, gY, gwork, ge;
   int64_t rblocks_main = 0, blocks_main = 0, blocks_l3 = 0;
   int rtiles = 4, gblocks = 1, nwaves = 4;
+  // autotuned launch parameters (0: built-in default)
+  int tune_target = 0;                      // streaming form: workgroups aimed at per launch
+  int tune_rtiles = 0, tune_gblocks = 0;    // fused kernel: R tiles per workgroup, g blocks
+  double tune_ms = 0.0;                     // best build time the tuner measured
   // profiling: event triples (build start, main start, main end, l3 start, l3 end, build end)
   int profiling = 0;
   std::vector<hipEvent_t> ev_pool;
@@ -489,6 +494,7 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
     c.V32.alloc(c.nauxp * c.ngp, &c.bytes);
     hip_check(to_f32(c.V.p, c.nauxp * c.ngp, c.V32.p, st), "to f32");
     hip_check(hipStreamSynchronize(st), "sync");
+    c.V.release(&c.bytes);      // the precision form keeps only the FP32 copy of V
   }
   c.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -542,6 +548,12 @@ void choose_shape(rps_context& c, int np, FusedArgs& a) {
       if (fused_lds_bytes(t) <= lds_cap) { a.rtiles = x; a.gblocks = y; }
     }
   }
+  if (c.tune_rtiles > 0 && c.tune_gblocks > 0 && c.tune_gblocks <= gt) {
+    FusedArgs t = a;
+    t.rtiles = c.tune_rtiles;
+    t.gblocks = c.tune_gblocks;
+    if (fused_lds_bytes(t) <= lds_cap) { a.rtiles = t.rtiles; a.gblocks = t.gblocks; }
+  }
 }
 
 void ensure_workspace(rps_context& c, int np) {
@@ -585,8 +597,9 @@ void ensure_workspace(rps_context& c, int np) {
 constexpr int64_t kSplitWork = 64ll << 20;   // doubles of split-K partials (512 MB)
 constexpr int kEnergyParts = 256;
 constexpr int kStreamMaxNp = 128;             // largest padded n of the streaming form
-constexpr int64_t kStreamPartRows = 65536;    // rows of split partials (nsplit * nx <= 512 * 128)
-constexpr int kStreamBlocks = 512;            // workgroups aimed at per streaming launch
+constexpr int kStreamBlocks = 512;            // workgroups aimed at per streaming launch (default)
+constexpr int kStreamMaxTarget = 1024;        // largest target the tuner tries
+constexpr int64_t kStreamPartRows = (int64_t)kStreamMaxTarget * 128;   // rows of split partials
 
 void ensure_general(rps_context& c, int np) {
   if (c.gws_np == np) return;
@@ -652,7 +665,7 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
       m2.V = c.V.p; m2.V32 = c.V32.p; m2.ldv = c.ngp; m2.trans = 0;
       m2.X = c.gUg.p; m2.ldx = np; m2.Y = c.gU.p; m2.ldy = np;
       m2.nx = c.nauxp; m2.ny = c.ngp; m2.np = np; m2.out = c.gSp.p;
-      const int sp = stream_splits(m2.nx, m2.ny, kStreamBlocks);
+      const int sp = stream_splits(m2.nx, m2.ny, c.tune_target > 0 ? c.tune_target : kStreamBlocks);
       hip_check(stream_product(m2, f32, sp, st), "stream M2");
       hip_check(sum_partials3(c.gSp.p, sp, c.nauxp * np, c.gM2.p, nullptr, 0, 0, nullptr, nullptr, 0, 0, nullptr, st),
                 "M2 partials");
@@ -679,7 +692,7 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
       l3.V = c.W.p; l3.ldv = c.nauxp; l3.trans = 0;
       l3.X = c.gUg.p; l3.ldx = np; l3.Y = c.gUg.p; l3.ldy = np;
       l3.nx = c.nauxp; l3.ny = c.nauxp; l3.np = np; l3.out = c.gSp.p;
-      const int sp = stream_splits(l3.nx, l3.ny, kStreamBlocks);
+      const int sp = stream_splits(l3.nx, l3.ny, c.tune_target > 0 ? c.tune_target : kStreamBlocks);
       hip_check(stream_product(l3, false, sp, st), "stream line 3");
       hip_check(sum_partials3(c.gSp.p, sp, c.nauxp * np, c.gY.p, nullptr, 0, 0, nullptr, nullptr, 0, 0, nullptr, st),
                 "line-3 partials");
@@ -698,7 +711,9 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
       Gemm a;   // A_c = V_c o (U_g[c] U^T)
       a.M = gc; a.N = c.ngp; a.K = np;
       a.A = c.gUg.p + g0 * np; a.lda = np; a.B = c.gU.p; a.ldb = np; a.transB = true;
-      a.C = c.gA.p; a.ldc = c.ngp; a.epi = EPI_HADAMARD_SRC; a.D = c.V.p + g0 * c.ngp; a.ldd = c.ngp;
+      a.C = c.gA.p; a.ldc = c.ngp; a.epi = EPI_HADAMARD_SRC; a.ldd = c.ngp;
+      if (c.V.p) a.D = c.V.p + g0 * c.ngp;
+      else a.D32 = c.V32.p + g0 * c.ngp;      // precision form: V held in FP32, products in FP64
       gemm_run(a, c, st, "A chunk", false);
       Gemm m2;  // M2[c] = A_c U
       m2.M = gc; m2.N = np; m2.K = c.ngp;
@@ -747,6 +762,14 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
             "finalize");
 }
 
+// The fused single-pass kernels cover N <= 128 with n <= 64 (FP64) or n <= 16
+// (FP32 form); everything else takes the general path.
+bool uses_general(const rps_context& c, int np) {
+  bool general = (np > 64) || (c.Np > 128) || (c.precision != RPS_PREC_FP64 && np > 16);
+  if (const char* bp = getenv("RPS_BUILD_PATH")) general = general || (strcmp(bp, "general") == 0);
+  return general;
+}
+
 // variant coefficients: K = dV (s1 K1 + s2 K2 + s3 K3), E = -dV (ce1 e1 + ce3 e3)
 void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, double* K, double* ex,
                 int32_t flags, hipStream_t st) {
@@ -756,8 +779,7 @@ void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, doub
   if (flags != RPS_PTRS_HOST && flags != RPS_PTRS_DEVICE) fail(RPS_ERR_ARG, "flags must be RPS_PTRS_HOST or RPS_PTRS_DEVICE");
   if (variant < RPS_VARIANT_RPS || variant > RPS_VARIANT_THC) fail(RPS_ERR_ARG, "unknown variant");
   const int np = (int)round_up(nocc, 16);
-  bool general = (np > 64) || (c.Np > 128);
-  if (const char* bp = getenv("RPS_BUILD_PATH")) general = general || (strcmp(bp, "general") == 0);
+  const bool general = uses_general(c, np);
   double s1 = 1, s2 = 1, s3 = -1, ce1 = 2, ce3 = -1;
   if (variant == RPS_VARIANT_PS) { s1 = 0; s2 = 1; s3 = 0; ce1 = 1; ce3 = 0; }
   if (variant == RPS_VARIANT_THC) { s1 = 0; s2 = 0; s3 = 1; ce1 = 0; ce3 = 1; }
@@ -845,6 +867,72 @@ void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, doub
   }
 }
 
+// ------------------------------------------------------------------ autotuner
+// Mean time of `reps` device-pointer builds after one warm-up build (which
+// also allocates any workspace the launch shape needs).
+double time_builds(rps_context& c, int32_t nocc, const double* C, double* K, double* ex, hipStream_t st, int reps) {
+  build_impl(c, RPS_VARIANT_RPS, nocc, C, K, ex, RPS_PTRS_DEVICE, st);
+  hipEvent_t e0, e1;
+  hip_check(hipEventCreate(&e0), "hipEventCreate");
+  hip_check(hipEventCreate(&e1), "hipEventCreate");
+  hip_check(hipEventRecord(e0, st), "hipEventRecord");
+  for (int r = 0; r < reps; ++r) build_impl(c, RPS_VARIANT_RPS, nocc, C, K, ex, RPS_PTRS_DEVICE, st);
+  hip_check(hipEventRecord(e1, st), "hipEventRecord");
+  hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+  float ms = 0.f;
+  hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / reps;
+}
+
+// Try the launch parameters that matter for this context's path on its own
+// inputs and keep the fastest: the streaming form's workgroup target (tail
+// balance of the split passes) or the fused kernel's R tiles per workgroup
+// and g blocks.  Results stay in the context and persist for later builds.
+void autotune(rps_context& c, int32_t nocc, const double* C, double* K, double* ex, hipStream_t st) {
+  const int np = (int)round_up(nocc, 16);
+  struct Cand { int target, rtiles, gblocks; };
+  std::vector<Cand> cands;
+  const int saved_prof = c.profiling;
+  c.profiling = 0;
+  if (uses_general(c, np)) {
+    for (int t : {256, 512, kStreamMaxTarget}) cands.push_back({t, 0, 0});
+  } else {
+    c.tune_rtiles = c.tune_gblocks = 0;
+    FusedArgs a{};
+    a.R_valid = c.ng;
+    choose_shape(c, np, a);
+    const int64_t rt = c.ngp / 64, gt = c.nauxp / 64;
+    cands.push_back({0, a.rtiles, a.gblocks});
+    if (a.rtiles > 1) cands.push_back({0, (a.rtiles + 1) / 2, a.gblocks});
+    cands.push_back({0, a.rtiles * 2, a.gblocks});
+    if (a.gblocks < gt) {
+      const int gb = a.gblocks + 1;
+      const int64_t target = std::max<int64_t>(1, 256 / gb);
+      cands.push_back({0, (int)std::max<int64_t>(1, (rt + target - 1) / target), gb});
+    }
+  }
+  double best = 1e300;
+  Cand bc = cands[0];
+  for (const Cand& k : cands) {
+    c.tune_target = k.target;
+    c.tune_rtiles = k.rtiles;
+    c.tune_gblocks = k.gblocks;
+    c.ws_np = -1;                 // re-derive the launch shape and its buffers
+    const double ms = time_builds(c, nocc, C, K, ex, st, 3);
+    if (ms < best) { best = ms; bc = k; }
+  }
+  c.tune_target = bc.target;
+  c.tune_rtiles = bc.rtiles;
+  c.tune_gblocks = bc.gblocks;
+  c.tune_ms = best;
+  c.ws_np = -1;
+  build_impl(c, RPS_VARIANT_RPS, nocc, C, K, ex, RPS_PTRS_DEVICE, st);
+  hip_check(hipStreamSynchronize(st), "sync");
+  c.profiling = saved_prof;
+}
+
 template <typename F>
 rps_status guarded(F&& f) {
   try {
@@ -864,6 +952,114 @@ rps_status guarded(F&& f) {
     g_err = "unknown failure";
     return RPS_ERR_DEVICE;
   }
+}
+
+}  // namespace
+
+// A captured batch of exchange builds over many contexts (the batching form).
+struct rps_batch {
+  std::vector<rps_context*> ctx;
+  std::vector<int32_t> nocc;
+  std::vector<const double*> C;
+  std::vector<double*> K;
+  double* ex = nullptr;
+  int nbranch = 1;
+  double tune_seconds = 0.0, capture_seconds = 0.0, replay_ms = 0.0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t origin = nullptr;        // capture stream (the legacy default stream cannot be captured)
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+  void release_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+  ~rps_batch() {
+    release_graph();
+    for (auto e : events) (void)hipEventDestroy(e);
+    for (auto st : streams) (void)hipStreamDestroy(st);
+    if (origin) (void)hipStreamDestroy(origin);
+  }
+};
+
+namespace {
+
+// Capture every build of the batch into one graph.  Cells are ordered by
+// their work (n N_aux N_g, largest first) and dealt to `nbranch` parallel
+// branches by least accumulated work, so small cells fill the device beside
+// the large ones; the branches fork from and join back into `origin`.
+void capture_batch(rps_batch& b, int nbranch, hipStream_t origin) {
+  b.release_graph();
+  const int nb = (int)b.ctx.size();
+  while ((int)b.streams.size() < nbranch) {
+    hipStream_t st;
+    hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+    b.streams.push_back(st);
+  }
+  while ((int)b.events.size() < nbranch + 1) {
+    hipEvent_t e;
+    hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+    b.events.push_back(e);
+  }
+  std::vector<int> order(nb);
+  for (int i = 0; i < nb; ++i) order[i] = i;
+  auto work = [&](int i) {
+    return (double)b.nocc[i] * (double)b.ctx[i]->naux * (double)b.ctx[i]->ng;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+  std::vector<double> load(nbranch, 0.0);
+  std::vector<int> assign(nb, 0);
+  for (int i : order) {
+    int br = 0;
+    for (int k = 1; k < nbranch; ++k)
+      if (load[k] < load[br]) br = k;
+    assign[i] = br;
+    load[br] += work(i);
+  }
+  std::vector<int> prof(nb);
+  for (int i = 0; i < nb; ++i) { prof[i] = b.ctx[i]->profiling; b.ctx[i]->profiling = 0; }
+  auto t0 = std::chrono::steady_clock::now();
+  hip_check(hipStreamBeginCapture(origin, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+  try {
+    hip_check(hipEventRecord(b.events[nbranch], origin), "fork");
+    for (int k = 0; k < nbranch; ++k) hip_check(hipStreamWaitEvent(b.streams[k], b.events[nbranch], 0), "fork wait");
+    for (int i : order)
+      build_impl(*b.ctx[i], RPS_VARIANT_RPS, b.nocc[i], b.C[i], b.K[i], b.ex ? b.ex + i : nullptr, RPS_PTRS_DEVICE,
+                 b.streams[assign[i]]);
+    for (int k = 0; k < nbranch; ++k) {
+      hip_check(hipEventRecord(b.events[k], b.streams[k]), "join");
+      hip_check(hipStreamWaitEvent(origin, b.events[k], 0), "join wait");
+    }
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(origin, &g);
+    if (g) (void)hipGraphDestroy(g);
+    for (int i = 0; i < nb; ++i) b.ctx[i]->profiling = prof[i];
+    throw;
+  }
+  hip_check(hipStreamEndCapture(origin, &b.graph), "hipStreamEndCapture");
+  hip_check(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  b.capture_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  b.nbranch = nbranch;
+  for (int i = 0; i < nb; ++i) b.ctx[i]->profiling = prof[i];
+}
+
+double time_replays(rps_batch& b, hipStream_t st, int reps) {
+  hip_check(hipGraphLaunch(b.exec, st), "hipGraphLaunch");
+  hipEvent_t e0, e1;
+  hip_check(hipEventCreate(&e0), "hipEventCreate");
+  hip_check(hipEventCreate(&e1), "hipEventCreate");
+  hip_check(hipEventRecord(e0, st), "hipEventRecord");
+  for (int r = 0; r < reps; ++r) hip_check(hipGraphLaunch(b.exec, st), "hipGraphLaunch");
+  hip_check(hipEventRecord(e1, st), "hipEventRecord");
+  hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+  float ms = 0.f;
+  hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / reps;
 }
 
 }  // namespace
@@ -926,6 +1122,91 @@ rps_status rps_build_exchange_occRI_batched(rps_context* const* ctx, int32_t nba
   });
 }
 
+rps_status rps_autotune(rps_context* ctx, int32_t nocc, const double* C, double* K, double* ex, void* hip_stream,
+                        double* best_ms) {
+  return guarded([&] {
+    if (!ctx || !C || !K) fail(RPS_ERR_ARG, "NULL argument");
+    if (nocc < 1) fail(RPS_ERR_ARG, "nocc must be >= 1");
+    autotune(*ctx, nocc, C, K, ex, (hipStream_t)hip_stream);
+    if (best_ms) *best_ms = ctx->tune_ms;
+  });
+}
+
+rps_status rps_batch_create(rps_context* const* ctx, int32_t nbatch, const int32_t* nocc, const double* const* C,
+                            double* const* K, double* ex, int32_t flags, void* hip_stream, rps_batch** out) {
+  return guarded([&] {
+    if (!out) fail(RPS_ERR_ARG, "out must not be NULL");
+    *out = nullptr;
+    if (!ctx || !nocc || !C || !K || nbatch < 1) fail(RPS_ERR_ARG, "NULL argument or nbatch < 1");
+    if (flags & ~(RPS_BATCH_AUTOTUNE | RPS_BATCH_FIXED_BRANCHES_MASK)) fail(RPS_ERR_ARG, "unknown flags");
+    for (int32_t i = 0; i < nbatch; ++i) {
+      if (!ctx[i] || !C[i] || !K[i]) fail(RPS_ERR_ARG, "NULL context or buffer in batch");
+      if (ctx[i]->ng == 0) fail(RPS_ERR_STATE, "context without a completed set-up in batch");
+      if (nocc[i] < 1) fail(RPS_ERR_ARG, "nocc must be >= 1");
+      for (int32_t j = 0; j < i; ++j)
+        if (ctx[j] == ctx[i]) fail(RPS_ERR_ARG, "a context appears twice in the batch (builds would share workspace)");
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    auto b = std::make_unique<rps_batch>();
+    b->ctx.assign(ctx, ctx + nbatch);
+    b->nocc.assign(nocc, nocc + nbatch);
+    b->C.assign(C, C + nbatch);
+    b->K.assign(K, K + nbatch);
+    b->ex = ex;
+    auto t0 = std::chrono::steady_clock::now();
+    for (int32_t i = 0; i < nbatch; ++i) {
+      if (flags & RPS_BATCH_AUTOTUNE)
+        autotune(*ctx[i], nocc[i], C[i], K[i], ex ? ex + i : nullptr, st);
+      else   // one eager build: allocates every workspace before capture
+        build_impl(*ctx[i], RPS_VARIANT_RPS, nocc[i], C[i], K[i], ex ? ex + i : nullptr, RPS_PTRS_DEVICE, st);
+    }
+    hip_check(hipStreamSynchronize(st), "sync");
+    hip_check(hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking), "hipStreamCreate");
+    hipStream_t org = b->origin;
+    const int fixed = (flags & RPS_BATCH_FIXED_BRANCHES_MASK) >> 8;
+    if (fixed > 0) {
+      capture_batch(*b, fixed, org);
+      b->replay_ms = time_replays(*b, org, 2);
+    } else {
+      // branch count: the fastest replay of 1, 2 and 4 parallel branches
+      double best = 1e300;
+      int bestk = 1;
+      for (int k : {1, 2, 4}) {
+        if (k > 1 && k > nbatch) break;
+        capture_batch(*b, k, org);
+        const double ms = time_replays(*b, org, 2);
+        if (ms < best) { best = ms; bestk = k; }
+      }
+      if (b->nbranch != bestk) capture_batch(*b, bestk, org);
+      b->replay_ms = best;
+    }
+    hip_check(hipStreamSynchronize(org), "sync");
+    b->tune_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = b.release();
+  });
+}
+
+rps_status rps_batch_run(rps_batch* b, void* hip_stream) {
+  return guarded([&] {
+    if (!b || !b->exec) fail(RPS_ERR_ARG, "NULL or empty batch");
+    hip_check(hipGraphLaunch(b->exec, (hipStream_t)hip_stream), "hipGraphLaunch");
+  });
+}
+
+rps_status rps_batch_info(const rps_batch* b, int32_t* nbranch, double* seconds) {
+  return guarded([&] {
+    if (!b) fail(RPS_ERR_ARG, "NULL batch");
+    if (nbranch) *nbranch = b->nbranch;
+    if (seconds) {
+      seconds[0] = b->tune_seconds;
+      seconds[1] = b->capture_seconds;
+      seconds[2] = b->replay_ms * 1e-3;
+    }
+  });
+}
+
+void rps_batch_destroy(rps_batch* b) { delete b; }
+
 rps_status rps_exchange_energy(int32_t nbas, int32_t nocc, const double* C, const double* K, double* ex) {
   return guarded([&] {
     if (nbas < 1 || nocc < 1) fail(RPS_ERR_ARG, "nbas and nocc must be >= 1");
@@ -985,7 +1266,10 @@ rps_status rps_get_array(const rps_context* ctx, int32_t which, int64_t row0, in
     int64_t rows = 0, cols = 0, ld = 0;
     const double* src = nullptr;
     if (which == 0) { rows = c.ng; cols = c.nbas; ld = c.Np; src = c.Phi.p; }
-    else if (which == 1) { rows = c.naux; cols = c.ng; ld = c.ngp; src = c.V.p; }
+    else if (which == 1) {
+      if (!c.V.p) fail(RPS_ERR_STATE, "this context keeps V in FP32 only (precision form)");
+      rows = c.naux; cols = c.ng; ld = c.ngp; src = c.V.p;
+    }
     else if (which == 2) { rows = c.naux; cols = c.naux; ld = c.nauxp; src = c.W.p; }
     else if (which == 3) {
       if (c.owner_host.empty()) fail(RPS_ERR_STATE, "no Voronoi assignment was computed (points were given)");

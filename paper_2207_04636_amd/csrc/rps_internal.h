@@ -24,6 +24,7 @@ struct Gemm {
   int epi = EPI_AXPBY;
   bool lower_only = false;   // skip output tiles strictly above the diagonal
   const double* D = nullptr; int64_t ldd = 0;   // EPI_HADAMARD_SRC operand
+  const float* D32 = nullptr;                    // FP32 form of that operand (used when D is NULL)
   int splitk = 1;            // > 1: K split over workgroups, partials in work (EPI_AXPBY only)
   double* work = nullptr;    // splitk * M * N doubles
 };

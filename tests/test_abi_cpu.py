@@ -101,6 +101,28 @@ def test_calls_without_context_fail_cleanly():
     lib.rps_destroy(None)
 
 
+def test_batch_and_tuner_argument_errors():
+    """The batching form and the autotuner reject bad arguments before any
+    device work (no GPU is touched on these paths)."""
+    import ctypes as ct
+    lib = P.load()
+    C = np.zeros((2, 2))
+    assert lib.rps_autotune(None, 2, C.ctypes.data, C.ctypes.data, None, None, None) == B.RPS_ERR_ARG
+    out = ct.c_void_p(123)
+    H = (ct.c_void_p * 1)(None)
+    nocc = (ct.c_int32 * 1)(2)
+    Cp = (ct.c_void_p * 1)(C.ctypes.data)
+    Kp = (ct.c_void_p * 1)(C.ctypes.data)
+    assert lib.rps_batch_create(H, 1, nocc, Cp, Kp, None, 0, None, ct.byref(out)) == B.RPS_ERR_ARG
+    assert out.value is None                       # cleared on failure
+    assert "NULL" in lib.rps_last_error().decode()
+    assert lib.rps_batch_create(H, 0, nocc, Cp, Kp, None, 0, None, ct.byref(out)) == B.RPS_ERR_ARG
+    assert lib.rps_batch_create(H, 1, nocc, Cp, Kp, None, 1 << 20, None, ct.byref(out)) == B.RPS_ERR_ARG
+    assert lib.rps_batch_run(None, None) == B.RPS_ERR_ARG
+    assert lib.rps_batch_info(None, None, None) == B.RPS_ERR_ARG
+    lib.rps_batch_destroy(None)
+
+
 def test_python_errors_are_loud():
     with pytest.raises(P.RpsError):
         P.Context(np.eye(3) * 5, [8, 8, 8], [[0, 0, 0]], [0], [0], [1.0], naux=0)
