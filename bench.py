@@ -119,6 +119,93 @@ def _traffic(kernel_tag):
     return float(fields["traffic bytes per launch"])
 
 
+def batch_bench(args):
+    """Batching form over 64 uneven diamond-like cells (shapes {1,2}^3, strain
+    +-5%, grids 32-72 per axis, N_aux = 6N, n_occ = 2 per atom): the mixed
+    builds of all cells captured in one HIP graph (autotuned) against the 64
+    FP64 builds issued one after another.  Each FP64 context is set up, timed
+    and released in turn (FP64 V of all cells together would not fit), then
+    the mixed contexts are set up on the same points and kept."""
+    import numpy as np
+    import torch
+    import paper_2207_04636_amd as P
+    import rps_inputs as ri
+    cells = ri.batch_cells(64)
+    dev = torch.device("cuda:0")
+    t_setup = time.perf_counter()
+    pts, Cs, E64, t64 = [], [], [], []
+    flops = 0.0
+    for i, w in enumerate(cells):
+        with P.Context.from_workload(w, seed=w.sketch_seed()) as ctx:
+            p = ctx.points()
+            C = ri.lowdin(ri.random_coefficients(w), ctx.overlap())
+            Cd = torch.from_numpy(C).to(dev)
+            K = torch.empty((w.nbas, w.nocc), dtype=torch.float64, device=dev)
+            ex = torch.zeros(1, dtype=torch.float64, device=dev)
+            ctx.build(Cd, K, ex)
+            torch.cuda.synchronize()
+            reps = 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.build(Cd, K, ex)
+            torch.cuda.synchronize()
+            t64.append((time.perf_counter() - t0) / reps)
+            E64.append(float(ex.item()))
+        pts.append(p)
+        Cs.append(C)
+        flops += 6.0 * w.nocc * w.naux * w.ngrid
+        print(f"[batch64] FP64 cell {i}: {w.name} {t64[-1] * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    ctxs = []
+    for i, w in enumerate(cells):
+        ctxs.append(P.Context.from_workload(w, points=pts[i], precision=P.PREC_FP32))
+    print("[batch64] mixed contexts ready", file=sys.stderr, flush=True)
+    setup_s = time.perf_counter() - t_setup
+    Cd = [torch.from_numpy(C).to(dev) for C in Cs]
+    Ks = [torch.empty((w.nbas, w.nocc), dtype=torch.float64, device=dev) for w in cells]
+    ex = torch.zeros(len(cells), dtype=torch.float64, device=dev)
+    bat = P.Batch(ctxs, Cd, Ks, ex, autotune=True)
+    info = bat.info()
+    for _ in range(max(1, args.warmup // 10)):
+        bat.run()
+    torch.cuda.synchronize()
+    steps = max(1, args.steps // 200)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bat.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    E32 = ex.cpu().numpy()
+    dE = E32 - np.array(E64)
+    seq = float(np.sum(t64))
+    achieved = flops / dt / 1e12
+    out = {
+        "metric": "exchange builds/s (K_occ + E_x)",
+        "value": round(len(cells) / dt, 2),
+        "unit": "builds/s",
+        "n_gpus": 1, "steps": steps, "warmup": max(1, args.warmup // 10),
+        "ms_per_step": round(dt * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (64 seeded diamond-like cells of uneven size, random S-orthonormal coefficients)",
+        "config": {"workload": "batch of 64 cells: shapes {1,2}^3, strain +-5%, grids 32-72, N_aux = 6N, "
+                               "n_occ = 2 per atom; one step = all 64 builds (one graph launch)",
+                   "global_batch": len(cells), "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "kernel": "whole batch (6 n N_aux N_g per cell over the replay time)"},
+        "batch": {"branches": info["branches"], "create_s": round(info["create_s"], 3),
+                  "nbas_range": [int(min(w.nbas for w in cells)), int(max(w.nbas for w in cells))],
+                  "nocc_range": [int(min(w.nocc for w in cells)), int(max(w.nocc for w in cells))]},
+        "fp64_sequential": {"builds_per_s": round(len(cells) / seq, 2), "seconds_for_64": round(seq, 4)},
+        "mixed_vs_fp64": {"speedup": round(seq / dt, 4), "max_abs_dE_x": float(np.abs(dE).max()),
+                          "dE_x_bar": 1e-6, "within_bar": bool(np.abs(dE).max() < 1e-6)},
+        "setup_s": round(setup_s, 2),
+    }
+    bat.close()
+    for c in ctxs:
+        c.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +215,10 @@ def main():
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32",
                     help="fp32 (default): the mixed form (V stored FP32, FP32 in-tile products, FP64 across "
                          "tiles), timed next to the FP64 path on the same points and C; fp64: the FP64 path only")
+    ap.add_argument("--workload", choices=["diamond1x1x1", "diamond2x2x2", "diamond3x3x3", "batch64"],
+                    default="diamond1x1x1",
+                    help="diamond1x1x1 (default, the headline line); diamond2x2x2 / diamond3x3x3: the precision "
+                         "form on the supercells (few steps); batch64: the batching form over 64 uneven cells")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (three times) and exit: the reference "
@@ -152,7 +243,14 @@ def main():
     import paper_2207_04636_amd as P
     import rps_inputs as ri
 
-    w = ri.diamond_cell(args.c)
+    if args.workload == "batch64":
+        return batch_bench(args)
+    if args.workload != "diamond1x1x1":
+        if args.steps == ap.get_default("steps"):
+            args.steps, args.warmup = 5, 1
+        args.no_cpu_baseline = True
+    w = {"diamond1x1x1": lambda: ri.diamond_cell(args.c), "diamond2x2x2": ri.diamond_2x2x2,
+         "diamond3x3x3": ri.diamond_3x3x3}[args.workload]()
     # interpolation points and the orthonormal occupied coefficients, shared by both paths
     t0 = time.perf_counter()
     with P.Context.from_workload(w, seed=w.sketch_seed()) as sel:
@@ -172,7 +270,8 @@ def main():
     achieved = flops / fused_s / 1e12
     peak = PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS
     tag = ("fused_f32" if mixed else "fused_f64") + f"_diamond1x1x1_c{args.c:g}"
-    traffic = _traffic(tag)
+    general = args.workload != "diamond1x1x1"
+    traffic = _traffic(tag) if args.workload == "diamond1x1x1" else None
     out = {
         "metric": "exchange builds/s (K_occ + E_x)",
         "value": round(run["builds_per_s"], 2),
@@ -186,16 +285,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if mixed else "f64",
         "data": "synthetic (seeded diamond-like cell, random S-orthonormal occupied coefficients)",
-        "config": {"workload": f"diamond 1x1x1 L=6.74 bohr, 48^3 grid, N={N}, n_occ={n}, N_aux={naux} "
-                               f"(c={args.c:g}), rPS occ-RI, "
+        "config": {"workload": f"{w.name}: {ng} grid points, N={N}, n_occ={n}, N_aux={naux}, rPS occ-RI, "
                                + ("mixed: V FP32, FP32 MFMA in-tile products, FP64 across tiles and in K"
                                   if mixed else "FP64"),
                    "global_batch": 1, "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": None if traffic is None else round(traffic),
-                     "kernel": ("fused_f32_kernel" if mixed else "fused_f64_kernel")
-                               + " (Eq. 16 lines 1-2 streaming V)",
+                     "kernel": ("stream_kernel passes" if general else
+                                ("fused_f32_kernel" if mixed else "fused_f64_kernel")) + " (Eq. 16 lines 1-2 streaming V)",
                      "kernel_avg_us": round(fused_s * 1e6, 3),
                      "algorithmic_flops_per_launch": flops,
                      "algorithmic_V_bytes_per_launch": vbytes,

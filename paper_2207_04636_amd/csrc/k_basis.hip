@@ -17,6 +17,17 @@
 namespace rps {
 namespace {
 
+// 1-D launches over more than 2^32 work-items (e.g. N_aux x N_g at the largest
+// sizes) do not fit one grid dimension: blocks are laid out over x and y.
+__device__ __forceinline__ int64_t flat_id() {
+  return ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
+}
+inline dim3 flat_grid(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  const int64_t gx = b < 65536 ? (b > 0 ? b : 1) : 65536;
+  return dim3((unsigned)gx, (unsigned)((b + gx - 1) / gx));
+}
+
 constexpr double kCutoff = 50.0;
 
 __device__ __forceinline__ void grid_point(const CellDev& c, int64_t idx, double r[3]) {
@@ -46,7 +57,7 @@ __device__ __forceinline__ void reduce_disp(const CellDev& c, double d[3]) {
 __global__ __launch_bounds__(256) void basis_kernel(CellDev cell, const ShellDev* __restrict__ shells,
                                                    int nshell, int64_t ngrid, double* __restrict__ Phi,
                                                    int64_t ld) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = flat_id();
   if (t >= ngrid * nshell) return;
   const int64_t R = t / nshell;
   const ShellDev sh = shells[t % nshell];
@@ -90,7 +101,7 @@ __global__ __launch_bounds__(256) void basis_kernel(CellDev cell, const ShellDev
 
 __global__ __launch_bounds__(256) void voronoi_kernel(CellDev cell, const double* __restrict__ atoms,
                                                      int natom, int64_t ngrid, int32_t* __restrict__ owner) {
-  const int64_t R = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t R = flat_id();
   if (R >= ngrid) return;
   double r[3];
   grid_point(cell, R, r);
@@ -115,24 +126,24 @@ __global__ __launch_bounds__(256) void voronoi_kernel(CellDev cell, const double
 
 __global__ void gather_kernel(const double* __restrict__ src, int64_t lds, const int64_t* __restrict__ idx,
                               int64_t nidx, int64_t nrows, int64_t ncols, double* __restrict__ dst, int64_t ldd) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = flat_id();
   if (t >= nrows * ncols) return;
   const int64_t r = t / ncols, c = t % ncols;
   dst[r * ldd + c] = (r < nidx) ? src[idx[r] * lds + c] : 0.0;
 }
 
 __global__ void add_diag_kernel(double* X, int64_t ld, int64_t i0, int64_t i1, double v) {
-  const int64_t i = i0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = i0 + flat_id();
   if (i < i1) X[i * ld + i] += v;
 }
 
 __global__ void fill_kernel(double* X, int64_t count, double v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = flat_id();
   if (i < count) X[i] = v;
 }
 
 __global__ void symmetrize_kernel(double* A, int64_t n, int64_t ld) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = flat_id();
   if (t >= n * n) return;
   const int64_t i = t / n, j = t % n;
   if (j >= i) return;
@@ -157,20 +168,20 @@ __global__ void transpose_kernel(const double* __restrict__ in, int64_t ldi, int
 }
 
 __global__ void unit_rows_kernel(double* X, int64_t ld, const int64_t* __restrict__ idx, int64_t n) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t g = flat_id();
   if (g < n) X[g * ld + idx[g]] = 1.0;
 }
 
 __global__ void gather_cols_kernel(const double* __restrict__ X, int64_t ldx, const int64_t* __restrict__ idx,
                                    int64_t n, double* __restrict__ Y, int64_t ldy) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = flat_id();
   if (t >= n * n) return;
   const int64_t r = t / n, c = t % n;
   Y[r * ldy + c] = X[r * ldx + idx[c]];
 }
 
 __global__ void to_f32_kernel(const double* __restrict__ X, int64_t count, float* __restrict__ Y) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = flat_id();
   if (i < count) Y[i] = (float)X[i];
 }
 
@@ -180,33 +191,33 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 hipError_t set_unit_rows(double* X, int64_t ld, const int64_t* idx, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(unit_rows_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, X, ld, idx, n);
+  hipLaunchKernelGGL(unit_rows_kernel, flat_grid(n), dim3(256), 0, s, X, ld, idx, n);
   return hipGetLastError();
 }
 
 hipError_t gather_cols(const double* X, int64_t ldx, const int64_t* idx, int64_t n, double* Y,
                        int64_t ldy, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gather_cols_kernel, dim3(nblk(n * n, 256)), dim3(256), 0, s, X, ldx, idx, n, Y, ldy);
+  hipLaunchKernelGGL(gather_cols_kernel, flat_grid(n * n), dim3(256), 0, s, X, ldx, idx, n, Y, ldy);
   return hipGetLastError();
 }
 
 hipError_t to_f32(const double* X, int64_t count, float* Y, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(to_f32_kernel, dim3(nblk(count, 256)), dim3(256), 0, s, X, count, Y);
+  hipLaunchKernelGGL(to_f32_kernel, flat_grid(count), dim3(256), 0, s, X, count, Y);
   return hipGetLastError();
 }
 
 hipError_t basis_eval(const CellDev& cell, const ShellDev* shells, int nshell, int64_t ngrid,
                       double* Phi, int64_t ldphi, hipStream_t s) {
-  hipLaunchKernelGGL(basis_kernel, dim3(nblk(ngrid * nshell, 256)), dim3(256), 0, s, cell, shells,
+  hipLaunchKernelGGL(basis_kernel, flat_grid(ngrid * nshell), dim3(256), 0, s, cell, shells,
                      nshell, ngrid, Phi, ldphi);
   return hipGetLastError();
 }
 
 hipError_t voronoi_assign(const CellDev& cell, const double* atoms, int natom, int64_t ngrid,
                           int32_t* owner, hipStream_t s) {
-  hipLaunchKernelGGL(voronoi_kernel, dim3(nblk(ngrid, 256)), dim3(256), 0, s, cell, atoms, natom,
+  hipLaunchKernelGGL(voronoi_kernel, flat_grid(ngrid), dim3(256), 0, s, cell, atoms, natom,
                      ngrid, owner);
   return hipGetLastError();
 }
@@ -214,25 +225,25 @@ hipError_t voronoi_assign(const CellDev& cell, const double* atoms, int natom, i
 hipError_t gather_rows(const double* src, int64_t lds, const int64_t* idx, int64_t nidx,
                        int64_t nrows, int64_t ncols, double* dst, int64_t ldd, hipStream_t s) {
   if (nrows * ncols == 0) return hipSuccess;
-  hipLaunchKernelGGL(gather_kernel, dim3(nblk(nrows * ncols, 256)), dim3(256), 0, s, src, lds, idx,
+  hipLaunchKernelGGL(gather_kernel, flat_grid(nrows * ncols), dim3(256), 0, s, src, lds, idx,
                      nidx, nrows, ncols, dst, ldd);
   return hipGetLastError();
 }
 
 hipError_t add_diag(double* X, int64_t ld, int64_t i0, int64_t i1, double v, hipStream_t s) {
   if (i1 <= i0) return hipSuccess;
-  hipLaunchKernelGGL(add_diag_kernel, dim3(nblk(i1 - i0, 256)), dim3(256), 0, s, X, ld, i0, i1, v);
+  hipLaunchKernelGGL(add_diag_kernel, flat_grid(i1 - i0), dim3(256), 0, s, X, ld, i0, i1, v);
   return hipGetLastError();
 }
 
 hipError_t fill(double* X, int64_t count, double v, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_kernel, dim3(nblk(count, 256)), dim3(256), 0, s, X, count, v);
+  hipLaunchKernelGGL(fill_kernel, flat_grid(count), dim3(256), 0, s, X, count, v);
   return hipGetLastError();
 }
 
 hipError_t symmetrize(double* A, int64_t n, int64_t ld, hipStream_t s) {
-  hipLaunchKernelGGL(symmetrize_kernel, dim3(nblk(n * n, 256)), dim3(256), 0, s, A, n, ld);
+  hipLaunchKernelGGL(symmetrize_kernel, flat_grid(n * n), dim3(256), 0, s, A, n, ld);
   return hipGetLastError();
 }
 
