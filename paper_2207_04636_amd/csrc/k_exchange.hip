@@ -77,16 +77,16 @@ __global__ __launch_bounds__(NW * 64) void fused_f64_kernel(FusedArgs a) {
 
   // V fragment of step t: lane holds V[g0 + 4r + lq][R0 + 16c + l16]
   double vnext[4][4];
-  auto step_coords = [&](int64_t t, int64_t& g0, int64_t& R0) {
-    const int64_t ri = t / nmy, si = t % nmy;
+  // coordinates of step (ri, si): R tile rt0 + ri, this wave's si-th g subtile
+  auto step_coords = [&](int64_t ri, int64_t si, int64_t& g0, int64_t& R0) {
     R0 = (rt0 + ri) * T;
     g0 = (gs0 + w + si * NW) * 16;
   };
   // U_g operands of step t: A operand of P, B operand of M1
   double ugAn[NI * 4], ugBn[4][NI];
-  auto load_v = [&](int64_t t) {
+  auto load_v = [&](int64_t ri, int64_t si) {
     int64_t g0, R0;
-    step_coords(t, g0, R0);
+    step_coords(ri, si, g0, R0);
     const double* base = a.Vm + (g0 + lq) * a.ldv + R0 + l16;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(NW * 64) void fused_f64_kernel(FusedArgs a) {
 #pragma unroll
       for (int j = 0; j < NI; ++j) ugBn[r][j] = ug[(4 * r + lq) * NP + 16 * j + l16];
   };
-  if (nstep > 0) load_v(0);
+  if (nstep > 0) load_v(0, 0);
 
   double e1 = 0.0;
   // K1 output tiles owned by this wave: m = w, w + NW, ...  (MTW of them)
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(NW * 64) void fused_f64_kernel(FusedArgs a) {
       for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int j = 0; j < NI; ++j) ugB[r][j] = ugBn[r][j];
-      if (t + 1 < nstep) load_v(t + 1);
+      if (t + 1 < nstep) load_v(si + 1 < nmy ? rt - rt0 : rt - rt0 + 1, si + 1 < nmy ? si + 1 : 0);
 
       // P[g][R] = sum_k U_g[g][k] U[R][k]
       d4_t p[4];
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(NW * 64) void fused_f64_kernel(FusedArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           av[r] = v[r][c] * p[c][r];
-          e1 += av[r] * p[c][r];
+          if (a.want_e) e1 += av[r] * p[c][r];
           slab[(4 * r + lq) * SLAB + 16 * c + l16] = av[r];
         }
 #pragma unroll
@@ -309,8 +309,7 @@ __global__ __launch_bounds__(NW * 64) void fused_m4_kernel(FusedArgs a) {
     for (int64_t e = tid; e < bg * NP; e += NW * 64) sM2[e] = 0.0;
 
   double vnext[4][4];
-  auto load_v = [&](int64_t t) {
-    const int64_t ri = t / nmy, si = t % nmy;
+  auto load_v = [&](int64_t ri, int64_t si) {
     const int64_t R0 = (rt0 + ri) * T, g0 = (gs0 + w + si * NW) * 16;
     const double* base = a.Vm + (g0 + lq) * a.ldv + R0 + l16;
 #pragma unroll
@@ -320,7 +319,7 @@ __global__ __launch_bounds__(NW * 64) void fused_m4_kernel(FusedArgs a) {
       for (int c = 0; c < 4; ++c) vnext[gq][c] = row[16 * c];
     }
   };
-  if (nstep > 0) load_v(0);
+  if (nstep > 0) load_v(0, 0);
 
   double e1 = 0.0;
   constexpr int MTW = (MT + NW - 1) / NW > 0 ? (MT + NW - 1) / NW : 1;
@@ -352,7 +351,7 @@ __global__ __launch_bounds__(NW * 64) void fused_m4_kernel(FusedArgs a) {
       for (int gq = 0; gq < 4; ++gq)
 #pragma unroll
         for (int c = 0; c < 4; ++c) v[gq][c] = vnext[gq][c];
-      if (t + 1 < nstep) load_v(t + 1);
+      if (t + 1 < nstep) load_v(si + 1 < nmy ? rt - rt0 : rt - rt0 + 1, si + 1 < nmy ? si + 1 : 0);
       const double* ugp = a.Ugp + g0 * NP;   // permuted U_g rows of this subtile
       double pA[4][4];                      // P A operand: U_g[g0 + 4gq + c4][4kk + lq] = ugp[.. + lq*4 + kk]
       double mB[4][4];                      // M1 B operand: U_g[g0 + 4gq + lq][4ich + c4] = ugp[.. + c4*4 + ich]
@@ -540,8 +539,7 @@ __global__ __launch_bounds__(NW * 64) void fused_f32_kernel(FusedArgs a) {
 
   // V fragment: lane holds V[g0 + 4lq + r][R0 + 16c + l16]; U_g operands of the step
   float vnext[4][4], ugAn[4], ugBn[4];
-  auto load_v = [&](int64_t t) {
-    const int64_t ri = t / nmy, si = t % nmy;
+  auto load_v = [&](int64_t ri, int64_t si) {
     const int64_t R0 = (rt0 + ri) * T, g0 = (gs0 + w + si * NW) * 16;
     const float* base = a.Vm32 + (g0 + 4 * lq) * a.ldv + R0 + l16;
 #pragma unroll
@@ -556,7 +554,7 @@ __global__ __launch_bounds__(NW * 64) void fused_f32_kernel(FusedArgs a) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) ugBn[r] = (float)ug[(4 * lq + r) * NP + l16];
   };
-  if (nstep > 0) load_v(0);
+  if (nstep > 0) load_v(0, 0);
 
   double e1 = 0.0;
   constexpr int MTW = (MT + NW - 1) / NW > 0 ? (MT + NW - 1) / NW : 1;
@@ -585,7 +583,7 @@ __global__ __launch_bounds__(NW * 64) void fused_f32_kernel(FusedArgs a) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) v[r][c] = vnext[r][c];
       }
-      if (t + 1 < nstep) load_v(t + 1);
+      if (t + 1 < nstep) load_v(si + 1 < nmy ? rt - rt0 : rt - rt0 + 1, si + 1 < nmy ? si + 1 : 0);
       // P[g0 + 4lq + r][R0 + 16c + l16]
       f4_t p[4];
 #pragma unroll
@@ -601,7 +599,7 @@ __global__ __launch_bounds__(NW * 64) void fused_f32_kernel(FusedArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           av[r] = v[r][c] * p[c][r];
-          e1 += (double)av[r] * (double)p[c][r];
+          if (a.want_e) e1 += (double)av[r] * (double)p[c][r];
           slab[(4 * lq + r) * SL + 16 * c + l16] = av[r];
         }
 #pragma unroll
@@ -691,57 +689,63 @@ __global__ __launch_bounds__(NW * 64) void fused_f32_kernel(FusedArgs a) {
 // of basis values up front (MT = Np/16 <= 8) so that the loads overlap.
 template <int NI, int MT>
 __global__ __launch_bounds__(256) void orbitals_kernel(const double* __restrict__ Phi, int64_t R,
-                                                      const double* __restrict__ Phig, int64_t G, int Np,
+                                                      const double* __restrict__ Phig, int64_t G, int /*Np*/,
                                                       const double* __restrict__ C, int N, int n,
                                                       double* __restrict__ U, double* __restrict__ Ug,
                                                       double* __restrict__ Ugp) {
   constexpr int NP = 16 * NI;
-  constexpr int PB = 16 * (MT * 16 + 1);      // one wave's staged block, padded rows
+  constexpr int NPK = 16 * MT;                 // padded N (the Np argument equals it)
   extern __shared__ double lds[];
   double* sC = lds;                            // [Np][NP]
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
-  double* sB = lds + Np * NP + w * PB;         // this wave's 16 x Np block, pitch Np + 1
-  const int ldb = MT * 16 + 1;
-  for (int e = tid; e < Np * NP; e += 256) {
+  constexpr int ldb = NPK + 1;
+  double* sB = lds + NPK * NP + w * 16 * ldb;  // this wave's 16 x Np block, pitch Np + 1
+  for (int e = tid; e < NPK * NP; e += 256) {
     const int r = e / NP, c = e % NP;
     sC[e] = (r < N && c < n) ? C[(int64_t)r * n + c] : 0.0;
   }
   __syncthreads();
   const int64_t nsub = (R + G) / 16;
-  const int nvec = 16 * Np / 2;                // 16-byte pieces of a 16-row block
-  for (int64_t sidx = (int64_t)blockIdx.x * 4 + w; sidx < nsub; sidx += (int64_t)gridDim.x * 4) {
+  constexpr int nvec = 16 * NPK / 2;           // 16-byte pieces of a 16-row block
+  constexpr int NQ = (nvec + 63) / 64;
+  // the 16 rows of a subtile are contiguous in memory (16*Np doubles); the
+  // next subtile's rows are loaded while the current one is multiplied
+  double2 buf[NQ];
+  auto fetch = [&](int64_t sidx) {
     const int64_t row0 = sidx * 16;
-    const double* src = (row0 < R) ? Phi + row0 * Np : Phig + (row0 - R) * Np;
-    double* dst = (row0 < R) ? U + row0 * NP : Ug + (row0 - R) * NP;
-    // the 16 rows are contiguous in memory: 16*Np doubles
+    const double* src = (row0 < R) ? Phi + row0 * NPK : Phig + (row0 - R) * NPK;
     const double2* src2 = reinterpret_cast<const double2*>(src);
-    double2 buf[(16 * MT * 16 / 2 + 63) / 64];
 #pragma unroll
-    for (int q = 0; q < (16 * MT * 16 / 2 + 63) / 64; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int v = q * 64 + lane;
       if (v < nvec) buf[q] = src2[v];
     }
+  };
+  const int64_t sfirst = (int64_t)blockIdx.x * 4 + w, sstep = (int64_t)gridDim.x * 4;
+  if (sfirst < nsub) fetch(sfirst);
+  for (int64_t sidx = sfirst; sidx < nsub; sidx += sstep) {
+    const int64_t row0 = sidx * 16;
+    double* dst = (row0 < R) ? U + row0 * NP : Ug + (row0 - R) * NP;
 #pragma unroll
-    for (int q = 0; q < (16 * MT * 16 / 2 + 63) / 64; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int v = q * 64 + lane;
       if (v < nvec) {
-        const int e = 2 * v, r = e / Np, c = e % Np;
+        const int e = 2 * v, r = e / NPK, c = e % NPK;
         sB[r * ldb + c] = buf[q].x;
         sB[r * ldb + c + 1] = buf[q].y;
       }
     }
+    if (sidx + sstep < nsub) fetch(sidx + sstep);
     __builtin_amdgcn_wave_barrier();
     d4_t acc[NI];
 #pragma unroll
     for (int j = 0; j < NI; ++j) acc[j] = zero_d4();
 #pragma unroll
     for (int kk = 0; kk < MT * 4; ++kk) {
-      if (4 * kk < Np) {
-        const double x = sB[l16 * ldb + 4 * kk + lq];
+      const double x = sB[l16 * ldb + 4 * kk + lq];
 #pragma unroll
-        for (int j = 0; j < NI; ++j) acc[j] = mfma_f64(x, sC[(4 * kk + lq) * NP + 16 * j + l16], acc[j]);
-      }
+      for (int j = 0; j < NI; ++j) acc[j] = mfma_f64(x, sC[(4 * kk + lq) * NP + 16 * j + l16], acc[j]);
     }
     __builtin_amdgcn_wave_barrier();
     double* out = dst + lq * NP + l16;
@@ -809,7 +813,8 @@ __global__ __launch_bounds__(512) void finalize_kernel(const double* __restrict_
                                                       int np, int Np, double s1, double s2, double s3, double dV,
                                                       double* __restrict__ K, const double* __restrict__ e1p,
                                                       int64_t ne1, const double* __restrict__ e3p, int64_t ne3,
-                                                      double ce1, double ce3, double* __restrict__ ex) {
+                                                      double ce1, double ce3, double* __restrict__ ex,
+                                                      EnergyDots dots) {
   __shared__ double red[8][64][4];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
@@ -819,6 +824,8 @@ __global__ __launch_bounds__(512) void finalize_kernel(const double* __restrict_
     double sa = 0.0, sb = 0.0;
     for (int64_t p = tid; p < ne1; p += 512) sa += e1p[p];
     for (int64_t p = tid; p < ne3; p += 512) sb += e3p[p];
+    for (int64_t p = tid; p < dots.n1; p += 512) sa += dots.x1[p] * dots.y1[p];
+    for (int64_t p = tid; p < dots.n3; p += 512) sb += dots.x3[p] * dots.y3[p];
     double* r1 = &red[0][0][0];
     r1[tid] = ce1 * sa + ce3 * sb;
     __syncthreads();
@@ -875,23 +882,6 @@ __global__ void pack_kernel(const double* __restrict__ C, int64_t rows, int64_t 
   if (t >= rows_p * ldp) return;
   const int64_t r = t / ldp, c = t % ldp;
   Cp[t] = (r < rows && c < cols) ? C[r * ldc + c] : 0.0;
-}
-
-// Partial dot products: out[b] = sum of x[i] y[i] over the block's range (tree).
-__global__ __launch_bounds__(256) void dot_partials_kernel(const double* __restrict__ x, const double* __restrict__ y,
-                                                          int64_t n, int64_t per, double* __restrict__ out) {
-  __shared__ double red[256];
-  const int64_t b0 = (int64_t)blockIdx.x * per;
-  const int64_t b1 = (b0 + per < n) ? b0 + per : n;
-  double s = 0.0;
-  for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) s += x[i] * y[i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -1029,10 +1019,9 @@ hipError_t orbitals(const double* Phi, int64_t R, const double* Phig, int64_t G,
                     int N, int n, int np, double* U, double* Ug, double* Ugp, hipStream_t s) {
   if (R % 16 != 0 || G % 16 != 0 || Np % 16 != 0 || np % 16 != 0 || Np > 128) return hipErrorInvalidValue;
   const int64_t nsub = (R + G) / 16;
-  const unsigned blocks = (unsigned)std::min<int64_t>((nsub + 3) / 4, 4096);
+  const unsigned blocks = (unsigned)std::min<int64_t>((nsub + 3) / 4, 512);   // two workgroups per CU
   const int mt = Np / 16;
-  const int mtc = (mt <= 2) ? 2 : (mt <= 4) ? 4 : 8;
-  const size_t lds = (size_t)Np * np * 8 + (size_t)4 * 16 * (mtc * 16 + 1) * 8;
+  const size_t lds = (size_t)Np * np * 8 + (size_t)4 * 16 * (Np + 1) * 8;
 #define RPS_ORB(NI_, MT_)                                                                                   \
   do {                                                                                                       \
     hipError_t e_ = hipFuncSetAttribute((const void*)orbitals_kernel<NI_, MT_>,                              \
@@ -1041,8 +1030,14 @@ hipError_t orbitals(const double* Phi, int64_t R, const double* Phig, int64_t G,
     hipLaunchKernelGGL((orbitals_kernel<NI_, MT_>), dim3(blocks), dim3(256), lds, s, Phi, R, Phig, G, Np, C, \
                        N, n, U, Ug, Ugp);                                                                    \
   } while (0)
-#define RPS_ORB_NI(NI_) \
-  do { if (mt <= 2) RPS_ORB(NI_, 2); else if (mt <= 4) RPS_ORB(NI_, 4); else RPS_ORB(NI_, 8); } while (0)
+#define RPS_ORB_NI(NI_)                                                                                     \
+  do {                                                                                                       \
+    switch (mt) {                                                                                            \
+      case 1: RPS_ORB(NI_, 1); break; case 2: RPS_ORB(NI_, 2); break; case 3: RPS_ORB(NI_, 3); break;        \
+      case 4: RPS_ORB(NI_, 4); break; case 5: RPS_ORB(NI_, 5); break; case 6: RPS_ORB(NI_, 6); break;        \
+      case 7: RPS_ORB(NI_, 7); break; default: RPS_ORB(NI_, 8); break;                                       \
+    }                                                                                                        \
+  } while (0)
   switch (np / 16) {
     case 1: RPS_ORB_NI(1); break;
     case 2: RPS_ORB_NI(2); break;
@@ -1057,10 +1052,11 @@ hipError_t orbitals(const double* Phi, int64_t R, const double* Phig, int64_t G,
 
 hipError_t finalize(const double* Phig, const double* M2, int64_t G, const double* K1, const double* K3, int N,
                     int n, int np, int Np, double s1, double s2, double s3, double dV, double* K, const double* e1p,
-                    int64_t ne1, const double* e3p, int64_t ne3, double ce1, double ce3, double* ex, hipStream_t s) {
+                    int64_t ne1, const double* e3p, int64_t ne3, double ce1, double ce3, double* ex, hipStream_t s,
+                    const EnergyDots& dots) {
   const int ntile = (Np / 16) * (np / 16);
   hipLaunchKernelGGL(finalize_kernel, dim3(ntile + 1), dim3(512), 0, s, Phig, M2, G, K1, K3, N, n, np, Np, s1, s2,
-                     s3, dV, K, e1p, ne1, e3p, ne3, ce1, ce3, ex);
+                     s3, dV, K, e1p, ne1, e3p, ne3, ce1, ce3, ex, dots);
   return hipGetLastError();
 }
 
@@ -1069,15 +1065,6 @@ hipError_t pack_matrix(const double* C, int64_t rows, int64_t cols, int64_t ldc,
   hipLaunchKernelGGL(pack_kernel, dim3(nblk(rows_p * ldp, 256)), dim3(256), 0, s, C, rows, cols, ldc, Cp, rows_p,
                      ldp);
   return hipGetLastError();
-}
-
-int dot_partials(const double* x, const double* y, int64_t n, double* out, int max_parts, hipStream_t s) {
-  int64_t parts = (n + 16383) / 16384;
-  if (parts > max_parts) parts = max_parts;
-  if (parts < 1) parts = 1;
-  const int64_t per = (n + parts - 1) / parts;
-  hipLaunchKernelGGL(dot_partials_kernel, dim3((unsigned)parts), dim3(256), 0, s, x, y, n, per, out);
-  return (hipGetLastError() == hipSuccess) ? (int)parts : -1;
 }
 
 }  // namespace rps

@@ -88,13 +88,34 @@ struct rps_context {
   // general path workspace
   int gws_np = -1;
   int64_t gchunk = 0;
-  DBuf<double> gCp, gU, gUg, gA, gSp, gM2, gM1T, gK1, gK3, gY, gwork, ge;
+  DBuf<double> gCp, gU, gUg, gA, gSp, gM2, gM1T, gK1, gK3, gY, gwork;
   int64_t rblocks_main = 0, blocks_main = 0, blocks_l3 = 0;
   int rtiles = 4, gblocks = 1, nwaves = 4;
   // autotuned launch parameters (0: built-in default)
   int tune_target = 0;                      // streaming form: workgroups aimed at per launch
   int tune_rtiles = 0, tune_gblocks = 0;    // fused kernel: R tiles per workgroup, g blocks
   double tune_ms = 0.0;                     // best build time the tuner measured
+  // replay of repeated device-pointer builds as a captured HIP graph
+  struct GraphEntry {
+    int variant, nocc;
+    const double* C;
+    double* K;
+    double* ex;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  GraphEntry last_call{-1, 0, nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipStream_t gstream = nullptr, gbranch = nullptr;   // capture stream and the line-3 branch
+  hipEvent_t gfork = nullptr, gjoin = nullptr;
+  void clear_graphs() {
+    for (auto& e : graphs) {
+      (void)hipGraphExecDestroy(e.exec);
+      (void)hipGraphDestroy(e.graph);
+    }
+    graphs.clear();
+    last_call.variant = -1;
+  }
   // profiling: event triples (build start, main start, main end, l3 start, l3 end, build end)
   int profiling = 0;
   std::vector<hipEvent_t> ev_pool;
@@ -105,11 +126,16 @@ struct rps_context {
     DBuf<double>* all[] = {&Phi, &Phig, &V, &W, &U, &Ug, &Ugp, &M2p, &K1p, &K3p, &e1p,
                            &e3p, &M2, &K1, &K3, &Kdev, &Cdev, &exdev};
     for (auto* b : all) b->release(nullptr);
-    DBuf<double>* gen[] = {&gCp, &gU, &gUg, &gA, &gSp, &gM2, &gM1T, &gK1, &gK3, &gY, &gwork, &ge};
+    DBuf<double>* gen[] = {&gCp, &gU, &gUg, &gA, &gSp, &gM2, &gM1T, &gK1, &gK3, &gY, &gwork};
     for (auto* b : gen) b->release(nullptr);
     V32.release(nullptr);
     dpoints.release(nullptr);
     for (auto e : ev_pool) (void)hipEventDestroy(e);
+    clear_graphs();
+    if (gfork) (void)hipEventDestroy(gfork);
+    if (gjoin) (void)hipEventDestroy(gjoin);
+    if (gstream) (void)hipStreamDestroy(gstream);
+    if (gbranch) (void)hipStreamDestroy(gbranch);
   }
 };
 
@@ -128,6 +154,11 @@ struct StageLog {
     fflush(stderr);
   }
 };
+constexpr int64_t kSplitWork = 64ll << 20;   // doubles of split-K partials (512 MB)
+constexpr int kStreamMaxNp = 128;             // largest padded n of the streaming form
+constexpr int kStreamBlocks = 512;            // workgroups aimed at per streaming launch (default)
+constexpr int kStreamMaxTarget = 1024;        // largest target the tuner tries
+constexpr int64_t kStreamPartRows = (int64_t)kStreamMaxTarget * 128;   // rows of split partials
 constexpr double kCutoff = 50.0;
 constexpr double kCholShift = 1e-13;
 constexpr int kOversample = 4;
@@ -558,6 +589,7 @@ void choose_shape(rps_context& c, int np, FusedArgs& a) {
 
 void ensure_workspace(rps_context& c, int np) {
   if (c.ws_np == np) return;
+  c.clear_graphs();          // captured builds refer to the buffers about to change
   int64_t* cnt = &c.bytes;
   FusedArgs a{};
   a.R_valid = c.ng;
@@ -594,15 +626,10 @@ void ensure_workspace(rps_context& c, int np) {
 //   M1^T += A_c^T U_g[c]
 // then K1 = Phi^T M1^T, K2 = Phi_g^T M2, B = W o (U_g U_g^T), Y = B U_g,
 // K3 = Phi_g^T Y, e1 = tr(U_g^T M2), e3 = tr(U_g^T Y)  (Eq. 16).
-constexpr int64_t kSplitWork = 64ll << 20;   // doubles of split-K partials (512 MB)
-constexpr int kEnergyParts = 256;
-constexpr int kStreamMaxNp = 128;             // largest padded n of the streaming form
-constexpr int kStreamBlocks = 512;            // workgroups aimed at per streaming launch (default)
-constexpr int kStreamMaxTarget = 1024;        // largest target the tuner tries
-constexpr int64_t kStreamPartRows = (int64_t)kStreamMaxTarget * 128;   // rows of split partials
 
 void ensure_general(rps_context& c, int np) {
   if (c.gws_np == np) return;
+  c.clear_graphs();
   int64_t* cnt = &c.bytes;
   const int64_t budget = 2000000000ll / 8;     // A chunk: about 2 GB
   int64_t gc = std::max<int64_t>(64, budget / c.ngp / 64 * 64);
@@ -624,7 +651,6 @@ void ensure_general(rps_context& c, int np) {
   c.gK3.alloc(c.Np * np, cnt);
   c.gY.alloc(c.nauxp * np, cnt);
   c.gwork.alloc(kSplitWork, cnt);
-  c.ge.alloc(2 * kEnergyParts, cnt);
   c.Cdev.alloc(c.nbas * np, cnt);
   c.Kdev.alloc(c.nbas * np, cnt);
   c.exdev.alloc(1, cnt);
@@ -654,7 +680,6 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
   const bool need_main = (variant != RPS_VARIANT_THC);
   const bool need_l3 = (variant != RPS_VARIANT_PS);
   const bool k1 = need_main && variant == RPS_VARIANT_RPS;
-  int ne1 = 0, ne3 = 0;
   const bool stream = c.gSp.p != nullptr && np <= kStreamMaxNp;
   if (stream) {
     // streaming form: O never materialises A = V o P (see k_stream.hip)
@@ -683,8 +708,6 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
         g.A = c.Phi.p; g.lda = c.Np; g.transA = true; g.B = c.gM1T.p; g.ldb = np; g.C = c.gK1.p; g.ldc = np;
         gemm_run(g, c, st, "K1", true);
       }
-      ne1 = dot_partials(c.gUg.p, c.gM2.p, c.nauxp * np, c.ge.p, kEnergyParts, st);
-      if (ne1 < 0) fail(RPS_ERR_DEVICE, "energy partials");
     }
     if (need_l3) {
       prof_mark(c, 3, st);
@@ -700,8 +723,6 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
       k3.M = c.Np; k3.N = np; k3.K = c.nauxp;
       k3.A = c.Phig.p; k3.lda = c.Np; k3.transA = true; k3.B = c.gY.p; k3.ldb = np; k3.C = c.gK3.p; k3.ldc = np;
       gemm_run(k3, c, st, "K3", true);
-      ne3 = dot_partials(c.gUg.p, c.gY.p, c.nauxp * np, c.ge.p + kEnergyParts, kEnergyParts, st);
-      if (ne3 < 0) fail(RPS_ERR_DEVICE, "energy partials");
       prof_mark(c, 4, st);
     }
   } else if (need_main) {
@@ -734,8 +755,6 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
       g.A = c.Phi.p; g.lda = c.Np; g.transA = true; g.B = c.gM1T.p; g.ldb = np; g.C = c.gK1.p; g.ldc = np;
       gemm_run(g, c, st, "K1", true);
     }
-    ne1 = dot_partials(c.gUg.p, c.gM2.p, c.nauxp * np, c.ge.p, kEnergyParts, st);
-    if (ne1 < 0) fail(RPS_ERR_DEVICE, "energy partials");
   }
   if (need_l3 && !stream) {
     prof_mark(c, 3, st);
@@ -752,13 +771,15 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
     k3.M = c.Np; k3.N = np; k3.K = c.nauxp;
     k3.A = c.Phig.p; k3.lda = c.Np; k3.transA = true; k3.B = c.gY.p; k3.ldb = np; k3.C = c.gK3.p; k3.ldc = np;
     gemm_run(k3, c, st, "K3", true);
-    ne3 = dot_partials(c.gUg.p, c.gY.p, c.nauxp * np, c.ge.p + kEnergyParts, kEnergyParts, st);
-    if (ne3 < 0) fail(RPS_ERR_DEVICE, "energy partials");
     prof_mark(c, 4, st);
   }
+  // e1 = tr(U_g^T M2), e3 = tr(U_g^T Y), formed by the finalize kernel
+  EnergyDots dots;
+  if (need_main) { dots.x1 = c.gUg.p; dots.y1 = c.gM2.p; dots.n1 = c.nauxp * np; }
+  if (need_l3) { dots.x3 = c.gUg.p; dots.y3 = c.gY.p; dots.n3 = c.nauxp * np; }
   hip_check(finalize(c.Phig.p, need_main ? c.gM2.p : nullptr, c.nauxp, k1 ? c.gK1.p : nullptr,
                      need_l3 ? c.gK3.p : nullptr, (int)c.nbas, nocc, np, (int)c.Np, s1, s2, s3, c.dV, Kout,
-                     c.ge.p, ne1, c.ge.p + kEnergyParts, ne3, ce1, ce3, exout, st),
+                     nullptr, 0, nullptr, 0, ce1, ce3, exout, st, dots),
             "finalize");
 }
 
@@ -771,19 +792,15 @@ bool uses_general(const rps_context& c, int np) {
 }
 
 // variant coefficients: K = dV (s1 K1 + s2 K2 + s3 K3), E = -dV (ce1 e1 + ce3 e3)
-void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, double* K, double* ex,
-                int32_t flags, hipStream_t st) {
-  if (c.ng == 0) fail(RPS_ERR_STATE, "context has no completed set-up");
-  if (nocc < 1) fail(RPS_ERR_ARG, "nocc must be >= 1");
-  if (!C || !K) fail(RPS_ERR_ARG, "C and K must not be NULL");
-  if (flags != RPS_PTRS_HOST && flags != RPS_PTRS_DEVICE) fail(RPS_ERR_ARG, "flags must be RPS_PTRS_HOST or RPS_PTRS_DEVICE");
-  if (variant < RPS_VARIANT_RPS || variant > RPS_VARIANT_THC) fail(RPS_ERR_ARG, "unknown variant");
+// Enqueue one build on st.  With st3 != NULL (graph capture only) the fit-fit
+// kernel of the fused path runs on st3, beside the V-streaming kernel.
+void enqueue_build(rps_context& c, int variant, int32_t nocc, const double* C, double* K, double* ex, bool dev,
+                   hipStream_t st, hipStream_t st3) {
   const int np = (int)round_up(nocc, 16);
   const bool general = uses_general(c, np);
   double s1 = 1, s2 = 1, s3 = -1, ce1 = 2, ce3 = -1;
   if (variant == RPS_VARIANT_PS) { s1 = 0; s2 = 1; s3 = 0; ce1 = 1; ce3 = 0; }
   if (variant == RPS_VARIANT_THC) { s1 = 0; s2 = 0; s3 = 1; ce1 = 0; ce3 = 1; }
-  const bool dev = (flags == RPS_PTRS_DEVICE);
   c.last_stream = st;
   if (general) ensure_general(c, np); else ensure_workspace(c, np);
   prof_mark(c, 0, st);
@@ -822,6 +839,7 @@ void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, doub
     a.G = c.nauxp; a.R = c.ngp; a.R_valid = c.ng; a.np = np; a.Np = (int)c.Np;
     a.rtiles = c.rtiles; a.gblocks = c.gblocks; a.nwaves = c.nwaves;
     a.want_m2 = 1; a.want_k1 = (variant == RPS_VARIANT_RPS) ? 1 : 0; a.want_m1 = 0;
+    a.want_e = m4 ? 1 : 0;     // sum A o P = tr(U_g^T M2) is formed after the M2 reduction instead
     a.prec = c.precision;
     a.Vm32 = (c.precision != RPS_PREC_FP64) ? c.V32.p : nullptr;
     a.Ugp = m4 ? c.Ugp.p : nullptr; a.use_m4 = m4 ? c.use_m4 : 0;
@@ -830,17 +848,27 @@ void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, doub
     hip_check(fused_exchange(a, st), "fused main");
     prof_mark(c, 2, st);
   }
+  hipStream_t sl3 = st;
+  if (need_l3 && st3) {      // fork after the orbitals: line 3 needs only U_g
+    hip_check(hipEventRecord(c.gfork, st), "fork");
+    hip_check(hipStreamWaitEvent(st3, c.gfork, 0), "fork wait");
+    sl3 = st3;
+  }
   if (need_l3) {
     FusedArgs a{};
     a.Vm = c.W.p; a.ldv = c.nauxp; a.Ug = c.Ug.p; a.Ur = c.Ug.p; a.Phir = c.Phig.p;
     a.G = c.nauxp; a.R = c.nauxp; a.R_valid = c.naux; a.np = np; a.Np = (int)c.Np;
     a.rtiles = 1; a.gblocks = (int)(c.nauxp / 64); a.nwaves = 4;
-    a.want_m2 = 0; a.want_k1 = 1; a.want_m1 = 0; a.prec = RPS_PREC_FP64;
+    a.want_m2 = 0; a.want_k1 = 1; a.want_m1 = 0; a.want_e = 1; a.prec = RPS_PREC_FP64;
     a.Ugp = m4 ? c.Ugp.p : nullptr; a.use_m4 = m4 ? c.use_m4 : 0;
     a.K1p = c.K3p.p; a.e1p = c.e3p.p;
-    prof_mark(c, 3, st);
-    hip_check(fused_exchange(a, st), "fused line 3");
-    prof_mark(c, 4, st);
+    prof_mark(c, 3, sl3);
+    hip_check(fused_exchange(a, sl3), "fused line 3");
+    prof_mark(c, 4, sl3);
+  }
+  if (sl3 != st) {
+    hip_check(hipEventRecord(c.gjoin, sl3), "join");
+    hip_check(hipStreamWaitEvent(st, c.gjoin, 0), "join wait");
   }
   double* Kout = dev ? K : c.Kdev.p;
   double* exout = dev ? ex : (ex ? c.exdev.p : nullptr);
@@ -849,10 +877,15 @@ void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, doub
                           need_main ? c.M2p.p : nullptr, c.rblocks_main, c.nauxp * np, c.M2.p,
                           need_l3 ? c.K3p.p : nullptr, c.blocks_l3, c.Np * np, c.K3.p, st),
             "partial sums");
+  int64_t ne1 = need_main ? c.blocks_main : 0;
+  EnergyDots dots;
+  if (need_main && !m4) {      // sum A o P = tr(U_g^T M2), formed by the finalize kernel
+    ne1 = 0;
+    dots.x1 = c.Ug.p; dots.y1 = c.M2.p; dots.n1 = c.nauxp * np;
+  }
   hip_check(finalize(c.Phig.p, need_main ? c.M2.p : nullptr, c.nauxp, k1 ? c.K1.p : nullptr,
                      need_l3 ? c.K3.p : nullptr, (int)c.nbas, nocc, np, (int)c.Np, s1, s2, s3, c.dV, Kout,
-                     c.e1p.p, need_main ? c.blocks_main : 0, c.e3p.p, need_l3 ? c.blocks_l3 : 0, ce1, ce3, exout,
-                     st),
+                     c.e1p.p, ne1, c.e3p.p, need_l3 ? c.blocks_l3 : 0, ce1, ce3, exout, st, dots),
             "finalize");
   prof_mark(c, 5, st);
   if (c.profiling && c.ev_used < kMaxProfiled) {
@@ -867,16 +900,83 @@ void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, doub
   }
 }
 
+bool graphs_enabled() {
+  static const bool on = getenv("RPS_NO_GRAPH") == nullptr;
+  return on;
+}
+
+// One exchange build.  A device-pointer build repeated with the same
+// arguments is captured into a HIP graph on its second call (the fit-fit
+// kernel on a parallel branch) and replayed from then on; host-pointer
+// builds, profiled builds and builds inside a batch capture run eagerly.
+void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, double* K, double* ex,
+                int32_t flags, hipStream_t st, bool allow_graph = true) {
+  if (c.ng == 0) fail(RPS_ERR_STATE, "context has no completed set-up");
+  if (nocc < 1) fail(RPS_ERR_ARG, "nocc must be >= 1");
+  if (!C || !K) fail(RPS_ERR_ARG, "C and K must not be NULL");
+  if (flags != RPS_PTRS_HOST && flags != RPS_PTRS_DEVICE) fail(RPS_ERR_ARG, "flags must be RPS_PTRS_HOST or RPS_PTRS_DEVICE");
+  if (variant < RPS_VARIANT_RPS || variant > RPS_VARIANT_THC) fail(RPS_ERR_ARG, "unknown variant");
+  const bool dev = (flags == RPS_PTRS_DEVICE);
+  if (!(dev && allow_graph && !c.profiling && graphs_enabled())) {
+    enqueue_build(c, variant, nocc, C, K, ex, dev, st, nullptr);
+    return;
+  }
+  auto same = [&](const rps_context::GraphEntry& e) {
+    return e.variant == variant && e.nocc == nocc && e.C == C && e.K == K && e.ex == ex;
+  };
+  for (auto& e : c.graphs)
+    if (same(e)) {
+      hip_check(hipGraphLaunch(e.exec, st), "hipGraphLaunch");
+      c.last_stream = st;
+      return;
+    }
+  if (!same(c.last_call)) {
+    // first sight of these arguments: eager (also sizes every workspace)
+    enqueue_build(c, variant, nocc, C, K, ex, dev, st, nullptr);
+    c.last_call = rps_context::GraphEntry{variant, nocc, C, K, ex, nullptr, nullptr};
+    return;
+  }
+  if (!c.gstream) {
+    hip_check(hipStreamCreateWithFlags(&c.gstream, hipStreamNonBlocking), "hipStreamCreate");
+    hip_check(hipStreamCreateWithFlags(&c.gbranch, hipStreamNonBlocking), "hipStreamCreate");
+    hip_check(hipEventCreateWithFlags(&c.gfork, hipEventDisableTiming), "hipEventCreate");
+    hip_check(hipEventCreateWithFlags(&c.gjoin, hipEventDisableTiming), "hipEventCreate");
+  }
+  // workspaces must exist before the capture (no allocation inside it)
+  const int np = (int)round_up(nocc, 16);
+  if (uses_general(c, np)) ensure_general(c, np); else ensure_workspace(c, np);
+  rps_context::GraphEntry e{variant, nocc, C, K, ex, nullptr, nullptr};
+  hip_check(hipStreamBeginCapture(c.gstream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+  try {
+    enqueue_build(c, variant, nocc, C, K, ex, dev, c.gstream, c.gbranch);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(c.gstream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  hip_check(hipStreamEndCapture(c.gstream, &e.graph), "hipStreamEndCapture");
+  hip_check(hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  if (c.graphs.size() >= 4) {
+    (void)hipGraphExecDestroy(c.graphs.front().exec);
+    (void)hipGraphDestroy(c.graphs.front().graph);
+    c.graphs.erase(c.graphs.begin());
+  }
+  c.graphs.push_back(e);
+  hip_check(hipGraphLaunch(e.exec, st), "hipGraphLaunch");
+  c.last_stream = st;
+}
+
 // ------------------------------------------------------------------ autotuner
 // Mean time of `reps` device-pointer builds after one warm-up build (which
 // also allocates any workspace the launch shape needs).
 double time_builds(rps_context& c, int32_t nocc, const double* C, double* K, double* ex, hipStream_t st, int reps) {
-  build_impl(c, RPS_VARIANT_RPS, nocc, C, K, ex, RPS_PTRS_DEVICE, st);
+  build_impl(c, RPS_VARIANT_RPS, nocc, C, K, ex, RPS_PTRS_DEVICE, st, false);
   hipEvent_t e0, e1;
   hip_check(hipEventCreate(&e0), "hipEventCreate");
   hip_check(hipEventCreate(&e1), "hipEventCreate");
   hip_check(hipEventRecord(e0, st), "hipEventRecord");
-  for (int r = 0; r < reps; ++r) build_impl(c, RPS_VARIANT_RPS, nocc, C, K, ex, RPS_PTRS_DEVICE, st);
+  for (int r = 0; r < reps; ++r) build_impl(c, RPS_VARIANT_RPS, nocc, C, K, ex, RPS_PTRS_DEVICE, st, false);
   hip_check(hipEventRecord(e1, st), "hipEventRecord");
   hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
   float ms = 0.f;
@@ -928,7 +1028,7 @@ void autotune(rps_context& c, int32_t nocc, const double* C, double* K, double* 
   c.tune_gblocks = bc.gblocks;
   c.tune_ms = best;
   c.ws_np = -1;
-  build_impl(c, RPS_VARIANT_RPS, nocc, C, K, ex, RPS_PTRS_DEVICE, st);
+  build_impl(c, RPS_VARIANT_RPS, nocc, C, K, ex, RPS_PTRS_DEVICE, st, false);
   hip_check(hipStreamSynchronize(st), "sync");
   c.profiling = saved_prof;
 }
@@ -1027,7 +1127,7 @@ void capture_batch(rps_batch& b, int nbranch, hipStream_t origin) {
     for (int k = 0; k < nbranch; ++k) hip_check(hipStreamWaitEvent(b.streams[k], b.events[nbranch], 0), "fork wait");
     for (int i : order)
       build_impl(*b.ctx[i], RPS_VARIANT_RPS, b.nocc[i], b.C[i], b.K[i], b.ex ? b.ex + i : nullptr, RPS_PTRS_DEVICE,
-                 b.streams[assign[i]]);
+                 b.streams[assign[i]], false);
     for (int k = 0; k < nbranch; ++k) {
       hip_check(hipEventRecord(b.events[k], b.streams[k]), "join");
       hip_check(hipStreamWaitEvent(origin, b.events[k], 0), "join wait");
@@ -1158,7 +1258,7 @@ rps_status rps_batch_create(rps_context* const* ctx, int32_t nbatch, const int32
       if (flags & RPS_BATCH_AUTOTUNE)
         autotune(*ctx[i], nocc[i], C[i], K[i], ex ? ex + i : nullptr, st);
       else   // one eager build: allocates every workspace before capture
-        build_impl(*ctx[i], RPS_VARIANT_RPS, nocc[i], C[i], K[i], ex ? ex + i : nullptr, RPS_PTRS_DEVICE, st);
+        build_impl(*ctx[i], RPS_VARIANT_RPS, nocc[i], C[i], K[i], ex ? ex + i : nullptr, RPS_PTRS_DEVICE, st, false);
     }
     hip_check(hipStreamSynchronize(st), "sync");
     hip_check(hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking), "hipStreamCreate");

@@ -110,6 +110,7 @@ struct FusedArgs {
   int want_m2;              // write M2 partials
   int want_k1;              // accumulate K1 partials (Phir^T (A^T Ug))
   int want_m1;              // write M1^T = A^T Ug rows (when K1 is not fused)
+  int want_e;               // accumulate sum A o P into e1p (else the caller forms it from M2)
   int prec;                 // rps_precision
   // outputs
   double* M2p;              // [rblocks][G][np]
@@ -128,18 +129,23 @@ hipError_t orbitals(const double* Phi, int64_t R, const double* Phig, int64_t G,
 // Cp [rows_p x ldp] = C [rows x cols] zero padded.
 hipError_t pack_matrix(const double* C, int64_t rows, int64_t cols, int64_t ldc, double* Cp, int64_t rows_p,
                        int64_t ldp, hipStream_t s);
-// out[0..parts) = partial sums of x . y (fixed order); returns parts (<= max_parts), -1 on error.
-int dot_partials(const double* x, const double* y, int64_t n, double* out, int max_parts, hipStream_t s);
 // Up to three partial sums in one launch: out_k[i] = sum_p in_k[p*count_k + i]
 // (fixed order); a segment with a NULL input is skipped.
 hipError_t sum_partials3(const double* in0, int64_t n0, int64_t c0, double* o0, const double* in1, int64_t n1,
                          int64_t c1, double* o1, const double* in2, int64_t n2, int64_t c2, double* o2,
                          hipStream_t s);
+// Energy terms given as dot products: e1 += x1 . y1 (n1 terms), e3 += x3 . y3.
+struct EnergyDots {
+  const double* x1 = nullptr; const double* y1 = nullptr; int64_t n1 = 0;
+  const double* x3 = nullptr; const double* y3 = nullptr; int64_t n3 = 0;
+};
 // K[mu][i] = dV (s1 K1 + s2 Phi_g^T M2 + s3 K3) for mu < N, i < n ([Np][np] arrays,
-// any may be NULL); ex = -dV (ce1 sum e1p + ce3 sum e3p) if ex is not NULL.
+// any may be NULL); ex = -dV (ce1 e1 + ce3 e3) if ex is not NULL, with
+// e1 = sum e1p + x1 . y1 and e3 = sum e3p + x3 . y3 (fixed summation order).
 hipError_t finalize(const double* Phig, const double* M2, int64_t G, const double* K1, const double* K3, int N,
                     int n, int np, int Np, double s1, double s2, double s3, double dV, double* K, const double* e1p,
-                    int64_t ne1, const double* e3p, int64_t ne3, double ce1, double ce3, double* ex, hipStream_t s);
+                    int64_t ne1, const double* e3p, int64_t ne3, double ce1, double ce3, double* ex, hipStream_t s,
+                    const EnergyDots& dots = EnergyDots());
 
 // ---------------------------------------------------------------- streaming form (general sizes)
 // O[x][c] = sum_y S[x][y] (sum_d X[x][d] Y[y][d]) Y[y][c], S = V (or W) stored

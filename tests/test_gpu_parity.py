@@ -153,6 +153,35 @@ def test_device_pointer_mode(lib, cfg1):
         assert float(ex.item()) == Eh
 
 
+def test_graph_replay_matches_host_builds(lib, cfg1):
+    """Repeated device-pointer builds are captured into a HIP graph on the
+    second call and replayed after it; every replay must equal the host-mode
+    build bit for bit, also after C changes in place and with eager work and
+    synchronisations between replays."""
+    _say("case: graph replay of repeated device builds")
+    import torch
+    w, st, C = cfg1["w"], cfg1["st"], cfg1["C"]
+    C2 = ri.lowdin(ri.random_coefficients(w, stream="perturbation"), basis.overlap(cfg1["Phi"], cfg1["dV"]))
+    with _ctx(lib, w, points=st["points"]) as ctx:
+        Kh, Eh = ctx.build(C)
+        Kh2, Eh2 = ctx.build(C2)
+        Cd = torch.from_numpy(C).cuda()
+        K = torch.empty((w.nbas, w.nocc), dtype=torch.float64, device="cuda")
+        ex = torch.zeros(1, dtype=torch.float64, device="cuda")
+        for it in range(5):          # eager, capture + launch, then replays
+            K.fill_(float("nan"))
+            ctx.build(Cd, K, ex)
+            torch.cuda.synchronize()
+            assert np.array_equal(K.cpu().numpy(), Kh), it
+            assert float(ex.item()) == Eh, it
+            ctx.build(C)             # eager host-mode work between replays
+        Cd.copy_(torch.from_numpy(C2))
+        ctx.build(Cd, K, ex)
+        torch.cuda.synchronize()
+        assert np.array_equal(K.cpu().numpy(), Kh2)
+        assert float(ex.item()) == Eh2
+
+
 # ------------------------------------------------------------------ config 2 (stored oracle results)
 @pytest.mark.parametrize("c", [4, 6, 8, 10])
 def test_build_config2_shared_points(lib, c):
