@@ -42,7 +42,7 @@ __host__ __device__ constexpr int64_t fused_lds_doubles(int64_t bg) {
   return (int64_t)NW * 16 * SLAB + (int64_t)T * (16 * NI + 1) + bg * 16 * NI;
 }
 
-template <int NW, int NI, int MT>
+template <int NW, int NI, int MT, bool WM2>
 __global__ __launch_bounds__(NW * 64) void fused_f64_kernel(FusedArgs a) {
   constexpr int NP = 16 * NI;
   constexpr int LDU = NP + 1;
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(NW * 64) void fused_f64_kernel(FusedArgs a) {
   const int64_t nmy = (gs1 - gs0 > w) ? (gs1 - gs0 - w + NW - 1) / NW : 0;
   const int64_t nstep = nmy * (rt1 > rt0 ? rt1 - rt0 : 0);
 
-  if (a.want_m2)
+  if constexpr (WM2)
     for (int64_t e = tid; e < bg * NP; e += NW * 64) sM2[e] = 0.0;
 
   // V fragment of step t: lane holds V[g0 + 4r + lq][R0 + 16c + l16]
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(NW * 64) void fused_f64_kernel(FusedArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           av[r] = v[r][c] * p[c][r];
-          if (a.want_e) e1 += av[r] * p[c][r];
+          if constexpr (!WM2) e1 += av[r] * p[c][r];   // fit-fit line: no M2 to form it from
           slab[(4 * r + lq) * SLAB + 16 * c + l16] = av[r];
         }
 #pragma unroll
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(NW * 64) void fused_f64_kernel(FusedArgs a) {
           for (int j = 0; j < NI; ++j) m1[c][j] = mfma_f64(av[r], ugB[r][j], m1[c][j]);
       }
       __builtin_amdgcn_wave_barrier();
-      if (a.want_m2) {
+      if constexpr (WM2) {
         // M2[g][i] = sum_R A[g][R] U[R][i]: A operand from the wave's own slab
         d4_t m2[NI];
 #pragma unroll
@@ -243,20 +243,22 @@ __global__ __launch_bounds__(NW * 64) void fused_f64_kernel(FusedArgs a) {
           for (int r = 0; r < 4; ++r) out[(int64_t)(16 * m + 4 * r + lq) * NP + 16 * j + l16] = k1[mm][j][r];
     }
   }
-  if (a.want_m2) {
+  if constexpr (WM2) {
     double* out = a.M2p + ((int64_t)rb * a.G + gs0 * 16) * NP;
     const int64_t rows = (gs1 - gs0) * 16;
     for (int64_t e = tid; e < rows * NP; e += NW * 64) out[e] = sM2[e];
   }
-  // energy partial: waves in fixed order
-  const double es = wave_sum(e1);
-  __syncthreads();
-  if (lane == 0) red[w] = es;
-  __syncthreads();
-  if (tid == 0) {
-    double s = 0.0;
-    for (int ww = 0; ww < NW; ++ww) s += red[ww];
-    a.e1p[wg] = s;
+  // energy partial (fit-fit line): waves in fixed order
+  if constexpr (!WM2) {
+    const double es = wave_sum(e1);
+    __syncthreads();
+    if (lane == 0) red[w] = es;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int ww = 0; ww < NW; ++ww) s += red[ww];
+      a.e1p[wg] = s;
+    }
   }
 }
 
@@ -537,8 +539,11 @@ __global__ __launch_bounds__(NW * 64) void fused_f32_kernel(FusedArgs a) {
   if (a.want_m2)
     for (int64_t e = tid; e < bg * NP; e += NW * 64) sM2[e] = 0.0;
 
-  // V fragment: lane holds V[g0 + 4lq + r][R0 + 16c + l16]; U_g operands of the step
-  float vnext[4][4], ugAn[4], ugBn[4];
+  // V fragment: lane holds V[g0 + 4lq + r][R0 + 16c + l16]; U_g operands of the
+  // step are prefetched in FP64 and rounded when used (a conversion right after
+  // the load would wait for the whole prefetch)
+  float vnext[4][4];
+  double ugAn[4], ugBn[4];
   auto load_v = [&](int64_t ri, int64_t si) {
     const int64_t R0 = (rt0 + ri) * T, g0 = (gs0 + w + si * NW) * 16;
     const float* base = a.Vm32 + (g0 + 4 * lq) * a.ldv + R0 + l16;
@@ -550,13 +555,12 @@ __global__ __launch_bounds__(NW * 64) void fused_f32_kernel(FusedArgs a) {
     }
     const double* ug = a.Ug + g0 * NP;
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) ugAn[kk] = (float)ug[l16 * NP + 4 * kk + lq];
+    for (int kk = 0; kk < 4; ++kk) ugAn[kk] = ug[l16 * NP + 4 * kk + lq];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) ugBn[r] = (float)ug[(4 * lq + r) * NP + l16];
+    for (int r = 0; r < 4; ++r) ugBn[r] = ug[(4 * lq + r) * NP + l16];
   };
   if (nstep > 0) load_v(0, 0);
 
-  double e1 = 0.0;
   constexpr int MTW = (MT + NW - 1) / NW > 0 ? (MT + NW - 1) / NW : 1;
   d4_t k1[MTW];
 #pragma unroll
@@ -578,8 +582,8 @@ __global__ __launch_bounds__(NW * 64) void fused_f32_kernel(FusedArgs a) {
       float v[4][4], ugA[4], ugB[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        ugA[r] = ugAn[r];
-        ugB[r] = ugBn[r];
+        ugA[r] = (float)ugAn[r];
+        ugB[r] = (float)ugBn[r];
 #pragma unroll
         for (int c = 0; c < 4; ++c) v[r][c] = vnext[r][c];
       }
@@ -592,14 +596,14 @@ __global__ __launch_bounds__(NW * 64) void fused_f32_kernel(FusedArgs a) {
       for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
         for (int c = 0; c < 4; ++c) p[c] = mfma_f32(ugA[kk], sU[(16 * c + l16) * LDU + 4 * kk + lq], p[c]);
-      // A = V o P; energy in FP64; slab; M1^T from the registers (slice r <-> g = 4lq + r)
+      // A = V o P; slab; M1^T from the registers (slice r <-> g = 4lq + r).  The
+      // energy term sum A o P is formed afterwards as tr(U_g^T M2).
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         f4_t av;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           av[r] = v[r][c] * p[c][r];
-          if (a.want_e) e1 += (double)av[r] * (double)p[c][r];
           slab[(4 * lq + r) * SL + 16 * c + l16] = av[r];
         }
 #pragma unroll
@@ -670,15 +674,6 @@ __global__ __launch_bounds__(NW * 64) void fused_f32_kernel(FusedArgs a) {
     double* out = a.M2p + ((int64_t)rb * a.G + gs0 * 16) * NP;
     const int64_t rows = (gs1 - gs0) * 16;
     for (int64_t e = tid; e < rows * NP; e += NW * 64) out[e] = sM2[e];
-  }
-  const double es = wave_sum(e1);
-  __syncthreads();
-  if (lane == 0) red[w] = es;
-  __syncthreads();
-  if (tid == 0) {
-    double s = 0.0;
-    for (int ww = 0; ww < NW; ++ww) s += red[ww];
-    a.e1p[wg] = s;
   }
 }
 
@@ -891,7 +886,9 @@ hipError_t launch_fused3(const FusedArgs& a, int blocks, hipStream_t s) {
   const int64_t gper = ((a.G / T + a.gblocks - 1) / a.gblocks) * (T / 16);
   const int64_t lds = fused_lds_doubles<NW, NI>(a.want_m2 ? gper * 16 : 0) * 8;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  auto k = fused_f64_kernel<NW, NI, MT>;
+  // the energy term is accumulated in the kernel exactly when M2 is not formed
+  if ((a.want_e != 0) == (a.want_m2 != 0)) return hipErrorInvalidValue;
+  auto k = a.want_m2 ? fused_f64_kernel<NW, NI, MT, true> : fused_f64_kernel<NW, NI, MT, false>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(blocks), dim3(NW * 64), (size_t)lds, s, a);
@@ -930,6 +927,7 @@ hipError_t launch_m4_mt(const FusedArgs& a, int blocks, hipStream_t s) {
 
 template <int NW, int MT>
 hipError_t launch_f32(const FusedArgs& a, int blocks, hipStream_t s) {
+  if (a.want_e) return hipErrorInvalidValue;   // this kernel leaves the energy to tr(U_g^T M2)
   const int64_t gper = ((a.G / T + a.gblocks - 1) / a.gblocks) * (T / 16);
   const int64_t lds = ((int64_t)NW * 16 * SLAB + (int64_t)T * 17 + (a.want_m2 ? gper * 16 : 0) * 16) * 8;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
