@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix = vector)
 PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 matrix
+PEAK_BF16X3_TFLOPS = 2500.0 / 3.0   # dense BF16 matrix peak over the three products of a split-BF16 product
 PEAK_HBM_GBS = 8000.0
 
 
@@ -137,6 +138,7 @@ def batch_bench(args):
     import rps_inputs as ri
     cells = ri.batch_cells(64)
     dev = torch.device("cuda:0")
+    mprec = P.PREC_BF16X3 if args.precision == "bf16x3" else P.PREC_FP32
     t_setup = time.perf_counter()
     pts, Cs, E64, t64 = [], [], [], []
     flops = 0.0
@@ -162,7 +164,7 @@ def batch_bench(args):
         print(f"[batch64] FP64 cell {i}: {w.name} {t64[-1] * 1e3:.2f} ms", file=sys.stderr, flush=True)
     ctxs = []
     for i, w in enumerate(cells):
-        ctxs.append(P.Context.from_workload(w, points=pts[i], precision=P.PREC_FP32))
+        ctxs.append(P.Context.from_workload(w, points=pts[i], precision=mprec))
     print("[batch64] mixed contexts ready", file=sys.stderr, flush=True)
     setup_s = time.perf_counter() - t_setup
     Cd = [torch.from_numpy(C).to(dev) for C in Cs]
@@ -183,19 +185,21 @@ def batch_bench(args):
     dE = E32 - np.array(E64)
     seq = float(np.sum(t64))
     achieved = flops / dt / 1e12
+    bpeak = PEAK_BF16X3_TFLOPS if mprec == P.PREC_BF16X3 else PEAK_FP32_TFLOPS
     out = {
         "metric": "exchange builds/s (K_occ + E_x)",
         "value": round(len(cells) / dt, 2),
         "unit": "builds/s",
         "n_gpus": 1, "steps": steps, "warmup": max(1, args.warmup // 10),
         "ms_per_step": round(dt * 1e3, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16x3" if mprec == P.PREC_BF16X3 else "f32",
         "data": "synthetic (64 seeded diamond-like cells of uneven size, random S-orthonormal coefficients)",
         "config": {"workload": "batch of 64 cells: shapes {1,2}^3, strain +-5%, grids 32-72, N_aux = 6N, "
                                "n_occ = 2 per atom; one step = all 64 builds (one graph launch)",
                    "global_batch": len(cells), "parallelism": "single GPU"},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(bpeak, 1), "unit": "TFLOP/s",
+                     "frac": round(achieved / bpeak, 4), "traffic": None,
                      "kernel": "whole batch (6 n N_aux N_g per cell over the replay time)"},
         "batch": {"branches": info["branches"], "create_s": round(info["create_s"], 3),
                   "nbas_range": [int(min(w.nbas for w in cells)), int(max(w.nbas for w in cells))],
@@ -217,9 +221,11 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--c", type=float, default=6.0, help="N_aux / N (4, 6, 8 or 10)")
-    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32",
+    ap.add_argument("--precision", choices=["fp32", "bf16x3", "fp64"], default="fp32",
                     help="fp32 (default): the mixed form (V stored FP32, FP32 in-tile products, FP64 across "
-                         "tiles), timed next to the FP64 path on the same points and C; fp64: the FP64 path only")
+                         "tiles), timed next to the FP64 path on the same points and C; bf16x3: V stored FP32, "
+                         "split-BF16 products on the streaming passes (general sizes; n <= 16 uses the FP32 "
+                         "kernel); fp64: the FP64 path only")
     ap.add_argument("--workload", choices=["diamond1x1x1", "diamond2x2x2", "diamond3x3x3", "batch64"],
                     default="diamond1x1x1",
                     help="diamond1x1x1 (default, the headline line); diamond2x2x2 / diamond3x3x3: the precision "
@@ -264,16 +270,18 @@ def main():
     select_s = time.perf_counter() - t0
     C = ri.lowdin(ri.random_coefficients(w), S)
 
-    mixed = args.precision == "fp32"
+    mixed = args.precision != "fp64"
+    mprec = P.PREC_BF16X3 if args.precision == "bf16x3" else P.PREC_FP32
     ref = _time_path(P, w, P.PREC_FP64, points, C, args.steps, args.warmup)
-    run = _time_path(P, w, P.PREC_FP32, points, C, args.steps, args.warmup) if mixed else ref
+    run = _time_path(P, w, mprec, points, C, args.steps, args.warmup) if mixed else ref
 
     n, naux, ng, N = w.nocc, w.naux, w.ngrid, w.nbas
     flops = 6.0 * n * naux * ng
     vbytes = (4.0 if mixed else 8.0) * naux * ng
     fused_s = run["fused_s"]
     achieved = flops / fused_s / 1e12
-    peak = PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS
+    bf = args.precision == "bf16x3" and args.workload != "diamond1x1x1"
+    peak = PEAK_BF16X3_TFLOPS if bf else (PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS)
     tag = ("fused_f32" if mixed else "fused_f64") + f"_diamond1x1x1_c{args.c:g}"
     general = args.workload != "diamond1x1x1"
     traffic = _traffic(tag) if args.workload == "diamond1x1x1" else None
@@ -288,10 +296,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if mixed else "f64",
+        "dtype": ("bf16x3" if bf else "f32") if mixed else "f64",
         "data": "synthetic (seeded diamond-like cell, random S-orthonormal occupied coefficients)",
         "config": {"workload": f"{w.name}: {ng} grid points, N={N}, n_occ={n}, N_aux={naux}, rPS occ-RI, "
-                               + ("mixed: V FP32, FP32 MFMA in-tile products, FP64 across tiles and in K"
+                               + (("mixed: V FP32, split-BF16 MFMA products (hi*hi + hi*lo + lo*hi), FP32 in "
+                                   "tile, FP64 across tiles and in K") if bf else
+                                  ("mixed: V FP32, FP32 MFMA in-tile products, FP64 across tiles and in K")
                                   if mixed else "FP64"),
                    "global_batch": 1, "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,

@@ -23,7 +23,8 @@
 //
 // Precision: TM = double is FP64 throughout.  TM = float reads the FP32 copy
 // of V, rounds X and Y to FP32, accumulates each 32-row tile in FP32 and adds
-// it to FP64 accumulators, so error does not grow with N_g.
+// it to FP64 accumulators, so error does not grow with N_g.  The split-BF16
+// form is a separate kernel below.
 #include <type_traits>
 
 #include "mfma.h"
@@ -185,6 +186,242 @@ __global__ __launch_bounds__(NW * 64) void stream_kernel(StreamArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Split-BF16 form (precision RPS_PREC_BF16X3) on v_mfma_f32_16x16x32_bf16
+// with FP32 accumulation inside a tile and FP64 across tiles.  Every operand
+// is split into three BF16 terms by repeated round-to-nearest, x = h + m + l
+// (24 significant bits, as FP32), and each product keeps the six term
+// products down to 2^-16 of the leading one (the dropped ones are at or below
+// 2^-24, FP32 rounding level):
+//   a b ~ ah bh + ah bm + am bh + ah bl + al bh + am bm
+// A two-term split (16 bits) was not enough: the orbital values X and Y enter
+// every product with the same rounding error, which then acts like a fixed
+// perturbation of the orbitals, and the sums over the points behind K cancel
+// strongly; both put |dE_x| above 1e-6 Ha on test cells.
+// Dataflow as in the FP64/FP32 kernel with K = 32 per instruction:
+//   P^T tile: A operand = Y rows (LDS, row-major planes), B = X (registers),
+//             k <-> d = 32 j + 8 q + e;
+//   O += A Y: A operand straight from the two P^T tiles of a 32-row tile with
+//             k = 8 q + e <-> y = 4 q + e (e < 4) or 16 + 4 q + e - 4 (e >= 4),
+//             B operand from transposed planes of the Y tile in LDS.
+typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split3_bf16(float x, __bf16& h, __bf16& m, __bf16& l) {
+  h = (__bf16)x;
+  const float r = x - (float)h;
+  m = (__bf16)r;
+  l = (__bf16)(r - (float)m);
+}
+
+template <int NC>
+struct Bf16Layout {
+  static constexpr int NP = 16 * NC;
+  static constexpr int NKC = (NP + 31) / 32;   // K chunks of the P^T product
+  static constexpr int NPP = NKC * 32;         // n padded to whole chunks (zero tail)
+  static constexpr int LR = NPP + 8;           // row-major plane pitch (bf16), 16-byte rows
+  static constexpr int LT = BY + 8;            // transposed plane pitch (bf16)
+  static constexpr int SZR = BY * LR, SZT = NP * LT;
+  static constexpr int BUF = 3 * SZR + 3 * SZT;   // bf16 per buffer: Y h/m/l, Y^T h/m/l
+};
+
+template <int NC, int TRANS, int NW>
+__global__ __launch_bounds__(NW * 64) void stream_bf16x3_kernel(StreamArgs a) {
+  using L = Bf16Layout<NC>;
+  constexpr int NP = L::NP, NKC = L::NKC, NPP = L::NPP, LR = L::LR, LT = L::LT;
+  constexpr int SZR = L::SZR, SZT = L::SZT;
+  constexpr int PER = BY * NP / (NW * 64);
+  static_assert(PER * NW * 64 == BY * NP, "tile split");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __bf16* sm = reinterpret_cast<__bf16*>(smem_raw);
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int64_t x0 = ((int64_t)blockIdx.x * NW + w) * 16;
+  const bool xvalid = x0 < a.nx;
+  const int64_t ys = (int64_t)blockIdx.y * a.ysplit;
+  const int64_t ye = (ys + a.ysplit < a.ny) ? ys + a.ysplit : a.ny;
+  const int64_t ntile = (ye > ys) ? (ye - ys) / BY : 0;
+
+  // X operand of the P^T product in three terms: lane holds X[x0 + l16][32 j + 8 lq + e]
+  bf8_t xh[NKC], xm[NKC], xl[NKC];
+#pragma unroll
+  for (int j = 0; j < NKC; ++j)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int d = 32 * j + 8 * lq + e;
+      const float v = (xvalid && d < NP) ? (float)a.X[(x0 + l16) * a.ldx + d] : 0.f;
+      __bf16 h, m, l;
+      split3_bf16(v, h, m, l);
+      xh[j][e] = h;
+      xm[j][e] = m;
+      xl[j][e] = l;
+    }
+
+  // zero tail columns [NP, NPP) of the row-major planes of both buffers (never staged)
+  if constexpr (NPP > NP) {
+    constexpr int TAIL = BY * (NPP - NP);
+    for (int e = tid; e < 2 * 3 * TAIL; e += NW * 64) {
+      const int plane = e / TAIL, rem = e % TAIL;
+      const int r = rem / (NPP - NP), c = NP + rem % (NPP - NP);
+      sm[(plane / 3) * L::BUF + (plane % 3) * SZR + r * LR + c] = (__bf16)0.f;
+    }
+  }
+
+  f4_t o[NC];
+  double od[NC][4];
+#pragma unroll
+  for (int cb = 0; cb < NC; ++cb) {
+    o[cb] = zero_f4();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) od[cb][r] = 0.0;
+  }
+
+  double ystage[PER];
+  auto stage_load = [&](int64_t t) {
+    const double* src = a.Y + (ys + t * BY) * a.ldy;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) ystage[k] = src[tid + k * NW * 64];
+  };
+  auto stage_store = [&](int buf) {
+    __bf16* b = sm + buf * L::BUF;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = tid + k * NW * 64;
+      const int r = e / NP, c = e % NP;
+      __bf16 h, m, l;
+      split3_bf16((float)ystage[k], h, m, l);
+      b[r * LR + c] = h;
+      b[SZR + r * LR + c] = m;
+      b[2 * SZR + r * LR + c] = l;
+      b[3 * SZR + c * LT + r] = h;
+      b[3 * SZR + SZT + c * LT + r] = m;
+      b[3 * SZR + 2 * SZT + c * LT + r] = l;
+    }
+  };
+
+  if (ntile > 0) {
+    stage_load(0);
+    stage_store(0);
+  }
+  __syncthreads();
+  for (int64_t t = 0; t < ntile; ++t) {
+    if (t + 1 < ntile) stage_load(t + 1);
+    const __bf16* b = sm + (t & 1) * L::BUF;
+    const int64_t yb = ys + t * BY;
+    if (xvalid) {
+      // S values at (x0 + l16, yb + y(e)), y(e) = 4 lq + e (e < 4), 16 + 4 lq + e - 4 (e >= 4)
+      float vv[8];
+      if constexpr (TRANS == 0) {
+        const float* p = a.V32 + (x0 + l16) * a.ldv + yb + 4 * lq;
+        const float4 u0 = *reinterpret_cast<const float4*>(p);
+        const float4 u1 = *reinterpret_cast<const float4*>(p + 16);
+        vv[0] = u0.x; vv[1] = u0.y; vv[2] = u0.z; vv[3] = u0.w;
+        vv[4] = u1.x; vv[5] = u1.y; vv[6] = u1.z; vv[7] = u1.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int64_t y = yb + ((e < 4) ? 4 * lq + e : 16 + 4 * lq + e - 4);
+          vv[e] = a.V32[y * a.ldv + x0 + l16];
+        }
+      }
+      // P^T tiles of the two 16-row halves: reg r <-> y = 16 sb + 4 lq + r, x = l16
+      f4_t sp[2];
+#pragma unroll
+      for (int sb = 0; sb < 2; ++sb) {
+        sp[sb] = zero_f4();
+        const __bf16* yr = b + (16 * sb + l16) * LR + 8 * lq;
+#pragma unroll
+        for (int j = 0; j < NKC; ++j) {
+          const bf8_t yh = *reinterpret_cast<const bf8_t*>(yr + 32 * j);
+          const bf8_t ym = *reinterpret_cast<const bf8_t*>(yr + SZR + 32 * j);
+          const bf8_t yl = *reinterpret_cast<const bf8_t*>(yr + 2 * SZR + 32 * j);
+          sp[sb] = mfma_bf16(yl, xh[j], sp[sb]);     // smallest terms first
+          sp[sb] = mfma_bf16(yh, xl[j], sp[sb]);
+          sp[sb] = mfma_bf16(ym, xm[j], sp[sb]);
+          sp[sb] = mfma_bf16(ym, xh[j], sp[sb]);
+          sp[sb] = mfma_bf16(yh, xm[j], sp[sb]);
+          sp[sb] = mfma_bf16(yh, xh[j], sp[sb]);
+        }
+      }
+      bf8_t ah, am, al;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float av = sp[e >> 2][e & 3] * vv[e];
+        __bf16 h, m, l;
+        split3_bf16(av, h, m, l);
+        ah[e] = h;
+        am[e] = m;
+        al[e] = l;
+      }
+      // O[x][c] += A[x][y] Y[y][c]
+      const __bf16* yt = b + 3 * SZR + l16 * LT + 4 * lq;
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb) {
+        const __bf16* ph = yt + 16 * cb * LT;
+        bf8_t bt[3];
+#pragma unroll
+        for (int pl = 0; pl < 3; ++pl) {
+          const bf4_t v0 = *reinterpret_cast<const bf4_t*>(ph + pl * SZT);
+          const bf4_t v1 = *reinterpret_cast<const bf4_t*>(ph + pl * SZT + 16);
+          bt[pl] = bf8_t{v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
+        }
+        o[cb] = mfma_bf16(al, bt[0], o[cb]);     // smallest terms first
+        o[cb] = mfma_bf16(ah, bt[2], o[cb]);
+        o[cb] = mfma_bf16(am, bt[1], o[cb]);
+        o[cb] = mfma_bf16(am, bt[0], o[cb]);
+        o[cb] = mfma_bf16(ah, bt[1], o[cb]);
+        o[cb] = mfma_bf16(ah, bt[0], o[cb]);
+      }
+      if ((t & 1) || t + 1 == ntile) {
+#pragma unroll
+        for (int cb = 0; cb < NC; ++cb) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) od[cb][r] += (double)o[cb][r];
+          o[cb] = zero_f4();
+        }
+      }
+    }
+    if (t + 1 < ntile) stage_store((t + 1) & 1);
+    __syncthreads();
+  }
+
+  if (!xvalid) return;
+  double* out = a.out + ((int64_t)blockIdx.y * a.nx) * a.np;
+#pragma unroll
+  for (int cb = 0; cb < NC; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[(x0 + 4 * lq + r) * a.np + 16 * cb + l16] = od[cb][r];
+}
+
+template <int NC, int TRANS>
+hipError_t launch_bf16x3(const StreamArgs& a, int nsplit, hipStream_t s) {
+  constexpr int NW = 8;
+  const size_t lds = (size_t)2 * Bf16Layout<NC>::BUF * 2;
+  auto kern = stream_bf16x3_kernel<NC, TRANS, NW>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  dim3 grid((unsigned)((a.nx + 16 * NW - 1) / (16 * NW)), (unsigned)nsplit);
+  hipLaunchKernelGGL(kern, grid, dim3(NW * 64), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int TRANS>
+hipError_t dispatch_bf16x3(const StreamArgs& a, int nsplit, hipStream_t s) {
+  switch (a.np / 16) {
+    case 1: return launch_bf16x3<1, TRANS>(a, nsplit, s);
+    case 2: return launch_bf16x3<2, TRANS>(a, nsplit, s);
+    case 3: return launch_bf16x3<3, TRANS>(a, nsplit, s);
+    case 4: return launch_bf16x3<4, TRANS>(a, nsplit, s);
+    case 5: return launch_bf16x3<5, TRANS>(a, nsplit, s);
+    case 6: return launch_bf16x3<6, TRANS>(a, nsplit, s);
+    case 7: return launch_bf16x3<7, TRANS>(a, nsplit, s);
+    case 8: return launch_bf16x3<8, TRANS>(a, nsplit, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename TM, int NC, int TRANS>
 hipError_t launch_stream(const StreamArgs& a, int nsplit, hipStream_t s) {
   constexpr int NW = 8;
@@ -225,14 +462,18 @@ int stream_splits(int64_t nx, int64_t ny, int target_blocks) {
   return (int)sp;
 }
 
-hipError_t stream_product(const StreamArgs& a, bool fp32, int nsplit, hipStream_t s) {
+hipError_t stream_product(const StreamArgs& a, int prec, int nsplit, hipStream_t s) {
   if (a.np < 16 || a.np > 128 || a.np % 16 || a.nx % 16 || a.ny % BY || a.ldy != a.np) return hipErrorInvalidValue;
   if (nsplit < 1) return hipErrorInvalidValue;
   StreamArgs b = a;
   // y rows per split, a multiple of the tile
   const int64_t tiles = a.ny / BY;
   b.ysplit = ((tiles + nsplit - 1) / nsplit) * BY;
-  if (fp32) {
+  if (prec == 2) {
+    if (!a.V32) return hipErrorInvalidValue;
+    return a.trans ? dispatch_bf16x3<1>(b, nsplit, s) : dispatch_bf16x3<0>(b, nsplit, s);
+  }
+  if (prec == 1) {
     if (!a.V32) return hipErrorInvalidValue;
     return a.trans ? dispatch_nc<float, 1>(b, nsplit, s) : dispatch_nc<float, 0>(b, nsplit, s);
   }

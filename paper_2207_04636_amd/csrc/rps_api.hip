@@ -683,7 +683,7 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
   const bool stream = c.gSp.p != nullptr && np <= kStreamMaxNp;
   if (stream) {
     // streaming form: O never materialises A = V o P (see k_stream.hip)
-    const bool f32 = c.precision != RPS_PREC_FP64;
+    const int prec = c.precision;
     if (need_main) {
       prof_mark(c, 1, st);
       StreamArgs m2;   // M2 = (V o P) U, x = interpolation points
@@ -691,7 +691,7 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
       m2.X = c.gUg.p; m2.ldx = np; m2.Y = c.gU.p; m2.ldy = np;
       m2.nx = c.nauxp; m2.ny = c.ngp; m2.np = np; m2.out = c.gSp.p;
       const int sp = stream_splits(m2.nx, m2.ny, c.tune_target > 0 ? c.tune_target : kStreamBlocks);
-      hip_check(stream_product(m2, f32, sp, st), "stream M2");
+      hip_check(stream_product(m2, prec, sp, st), "stream M2");
       hip_check(sum_partials3(c.gSp.p, sp, c.nauxp * np, c.gM2.p, nullptr, 0, 0, nullptr, nullptr, 0, 0, nullptr, st),
                 "M2 partials");
       if (k1) {
@@ -699,7 +699,7 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
         m1.V = c.V.p; m1.V32 = c.V32.p; m1.ldv = c.ngp; m1.trans = 1;
         m1.X = c.gU.p; m1.ldx = np; m1.Y = c.gUg.p; m1.ldy = np;
         m1.nx = c.ngp; m1.ny = c.nauxp; m1.np = np; m1.out = c.gM1T.p;
-        hip_check(stream_product(m1, f32, 1, st), "stream M1");
+        hip_check(stream_product(m1, prec, 1, st), "stream M1");
       }
       prof_mark(c, 2, st);
       if (k1) {
@@ -716,7 +716,7 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
       l3.X = c.gUg.p; l3.ldx = np; l3.Y = c.gUg.p; l3.ldy = np;
       l3.nx = c.nauxp; l3.ny = c.nauxp; l3.np = np; l3.out = c.gSp.p;
       const int sp = stream_splits(l3.nx, l3.ny, c.tune_target > 0 ? c.tune_target : kStreamBlocks);
-      hip_check(stream_product(l3, false, sp, st), "stream line 3");
+      hip_check(stream_product(l3, RPS_PREC_FP64, sp, st), "stream line 3");
       hip_check(sum_partials3(c.gSp.p, sp, c.nauxp * np, c.gY.p, nullptr, 0, 0, nullptr, nullptr, 0, 0, nullptr, st),
                 "line-3 partials");
       Gemm k3;    // K3 = Phi_g^T Y

@@ -167,6 +167,7 @@ struct StreamArgs {
 };
 // Split count along y giving about target_blocks workgroups.
 int stream_splits(int64_t nx, int64_t ny, int target_blocks);
-hipError_t stream_product(const StreamArgs& a, bool fp32, int nsplit, hipStream_t s);
+// prec: 0 FP64 (V), 1 FP32 (V32, FP32 products), 2 split-BF16 products on V32.
+hipError_t stream_product(const StreamArgs& a, int prec, int nsplit, hipStream_t s);
 
 }  // namespace rps

@@ -103,6 +103,21 @@ def test_general_fp32(lib, name):
     assert dk < 1e-4
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_general_bf16x3(lib, name):
+    """Split-BF16 products (a_hi b_hi + a_hi b_lo + a_lo b_hi, FP32 accumulation
+    within a tile, FP64 across tiles) on the streaming passes."""
+    _say(f"case: general split-BF16 form {name}")
+    cs = _case(name)
+    with lib.Context.from_workload(cs["w"], points=cs["points"], precision=lib.PREC_BF16X3) as ctx:
+        K, E = ctx.build(cs["C"])
+        assert ctx.info()["precision"] == lib.PREC_BF16X3
+    dk = _kerr(K, cs["K"])
+    _say(f"  BF16x3 form: dE={E - cs['E']:.3e} max|dK|/max|K|={dk:.3e}")
+    assert abs(E - cs["E"]) < 1e-6
+    assert dk < 1e-4
+
+
 @pytest.mark.parametrize("variant", ["ps", "thc"])
 def test_general_variants(lib, variant):
     _say(f"case: general {variant} 2x1x1-n40")
