@@ -510,7 +510,7 @@ template <int NW, int MT>
 __global__ __launch_bounds__(NW * 64) void fused_f32_kernel(FusedArgs a) {
   constexpr int NP = 16;
   constexpr int LDU = NP + 1;
-  constexpr int SL = T + 1;                // FP32 slab pitch (floats)
+  constexpr int SL = T + 4;                // FP32 slab pitch (floats): conflict-free rows for both access patterns
   extern __shared__ double smem[];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
