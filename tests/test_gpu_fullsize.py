@@ -1,0 +1,110 @@
+"""Full-size GPU checks (supercells 2x2x2 and 3x3x3) through properties that
+hold at any size, in the launch configuration the benchmark times.
+
+At these sizes the oracle cannot form V (15 GB and 121 GB in FP64), so the
+checks are the invariants of Eq. 16 and of the occ-RI exchange:
+  - C^T K_occ is symmetric;
+  - both energy routes agree: the library's E_x = -dV (2 sum A o P - sum B o P_g)
+    and -tr(C^T K) formed on the host;
+  - an occupied rotation C -> C Q leaves E_x unchanged and maps K -> K Q;
+  - builds are deterministic;
+  - SCF-like steps (occupied-virtual rotations of angle 0.01) keep the mixed
+    forms within |dE_x| < 1e-6 Ha of the FP64 path at every step.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import rps_inputs as ri
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2207_04636_amd as P
+    P.load()
+    return P
+
+
+def _orth(n, seed):
+    q, _ = np.linalg.qr(np.random.default_rng(seed).standard_normal((n, n)))
+    return q
+
+
+def _check_invariants(lib, ctx, C, tag):
+    K, E = ctx.build(C)
+    K2, E2 = ctx.build(C)
+    assert np.array_equal(K, K2) and E == E2, "not deterministic"
+    CK = C.T @ K
+    sym = np.abs(CK - CK.T).max() / np.abs(CK).max()
+    Eh = lib.exchange_energy(C, K)
+    Q = _orth(C.shape[1], 11)
+    KQ, EQ = ctx.build(C @ Q)
+    rot_k = np.abs(KQ - K @ Q).max() / np.abs(K).max()
+    _say(f"  {tag}: E={E:.10f} sym={sym:.2e} routes={abs(Eh - E):.2e} rotE={abs(EQ - E):.2e} rotK={rot_k:.2e}")
+    return K, E, sym, abs(Eh - E) / abs(E), abs(EQ - E) / abs(E), rot_k
+
+
+def test_supercell_2x2x2_forms(lib):
+    """Config 3: FP64, FP32 and split-BF16 streaming forms, with library-chosen points."""
+    w = ri.diamond_2x2x2()
+    _say(f"case: {w.name} FP64 / FP32 / split-BF16")
+    with lib.Context.from_workload(w, seed=w.sketch_seed()) as ctx:
+        pts = ctx.points()
+        S = ctx.overlap()
+        C = ri.lowdin(ri.random_coefficients(w), S)
+        K, E, sym, routes, rotE, rotK = _check_invariants(lib, ctx, C, "FP64")
+        assert E < 0
+        assert sym < 1e-12 and routes < 1e-12 and rotE < 1e-12 and rotK < 1e-11
+        steps = [C]
+        for s in range(1, 4):
+            steps.append(ri.perturbed(steps[-1], S, s, angle=0.01, w=w))
+        E64 = [ctx.build(Cs)[1] for Cs in steps]
+    for prec, name in ((lib.PREC_FP32, "FP32"), (lib.PREC_BF16X3, "split-BF16")):
+        with lib.Context.from_workload(w, points=pts, precision=prec) as ctx:
+            Km, Em, sym_m, routes_m, rotE_m, rotK_m = _check_invariants(lib, ctx, C, name)
+            assert abs(Em - E) < 1e-6
+            assert np.abs(Km - K).max() / np.abs(K).max() < 1e-4
+            assert sym_m < 1e-7 and routes_m < 1e-9 and rotE_m < 1e-8
+            for s, Cs in enumerate(steps):
+                Es = ctx.build(Cs)[1]
+                _say(f"  {name} SCF step {s}: dE={Es - E64[s]:.3e}")
+                assert abs(Es - E64[s]) < 1e-6
+
+
+def test_supercell_3x3x3_scf_steps(lib):
+    """Config 4: FP64 GEMM form, then the precision form (FP32 V) on the same
+    points, over SCF-like steps.  The two contexts live one after the other
+    (FP64 V alone is 121 GB)."""
+    w = ri.diamond_3x3x3()
+    _say(f"case: {w.name} FP64 then FP32 V, 3 SCF-like steps")
+    with lib.Context.from_workload(w, seed=w.sketch_seed()) as ctx:
+        pts = ctx.points()
+        S = ctx.overlap()
+        C = ri.lowdin(ri.random_coefficients(w), S)
+        steps = [C]
+        for s in range(1, 3):
+            steps.append(ri.perturbed(steps[-1], S, s, angle=0.01, w=w))
+        ref = []
+        for s, Cs in enumerate(steps):
+            K, E = ctx.build(Cs)
+            CK = Cs.T @ K
+            sym = np.abs(CK - CK.T).max() / np.abs(CK).max()
+            _say(f"  FP64 step {s}: E={E:.10f} sym={sym:.2e}")
+            assert E < 0 and sym < 1e-12
+            assert abs(lib.exchange_energy(Cs, K) - E) < 1e-10 * abs(E)
+            ref.append((K, E))
+    with lib.Context.from_workload(w, points=pts, precision=lib.PREC_FP32) as ctx:
+        for s, Cs in enumerate(steps):
+            K, E = ctx.build(Cs)
+            dk = np.abs(K - ref[s][0]).max() / np.abs(ref[s][0]).max()
+            _say(f"  FP32-V step {s}: dE={E - ref[s][1]:.3e} dK={dk:.3e}")
+            assert abs(E - ref[s][1]) < 1e-6
+            assert dk < 1e-4
