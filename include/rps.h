@@ -160,8 +160,14 @@ rps_status rps_build_exchange_variant(rps_context *ctx, int32_t variant, int32_t
 /*
  * Full exchange matrix K_{mu nu} = sum_i (mu i | i nu) with rPS integrals
  * (Eq. 15 and its two partner terms of Eq. 13):
- *   K = dV [Phi_g^T A Phi + (Phi_g^T A Phi)^T - Phi_g^T B Phi_g].
- * Needed once at the end of an SCF run (Sec. 3.3).  K: [N][N] FP64.
+ *   K = dV [Phi_g^T A Phi + (Phi_g^T A Phi)^T - Phi_g^T B Phi_g],
+ * A = V o (U_g U^T), B = W o (U_g U_g^T); K_full C equals K_occ.  Needed once
+ * at the end of an SCF run (Sec. 3.3).  nocc, C as for
+ * rps_build_exchange_occRI; K: [N][N] FP64 output (host or device per flags).
+ * Works on any context (FP64 products; the precision form reads its FP32 V).
+ * Allocates its temporaries for the call (about 2 GB plus 8 N_aux^2 bytes)
+ * and synchronises hip_stream before returning.
+ * Errors: RPS_ERR_ARG, RPS_ERR_STATE, RPS_ERR_NOMEM, RPS_ERR_DEVICE.
  */
 rps_status rps_build_exchange_full(rps_context *ctx, int32_t nocc, const double *C, double *K,
                                    int32_t flags, void *hip_stream);

@@ -879,6 +879,15 @@ __global__ void pack_kernel(const double* __restrict__ C, int64_t rows, int64_t 
   Cp[t] = (r < rows && c < cols) ? C[r * ldc + c] : 0.0;
 }
 
+// K[i][j] = dV (T[i][j] + T[j][i] - K3[i][j]) for i, j < N (T, K3 pitch Np).
+__global__ void full_combine_kernel(const double* __restrict__ T, const double* __restrict__ K3, int64_t Np,
+                                    int64_t N, double dV, double* __restrict__ K) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * N) return;
+  const int64_t i = t / N, j = t % N;
+  K[t] = dV * (T[i * Np + j] + T[j * Np + i] - K3[i * Np + j]);
+}
+
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <int NW, int NI, int MT>
@@ -1062,6 +1071,13 @@ hipError_t pack_matrix(const double* C, int64_t rows, int64_t cols, int64_t ldc,
                        int64_t ldp, hipStream_t s) {
   hipLaunchKernelGGL(pack_kernel, dim3(nblk(rows_p * ldp, 256)), dim3(256), 0, s, C, rows, cols, ldc, Cp, rows_p,
                      ldp);
+  return hipGetLastError();
+}
+
+hipError_t full_combine(const double* T, const double* K3, int64_t Np, int64_t N, double dV, double* K,
+                        hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(full_combine_kernel, dim3(nblk(N * N, 256)), dim3(256), 0, s, T, K3, Np, N, dV, K);
   return hipGetLastError();
 }
 

@@ -967,6 +967,92 @@ void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, doub
   c.last_stream = st;
 }
 
+// Full exchange matrix with rPS integrals (Eq. 15 and its partner terms of
+// Eq. 13): K = dV [Phi_g^T (A Phi) + (Phi_g^T (A Phi))^T - Phi_g^T (B Phi_g)],
+// A = V o (U_g U^T), B = W o (U_g U_g^T).  Needed once at the end of an SCF
+// run (Sec. 3.3), so it takes the simple route: A in g chunks by the GEMM with
+// the Hadamard epilogue, then plain GEMMs; temporaries live for the call.
+void build_full_impl(rps_context& c, int32_t nocc, const double* C, double* K, int32_t flags, hipStream_t st) {
+  if (c.ng == 0) fail(RPS_ERR_STATE, "context has no completed set-up");
+  if (nocc < 1) fail(RPS_ERR_ARG, "nocc must be >= 1");
+  if (!C || !K) fail(RPS_ERR_ARG, "C and K must not be NULL");
+  if (flags != RPS_PTRS_HOST && flags != RPS_PTRS_DEVICE) fail(RPS_ERR_ARG, "flags must be RPS_PTRS_HOST or RPS_PTRS_DEVICE");
+  const bool dev = (flags == RPS_PTRS_DEVICE);
+  const int64_t np = round_up(nocc, 16), Np = c.Np, G = c.nauxp, R = c.ngp;
+  int64_t tmp = 0;
+  DBuf<double> Cd, Cp, U, Ug, A, O, T, B, BP, K3, Kd, work;
+  const double* Csrc = C;
+  if (!dev) {
+    Cd.alloc(c.nbas * nocc, &tmp);
+    hip_check(hipMemcpyAsync(Cd.p, C, (size_t)c.nbas * nocc * 8, hipMemcpyHostToDevice, st), "copy C");
+    Csrc = Cd.p;
+  }
+  const int64_t gc = std::min<int64_t>(G, std::max<int64_t>(64, (2000000000ll / 8) / R / 64 * 64));
+  Cp.alloc(Np * np, &tmp);
+  U.alloc(R * np, &tmp);
+  Ug.alloc(G * np, &tmp);
+  A.alloc(std::max(gc * R, G * G), &tmp);
+  O.alloc(G * Np, &tmp);
+  T.alloc(Np * Np, &tmp);
+  B.alloc(G * G, &tmp);
+  BP.alloc(G * Np, &tmp);
+  K3.alloc(Np * Np, &tmp);
+  work.alloc(kSplitWork, &tmp);
+  if (!dev) Kd.alloc(c.nbas * c.nbas, &tmp);
+  auto run = [&](Gemm g, const char* what, bool split) {
+    if (split && g.epi == EPI_AXPBY) {
+      g.splitk = gemm_splitk_for(g.M, g.N, g.K, kSplitWork);
+      g.work = work.p;
+    }
+    hip_check(gemm_f64(g, st), what);
+  };
+  hip_check(pack_matrix(Csrc, c.nbas, nocc, nocc, Cp.p, Np, np, st), "pack C");
+  {
+    Gemm g;   // U = Phi C
+    g.M = R; g.N = np; g.K = Np;
+    g.A = c.Phi.p; g.lda = Np; g.B = Cp.p; g.ldb = np; g.C = U.p; g.ldc = np;
+    run(g, "U", false);
+  }
+  hip_check(gather_rows(U.p, np, c.dpoints.p, c.naux, G, np, Ug.p, np, st), "U_g");
+  for (int64_t g0 = 0; g0 < G; g0 += gc) {
+    const int64_t m = std::min(gc, G - g0);
+    Gemm a;   // A_c = V_c o (U_g[c] U^T)
+    a.M = m; a.N = R; a.K = np;
+    a.A = Ug.p + g0 * np; a.lda = np; a.B = U.p; a.ldb = np; a.transB = true;
+    a.C = A.p; a.ldc = R; a.epi = EPI_HADAMARD_SRC; a.ldd = R;
+    if (c.V.p) a.D = c.V.p + g0 * R;
+    else a.D32 = c.V32.p + g0 * R;
+    run(a, "A chunk", false);
+    Gemm o;   // O[c] = A_c Phi
+    o.M = m; o.N = Np; o.K = R;
+    o.A = A.p; o.lda = R; o.B = c.Phi.p; o.ldb = Np; o.C = O.p + g0 * Np; o.ldc = Np;
+    run(o, "A Phi", true);
+  }
+  {
+    Gemm t;   // T = Phi_g^T O
+    t.M = Np; t.N = Np; t.K = G;
+    t.A = c.Phig.p; t.lda = Np; t.transA = true; t.B = O.p; t.ldb = Np; t.C = T.p; t.ldc = Np;
+    run(t, "Phi_g^T (A Phi)", true);
+    Gemm b;   // B = W o (U_g U_g^T)
+    b.M = G; b.N = G; b.K = np;
+    b.A = Ug.p; b.lda = np; b.B = Ug.p; b.ldb = np; b.transB = true;
+    b.C = B.p; b.ldc = G; b.epi = EPI_HADAMARD_SRC; b.D = c.W.p; b.ldd = G;
+    run(b, "B", false);
+    Gemm bp;  // B Phi_g
+    bp.M = G; bp.N = Np; bp.K = G;
+    bp.A = B.p; bp.lda = G; bp.B = c.Phig.p; bp.ldb = Np; bp.C = BP.p; bp.ldc = Np;
+    run(bp, "B Phi_g", true);
+    Gemm k3;  // K3 = Phi_g^T (B Phi_g)
+    k3.M = Np; k3.N = Np; k3.K = G;
+    k3.A = c.Phig.p; k3.lda = Np; k3.transA = true; k3.B = BP.p; k3.ldb = Np; k3.C = K3.p; k3.ldc = Np;
+    run(k3, "Phi_g^T (B Phi_g)", true);
+  }
+  double* Kout = dev ? K : Kd.p;
+  hip_check(full_combine(T.p, K3.p, Np, c.nbas, c.dV, Kout, st), "combine");
+  if (!dev) hip_check(hipMemcpyAsync(K, Kd.p, (size_t)c.nbas * c.nbas * 8, hipMemcpyDeviceToHost, st), "copy K");
+  hip_check(hipStreamSynchronize(st), "sync");   // temporaries are released on return
+}
+
 // ------------------------------------------------------------------ autotuner
 // Mean time of `reps` device-pointer builds after one warm-up build (which
 // also allocates any workspace the launch shape needs).
@@ -1202,10 +1288,11 @@ rps_status rps_build_exchange_variant(rps_context* ctx, int32_t variant, int32_t
   });
 }
 
-rps_status rps_build_exchange_full(rps_context* ctx, int32_t, const double*, double*, int32_t, void*) {
+rps_status rps_build_exchange_full(rps_context* ctx, int32_t nocc, const double* C, double* K, int32_t flags,
+                                   void* hip_stream) {
   return guarded([&] {
     if (!ctx) fail(RPS_ERR_ARG, "ctx must not be NULL");
-    fail(RPS_ERR_STATE, "full exchange matrix is not available in this build");
+    build_full_impl(*ctx, nocc, C, K, flags, (hipStream_t)hip_stream);
   });
 }
 

@@ -147,6 +147,11 @@ hipError_t finalize(const double* Phig, const double* M2, int64_t G, const doubl
                     int64_t ne1, const double* e3p, int64_t ne3, double ce1, double ce3, double* ex, hipStream_t s,
                     const EnergyDots& dots = EnergyDots());
 
+// Full exchange matrix: K[i][j] = dV (T[i][j] + T[j][i] - K3[i][j]) for i, j < N
+// from [Np][Np] arrays T = Phi_g^T (A Phi) and K3 = Phi_g^T (B Phi_g).
+hipError_t full_combine(const double* T, const double* K3, int64_t Np, int64_t N, double dV, double* K,
+                        hipStream_t s);
+
 // ---------------------------------------------------------------- streaming form (general sizes)
 // O[x][c] = sum_y S[x][y] (sum_d X[x][d] Y[y][d]) Y[y][c], S = V (or W) stored
 // row-major [rows][cols] with pitch ldv; trans = 0: x indexes rows of S,

@@ -130,6 +130,19 @@ def test_general_variants(lib, variant):
     assert _kerr(K, Kref) < 1e-7
 
 
+def test_full_exchange_general(lib):
+    """Full K_{mu nu} for N = 208 (N > 128) against the oracle; K_full C = K_occ."""
+    _say("case: full exchange matrix 2x1x1-n32")
+    cs = _case("2x1x1-n32")
+    Kref = rps.build_full(*cs["args"])
+    with lib.Context.from_workload(cs["w"], points=cs["points"]) as ctx:
+        Kf = ctx.build_full(cs["C"])
+        Ko, _ = ctx.build(cs["C"])
+    assert _kerr(Kf, Kref) < 1e-7
+    assert np.abs(Kf - Kf.T).max() < 1e-12 * np.abs(Kf).max()
+    assert _kerr(Kf @ cs["C"], Ko) < 1e-10
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_gemm_form(lib, monkeypatch, prec):
     """The chunked GEMM form (used for padded n > 128) on the same case; in the

@@ -153,6 +153,19 @@ def test_device_pointer_mode(lib, cfg1):
         assert float(ex.item()) == Eh
 
 
+def test_full_exchange_config1(lib, cfg1):
+    """Full K_{mu nu} (Eq. 15 and partners) against the oracle; K_full C = K_occ."""
+    _say("case: config-1 full exchange matrix")
+    w, st, C, dV, Phi = cfg1["w"], cfg1["st"], cfg1["C"], cfg1["dV"], cfg1["Phi"]
+    Kref = rps.build_full(Phi, st["points"], st["V"], st["W"], C, dV)
+    with _ctx(lib, w, points=st["points"]) as ctx:
+        Kf = ctx.build_full(C)
+        Ko, _ = ctx.build(C)
+    assert _kerr(Kf, Kref) < 1e-7
+    assert np.abs(Kf - Kf.T).max() < 1e-12 * np.abs(Kf).max()
+    assert _kerr(Kf @ C, Ko) < 1e-10
+
+
 def test_graph_replay_matches_host_builds(lib, cfg1):
     """Repeated device-pointer builds are captured into a HIP graph on the
     second call and replayed after it; every replay must equal the host-mode
