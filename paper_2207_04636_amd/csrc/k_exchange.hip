@@ -814,13 +814,26 @@ __global__ __launch_bounds__(512) void finalize_kernel(const double* __restrict_
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
   const int ntile = (Np / 16) * (np / 16);
-  if ((int)blockIdx.x == ntile) {
+  if ((int)blockIdx.x >= ntile) {
+    // energy: block eb of neb takes a contiguous slice of the dot products; with
+    // one block the result goes to ex, else to the partial list summed later
     if (!ex) return;
+    const int eb = (int)blockIdx.x - ntile, neb = (int)gridDim.x - ntile;
+    auto slice = [&](int64_t n, int64_t& b0, int64_t& b1) {
+      const int64_t per = (n + neb - 1) / neb;
+      b0 = (int64_t)eb * per;
+      b1 = (b0 + per < n) ? b0 + per : n;
+    };
     double sa = 0.0, sb = 0.0;
-    for (int64_t p = tid; p < ne1; p += 512) sa += e1p[p];
-    for (int64_t p = tid; p < ne3; p += 512) sb += e3p[p];
-    for (int64_t p = tid; p < dots.n1; p += 512) sa += dots.x1[p] * dots.y1[p];
-    for (int64_t p = tid; p < dots.n3; p += 512) sb += dots.x3[p] * dots.y3[p];
+    if (eb == 0) {
+      for (int64_t p = tid; p < ne1; p += 512) sa += e1p[p];
+      for (int64_t p = tid; p < ne3; p += 512) sb += e3p[p];
+    }
+    int64_t b0, b1;
+    slice(dots.n1, b0, b1);
+    for (int64_t p = b0 + tid; p < b1; p += 512) sa += dots.x1[p] * dots.y1[p];
+    slice(dots.n3, b0, b1);
+    for (int64_t p = b0 + tid; p < b1; p += 512) sb += dots.x3[p] * dots.y3[p];
     double* r1 = &red[0][0][0];
     r1[tid] = ce1 * sa + ce3 * sb;
     __syncthreads();
@@ -828,7 +841,10 @@ __global__ __launch_bounds__(512) void finalize_kernel(const double* __restrict_
       if (tid < off) r1[tid] += r1[tid + off];
       __syncthreads();
     }
-    if (tid == 0) *ex = -dV * r1[0];
+    if (tid == 0) {
+      if (neb == 1) *ex = -dV * r1[0];
+      else dots.part[eb] = r1[0];
+    }
     return;
   }
   const int m = blockIdx.x / (np / 16), j = blockIdx.x % (np / 16);
@@ -877,6 +893,15 @@ __global__ void pack_kernel(const double* __restrict__ C, int64_t rows, int64_t 
   if (t >= rows_p * ldp) return;
   const int64_t r = t / ldp, c = t % ldp;
   Cp[t] = (r < rows && c < cols) ? C[r * ldc + c] : 0.0;
+}
+
+// ex = -dV sum of the energy partials of the finalize kernel, in order.
+__global__ void energy_sum_kernel(const double* __restrict__ part, int n, double dV, double* __restrict__ ex) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    *ex = -dV * s;
+  }
 }
 
 // K[i][j] = dV (T[i][j] + T[j][i] - K3[i][j]) for i, j < N (T, K3 pitch Np).
@@ -1062,8 +1087,12 @@ hipError_t finalize(const double* Phig, const double* M2, int64_t G, const doubl
                     int64_t ne1, const double* e3p, int64_t ne3, double ce1, double ce3, double* ex, hipStream_t s,
                     const EnergyDots& dots) {
   const int ntile = (Np / 16) * (np / 16);
-  hipLaunchKernelGGL(finalize_kernel, dim3(ntile + 1), dim3(512), 0, s, Phig, M2, G, K1, K3, N, n, np, Np, s1, s2,
+  // energy blocks: one per 64K dot-product terms (up to the partial list size)
+  int neb = (int)std::min<int64_t>((dots.n1 + dots.n3 + 65535) / 65536, dots.part ? dots.nparts : 1);
+  if (neb < 1) neb = 1;
+  hipLaunchKernelGGL(finalize_kernel, dim3(ntile + neb), dim3(512), 0, s, Phig, M2, G, K1, K3, N, n, np, Np, s1, s2,
                      s3, dV, K, e1p, ne1, e3p, ne3, ce1, ce3, ex, dots);
+  if (neb > 1 && ex) hipLaunchKernelGGL(energy_sum_kernel, dim3(1), dim3(64), 0, s, dots.part, neb, dV, ex);
   return hipGetLastError();
 }
 

@@ -88,7 +88,7 @@ struct rps_context {
   // general path workspace
   int gws_np = -1;
   int64_t gchunk = 0;
-  DBuf<double> gCp, gU, gUg, gA, gSp, gM2, gM1T, gK1, gK3, gY, gwork;
+  DBuf<double> gCp, gU, gUg, gA, gSp, gM2, gM1T, gK1, gK3, gY, gwork, epart;
   int64_t rblocks_main = 0, blocks_main = 0, blocks_l3 = 0;
   int rtiles = 4, gblocks = 1, nwaves = 4;
   // autotuned launch parameters (0: built-in default)
@@ -126,7 +126,7 @@ struct rps_context {
     DBuf<double>* all[] = {&Phi, &Phig, &V, &W, &U, &Ug, &Ugp, &M2p, &K1p, &K3p, &e1p,
                            &e3p, &M2, &K1, &K3, &Kdev, &Cdev, &exdev};
     for (auto* b : all) b->release(nullptr);
-    DBuf<double>* gen[] = {&gCp, &gU, &gUg, &gA, &gSp, &gM2, &gM1T, &gK1, &gK3, &gY, &gwork};
+    DBuf<double>* gen[] = {&gCp, &gU, &gUg, &gA, &gSp, &gM2, &gM1T, &gK1, &gK3, &gY, &gwork, &epart};
     for (auto* b : gen) b->release(nullptr);
     V32.release(nullptr);
     dpoints.release(nullptr);
@@ -155,6 +155,7 @@ struct StageLog {
   }
 };
 constexpr int64_t kSplitWork = 64ll << 20;   // doubles of split-K partials (512 MB)
+constexpr int kEnergyBlocks = 256;            // most blocks the energy dot products are split over
 constexpr int kStreamMaxNp = 128;             // largest padded n of the streaming form
 constexpr int kStreamBlocks = 512;            // workgroups aimed at per streaming launch (default)
 constexpr int kStreamMaxTarget = 1024;        // largest target the tuner tries
@@ -651,6 +652,7 @@ void ensure_general(rps_context& c, int np) {
   c.gK3.alloc(c.Np * np, cnt);
   c.gY.alloc(c.nauxp * np, cnt);
   c.gwork.alloc(kSplitWork, cnt);
+  if (!c.epart.p) c.epart.alloc(kEnergyBlocks, cnt);
   c.Cdev.alloc(c.nbas * np, cnt);
   c.Kdev.alloc(c.nbas * np, cnt);
   c.exdev.alloc(1, cnt);
@@ -777,6 +779,7 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
   EnergyDots dots;
   if (need_main) { dots.x1 = c.gUg.p; dots.y1 = c.gM2.p; dots.n1 = c.nauxp * np; }
   if (need_l3) { dots.x3 = c.gUg.p; dots.y3 = c.gY.p; dots.n3 = c.nauxp * np; }
+  dots.part = c.epart.p; dots.nparts = kEnergyBlocks;
   hip_check(finalize(c.Phig.p, need_main ? c.gM2.p : nullptr, c.nauxp, k1 ? c.gK1.p : nullptr,
                      need_l3 ? c.gK3.p : nullptr, (int)c.nbas, nocc, np, (int)c.Np, s1, s2, s3, c.dV, Kout,
                      nullptr, 0, nullptr, 0, ce1, ce3, exout, st, dots),

@@ -135,9 +135,12 @@ hipError_t sum_partials3(const double* in0, int64_t n0, int64_t c0, double* o0, 
                          int64_t c1, double* o1, const double* in2, int64_t n2, int64_t c2, double* o2,
                          hipStream_t s);
 // Energy terms given as dot products: e1 += x1 . y1 (n1 terms), e3 += x3 . y3.
+// Long dots are split over several blocks whose partials go to part[nparts]
+// (summed in order by a second kernel); NULL part keeps one block.
 struct EnergyDots {
   const double* x1 = nullptr; const double* y1 = nullptr; int64_t n1 = 0;
   const double* x3 = nullptr; const double* y3 = nullptr; int64_t n3 = 0;
+  double* part = nullptr; int nparts = 0;
 };
 // K[mu][i] = dV (s1 K1 + s2 Phi_g^T M2 + s3 K3) for mu < N, i < n ([Np][np] arrays,
 // any may be NULL); ex = -dV (ce1 e1 + ce3 e3) if ex is not NULL, with
