@@ -25,6 +25,7 @@ brute        dense Coulomb matrix by direct G summation (no FFT), tiny grids
 rng          Philox4x32-10 counter-based generator (sketch matrices)
 isdf         point selection (randomized QRCP, Voronoi ISDF), fit, V, W (Sec. 3.1, 4.1, 4.3)
 rps          rPS / PS / THC exchange in occ-RI and full form (Sec. 3.2, 3.3)
+coulomb      Coulomb matrix J and E_J on the grid (Sec. 2.3, steps 1-4)
 
 Parity status: every function is pinned by a CPU test except the specific
 interpolation point set produced by the randomized selection, which depends on

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import rps_inputs as ri
-from oracle import basis, brute, conventional, grid, isdf, rng, rps
+from oracle import basis, brute, conventional, coulomb, grid, isdf, rng, rps
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -374,3 +374,85 @@ def test_lowdin_orthonormal():
     C2 = ri.perturbed(C, S, 1, cid=3)
     np.testing.assert_allclose(C2.T @ S @ C2, np.eye(7), atol=1e-12)
     assert 1e-4 < np.abs(C2 - C).max() < 0.2
+
+
+# ---------------------------------------------------------------- Coulomb matrix (Sec. 2.3)
+def test_coulomb_matrix_equals_four_index_contraction():
+    """J_{mu nu} = sum_{lambda sigma} D_{lambda sigma} (mu nu|lambda sigma) with the
+    four-index integrals formed explicitly from the dense Coulomb matrix of
+    direct G sums (no FFT, no density on the grid), D = C C^T."""
+    w = ri.tiny_s_cell(5, 6, 4.0, 2, 8, lmax=1)
+    Phi = basis.eval_basis(w)
+    dV = grid.dvol(w.lattice, w.mesh)
+    C = ri.lowdin(ri.random_coefficients(w), basis.overlap(Phi, dV))
+    J, E, vh = coulomb.build_j(Phi, C, w.lattice, w.mesh)
+    N = Phi.shape[1]
+    pairs = (Phi[:, :, None] * Phi[:, None, :]).reshape(Phi.shape[0], N * N)
+    # (f|g) = dV f . Vc g with Vc the dense matrix (it carries the other dV)
+    eri = dV * pairs.T @ brute.dense_coulomb(w.lattice, w.mesh) @ pairs   # (N^2, N^2)
+    D = C @ C.T
+    Jref = (eri @ D.reshape(-1)).reshape(N, N)
+    assert np.abs(J - Jref).max() < 1e-13 * np.abs(Jref).max()
+    Eref = 0.0
+    for i in range(C.shape[1]):          # sum_ij (ii|jj) from the same tensor
+        ci = np.outer(C[:, i], C[:, i]).reshape(-1)
+        for j in range(C.shape[1]):
+            Eref += ci @ eri @ np.outer(C[:, j], C[:, j]).reshape(-1)
+    assert abs(E - Eref) < 1e-13 * abs(Eref)
+    assert E > 0
+
+
+def test_coulomb_single_orbital_equals_exchange():
+    """One occupied orbital: (mu 1|1 1) is both the Coulomb and the exchange
+    integral, so J C = K_occ and E_J = -E_x of the conventional exchange."""
+    w = ri.tiny_s_cell(5, 6, 4.0, 1, 8, lmax=1)
+    Phi = basis.eval_basis(w)
+    dV = grid.dvol(w.lattice, w.mesh)
+    C = ri.lowdin(ri.random_coefficients(w), basis.overlap(Phi, dV))
+    assert C.shape[1] == 1
+    J, E, _ = coulomb.build_j(Phi, C, w.lattice, w.mesh)
+    K, Ex = conventional.exchange_occ(Phi, C, w.lattice, w.mesh)
+    np.testing.assert_allclose(J @ C, K, atol=1e-14 * np.abs(K).max())
+    assert abs(E + Ex) < 1e-14 * abs(Ex)
+
+
+def test_coulomb_closed_form_two_s():
+    """Two s functions far from their images, density of the second one:
+    J_00 = (phi_a^2 | phi_b^2) and J_11 = E_J = (phi_b^2 | phi_b^2), each
+    squared Gaussian an s Gaussian of twice the exponent whose Coulomb energy
+    is the analytic lattice sum."""
+    L, a, b = 10.0, 1.2, 1.6
+    lat = np.eye(3) * L
+    A = np.array([3.0, 3.5, 4.0])
+    B = np.array([5.0, 4.6, 4.9])
+    w = ri.Workload("t", lat, np.array([64] * 3), np.stack([A, B]), np.array([0, 1]),
+                    np.array([0, 0]), np.array([a, b]), 1, 1, 0)
+    Phi = basis.eval_basis(w)
+    J, E, _ = coulomb.build_j(Phi, np.array([[0.0], [1.0]]), lat, w.mesh)
+
+    def nrm(x):
+        return (2 * x / math.pi) ** 0.75
+    ca, cb = nrm(a) ** 2 / nrm(2 * a), nrm(b) ** 2 / nrm(2 * b)
+    j00 = ca * cb * brute.analytic_s_coulomb(lat, A, 2 * a, B, 2 * b)
+    j11 = cb * cb * brute.analytic_s_coulomb(lat, B, 2 * b, B, 2 * b)
+    assert abs(J[0, 0] - j00) < 1e-10 * abs(j00)
+    assert abs(J[1, 1] - j11) < 1e-10 * abs(j11)
+    assert abs(E - j11) < 1e-10 * abs(j11)
+
+
+def test_coulomb_invariants():
+    """J is symmetric, depends on C only through D (occupied rotations leave
+    it unchanged), is additive over blocks of orbitals, and E_J = tr(D J) > 0."""
+    w = ri.tiny_s_cell(6, 8, 4.0, 3, 8, lmax=1)
+    Phi = basis.eval_basis(w)
+    dV = grid.dvol(w.lattice, w.mesh)
+    C = ri.lowdin(ri.random_coefficients(w), basis.overlap(Phi, dV))
+    J, E, _ = coulomb.build_j(Phi, C, w.lattice, w.mesh)
+    np.testing.assert_allclose(J, J.T, atol=1e-15 * np.abs(J).max())
+    Q, _ = np.linalg.qr(np.random.default_rng(4).standard_normal((3, 3)))
+    JQ, EQ, _ = coulomb.build_j(Phi, C @ Q, w.lattice, w.mesh)
+    np.testing.assert_allclose(JQ, J, atol=1e-13 * np.abs(J).max())
+    J1, _, _ = coulomb.build_j(Phi, C[:, :1], w.lattice, w.mesh)
+    J2, _, _ = coulomb.build_j(Phi, C[:, 1:], w.lattice, w.mesh)
+    np.testing.assert_allclose(J1 + J2, J, atol=1e-13 * np.abs(J).max())
+    assert abs(E - np.trace(C.T @ J @ C)) < 1e-13 * abs(E) and E > 0 and abs(EQ - E) < 1e-13 * E
