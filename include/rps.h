@@ -173,6 +173,27 @@ rps_status rps_build_exchange_full(rps_context *ctx, int32_t nocc, const double 
                                    int32_t flags, void *hip_stream);
 
 /*
+ * Coulomb matrix on the same grid (Sec. 2.3, "Coulomb matrix", steps 1-4, with
+ * the density matrix D = C C^T of Sec. 2.3):
+ *   rho(R) = sum_i u_i(R)^2 (u = Phi C), V_H = Vc rho (G = 0 removed),
+ *   J_{mu nu} = dV sum_R phi_mu(R) phi_nu(R) V_H(R),
+ *   ej = dV sum_R rho(R) V_H(R) = sum_ij (ii|jj) = tr(D J).
+ * With doubly occupied spatial orbitals the closed-shell two-electron energy
+ * is 2 ej + ex (ex from rps_build_exchange_occRI).  Every step runs in FP64 on
+ * any context (the precision option applies to exchange only); Phi is dense,
+ * so the cost is 2 N_g N n + N_g N^2 multiply-adds.
+ * nocc, C : as for rps_build_exchange_occRI
+ * J       : [N][N] FP64 output, symmetric (host or device per flags)
+ * ej      : FP64 output E_J, or NULL (host or device per flags)
+ * Device-pointer calls are asynchronous on hip_stream; host-pointer calls
+ * synchronise it.  Workspace (about 256 MB plus 24 N_g bytes and the split
+ * partials of J) is allocated on the first call and kept by the context.
+ * Errors: RPS_ERR_ARG, RPS_ERR_STATE, RPS_ERR_NOMEM, RPS_ERR_DEVICE.
+ */
+rps_status rps_build_coulomb(rps_context *ctx, int32_t nocc, const double *C, double *J, double *ej,
+                             int32_t flags, void *hip_stream);
+
+/*
  * Batched builds over several contexts (cells of different sizes), one call,
  * issued one after another on hip_stream: C[b], K[b] as for
  * rps_build_exchange_occRI, ex[b] per cell (ex may be NULL).  All pointers are

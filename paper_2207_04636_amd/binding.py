@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "RPS_OK", 1: "RPS_ERR_ARG", 2: "RPS_ERR_SHAPE", 3: "RPS_ERR_N
 
 # every symbol declared in include/rps.h
 EXPORTS = ("rps_setup_isdf", "rps_build_exchange_occRI", "rps_build_exchange_variant",
-           "rps_build_exchange_full", "rps_build_exchange_occRI_batched", "rps_exchange_energy",
+           "rps_build_exchange_full", "rps_build_coulomb", "rps_build_exchange_occRI_batched",
+           "rps_exchange_energy",
            "rps_overlap", "rps_get_points", "rps_get_info", "rps_get_array", "rps_destroy",
            "rps_last_error", "rps_abi_version", "rps_set_profiling", "rps_get_profile", "rps_autotune",
            "rps_batch_create", "rps_batch_run", "rps_batch_info", "rps_batch_destroy")
@@ -89,6 +90,7 @@ def load(path: str = LIB_PATH):
     lib.rps_build_exchange_occRI.argtypes = [P, I32, P, P, P, I32, P]
     lib.rps_build_exchange_variant.argtypes = [P, I32, I32, P, P, P, I32, P]
     lib.rps_build_exchange_full.argtypes = [P, I32, P, P, I32, P]
+    lib.rps_build_coulomb.argtypes = [P, I32, P, P, P, I32, P]
     lib.rps_build_exchange_occRI_batched.argtypes = [ct.POINTER(P), I32, ct.POINTER(I32), ct.POINTER(P),
                                                      ct.POINTER(P), P, I32, P]
     lib.rps_exchange_energy.argtypes = [I32, I32, P, P, ct.POINTER(D)]
@@ -213,6 +215,27 @@ class Context:
         _check(self._lib.rps_build_exchange_full(self._h, int(C.shape[1]), C.ctypes.data, Kh.ctypes.data,
                                                  PTRS_HOST, None))
         return Kh
+
+    def build_coulomb(self, C, J=None, ej=None, stream=None):
+        """Coulomb matrix J (N x N) and E_J (rps_build_coulomb).  numpy C ->
+        synchronous host call returning (J, E_J); torch CUDA C -> stream-ordered
+        call writing J (and ej, a 1-element float64 tensor) and returning them."""
+        if _is_device(C):
+            import torch
+            if C.dtype != torch.float64 or not C.is_contiguous():
+                raise ValueError("C must be a contiguous float64 tensor")
+            if J is None:
+                J = torch.empty((self.nbas, self.nbas), dtype=torch.float64, device=C.device)
+            _check(self._lib.rps_build_coulomb(self._h, int(C.shape[1]), _ptr(C), _ptr(J),
+                                               None if ej is None else _ptr(ej), PTRS_DEVICE,
+                                               _stream_handle(stream)))
+            return J, ej
+        C = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
+        Jh = np.empty((self.nbas, self.nbas))
+        e = ct.c_double(0.0)
+        _check(self._lib.rps_build_coulomb(self._h, int(C.shape[1]), C.ctypes.data, Jh.ctypes.data,
+                                           ct.addressof(e), PTRS_HOST, None))
+        return Jh, e.value
 
     # ---------------------------------------------------------------- inspection
     def points(self) -> np.ndarray:

@@ -1,0 +1,102 @@
+// Coulomb matrix on the grid (Sec. 2.3, "Coulomb matrix", steps 1-4; Sec. 4.2):
+//   1. rho(R) = sum_i U(R, i)^2 with U = Phi C, the density of D = C C^T,
+//   2-3. V_H = Vc rho (the set-up's Poisson solve, one row pair),
+//   4. J = dV Phi^T diag(V_H) Phi, a matrix-core product over the grid whose
+//      second operand is scaled row by row as it is loaded (lower tiles only,
+//      mirrored here),
+// and E_J = dV sum_R rho(R) V_H(R) = sum_ij (ii|jj).
+//
+// The kernels below are the small steps around the products: the density of a
+// block of grid rows, a fixed-order dot product and the symmetric reduction of
+// the split-K partials of J.
+#include "rps_internal.h"
+
+namespace rps {
+namespace {
+
+// rho[r] = sum_i U[r][i]^2 for r < rows, written to out[r] and out[2 ld + r];
+// out[ld + r] = 0 (the imaginary row of the Poisson pair).  np is even.
+__global__ __launch_bounds__(256) void density_rows_kernel(const double* __restrict__ U, int64_t rows, int np,
+                                                           double* __restrict__ out, int64_t ld) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const double2* u = reinterpret_cast<const double2*>(U + r * np);
+  double s0 = 0.0, s1 = 0.0;
+  for (int i = 0; i < np / 2; ++i) {
+    const double2 v = u[i];
+    s0 += v.x * v.x;
+    s1 += v.y * v.y;
+  }
+  const double rho = s0 + s1;
+  out[r] = rho;
+  out[ld + r] = 0.0;
+  out[2 * ld + r] = rho;
+}
+
+// part[b] = sum over block b's slice of x[p] y[p]
+__global__ __launch_bounds__(256) void dot_blocks_kernel(const double* __restrict__ x, const double* __restrict__ y,
+                                                         int64_t n, double* __restrict__ part) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * per;
+  const int64_t b1 = (b0 + per < n) ? b0 + per : n;
+  double s = 0.0;
+  for (int64_t p = b0 + tid; p < b1; p += 256) s += x[p] * y[p];
+  red[tid] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void sum_scaled_kernel(const double* __restrict__ part, int n, double scale, double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    *out = scale * s;
+  }
+}
+
+// J[i][j] = scale * sum_z work[z][max(i,j)][min(i,j)]
+__global__ __launch_bounds__(256) void sym_from_lower_kernel(const double* __restrict__ work, int nz, int64_t Np,
+                                                             int64_t N, double scale, double* __restrict__ J) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * N) return;
+  const int64_t i = t / N, j = t % N;
+  const int64_t hi = (i > j) ? i : j, lo = (i > j) ? j : i;
+  const double* w = work + hi * Np + lo;
+  double s = 0.0;
+  for (int z = 0; z < nz; ++z) s += w[(int64_t)z * Np * Np];
+  J[t] = scale * s;
+}
+
+}  // namespace
+
+hipError_t density_rows(const double* U, int64_t rows, int np, double* out, int64_t ld, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  if (np % 2 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(density_rows_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, U, rows, np, out, ld);
+  return hipGetLastError();
+}
+
+hipError_t dot_scaled(const double* x, const double* y, int64_t n, double scale, double* part, int nparts,
+                      double* out, hipStream_t s) {
+  if (nparts < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(dot_blocks_kernel, dim3((unsigned)nparts), dim3(256), 0, s, x, y, n, part);
+  hipLaunchKernelGGL(sum_scaled_kernel, dim3(1), dim3(64), 0, s, part, nparts, scale, out);
+  return hipGetLastError();
+}
+
+hipError_t sym_from_lower(const double* work, int nz, int64_t Np, int64_t N, double scale, double* J,
+                          hipStream_t s) {
+  const int64_t cnt = N * N;
+  if (cnt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sym_from_lower_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, work, nz, Np, N,
+                     scale, J);
+  return hipGetLastError();
+}
+
+}  // namespace rps

@@ -56,7 +56,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(Gemm g) {
       if (g.transB) { k = e % BK; n = e / BK; } else { n = e % BN; k = e / BN; }
       int64_t gn = n0 + n, gk = k0 + k;
       double v = 0.0;
-      if (gn < g.N && gk < kend) v = g.transB ? g.B[gn * g.ldb + gk] : g.B[gk * g.ldb + gn];
+      if (gn < g.N && gk < kend) {
+        v = g.transB ? g.B[gn * g.ldb + gk] : g.B[gk * g.ldb + gn];
+        if (g.kscale) v *= g.kscale[gk];
+      }
       Bs[k][n] = v;
     }
     __syncthreads();
@@ -101,8 +104,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(Gemm g) {
 
 // Large tiles: 4 waves in 2 x 2, each wave (16*TM) x (16*TN) of C, BK = 16,
 // operands prefetched into registers while the matrix cores work on the
-// current LDS buffer (two buffers, one barrier per K step).
-template <int TM, int TN, bool TA, bool TB>
+// current LDS buffer (two buffers, one barrier per K step).  KS: row k of
+// op(B) is scaled by kscale[k] as it is loaded.
+template <int TM, int TN, bool TA, bool TB, bool KS = false>
 __global__ __launch_bounds__(256, 2) void gemm_big_kernel(Gemm g) {
   constexpr int BM = 32 * TM, BN = 32 * TN;
   constexpr int PA = BM * BK / 256, PB = BN * BK / 256;
@@ -135,6 +139,7 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(Gemm g) {
     const int64_t kc = (k0 < kend) ? k0 : kbeg;   // keeps the base in bounds past the last step
     const double* ba = g.A + (TA ? kc * g.lda + m0 : m0 * g.lda + kc);
     const double* bb = g.B + (TB ? n0 * g.ldb + kc : kc * g.ldb + n0);
+    const double* bk = KS ? g.kscale + kc : nullptr;
     if (full) {     // uniform: whole tile inside, straight-line loads
 #pragma unroll
       for (int i = 0; i < PA; ++i) {
@@ -147,6 +152,7 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(Gemm g) {
         const int e = tid + 256 * i;
         const int n = TB ? e / BK : e % BN, k = TB ? e % BK : e / BN;
         rb[i] = bb[TB ? n * ldb + k : k * ldb + n];
+        if constexpr (KS) rb[i] *= bk[k];
       }
     } else {
 #pragma unroll
@@ -159,7 +165,7 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(Gemm g) {
       for (int i = 0; i < PB; ++i) {
         const int e = tid + 256 * i;
         const int n = TB ? e / BK : e % BN, k = TB ? e % BK : e / BN;
-        rb[i] = (n0 + n < g.N && k0 + k < kend) ? bb[TB ? n * ldb + k : k * ldb + n] : 0.0;
+        rb[i] = (n0 + n < g.N && k0 + k < kend) ? bb[TB ? n * ldb + k : k * ldb + n] * (KS ? bk[k] : 1.0) : 0.0;
       }
     }
   };
@@ -249,7 +255,8 @@ __global__ void splitk_reduce_kernel(const double* __restrict__ work, int splitk
 
 template <int TM, int TN>
 void launch_big(const Gemm& g, dim3 grid, hipStream_t s) {
-  if (!g.transA && !g.transB) hipLaunchKernelGGL((gemm_big_kernel<TM, TN, false, false>), grid, dim3(256), 0, s, g);
+  if (g.kscale) hipLaunchKernelGGL((gemm_big_kernel<TM, TN, true, false, true>), grid, dim3(256), 0, s, g);
+  else if (!g.transA && !g.transB) hipLaunchKernelGGL((gemm_big_kernel<TM, TN, false, false>), grid, dim3(256), 0, s, g);
   else if (g.transA && !g.transB) hipLaunchKernelGGL((gemm_big_kernel<TM, TN, true, false>), grid, dim3(256), 0, s, g);
   else if (!g.transA && g.transB) hipLaunchKernelGGL((gemm_big_kernel<TM, TN, false, true>), grid, dim3(256), 0, s, g);
   else hipLaunchKernelGGL((gemm_big_kernel<TM, TN, true, true>), grid, dim3(256), 0, s, g);
@@ -274,6 +281,7 @@ hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
   if (g.epi == EPI_HADAMARD_SRC && !g.D && !g.D32) return hipErrorInvalidValue;
   if (g.splitk < 1) g.splitk = 1;
   const int bn = gemm_tile_n(g.M, g.N);
+  if (g.kscale && bn != 16 && !(g.transA && !g.transB)) return hipErrorInvalidValue;
   if (bn == 16) {
     dim3 grid((unsigned)((g.N + 15) / 16), (unsigned)((g.M + 127) / 128), (unsigned)g.splitk);
     hipLaunchKernelGGL((gemm_kernel<4, 2, 1>), grid, dim3(256), 0, s, g);
@@ -284,7 +292,7 @@ hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
     dim3 grid((unsigned)((g.N + 127) / 128), (unsigned)((g.M + 127) / 128), (unsigned)g.splitk);
     launch_big<4, 4>(g, grid, s);
   }
-  if (g.splitk > 1) {
+  if (g.splitk > 1 && !g.keep_partials) {
     const int64_t cnt = g.M * g.N;
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, g.work,
                        g.splitk, g.M, g.N, g.C, g.ldc, g.beta);

@@ -91,6 +91,11 @@ struct rps_context {
   DBuf<double> gCp, gU, gUg, gA, gSp, gM2, gM1T, gK1, gK3, gY, gwork, epart;
   int64_t rblocks_main = 0, blocks_main = 0, blocks_l3 = 0;
   int rtiles = 4, gblocks = 1, nwaves = 4;
+  // Coulomb matrix: kernel table k(G) / N_g kept from the set-up, and workspace
+  DBuf<double> kern;
+  int jws_np = -1;
+  int64_t jchunk = 0;
+  DBuf<double> jCp, jCin, jU, jrho, jwork, jpart, jJ;
   // autotuned launch parameters (0: built-in default)
   int tune_target = 0;                      // streaming form: workgroups aimed at per launch
   int tune_rtiles = 0, tune_gblocks = 0;    // fused kernel: R tiles per workgroup, g blocks
@@ -128,6 +133,8 @@ struct rps_context {
     for (auto* b : all) b->release(nullptr);
     DBuf<double>* gen[] = {&gCp, &gU, &gUg, &gA, &gSp, &gM2, &gM1T, &gK1, &gK3, &gY, &gwork, &epart};
     for (auto* b : gen) b->release(nullptr);
+    DBuf<double>* jb[] = {&kern, &jCp, &jCin, &jU, &jrho, &jwork, &jpart, &jJ};
+    for (auto* b : jb) b->release(nullptr);
     V32.release(nullptr);
     dpoints.release(nullptr);
     for (auto e : ev_pool) (void)hipEventDestroy(e);
@@ -413,15 +420,15 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
   c.W.alloc(c.nauxp * c.nauxp, &c.bytes);
   hip_check(fill(c.W.p, c.nauxp * c.nauxp, 0.0, st), "fill");
   std::vector<double> kern = coulomb_kernel_table(c.lat, c.mesh);
-  DBuf<double> dkern;
+  c.kern.alloc(c.ng, &c.bytes);   // kept for the Coulomb matrix builds
+  const double* dkern = c.kern.p;
   int64_t tmpb = 0;
-  dkern.alloc(c.ng, &tmpb);
-  hip_check(hipMemcpyAsync(dkern.p, kern.data(), c.ng * 8, hipMemcpyHostToDevice, st), "copy kernel");
+  hip_check(hipMemcpyAsync(c.kern.p, kern.data(), c.ng * 8, hipMemcpyHostToDevice, st), "copy kernel");
 
   if (c.exact) {
     // chi = identity on the chosen order: V[g] = Vc e_{points[g]}, W[g][g'] = V[g][points[g']]
     hip_check(set_unit_rows(c.V.p, c.ngp, c.dpoints.p, c.naux, st), "unit rows");
-    hip_check(poisson_rows(c.V.p, c.nauxp, c.ngp, c.mesh, dkern.p, st), "poisson");
+    hip_check(poisson_rows(c.V.p, c.nauxp, c.ngp, c.mesh, dkern, st), "poisson");
     hip_check(gather_cols(c.V.p, c.ngp, c.dpoints.p, c.naux, c.W.p, c.nauxp, st), "W");
   } else {
     // ---- fitting metric and Cholesky (Sec. 3.1 Eq. 11, Sec. 4.3)
@@ -487,7 +494,7 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
     }
     stage("fitting functions chi", st);
     // ---- V = Vc chi (Sec. 3.2)
-    hip_check(poisson_rows(c.V.p, c.nauxp, c.ngp, c.mesh, dkern.p, st), "poisson");
+    hip_check(poisson_rows(c.V.p, c.nauxp, c.ngp, c.mesh, dkern, st), "poisson");
     stage("potentials V", st);
     // ---- W = V chi^T = (V X_gR^T) X_gg^-1  (Eq. 14), X_gR recomputed in column blocks
     {
@@ -521,7 +528,6 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
     stage("W", st);
   }
   hip_check(hipStreamSynchronize(st), "sync");
-  dkern.release(nullptr);
   if (prec != RPS_PREC_FP64) {
     c.V32.alloc(c.nauxp * c.ngp, &c.bytes);
     hip_check(to_f32(c.V.p, c.nauxp * c.ngp, c.V32.p, st), "to f32");
@@ -1056,6 +1062,84 @@ void build_full_impl(rps_context& c, int32_t nocc, const double* C, double* K, i
   hip_check(hipStreamSynchronize(st), "sync");   // temporaries are released on return
 }
 
+// ------------------------------------------------------------------ Coulomb matrix
+constexpr int64_t kCoulombChunk = 32ll << 20;   // doubles of U rows per chunk (256 MB)
+constexpr int kCoulombParts = 256;              // blocks of the E_J dot product
+
+// Split count of the J product over the grid (enough workgroups, partials within kSplitWork).
+int coulomb_splits(const rps_context& c) { return gemm_splitk_for(c.Np, c.Np, c.ngp, kSplitWork); }
+
+void ensure_coulomb(rps_context& c, int np) {
+  if (c.jws_np == np) return;
+  int64_t* cnt = &c.bytes;
+  c.jchunk = std::min<int64_t>(c.ngp, std::max<int64_t>(64, kCoulombChunk / np / 64 * 64));
+  c.jCp.alloc(c.Np * np, cnt);
+  c.jCin.alloc(c.nbas * np, cnt);
+  c.jU.alloc(c.jchunk * np, cnt);
+  if (!c.jrho.p) c.jrho.alloc(3 * c.ngp, cnt);
+  if (!c.jwork.p) c.jwork.alloc(std::max(1, coulomb_splits(c)) * c.Np * c.Np, cnt);
+  if (!c.jpart.p) c.jpart.alloc(kCoulombParts, cnt);
+  c.jws_np = np;
+}
+
+// J = dV Phi^T diag(Vc rho) Phi, rho(R) = sum_i U(R, i)^2, U = Phi C (Sec. 2.3, steps 1-4);
+// ej = dV sum_R rho V_H.  All steps run on st in FP64.
+void build_coulomb_impl(rps_context& c, int32_t nocc, const double* C, double* J, double* ej, int32_t flags,
+                        hipStream_t st) {
+  if (c.ng == 0) fail(RPS_ERR_STATE, "context has no completed set-up");
+  if (nocc < 1) fail(RPS_ERR_ARG, "nocc must be >= 1");
+  if (!C || !J) fail(RPS_ERR_ARG, "C and J must not be NULL");
+  if (flags != RPS_PTRS_HOST && flags != RPS_PTRS_DEVICE) fail(RPS_ERR_ARG, "flags must be RPS_PTRS_HOST or RPS_PTRS_DEVICE");
+  if (!c.kern.p) fail(RPS_ERR_STATE, "context has no Coulomb kernel table");
+  const bool dev = (flags == RPS_PTRS_DEVICE);
+  const int np = (int)round_up(nocc, 16);
+  const int64_t Np = c.Np, R = c.ngp, N = c.nbas;
+  ensure_coulomb(c, np);
+  const double* Csrc = C;
+  if (!dev) {
+    hip_check(hipMemcpyAsync(c.jCin.p, C, (size_t)N * nocc * 8, hipMemcpyHostToDevice, st), "copy C");
+    Csrc = c.jCin.p;
+    if (!c.jJ.p) c.jJ.alloc(N * N, &c.bytes);
+  }
+  hip_check(pack_matrix(Csrc, N, nocc, nocc, c.jCp.p, Np, np, st), "pack C");
+  // step 1: density, one chunk of grid rows at a time (rows past N_g have Phi = 0, so rho = 0)
+  for (int64_t r0 = 0; r0 < R; r0 += c.jchunk) {
+    const int64_t m = std::min(c.jchunk, R - r0);
+    Gemm g;   // U = Phi[r0:r0+m] C
+    g.M = m; g.N = np; g.K = Np;
+    g.A = c.Phi.p + r0 * Np; g.lda = Np; g.B = c.jCp.p; g.ldb = np; g.C = c.jU.p; g.ldc = np;
+    hip_check(gemm_f64(g, st), "U chunk");
+    hip_check(density_rows(c.jU.p, m, np, c.jrho.p + r0, R, st), "density");
+  }
+  // steps 2-3: V_H = Vc rho in place on the pair (rho, 0); row 2 keeps rho
+  hip_check(poisson_rows(c.jrho.p, 2, R, c.mesh, c.kern.p, st), "poisson");
+  double* exout = nullptr;
+  if (ej) {
+    exout = dev ? ej : c.jpart.p + (kCoulombParts - 1);
+    hip_check(dot_scaled(c.jrho.p, c.jrho.p + 2 * R, R, c.dV, c.jpart.p, kCoulombParts - 1, exout, st), "E_J");
+  }
+  // step 4: lower tiles of Phi^T diag(V_H) Phi, split over the grid, mirrored and scaled by dV
+  Gemm g;
+  g.M = Np; g.N = Np; g.K = R;
+  g.A = c.Phi.p; g.lda = Np; g.transA = true; g.B = c.Phi.p; g.ldb = Np;
+  g.kscale = c.jrho.p; g.lower_only = true;
+  g.splitk = coulomb_splits(c);
+  if (g.splitk > 1) {
+    g.work = c.jwork.p;
+    g.keep_partials = true;
+  } else {
+    g.C = c.jwork.p; g.ldc = Np;
+  }
+  hip_check(gemm_f64(g, st), "Phi^T diag(V_H) Phi");
+  double* Jout = dev ? J : c.jJ.p;
+  hip_check(sym_from_lower(c.jwork.p, g.splitk, Np, N, c.dV, Jout, st), "J");
+  if (!dev) {
+    hip_check(hipMemcpyAsync(J, c.jJ.p, (size_t)N * N * 8, hipMemcpyDeviceToHost, st), "copy J");
+    if (ej) hip_check(hipMemcpyAsync(ej, exout, 8, hipMemcpyDeviceToHost, st), "copy E_J");
+    hip_check(hipStreamSynchronize(st), "sync");
+  }
+}
+
 // ------------------------------------------------------------------ autotuner
 // Mean time of `reps` device-pointer builds after one warm-up build (which
 // also allocates any workspace the launch shape needs).
@@ -1296,6 +1380,14 @@ rps_status rps_build_exchange_full(rps_context* ctx, int32_t nocc, const double*
   return guarded([&] {
     if (!ctx) fail(RPS_ERR_ARG, "ctx must not be NULL");
     build_full_impl(*ctx, nocc, C, K, flags, (hipStream_t)hip_stream);
+  });
+}
+
+rps_status rps_build_coulomb(rps_context* ctx, int32_t nocc, const double* C, double* J, double* ej, int32_t flags,
+                             void* hip_stream) {
+  return guarded([&] {
+    if (!ctx) fail(RPS_ERR_ARG, "ctx must not be NULL");
+    build_coulomb_impl(*ctx, nocc, C, J, ej, flags, (hipStream_t)hip_stream);
   });
 }
 

@@ -27,6 +27,8 @@ struct Gemm {
   const float* D32 = nullptr;                    // FP32 form of that operand (used when D is NULL)
   int splitk = 1;            // > 1: K split over workgroups, partials in work (EPI_AXPBY only)
   double* work = nullptr;    // splitk * M * N doubles
+  bool keep_partials = false;          // splitk > 1: leave the partials in work, no reduction
+  const double* kscale = nullptr;      // op(B)[k][n] *= kscale[k] (transA && !transB, or N <= 16)
 };
 hipError_t gemm_f64(const Gemm& g, hipStream_t s);
 // Split count giving enough workgroups for a long-K product within work_cap doubles.
@@ -89,6 +91,19 @@ hipError_t pivoted_cholesky(double* G, int64_t n, int64_t ld, int64_t k, int64_t
 // of the grid mesh, leading dimension ld.  kern[N_g]: k(G) / N_g in FFT order.
 hipError_t poisson_rows(double* V, int64_t nrows, int64_t ld, const int mesh[3],
                         const double* kern, hipStream_t s);
+
+// ---------------------------------------------------------------- Coulomb matrix
+// For r < rows: out[r] = out[2 ld + r] = sum_{i < np} U[r][i]^2 (U pitch np, np even)
+// and out[ld + r] = 0, i.e. the density as the real row of a Poisson pair plus a copy.
+hipError_t density_rows(const double* U, int64_t rows, int np, double* out, int64_t ld, hipStream_t s);
+// *out = scale * sum_{p < n} x[p] y[p], summed in a fixed order over nparts blocks
+// (part: nparts doubles of workspace).
+hipError_t dot_scaled(const double* x, const double* y, int64_t n, double scale, double* part, int nparts,
+                      double* out, hipStream_t s);
+// J[i][j] = scale * sum_{z < nz} work[z][max(i,j)][min(i,j)] for i, j < N (work [nz][Np][Np],
+// lower triangle valid).
+hipError_t sym_from_lower(const double* work, int nz, int64_t Np, int64_t N, double scale, double* J,
+                          hipStream_t s);
 
 // ---------------------------------------------------------------- exchange build
 struct FusedArgs {

@@ -27,6 +27,10 @@ def test_header_and_exports_agree():
     lib = P.load()
     for name in decl:
         assert hasattr(lib, name), name
+        # every entry point that takes arguments has them declared (ctypes would
+        # otherwise pass 64-bit pointers as 32-bit ints)
+        if name not in ("rps_abi_version", "rps_last_error"):
+            assert getattr(lib, name).argtypes, name
     assert lib.rps_abi_version() == 1
 
 
@@ -98,6 +102,8 @@ def test_calls_without_context_fail_cleanly():
     assert lib.rps_build_exchange_occRI(None, 2, C.ctypes.data, K.ctypes.data, None, 0, None) == B.RPS_ERR_ARG
     assert "ctx" in lib.rps_last_error().decode()
     assert lib.rps_get_points(None, None) == B.RPS_ERR_ARG
+    assert lib.rps_build_coulomb(None, 2, C.ctypes.data, K.ctypes.data, None, 0, None) == B.RPS_ERR_ARG
+    assert "ctx" in lib.rps_last_error().decode()
     lib.rps_destroy(None)
 
 

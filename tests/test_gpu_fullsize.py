@@ -1,5 +1,6 @@
 """Full-size GPU checks (supercells 2x2x2 and 3x3x3) through properties that
-hold at any size, in the launch configuration the benchmark times.
+hold at any size, in the launch configuration the benchmark times, plus the
+2x2x2 Coulomb matrix against the oracle at full size.
 
 At these sizes the oracle cannot form V (15 GB and 121 GB in FP64), so the
 checks are the invariants of Eq. 16 and of the occ-RI exchange:
@@ -17,6 +18,7 @@ import numpy as np
 import pytest
 
 import rps_inputs as ri
+from oracle import basis, coulomb, grid
 
 pytestmark = pytest.mark.gpu
 
@@ -79,6 +81,24 @@ def test_supercell_2x2x2_forms(lib):
                 assert abs(Es - E64[s]) < 1e-6
 
 
+def test_supercell_2x2x2_coulomb_against_oracle(lib):
+    """Config 3 Coulomb matrix against the FP64 oracle at full size (the oracle
+    evaluates its own basis on the 72^3 grid: about a minute of CPU)."""
+    w = ri.diamond_2x2x2()
+    _say(f"case: {w.name} Coulomb matrix vs oracle")
+    Phi = basis.eval_basis(w)
+    dV = grid.dvol(w.lattice, w.mesh)
+    C = ri.lowdin(ri.random_coefficients(w), basis.overlap(Phi, dV))
+    Jref, Eref, _ = coulomb.build_j(Phi, C, w.lattice, w.mesh)
+    del Phi
+    with lib.Context.from_workload(w, seed=w.sketch_seed()) as ctx:
+        J, E = ctx.build_coulomb(C)
+    d = np.abs(J - Jref).max() / np.abs(Jref).max()
+    _say(f"  E_J={E:.10f} dE_J={E - Eref:.3e} max|dJ|/max|J|={d:.3e}")
+    assert d < 1e-11 and abs(E - Eref) < 1e-11 * abs(Eref)
+    assert np.array_equal(J, J.T)
+
+
 def test_supercell_3x3x3_scf_steps(lib):
     """Config 4: FP64 GEMM form, then the precision form (FP32 V) on the same
     points, over SCF-like steps.  The two contexts live one after the other
@@ -92,6 +112,15 @@ def test_supercell_3x3x3_scf_steps(lib):
         steps = [C]
         for s in range(1, 3):
             steps.append(ri.perturbed(steps[-1], S, s, angle=0.01, w=w))
+        # Coulomb matrix at full size: exact symmetry, both energy routes, occupied rotation
+        J, EJ = ctx.build_coulomb(C)
+        JQ, EJQ = ctx.build_coulomb(C @ _orth(C.shape[1], 12))
+        eh = float(np.einsum("mi,mn,ni->", C, J, C))
+        dq = np.abs(JQ - J).max() / np.abs(J).max()
+        _say(f"  Coulomb: E_J={EJ:.10f} routes={abs(eh - EJ) / EJ:.2e} rotJ={dq:.2e} rotE={abs(EJQ - EJ) / EJ:.2e}")
+        assert EJ > 0 and np.array_equal(J, J.T)
+        assert abs(eh - EJ) < 1e-10 * EJ and dq < 1e-10 and abs(EJQ - EJ) < 1e-10 * EJ
+        del J, JQ
         ref = []
         for s, Cs in enumerate(steps):
             K, E = ctx.build(Cs)
