@@ -7,7 +7,9 @@ reductions and the final combine.  Repeated device-pointer builds replay the
 library's captured HIP graph of the build (the fit-fit kernel on a parallel
 branch); kernel times come from a separate profiled pass of eager builds.  The ISDF set-up (points, V, W) runs once
 before the timed region and is reported separately.  Inputs (C) are resident
-in device memory when the timed region starts.
+in device memory when the timed region starts.  The Coulomb matrix build (J,
+E_J; Sec. 2.3) is timed after it on the FP64 context and reported with the
+paper's cost ratio K / J.
 
 Default workload: the 8-atom diamond-like cell (L = 6.74 bohr, 48^3 grid,
 N = 104, n_occ = 16) with N_aux = 6N = 624.  The timed path (`value`) is the
@@ -69,9 +71,10 @@ def cpu_baseline(w, nrep: int = 3):
                       f"on seeded arrays, after one warm-up; {dt:.3f} s per build"}
 
 
-def _time_path(P, w, prec, points, C, steps, warmup):
+def _time_path(P, w, prec, points, C, steps, warmup, coulomb=False):
     """Set up one context (given points), then time `steps` builds after
-    `warmup` untimed ones, C and the outputs resident in device memory."""
+    `warmup` untimed ones, C and the outputs resident in device memory.
+    coulomb: also time the Coulomb matrix build (J, E_J) the same way."""
     import torch
     t0 = time.perf_counter()
     ctx = P.Context.from_workload(w, points=points, precision=prec)
@@ -102,6 +105,19 @@ def _time_path(P, w, prec, points, C, steps, warmup):
            "build_us_events": prof["build_ms"] / nb * 1e3, "setup_s": setup_s,
            "setup_s_library": float(ctx.info()["setup_seconds"]),
            "E_x": float(ex.item()), "K": K.cpu().numpy(), "tuned_ms": tuned_ms}
+    if coulomb:
+        J = torch.empty((w.nbas, w.nbas), dtype=torch.float64, device=dev)
+        ej = torch.zeros(1, dtype=torch.float64, device=dev)
+        js = max(1, min(steps, 200))
+        for _ in range(max(1, min(warmup, 10))):
+            ctx.build_coulomb(Cd, J, ej)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(js):
+            ctx.build_coulomb(Cd, J, ej)
+        torch.cuda.synchronize()
+        res["coulomb_ms"] = (time.perf_counter() - t0) / js * 1e3
+        res["E_J"] = float(ej.item())
     ctx.close()
     return res
 
@@ -273,7 +289,7 @@ def main():
 
     mixed = args.precision != "fp64"
     mprec = P.PREC_BF16X3 if args.precision == "bf16x3" else P.PREC_FP32
-    ref = _time_path(P, w, P.PREC_FP64, points, C, args.steps, args.warmup)
+    ref = _time_path(P, w, P.PREC_FP64, points, C, args.steps, args.warmup, coulomb=True)
     run = _time_path(P, w, mprec, points, C, args.steps, args.warmup) if mixed else ref
 
     n, naux, ng, N = w.nocc, w.naux, w.ngrid, w.nbas
@@ -320,6 +336,16 @@ def main():
         "build_avg_us_events": round(run["build_us_events"], 3),
         "setup_s": round(select_s + run["setup_s"], 3),
         "E_x": run["E_x"],
+        # Coulomb matrix on the same grid (FP64, dense Phi) and the paper's cost ratio K / J
+        "coulomb": {"build_ms": round(ref["coulomb_ms"], 5), "E_J": ref["E_J"],
+                    # algorithmic work: U = Phi C (2 N_g N n) and the lower triangle of J (N_g N (N + 1))
+                    "algorithmic_flops": 2.0 * ng * N * n + float(ng) * N * (N + 1),
+                    "achieved_tflops_fp64": round((2.0 * ng * N * n + float(ng) * N * (N + 1))
+                                                  / (ref["coulomb_ms"] * 1e-3) / 1e12, 3),
+                    "frac_fp64_peak": round((2.0 * ng * N * n + float(ng) * N * (N + 1))
+                                            / (ref["coulomb_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+                    "k_over_j_fp64": round(ref["ms_per_step"] / ref["coulomb_ms"], 4),
+                    "k_over_j_timed_path": round(run["ms_per_step"] / ref["coulomb_ms"], 4)},
     }
     if mixed:
         dK = float(np.abs(run["K"] - ref["K"]).max() / np.abs(ref["K"]).max())

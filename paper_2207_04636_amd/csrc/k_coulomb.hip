@@ -52,25 +52,45 @@ __global__ __launch_bounds__(256) void dot_blocks_kernel(const double* __restric
   if (tid == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void sum_scaled_kernel(const double* __restrict__ part, int n, double scale, double* __restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += part[i];
-    *out = scale * s;
+// *out = scale * sum_i part[i]: one block, strided partial sums, fixed-order tree
+__global__ __launch_bounds__(256) void sum_scaled_kernel(const double* __restrict__ part, int n, double scale,
+                                                         double* __restrict__ out) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int i = tid; i < n; i += 256) s += part[i];
+  red[tid] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
   }
+  if (tid == 0) *out = scale * red[0];
 }
 
-// J[i][j] = scale * sum_z work[z][max(i,j)][min(i,j)]
-__global__ __launch_bounds__(256) void sym_from_lower_kernel(const double* __restrict__ work, int nz, int64_t Np,
-                                                             int64_t N, double scale, double* __restrict__ J) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= N * N) return;
-  const int64_t i = t / N, j = t % N;
-  const int64_t hi = (i > j) ? i : j, lo = (i > j) ? j : i;
-  const double* w = work + hi * Np + lo;
+// J[i][j] = J[j][i] = scale * sum_z work[z][i][j] for j <= i < N.  Block (64, ZG):
+// 64 consecutive elements of the [Np][Np] partials, ZG interleaved groups of z
+// summed separately, then combined in a fixed order.
+constexpr int ZG = 4;
+__global__ __launch_bounds__(64 * ZG) void sym_from_lower_kernel(const double* __restrict__ work, int nz, int64_t Np,
+                                                                 int64_t N, double scale, double* __restrict__ J) {
+  __shared__ double red[ZG][64];
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int64_t e = (int64_t)blockIdx.x * 64 + tx;
+  const int64_t i = e / Np, j = e % Np;
+  const bool live = (i < N) && (j <= i);
   double s = 0.0;
-  for (int z = 0; z < nz; ++z) s += w[(int64_t)z * Np * Np];
-  J[t] = scale * s;
+  if (live)
+    for (int z = ty; z < nz; z += ZG) s += work[(int64_t)z * Np * Np + e];
+  red[ty][tx] = s;
+  __syncthreads();
+  if (ty == 0 && live) {
+    double t = red[0][tx];
+    for (int g = 1; g < ZG; ++g) t += red[g][tx];
+    t *= scale;
+    J[i * N + j] = t;
+    J[j * N + i] = t;
+  }
 }
 
 }  // namespace
@@ -86,15 +106,15 @@ hipError_t dot_scaled(const double* x, const double* y, int64_t n, double scale,
                       double* out, hipStream_t s) {
   if (nparts < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(dot_blocks_kernel, dim3((unsigned)nparts), dim3(256), 0, s, x, y, n, part);
-  hipLaunchKernelGGL(sum_scaled_kernel, dim3(1), dim3(64), 0, s, part, nparts, scale, out);
+  hipLaunchKernelGGL(sum_scaled_kernel, dim3(1), dim3(256), 0, s, part, nparts, scale, out);
   return hipGetLastError();
 }
 
 hipError_t sym_from_lower(const double* work, int nz, int64_t Np, int64_t N, double scale, double* J,
                           hipStream_t s) {
-  const int64_t cnt = N * N;
-  if (cnt <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sym_from_lower_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, work, nz, Np, N,
+  if (N <= 0) return hipSuccess;
+  const int64_t cnt = N * Np;   // rows below N of the partials
+  hipLaunchKernelGGL(sym_from_lower_kernel, dim3((unsigned)((cnt + 63) / 64)), dim3(64, ZG), 0, s, work, nz, Np, N,
                      scale, J);
   return hipGetLastError();
 }

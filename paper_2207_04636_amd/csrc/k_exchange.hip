@@ -895,13 +895,21 @@ __global__ void pack_kernel(const double* __restrict__ C, int64_t rows, int64_t 
   Cp[t] = (r < rows && c < cols) ? C[r * ldc + c] : 0.0;
 }
 
-// ex = -dV sum of the energy partials of the finalize kernel, in order.
-__global__ void energy_sum_kernel(const double* __restrict__ part, int n, double dV, double* __restrict__ ex) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += part[i];
-    *ex = -dV * s;
+// ex = -dV sum of the energy partials of the finalize kernel (one block of 256,
+// strided partial sums, fixed-order tree).
+__global__ __launch_bounds__(256) void energy_sum_kernel(const double* __restrict__ part, int n, double dV,
+                                                         double* __restrict__ ex) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int i = tid; i < n; i += 256) s += part[i];
+  red[tid] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
   }
+  if (tid == 0) *ex = -dV * red[0];
 }
 
 // K[i][j] = dV (T[i][j] + T[j][i] - K3[i][j]) for i, j < N (T, K3 pitch Np).
@@ -1092,7 +1100,7 @@ hipError_t finalize(const double* Phig, const double* M2, int64_t G, const doubl
   if (neb < 1) neb = 1;
   hipLaunchKernelGGL(finalize_kernel, dim3(ntile + neb), dim3(512), 0, s, Phig, M2, G, K1, K3, N, n, np, Np, s1, s2,
                      s3, dV, K, e1p, ne1, e3p, ne3, ce1, ce3, ex, dots);
-  if (neb > 1 && ex) hipLaunchKernelGGL(energy_sum_kernel, dim3(1), dim3(64), 0, s, dots.part, neb, dV, ex);
+  if (neb > 1 && ex) hipLaunchKernelGGL(energy_sum_kernel, dim3(1), dim3(256), 0, s, dots.part, neb, dV, ex);
   return hipGetLastError();
 }
 

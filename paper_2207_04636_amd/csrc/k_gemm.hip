@@ -116,13 +116,14 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(Gemm g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int l16 = lane & 15, lq = lane >> 4;
+  const int bz = blockIdx.z;
   const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
   if (g.lower_only && n0 > m0 + BM - 1) return;
 
   int64_t kbeg = 0, kend = g.K;
   if (g.splitk > 1) {
     const int64_t per = ((g.K + g.splitk - 1) / g.splitk + BK - 1) / BK * BK;
-    kbeg = (int64_t)blockIdx.z * per;
+    kbeg = (int64_t)bz * per;
     kend = (kbeg + per < g.K) ? kbeg + per : g.K;
   }
   const int64_t nk = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
@@ -229,7 +230,7 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(Gemm g) {
         if (gm < g.M && gn < g.N) {
           const double v = g.alpha * acc[i][j][r];
           if (g.splitk > 1) {
-            g.work[((int64_t)blockIdx.z * g.M + gm) * g.N + gn] = v;
+            g.work[((int64_t)bz * g.M + gm) * g.N + gn] = v;
             continue;
           }
           double* c = g.C + gm * g.ldc + gn;

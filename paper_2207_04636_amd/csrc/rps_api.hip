@@ -1066,8 +1066,19 @@ void build_full_impl(rps_context& c, int32_t nocc, const double* C, double* K, i
 constexpr int64_t kCoulombChunk = 32ll << 20;   // doubles of U rows per chunk (256 MB)
 constexpr int kCoulombParts = 256;              // blocks of the E_J dot product
 
-// Split count of the J product over the grid (enough workgroups, partials within kSplitWork).
-int coulomb_splits(const rps_context& c) { return gemm_splitk_for(c.Np, c.Np, c.ngp, kSplitWork); }
+// Split count of the J product over the grid: the smallest power of two giving at
+// least two workgroups per compute unit over the lower output tiles, at least 128
+// grid rows per split and partials within kSplitWork.
+int coulomb_splits(const rps_context& c) {
+  const int64_t bn = (c.Np <= 16) ? 16 : (c.Np <= 64) ? 64 : 128;   // output tile width of gemm_f64
+  const int64_t tm = (c.Np + 127) / 128, tn = (c.Np + bn - 1) / bn;
+  int64_t active = 0;
+  for (int64_t i = 0; i < tm; ++i)
+    for (int64_t j = 0; j < tn; ++j) active += (j * bn <= i * 128 + 127);
+  int64_t z = 1;
+  while (active * z < 512 && c.ngp / (z * 2) >= 128 && (z * 2) * c.Np * c.Np <= kSplitWork) z *= 2;
+  return (int)z;
+}
 
 void ensure_coulomb(rps_context& c, int np) {
   if (c.jws_np == np) return;
