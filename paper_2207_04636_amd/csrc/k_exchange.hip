@@ -23,6 +23,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "mfma.h"
 #include "rps_internal.h"
@@ -677,6 +678,244 @@ __global__ __launch_bounds__(NW * 64) void fused_f32_kernel(FusedArgs a) {
   }
 }
 
+// Precision form, n <= 16, with the orbitals formed tile by tile in the kernel.
+// Per R tile (64 grid rows) the FP32 basis rows are staged in LDS once and serve
+// both ends of the tile:
+//   start: U = Phi C on the FP64 matrix cores (FP32 basis values, FP64 C),
+//          rounded to FP32 for the in-tile products (as U is in the form above);
+//   end:   K1 += Phi^T M1^T in FP64.
+// The orbitals therefore never leave the chip and the basis is read once per
+// build in FP32.  Other choices, all for the latency of the V stream:
+//  * every wave steps through NMY g subtiles per tile (the workgroup's block of
+//    g rows split over 8 waves; a wave with fewer subtiles idles on the rest),
+//    so the double buffer of V fragments has a fixed parity per step and V is
+//    requested two steps ahead (tiles are processed in pairs for that);
+//  * inside a tile, position p = 16 c + j of the 64 columns is grid row
+//    R0 + 4 j + c, so a lane's four V values of a row are one 16-byte load;
+//  * U_g rows of the workgroup sit in LDS in FP32; M2 accumulates in FP64
+//    registers; the U operands of the tile's products sit in registers.
+// NW = 8 waves; Np <= 128.
+template <int NMY>
+__global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
+  constexpr int NW = 8;
+  constexpr int NP = 16;
+  constexpr int LDU = NP + 1;
+  constexpr int SL = T + 4;                // FP32 slab pitch (floats)
+  extern __shared__ double smem[];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int Np = a.Np, PP = Np + 4;
+
+  const int64_t gsub_total = a.G / 16;
+  const int64_t gper = ((a.G / T + a.gblocks - 1) / a.gblocks) * (T / 16);
+  const int gb = blockIdx.x % a.gblocks;
+  const int rb = blockIdx.x / a.gblocks;
+  const int64_t gs0 = gb * gper;
+  const int64_t gs1 = (gs0 + gper < gsub_total) ? gs0 + gper : gsub_total;
+  const int64_t rtiles_valid = (a.R_valid + T - 1) / T;
+  const int64_t rt0 = (int64_t)rb * a.rtiles;
+  const int64_t rt1 = (rt0 + a.rtiles < rtiles_valid) ? rt0 + a.rtiles : rtiles_valid;
+
+  // LDS (bytes): area0 | sPhi [T][PP] f32 | sC [Np][16] f64 | m1s [T][16] f64 | sU [T][LDU] f32
+  //              | sUg [gper*16][LDU] f32
+  // area0 holds, one after another within a tile: the U partials [2][T][16] f64,
+  // the waves' A slabs [NW][16][SL] f32, the M1 partials [NW][T][16] f32.
+  constexpr int AREA0 = NW * 16 * SL * 4;
+  char* base = reinterpret_cast<char*>(smem);
+  double* upart = reinterpret_cast<double*>(base);
+  float* slab = reinterpret_cast<float*>(base) + w * 16 * SL;
+  float* red = reinterpret_cast<float*>(base);
+  float* sPhi = reinterpret_cast<float*>(base + AREA0);
+  double* sC = reinterpret_cast<double*>(base + AREA0 + (int64_t)T * PP * 4);
+  double* m1s = sC + Np * NP;
+  float* sU = reinterpret_cast<float*>(m1s + T * NP);
+  float* sUg = sU + T * LDU;
+
+  const int nmy = (gs1 - gs0 > w) ? (int)((gs1 - gs0 - w + NW - 1) / NW) : 0;   // <= NMY (host check)
+
+  for (int e = tid; e < Np * NP; e += NW * 64) {
+    const int r = e / NP, c = e % NP;
+    sC[e] = (r < a.N && c < a.n) ? a.Cm[(int64_t)r * a.n + c] : 0.0;
+  }
+  for (int64_t e = tid; e < (gs1 - gs0) * 16 * NP; e += NW * 64)
+    sUg[(e / NP) * LDU + (e % NP)] = (float)a.Ug[gs0 * 16 * NP + e];
+
+  // V fragment of step (tile rt, subtile si): lane holds V[g0 + 4lq + r][R0 + 4 l16 + c]
+  float vb[2][4][4];
+  auto load_v = [&](float (&dst)[4][4], int64_t rt, int si) {
+    const int64_t R0 = rt * T, g0 = (gs0 + w + (int64_t)si * NW) * 16;
+    const float* src = a.Vm32 + (g0 + 4 * lq) * a.ldv + R0 + 4 * l16;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float4 q = *reinterpret_cast<const float4*>(src + (int64_t)r * a.ldv);
+      dst[r][0] = q.x; dst[r][1] = q.y; dst[r][2] = q.z; dst[r][3] = q.w;
+    }
+  };
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int64_t rt = rt0 + s / NMY;
+    const int si = s % NMY;
+    if (rt < rt1 && si < nmy) load_v(vb[s & 1], rt, si);
+  }
+
+  double m2acc[NMY][4];
+#pragma unroll
+  for (int si = 0; si < NMY; ++si)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) m2acc[si][r] = 0.0;
+  d4_t k1 = zero_d4();
+  const int mt = Np / 16;
+
+  auto tile = [&](auto tau, int64_t rt) {
+    constexpr int TAU = decltype(tau)::value;
+    const int64_t R0 = rt * T;
+    __syncthreads();   // the previous tile is done with sPhi, m1s and area0
+    {
+      // basis rows of the tile: row r of T, Np floats (Np / 4 float4 pieces, one per lane)
+      const float4* src = reinterpret_cast<const float4*>(a.Phi32 + R0 * Np);
+      const int nq = Np / 4;
+      for (int r = w; r < T; r += NW)
+        if (lane < nq) {
+          const float4 v = src[(int64_t)r * nq + lane];
+          float* d = sPhi + r * PP + 4 * lane;
+          d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+        }
+    }
+    __syncthreads();
+    {
+      // U partials: wave w -> rows 16 (w % 4) .. +15, basis functions of half w / 4
+      const int sub = w & 3, half = w >> 2;
+      const int kh = Np / 8;                 // k steps of 4 per half
+      const float* pa = sPhi + (16 * sub + l16) * PP + half * (Np / 2) + lq;
+      const double* pb = sC + (half * (Np / 2) + lq) * NP + l16;
+      d4_t acc = zero_d4();
+      for (int kk = 0; kk < kh; ++kk) acc = mfma_f64((double)pa[4 * kk], pb[4 * kk * NP], acc);
+      double* up = upart + half * T * NP + (16 * sub + lq) * NP + l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) up[4 * r * NP] = acc[r];
+    }
+    __syncthreads();
+    for (int e = tid; e < T * NP; e += NW * 64) sU[(e / NP) * LDU + (e % NP)] = (float)(upart[e] + upart[T * NP + e]);
+    __syncthreads();
+    // U operands of the tile's products (column position p = 16 c + j is row 4 j + c):
+    // P = U_g U^T: B[k = i][n = p]; M2 = A U: B[k = p][n = i], in registers when room
+    constexpr bool BMREG = (NMY <= 4);
+    float bP[4][4], bM[16];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bP[kk][c] = sU[(4 * l16 + c) * LDU + 4 * kk + lq];
+    auto bm_row = [&](int kk) { return 4 * ((4 * kk + lq) & 15) + (kk >> 2); };
+    if (BMREG)
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) bM[kk] = sU[bm_row(kk) * LDU + l16];
+
+    f4_t m1[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) m1[c] = zero_f4();
+
+#pragma unroll
+    for (int si = 0; si < NMY; ++si) {
+      const int b = (TAU * NMY + si) & 1;
+      float v[4][4];
+      if (si < nmy) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) v[r][c] = vb[b][r][c];
+      }
+      {
+        // request the V fragment two steps ahead into the buffer just read
+        const int tg = si + 2;
+        const int64_t trt = rt + tg / NMY;
+        const int tsi = tg % NMY;
+        if (trt < rt1 && tsi < nmy) load_v(vb[b], trt, tsi);
+      }
+      if (si < nmy) {
+        const int gl = (w + si * NW) * 16;     // local row of the subtile in sUg
+        float ugA[4], ugB[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) ugA[kk] = sUg[(gl + l16) * LDU + 4 * kk + lq];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ugB[r] = sUg[(gl + 4 * lq + r) * LDU + l16];
+        f4_t p[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) p[c] = zero_f4();
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) p[c] = mfma_f32(ugA[kk], bP[kk][c], p[c]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          f4_t av;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            av[r] = v[r][c] * p[c][r];
+            slab[(4 * lq + r) * SL + 16 * c + l16] = av[r];
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) m1[c] = mfma_f32(av[r], ugB[r], m1[c]);
+        }
+        __builtin_amdgcn_wave_barrier();
+        f4_t m2 = zero_f4();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk)
+          m2 = mfma_f32(slab[l16 * SL + 4 * kk + lq], BMREG ? bM[kk] : sU[bm_row(kk) * LDU + l16], m2);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) m2acc[si][r] += (double)m2[r];
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+
+    __syncthreads();
+    // wave w's partial M1^T: m1[c][r] is row R0 + 4 (4 lq + r) + c, column l16 -> red (FP32)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[(w * 64 + 16 * lq + 4 * r + c) * 16 + l16] = m1[c][r];
+    __syncthreads();
+    if (w < 4) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double s = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) s += (double)red[(ww * 64 + 16 * w + 4 * r + lq) * 16 + l16];
+        m1s[(16 * w + 4 * r + lq) * 16 + l16] = s;
+      }
+    }
+    __syncthreads();
+    if (a.want_k1 && w < mt) {
+      const float* ph = sPhi + lq * PP + 16 * w + l16;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          k1 = mfma_f64((double)ph[(16 * q + 4 * r) * PP], m1s[(16 * q + 4 * r + lq) * 16 + l16], k1);
+    }
+  };
+
+  for (int64_t rt = rt0; rt < rt1; rt += 2) {
+    tile(std::integral_constant<int, 0>{}, rt);
+    if (rt + 1 < rt1) tile(std::integral_constant<int, 1>{}, rt + 1);
+  }
+
+  const int wg = blockIdx.x;
+  if (a.want_k1 && w < mt) {
+    double* out = a.K1p + (int64_t)wg * a.Np * NP;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[(int64_t)(16 * w + 4 * r + lq) * NP + l16] = k1[r];
+  }
+  // M2 rows of the wave's subtiles: M2[g0 + 4lq + r][l16]
+  double* out = a.M2p + (int64_t)rb * a.G * NP;
+#pragma unroll
+  for (int si = 0; si < NMY; ++si)
+    if (si < nmy) {
+      const int64_t g0 = (gs0 + w + si * NW) * 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[(g0 + 4 * lq + r) * NP + l16] = m2acc[si][r];
+    }
+}
+
 // Orbitals on the grid and at the points: U = Phi C and U_g = Phi_g C.
 // Row subtiles 16 at a time on the FP64 matrix cores; rows [0, R) come from
 // Phi, rows [R, R + G) from Phi_g.  C [N x n] (row pitch n) is read once into
@@ -980,6 +1219,24 @@ hipError_t launch_f32(const FusedArgs& a, int blocks, hipStream_t s) {
   return hipGetLastError();
 }
 
+// LDS bytes of fused_f32u_kernel (8 waves) for gper g subtiles per workgroup
+int64_t f32u_lds_bytes(int Np, int64_t gper) {
+  return (int64_t)8 * 16 * (T + 4) * 4 + (int64_t)T * (Np + 4) * 4 + (int64_t)Np * 16 * 8 + (int64_t)T * 16 * 8 +
+         (int64_t)T * 17 * 4 + gper * 16 * 17 * 4;
+}
+
+template <int NMY>
+hipError_t launch_f32u(const FusedArgs& a, int blocks, hipStream_t s) {
+  const int64_t gper = ((a.G / T + a.gblocks - 1) / a.gblocks) * (T / 16);
+  const int64_t lds = f32u_lds_bytes(a.Np, gper);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  auto k = fused_f32u_kernel<NMY>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(512), (size_t)lds, s, a);
+  return hipGetLastError();
+}
+
 template <int NW>
 hipError_t launch_f32_mt(const FusedArgs& a, int blocks, hipStream_t s) {
   const int mt = a.want_k1 ? a.Np / 16 : 0;
@@ -991,6 +1248,22 @@ hipError_t launch_f32_mt(const FusedArgs& a, int blocks, hipStream_t s) {
 
 template <int NI>
 hipError_t launch_fused1(const FusedArgs& a, int blocks, hipStream_t s) {
+  if (NI == 1 && a.prec != 0 && a.Vm32 && a.Phi32) {
+    // orbitals formed in the kernel: M2 (and K1) fused, no M1 output, no energy partials
+    if (!a.Cm || !a.want_m2 || a.want_m1 || a.want_e || a.nwaves != 8 || a.Np > 128)
+      return hipErrorInvalidValue;
+    switch (fused_f32u_nmy(a)) {   // subtiles per wave, exactly (the kernel's step count per tile)
+      case 1: return launch_f32u<1>(a, blocks, s);
+      case 2: return launch_f32u<2>(a, blocks, s);
+      case 3: return launch_f32u<3>(a, blocks, s);
+      case 4: return launch_f32u<4>(a, blocks, s);
+      case 5: return launch_f32u<5>(a, blocks, s);
+      case 6: return launch_f32u<6>(a, blocks, s);
+      case 7: return launch_f32u<7>(a, blocks, s);
+      case 8: return launch_f32u<8>(a, blocks, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (NI == 1 && a.prec != 0 && a.Vm32) {
     if (a.nwaves == 8) return launch_f32_mt<8>(a, blocks, s);
     return launch_f32_mt<4>(a, blocks, s);
@@ -1008,6 +1281,16 @@ hipError_t launch_fused1(const FusedArgs& a, int blocks, hipStream_t s) {
 }
 
 }  // namespace
+
+int64_t fused_f32u_nmy(const FusedArgs& a) {
+  const int64_t gper = ((a.G / T + a.gblocks - 1) / a.gblocks) * (T / 16);
+  return (gper + 7) / 8;
+}
+
+int64_t fused_f32u_lds(const FusedArgs& a) {
+  const int64_t gper = ((a.G / T + a.gblocks - 1) / a.gblocks) * (T / 16);
+  return f32u_lds_bytes(a.Np, gper);
+}
 
 int fused_rblocks(const FusedArgs& a) {
   const int64_t rt = (a.R_valid + T - 1) / T;

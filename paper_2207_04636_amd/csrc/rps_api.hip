@@ -80,6 +80,7 @@ struct rps_context {
   // persistent device data
   DBuf<double> Phi, Phig, V, W;
   DBuf<float> V32;
+  DBuf<float> Phi32;   // precision form, N <= 128: FP32 basis for the in-kernel orbitals
   DBuf<int64_t> dpoints;
   // build workspace (grows on demand)
   int ws_np = -1;
@@ -136,6 +137,7 @@ struct rps_context {
     DBuf<double>* jb[] = {&kern, &jCp, &jCin, &jU, &jrho, &jwork, &jpart, &jJ};
     for (auto* b : jb) b->release(nullptr);
     V32.release(nullptr);
+    Phi32.release(nullptr);
     dpoints.release(nullptr);
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     clear_graphs();
@@ -533,6 +535,12 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
     hip_check(to_f32(c.V.p, c.nauxp * c.ngp, c.V32.p, st), "to f32");
     hip_check(hipStreamSynchronize(st), "sync");
     c.V.release(&c.bytes);      // the precision form keeps only the FP32 copy of V
+    const char* fu = getenv("RPS_F32_FUSED_U");
+    if (c.Np <= 128 && !(fu && fu[0] == '0')) {
+      c.Phi32.alloc(c.ngp * c.Np, &c.bytes);
+      hip_check(to_f32(c.Phi.p, c.ngp * c.Np, c.Phi32.p, st), "Phi to f32");
+      hip_check(hipStreamSynchronize(st), "sync");
+    }
   }
   c.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -560,6 +568,10 @@ void prof_mark(rps_context& c, int slot, hipStream_t st) {
 // one workgroup per CU (8 waves when np == 16, else 4), all g rows of a
 // workgroup kept in LDS (M2 accumulators) unless they do not fit, then
 // g blocks; R tiles split so that the workgroups cover the CUs once.
+// The precision form with n <= 16 forms the orbitals in its kernel when the FP32
+// basis is stored (N <= 128).
+bool uses_f32u(const rps_context& c, int np) { return c.Phi32.p && np == 16; }
+
 void choose_shape(rps_context& c, int np, FusedArgs& a) {
   a.nwaves = (np == 16) ? 8 : 4;
   a.np = np;
@@ -567,10 +579,17 @@ void choose_shape(rps_context& c, int np, FusedArgs& a) {
   a.want_m2 = 1;
   const int64_t lds_cap = 160 * 1024;
   const int64_t gt = c.nauxp / 64;
+  const bool f32u = uses_f32u(c, np);
+  // the in-kernel-orbitals kernel holds M2 in registers (at most 8 g subtiles per
+  // wave); the others hold this workgroup's M2 block in LDS
+  a.Np = (int)c.Np;
+  auto fits = [&](const FusedArgs& t) {
+    return f32u ? (fused_f32u_nmy(t) <= 8 && fused_f32u_lds(t) <= lds_cap) : fused_lds_bytes(t) <= lds_cap;
+  };
   a.gblocks = 1;
   a.rtiles = 1;
   while (true) {
-    if (fused_lds_bytes(a) <= lds_cap || a.gblocks >= gt) break;
+    if (fits(a) || a.gblocks >= gt) break;
     ++a.gblocks;
   }
   const int64_t rt = c.ngp / 64;
@@ -583,14 +602,14 @@ void choose_shape(rps_context& c, int np, FusedArgs& a) {
       FusedArgs t = a;
       t.rtiles = x;
       t.gblocks = y;
-      if (fused_lds_bytes(t) <= lds_cap) { a.rtiles = x; a.gblocks = y; }
+      if (fits(t)) { a.rtiles = x; a.gblocks = y; }
     }
   }
   if (c.tune_rtiles > 0 && c.tune_gblocks > 0 && c.tune_gblocks <= gt) {
     FusedArgs t = a;
     t.rtiles = c.tune_rtiles;
     t.gblocks = c.tune_gblocks;
-    if (fused_lds_bytes(t) <= lds_cap) { a.rtiles = t.rtiles; a.gblocks = t.gblocks; }
+    if (fits(t)) { a.rtiles = t.rtiles; a.gblocks = t.gblocks; }
   }
 }
 
@@ -835,10 +854,12 @@ void enqueue_build(rps_context& c, int variant, int32_t nocc, const double* C, d
     }
     return;
   }
-  // U = Phi C (orbitals on the grid) and U_g = Phi_g C (at the points)
+  // U = Phi C (orbitals on the grid) and U_g = Phi_g C (at the points); the
+  // in-kernel-orbitals precision kernel needs U_g only
   const bool m4 = (np == 16) && c.use_m4;
-  hip_check(orbitals(c.Phi.p, c.ngp, c.Phig.p, c.nauxp, (int)c.Np, Csrc, (int)c.nbas, nocc, np, c.U.p, c.Ug.p,
-                     m4 ? c.Ugp.p : nullptr, st),
+  const bool f32u = uses_f32u(c, np);
+  hip_check(orbitals(c.Phi.p, f32u ? 0 : c.ngp, c.Phig.p, c.nauxp, (int)c.Np, Csrc, (int)c.nbas, nocc, np, c.U.p,
+                     c.Ug.p, m4 ? c.Ugp.p : nullptr, st),
             "orbitals");
   const bool need_main = (variant != RPS_VARIANT_THC);
   const bool need_l3 = (variant != RPS_VARIANT_PS);
@@ -852,6 +873,7 @@ void enqueue_build(rps_context& c, int variant, int32_t nocc, const double* C, d
     a.prec = c.precision;
     a.Vm32 = (c.precision != RPS_PREC_FP64) ? c.V32.p : nullptr;
     a.Ugp = m4 ? c.Ugp.p : nullptr; a.use_m4 = m4 ? c.use_m4 : 0;
+    if (f32u) { a.Phi32 = c.Phi32.p; a.Cm = Csrc; a.N = (int)c.nbas; a.n = nocc; }
     a.M2p = c.M2p.p; a.K1p = c.K1p.p; a.e1p = c.e1p.p;
     prof_mark(c, 1, st);
     hip_check(fused_exchange(a, st), "fused main");

@@ -127,6 +127,10 @@ struct FusedArgs {
   int want_m1;              // write M1^T = A^T Ug rows (when K1 is not fused)
   int want_e;               // accumulate sum A o P into e1p (else the caller forms it from M2)
   int prec;                 // rps_precision
+  // precision form with the orbitals of each R tile formed in the kernel (NULL Phi32: U from Ur)
+  const float* Phi32;       // [Rp x Np] FP32 basis values
+  const double* Cm;         // [N x n] occupied coefficients (row pitch n)
+  int N, n;
   // outputs
   double* M2p;              // [rblocks][G][np]
   double* K1p;              // [gblocks*rblocks][Np][np]
@@ -134,6 +138,10 @@ struct FusedArgs {
   double* e1p;              // [gblocks*rblocks]
 };
 int fused_rblocks(const FusedArgs& a);
+// g subtiles per wave of the in-kernel-orbitals precision kernel (Phi32 set; at most 8)
+// and its LDS bytes (at most 160 KiB).
+int64_t fused_f32u_nmy(const FusedArgs& a);
+int64_t fused_f32u_lds(const FusedArgs& a);
 int64_t fused_lds_bytes(const FusedArgs& a);
 hipError_t fused_exchange(const FusedArgs& a, hipStream_t s);
 // U [R x np] = Phi [R x Np] C and U_g [G x np] = Phi_g [G x Np] C, with C [N x n]
