@@ -766,22 +766,37 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
   d4_t k1 = zero_d4();
   const int mt = Np / 16;
 
+  // Basis rows of a tile (T x Np floats, contiguous): float4 piece q = tid + 512 j of
+  // the tile goes to sPhi row q / (Np/4), column 4 (q % (Np/4)).  The next tile's
+  // pieces are requested into registers while the current tile runs.
+  constexpr int PFJ = 4;                   // pieces per thread: T * 128 / 4 / 512
+  const int nq = Np / 4;
+  int pf_lds[PFJ];
+#pragma unroll
+  for (int j = 0; j < PFJ; ++j) {
+    const int q = tid + 512 * j;
+    pf_lds[j] = (q < T * nq) ? (q / nq) * PP + 4 * (q % nq) : -1;
+  }
+  float4 pf[PFJ];
+  auto fetch_phi = [&](int64_t rt) {
+    const float4* src = reinterpret_cast<const float4*>(a.Phi32 + rt * T * Np);
+#pragma unroll
+    for (int j = 0; j < PFJ; ++j)
+      if (pf_lds[j] >= 0) pf[j] = src[tid + 512 * j];
+  };
+  if (rt0 < rt1) fetch_phi(rt0);
+
   auto tile = [&](auto tau, int64_t rt) {
     constexpr int TAU = decltype(tau)::value;
-    const int64_t R0 = rt * T;
     __syncthreads();   // the previous tile is done with sPhi, m1s and area0
-    {
-      // basis rows of the tile: row r of T, Np floats (Np / 4 float4 pieces, one per lane)
-      const float4* src = reinterpret_cast<const float4*>(a.Phi32 + R0 * Np);
-      const int nq = Np / 4;
-      for (int r = w; r < T; r += NW)
-        if (lane < nq) {
-          const float4 v = src[(int64_t)r * nq + lane];
-          float* d = sPhi + r * PP + 4 * lane;
-          d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
-        }
-    }
+#pragma unroll
+    for (int j = 0; j < PFJ; ++j)
+      if (pf_lds[j] >= 0) {
+        float* d = sPhi + pf_lds[j];
+        d[0] = pf[j].x; d[1] = pf[j].y; d[2] = pf[j].z; d[3] = pf[j].w;
+      }
     __syncthreads();
+    if (rt + 1 < rt1) fetch_phi(rt + 1);
     {
       // U partials: wave w -> rows 16 (w % 4) .. +15, basis functions of half w / 4
       const int sub = w & 3, half = w >> 2;
