@@ -104,6 +104,7 @@ typedef struct {
     int64_t device_bytes; /* device memory held by the context */
     int32_t precision;
     int32_t exact;        /* 1 if n_aux == N_g (chi = identity) */
+    double madelung;      /* Madelung constant M of the cell (see rps_madelung_constant) */
 } rps_info;
 
 /*
@@ -192,6 +193,28 @@ rps_status rps_build_exchange_full(rps_context *ctx, int32_t nocc, const double 
  */
 rps_status rps_build_coulomb(rps_context *ctx, int32_t nocc, const double *C, double *J, double *ej,
                              int32_t flags, void *hip_stream);
+
+/*
+ * Madelung constant of a lattice (Sec. 4.5: the exchange drops G = 0 and adds
+ * nM/2 back for n electrons).  M is minus the potential at a lattice site of
+ * unit point charges on all sites with a uniform neutralising background, the
+ * site's own 1/r removed, by Ewald's splitting (M L = 2.8372975 for a simple
+ * cubic cell of side L).  lattice: rows a1, a2, a3 in bohr.  Host only.
+ * Errors: RPS_ERR_ARG (NULL or degenerate lattice).
+ */
+rps_status rps_madelung_constant(const double lattice[9], double *M);
+
+/*
+ * Madelung term of an exchange build (Sec. 4.5), applied in place to the
+ * outputs of rps_build_exchange_occRI: K += M S C and, if ex is not NULL,
+ * ex -= M tr(C^T S C), with S = dV Phi^T Phi the grid overlap (formed on the
+ * first call and kept by the context, 8 N^2 bytes).  For S-orthonormal C the
+ * energy shift is n_occ M = nM/2 (n = 2 n_occ electrons).
+ * nocc, C, K, ex, flags, hip_stream as for rps_build_exchange_occRI.
+ * Errors: RPS_ERR_ARG, RPS_ERR_STATE, RPS_ERR_NOMEM, RPS_ERR_DEVICE.
+ */
+rps_status rps_madelung_correct(rps_context *ctx, int32_t nocc, const double *C, double *K, double *ex,
+                                int32_t flags, void *hip_stream);
 
 /*
  * Batched builds over several contexts (cells of different sizes), one call,

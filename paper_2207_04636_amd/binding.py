@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "RPS_OK", 1: "RPS_ERR_ARG", 2: "RPS_ERR_SHAPE", 3: "RPS_ERR_N
 
 # every symbol declared in include/rps.h
 EXPORTS = ("rps_setup_isdf", "rps_build_exchange_occRI", "rps_build_exchange_variant",
-           "rps_build_exchange_full", "rps_build_coulomb", "rps_build_exchange_occRI_batched",
+           "rps_build_exchange_full", "rps_build_coulomb", "rps_madelung_constant", "rps_madelung_correct",
+           "rps_build_exchange_occRI_batched",
            "rps_exchange_energy",
            "rps_overlap", "rps_get_points", "rps_get_info", "rps_get_array", "rps_destroy",
            "rps_last_error", "rps_abi_version", "rps_set_profiling", "rps_get_profile", "rps_autotune",
@@ -59,7 +60,7 @@ class Info(ct.Structure):
                 ("ngrid_pad", ct.c_int64), ("nbas_pad", ct.c_int64), ("naux_pad", ct.c_int64),
                 ("n_candidates", ct.c_int64), ("dvol", ct.c_double), ("chol_shift", ct.c_double),
                 ("setup_seconds", ct.c_double), ("device_bytes", ct.c_int64),
-                ("precision", ct.c_int32), ("exact", ct.c_int32)]
+                ("precision", ct.c_int32), ("exact", ct.c_int32), ("madelung", ct.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -91,6 +92,8 @@ def load(path: str = LIB_PATH):
     lib.rps_build_exchange_variant.argtypes = [P, I32, I32, P, P, P, I32, P]
     lib.rps_build_exchange_full.argtypes = [P, I32, P, P, I32, P]
     lib.rps_build_coulomb.argtypes = [P, I32, P, P, P, I32, P]
+    lib.rps_madelung_constant.argtypes = [P, ct.POINTER(D)]
+    lib.rps_madelung_correct.argtypes = [P, I32, P, P, P, I32, P]
     lib.rps_build_exchange_occRI_batched.argtypes = [ct.POINTER(P), I32, ct.POINTER(I32), ct.POINTER(P),
                                                      ct.POINTER(P), P, I32, P]
     lib.rps_exchange_energy.argtypes = [I32, I32, P, P, ct.POINTER(D)]
@@ -120,6 +123,15 @@ def load(path: str = LIB_PATH):
 def _check(st: int):
     if st != RPS_OK:
         raise RpsError(st, _lib.rps_last_error().decode())
+
+
+def madelung_constant(lattice) -> float:
+    """Madelung constant of the lattice (rows a1, a2, a3 in bohr); host only."""
+    lib = load()
+    lat = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(9))
+    m = ct.c_double(0.0)
+    _check(lib.rps_madelung_constant(lat.ctypes.data, ct.byref(m)))
+    return m.value
 
 
 def _ptr(x) -> int:
@@ -236,6 +248,22 @@ class Context:
         _check(self._lib.rps_build_coulomb(self._h, int(C.shape[1]), C.ctypes.data, Jh.ctypes.data,
                                            ct.addressof(e), PTRS_HOST, None))
         return Jh, e.value
+
+    def madelung_correct(self, C, K, ex=None, stream=None):
+        """Madelung term in place (rps_madelung_correct).  numpy C, K: returns
+        (K + M S C, E - M tr(C^T S C)) with E = ex (a float, or None); torch
+        CUDA C, K (and ex, a 1-element float64 tensor): stream-ordered, returns (K, ex)."""
+        if _is_device(C):
+            _check(self._lib.rps_madelung_correct(self._h, int(C.shape[1]), _ptr(C), _ptr(K),
+                                                  None if ex is None else _ptr(ex), PTRS_DEVICE,
+                                                  _stream_handle(stream)))
+            return K, ex
+        C = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
+        Kh = np.array(K, dtype=np.float64, order="C", copy=True)
+        e = ct.c_double(0.0 if ex is None else float(ex))
+        _check(self._lib.rps_madelung_correct(self._h, int(C.shape[1]), C.ctypes.data, Kh.ctypes.data,
+                                              None if ex is None else ct.addressof(e), PTRS_HOST, None))
+        return Kh, (None if ex is None else e.value)
 
     # ---------------------------------------------------------------- inspection
     def points(self) -> np.ndarray:

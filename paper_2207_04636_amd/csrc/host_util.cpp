@@ -4,6 +4,8 @@
 
 #include <math.h>
 
+#include <cmath>
+
 namespace rps {
 
 double det3(const double a[9]) {
@@ -54,6 +56,51 @@ std::vector<double> coulomb_kernel_table(const double lat[9], const int mesh[3])
         k[(i1 * n2 + i2) * n3 + i3] = 0.5 * (v + vm) / (double)ng;
       }
   return k;
+}
+
+double madelung_constant(const double lat[9]) {
+  // phi(0) = sum_{T != 0} erfc(a |T|)/|T| + (4 pi / Omega) sum_{G != 0} exp(-G^2 / 4a^2) / G^2
+  //          - 2a / sqrt(pi) - pi / (a^2 Omega),  with a = sqrt(pi) / Omega^(1/3);
+  // both lattice sums run over a box of images wide enough for 1e-17 terms.
+  const double om = std::fabs(det3(lat));
+  const double a = std::sqrt(M_PI) / std::cbrt(om);
+  double ai[9];
+  inv3(lat, ai);
+  double B[9];
+  for (int j = 0; j < 3; ++j)
+    for (int k = 0; k < 3; ++k) B[j * 3 + k] = 2.0 * M_PI * ai[k * 3 + j];
+  auto norm = [](const double* v) { return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); };
+  // image boxes: a lattice vector n . a of length <= cut has |n_i| <= cut |b_i| / (2 pi)
+  // (b_i the reciprocal rows), and a reciprocal vector m . b has |m_i| <= cut |a_i| / (2 pi)
+  const double rcut = 6.5 / a;      // erfc(6.5) ~ 4e-20
+  int mr[3];
+  for (int i = 0; i < 3; ++i) mr[i] = (int)std::ceil(rcut * norm(B + 3 * i) / (2.0 * M_PI)) + 1;
+  double real = 0.0;
+  for (int i = -mr[0]; i <= mr[0]; ++i)
+    for (int j = -mr[1]; j <= mr[1]; ++j)
+      for (int k = -mr[2]; k <= mr[2]; ++k) {
+        if (i == 0 && j == 0 && k == 0) continue;
+        double t[3];
+        for (int c = 0; c < 3; ++c) t[c] = i * lat[c] + j * lat[3 + c] + k * lat[6 + c];
+        const double r = norm(t);
+        real += std::erfc(a * r) / r;
+      }
+  const double gcut = 2.0 * a * std::sqrt(-std::log(1e-17));
+  int mg[3];
+  for (int i = 0; i < 3; ++i) mg[i] = (int)std::ceil(gcut * norm(lat + 3 * i) / (2.0 * M_PI)) + 1;
+  double recip = 0.0;
+  for (int i = -mg[0]; i <= mg[0]; ++i)
+    for (int j = -mg[1]; j <= mg[1]; ++j)
+      for (int k = -mg[2]; k <= mg[2]; ++k) {
+        if (i == 0 && j == 0 && k == 0) continue;
+        double g[3];
+        for (int c = 0; c < 3; ++c) g[c] = i * B[c] + j * B[3 + c] + k * B[6 + c];
+        const double g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+        recip += std::exp(-g2 / (4.0 * a * a)) / g2;
+      }
+  recip *= 4.0 * M_PI / om;
+  const double phi0 = real + recip - 2.0 * a / std::sqrt(M_PI) - M_PI / (a * a * om);
+  return -phi0;
 }
 
 void philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {

@@ -15,6 +15,12 @@ bool inv3(const double a[9], double out[9]);
 // symmetrised over G <-> -G (mod mesh).
 std::vector<double> coulomb_kernel_table(const double lattice[9], const int mesh[3]);
 
+// Madelung constant M of the lattice (rows a1, a2, a3): minus the potential at a
+// site of unit point charges on all sites with a uniform neutralising background,
+// the site's own 1/r removed (Ewald splitting; M L = 2.8372975 for a simple cubic
+// lattice of side L).
+double madelung_constant(const double lattice[9]);
+
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds, multipliers 0xD2511F53 and
 // 0xCD9E8D57, Weyl key increments 0x9E3779B9 and 0xBB67AE85.
 void philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

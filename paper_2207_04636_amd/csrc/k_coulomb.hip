@@ -8,7 +8,8 @@
 //
 // The kernels below are the small steps around the products: the density of a
 // block of grid rows, a fixed-order dot product and the symmetric reduction of
-// the split-K partials of J.
+// the split-K partials of J; and the Madelung term of the exchange (Sec. 4.5):
+// K_occ += M S C, E_x -= M tr(C^T S C).
 #include "rps_internal.h"
 
 namespace rps {
@@ -93,7 +94,59 @@ __global__ __launch_bounds__(64 * ZG) void sym_from_lower_kernel(const double* _
   }
 }
 
+// K[mu][i] += M SC[mu][i] for mu < N, i < n (K pitch n, SC pitch ldsc);
+// part[b] = sum over block b's slice of C[mu][i] SC[mu][i] (C pitch n)
+__global__ __launch_bounds__(256) void madelung_k_kernel(const double* __restrict__ SC, int64_t ldsc,
+                                                         const double* __restrict__ C, int64_t N, int64_t n,
+                                                         double M, double* __restrict__ K,
+                                                         double* __restrict__ part) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  const int64_t cnt = N * n;
+  const int64_t per = (cnt + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * per;
+  const int64_t b1 = (b0 + per < cnt) ? b0 + per : cnt;
+  double s = 0.0;
+  for (int64_t e = b0 + tid; e < b1; e += 256) {
+    const int64_t mu = e / n, i = e % n;
+    const double sc = SC[mu * ldsc + i];
+    K[e] += M * sc;
+    s += C[e] * sc;
+  }
+  red[tid] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) part[blockIdx.x] = red[0];
+}
+
+// ex -= M * sum_b part[b] (one block, fixed-order tree)
+__global__ __launch_bounds__(256) void madelung_e_kernel(const double* __restrict__ part, int n, double M,
+                                                         double* __restrict__ ex) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int i = tid; i < n; i += 256) s += part[i];
+  red[tid] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) *ex -= M * red[0];
+}
+
 }  // namespace
+
+hipError_t madelung_apply(const double* SC, int64_t ldsc, const double* C, int64_t N, int64_t n, double M,
+                          double* K, double* ex, double* part, int nparts, hipStream_t s) {
+  if (nparts < 1 || nparts > 256 || N * n <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(madelung_k_kernel, dim3((unsigned)nparts), dim3(256), 0, s, SC, ldsc, C, N, n, M, K, part);
+  if (ex) hipLaunchKernelGGL(madelung_e_kernel, dim3(1), dim3(256), 0, s, part, nparts, M, ex);
+  return hipGetLastError();
+}
 
 hipError_t density_rows(const double* U, int64_t rows, int np, double* out, int64_t ld, hipStream_t s) {
   if (rows <= 0) return hipSuccess;

@@ -72,6 +72,7 @@ struct rps_context {
   int precision = 0;
   int exact = 0;
   double shift = 0.0;
+  double madelung = 0.0;   // Madelung constant of the cell (Sec. 4.5)
   double setup_seconds = 0.0;
   int64_t ncand = 0;
   int64_t bytes = 0;
@@ -97,6 +98,8 @@ struct rps_context {
   int jws_np = -1;
   int64_t jchunk = 0;
   DBuf<double> jCp, jCin, jU, jrho, jwork, jpart, jJ;
+  // Madelung term: S = dV Phi^T Phi (kept once formed) and workspace
+  DBuf<double> Sdev, mCp, mSC, mpart;
   // autotuned launch parameters (0: built-in default)
   int tune_target = 0;                      // streaming form: workgroups aimed at per launch
   int tune_rtiles = 0, tune_gblocks = 0;    // fused kernel: R tiles per workgroup, g blocks
@@ -134,7 +137,7 @@ struct rps_context {
     for (auto* b : all) b->release(nullptr);
     DBuf<double>* gen[] = {&gCp, &gU, &gUg, &gA, &gSp, &gM2, &gM1T, &gK1, &gK3, &gY, &gwork, &epart};
     for (auto* b : gen) b->release(nullptr);
-    DBuf<double>* jb[] = {&kern, &jCp, &jCin, &jU, &jrho, &jwork, &jpart, &jJ};
+    DBuf<double>* jb[] = {&kern, &jCp, &jCin, &jU, &jrho, &jwork, &jpart, &jJ, &Sdev, &mCp, &mSC, &mpart};
     for (auto* b : jb) b->release(nullptr);
     V32.release(nullptr);
     Phi32.release(nullptr);
@@ -348,6 +351,7 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
   c.nbas = nb;
   c.ng = (int64_t)c.mesh[0] * c.mesh[1] * c.mesh[2];
   c.dV = vol / (double)c.ng;
+  c.madelung = madelung_constant(c.lat);
   if (n_aux < 1 || n_aux > c.ng) fail(RPS_ERR_SHAPE, "n_aux must be in [1, N_g]");
   c.naux = n_aux;
   c.precision = prec;
@@ -1174,6 +1178,71 @@ void build_coulomb_impl(rps_context& c, int32_t nocc, const double* C, double* J
   }
 }
 
+// ------------------------------------------------------------------ Madelung term
+// K_occ += M S C and ex -= M tr(C^T S C) with S = dV Phi^T Phi (Sec. 4.5; for S-orthonormal C
+// the energy shift is n_occ M = nM/2 with n = 2 n_occ electrons).
+void madelung_impl(rps_context& c, int32_t nocc, const double* C, double* K, double* ex, int32_t flags,
+                   hipStream_t st) {
+  if (c.ng == 0) fail(RPS_ERR_STATE, "context has no completed set-up");
+  if (nocc < 1) fail(RPS_ERR_ARG, "nocc must be >= 1");
+  if (!C || !K) fail(RPS_ERR_ARG, "C and K must not be NULL");
+  if (flags != RPS_PTRS_HOST && flags != RPS_PTRS_DEVICE) fail(RPS_ERR_ARG, "flags must be RPS_PTRS_HOST or RPS_PTRS_DEVICE");
+  const bool dev = (flags == RPS_PTRS_DEVICE);
+  const int64_t N = c.nbas, Np = c.Np, np = round_up(nocc, 16);
+  int64_t* cnt = &c.bytes;
+  if (!c.Sdev.p) {
+    c.Sdev.alloc(Np * Np, cnt);
+    const int z = coulomb_splits(c);
+    int64_t tmp = 0;
+    DBuf<double> work;
+    Gemm g;
+    g.M = Np; g.N = Np; g.K = c.ngp;
+    g.A = c.Phi.p; g.lda = Np; g.transA = true; g.B = c.Phi.p; g.ldb = Np;
+    g.C = c.Sdev.p; g.ldc = Np; g.alpha = c.dV;
+    if (z > 1) {
+      work.alloc(z * Np * Np, &tmp);
+      g.splitk = z; g.work = work.p;
+    }
+    hip_check(gemm_f64(g, st), "overlap");
+    hip_check(hipStreamSynchronize(st), "sync");
+  }
+  if (c.mCp.n < Np * np) {
+    c.mCp.alloc(Np * np, cnt);
+    c.mSC.alloc(Np * np, cnt);
+  }
+  if (!c.mpart.p) c.mpart.alloc(256, cnt);
+  int64_t tmp = 0;
+  DBuf<double> hC, hK, hE;
+  const double* Cd = C;
+  double* Kd = K;
+  double* Ed = ex;
+  if (!dev) {
+    hC.alloc(N * nocc, &tmp);
+    hK.alloc(N * nocc, &tmp);
+    hip_check(hipMemcpyAsync(hC.p, C, (size_t)N * nocc * 8, hipMemcpyHostToDevice, st), "copy C");
+    hip_check(hipMemcpyAsync(hK.p, K, (size_t)N * nocc * 8, hipMemcpyHostToDevice, st), "copy K");
+    Cd = hC.p;
+    Kd = hK.p;
+    if (ex) {
+      hE.alloc(1, &tmp);
+      hip_check(hipMemcpyAsync(hE.p, ex, 8, hipMemcpyHostToDevice, st), "copy ex");
+      Ed = hE.p;
+    }
+  }
+  hip_check(pack_matrix(Cd, N, nocc, nocc, c.mCp.p, Np, np, st), "pack C");
+  Gemm g;   // SC = S Cp
+  g.M = Np; g.N = np; g.K = Np;
+  g.A = c.Sdev.p; g.lda = Np; g.B = c.mCp.p; g.ldb = np; g.C = c.mSC.p; g.ldc = np;
+  hip_check(gemm_f64(g, st), "S C");
+  const int nparts = (int)std::min<int64_t>(256, std::max<int64_t>(1, (N * nocc + 4095) / 4096));
+  hip_check(madelung_apply(c.mSC.p, np, Cd, N, nocc, c.madelung, Kd, Ed, c.mpart.p, nparts, st), "Madelung");
+  if (!dev) {
+    hip_check(hipMemcpyAsync(K, hK.p, (size_t)N * nocc * 8, hipMemcpyDeviceToHost, st), "copy K");
+    if (ex) hip_check(hipMemcpyAsync(ex, hE.p, 8, hipMemcpyDeviceToHost, st), "copy ex");
+    hip_check(hipStreamSynchronize(st), "sync");
+  }
+}
+
 // ------------------------------------------------------------------ autotuner
 // Mean time of `reps` device-pointer builds after one warm-up build (which
 // also allocates any workspace the launch shape needs).
@@ -1425,6 +1494,22 @@ rps_status rps_build_coulomb(rps_context* ctx, int32_t nocc, const double* C, do
   });
 }
 
+rps_status rps_madelung_constant(const double lattice[9], double* M) {
+  return guarded([&] {
+    if (!lattice || !M) fail(RPS_ERR_ARG, "NULL argument");
+    if (!(std::fabs(det3(lattice)) > 0.0)) fail(RPS_ERR_ARG, "lattice vectors are degenerate");
+    *M = madelung_constant(lattice);
+  });
+}
+
+rps_status rps_madelung_correct(rps_context* ctx, int32_t nocc, const double* C, double* K, double* ex, int32_t flags,
+                                void* hip_stream) {
+  return guarded([&] {
+    if (!ctx) fail(RPS_ERR_ARG, "ctx must not be NULL");
+    madelung_impl(*ctx, nocc, C, K, ex, flags, (hipStream_t)hip_stream);
+  });
+}
+
 rps_status rps_build_exchange_occRI_batched(rps_context* const* ctx, int32_t nbatch, const int32_t* nocc,
                                             const double* const* C, double* const* K, double* ex, int32_t flags,
                                             void* hip_stream) {
@@ -1570,7 +1655,7 @@ rps_status rps_get_info(const rps_context* ctx, rps_info* info) {
     info->ngrid_pad = c.ngp; info->nbas_pad = c.Np; info->naux_pad = c.nauxp;
     info->n_candidates = c.ncand; info->dvol = c.dV; info->chol_shift = c.shift;
     info->setup_seconds = c.setup_seconds; info->device_bytes = c.bytes;
-    info->precision = c.precision; info->exact = c.exact;
+    info->precision = c.precision; info->exact = c.exact; info->madelung = c.madelung;
   });
 }
 

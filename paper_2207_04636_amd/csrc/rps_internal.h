@@ -105,6 +105,11 @@ hipError_t dot_scaled(const double* x, const double* y, int64_t n, double scale,
 hipError_t sym_from_lower(const double* work, int nz, int64_t Np, int64_t N, double scale, double* J,
                           hipStream_t s);
 
+// Madelung term: K[mu][i] += M SC[mu][i] (K, C: [N][n]; SC pitch ldsc) and, if ex,
+// *ex -= M sum C o SC, summed over nparts (<= 256) blocks in a fixed order (part: workspace).
+hipError_t madelung_apply(const double* SC, int64_t ldsc, const double* C, int64_t N, int64_t n, double M,
+                          double* K, double* ex, double* part, int nparts, hipStream_t s);
+
 // ---------------------------------------------------------------- exchange build
 struct FusedArgs {
   // A = Vm o (Ug Ur^T); Vm: [G x R] row pitch ldv

@@ -132,3 +132,14 @@ def test_batch_and_tuner_argument_errors():
 def test_python_errors_are_loud():
     with pytest.raises(P.RpsError):
         P.Context(np.eye(3) * 5, [8, 8, 8], [[0, 0, 0]], [0], [0], [1.0], naux=0)
+
+
+def test_madelung_constant_host():
+    """The library's host Ewald sum (its own implementation) against the oracle's."""
+    from oracle import madelung as om
+    for lat in (np.eye(3) * 6.74, np.array([[0, .5, .5], [.5, 0, .5], [.5, .5, 0]]) * 3.1,
+                np.array([[6.0, 0, 0], [0.8, 5.5, 0], [0.3, 0.2, 6.2]])):
+        assert abs(P.madelung_constant(lat) - om.madelung(lat)) < 1e-13 * om.madelung(lat)
+    with pytest.raises(P.RpsError):
+        P.madelung_constant(np.array([[1.0, 0, 0], [2.0, 0, 0], [0, 0, 1.0]]))
+

@@ -1,4 +1,5 @@
-"""GPU parity of the Coulomb matrix build (rps_build_coulomb) against the FP64
+"""GPU parity of the Coulomb matrix build (rps_build_coulomb) and of the
+Madelung term of the exchange (rps_madelung_correct, Sec. 4.5) against the FP64
 oracle (Sec. 2.3, steps 1-4).
 
 Every step runs in FP64 on both sides; they differ only in summation order
@@ -14,7 +15,7 @@ import numpy as np
 import pytest
 
 import rps_inputs as ri
-from oracle import basis, coulomb, grid
+from oracle import basis, coulomb, grid, madelung
 
 pytestmark = pytest.mark.gpu
 
@@ -86,3 +87,35 @@ def test_coulomb_device_pointers_and_precision_form(lib):
     with lib.Context.from_workload(w, points=pts, precision=lib.PREC_FP32) as ctx:
         J32, E32 = ctx.build_coulomb(C)
     assert np.array_equal(J32, Jh) and E32 == Eh
+
+
+@pytest.mark.parametrize("name", ["config1", "config2-c4"])
+def test_madelung_correction_against_oracle(lib, name):
+    """K + M S C and E - M tr(C^T S C) on the library's exchange outputs, against
+    the oracle's correction of the same K and E with its own S and M."""
+    import torch
+    w, _ = _cases()[name]
+    _say(f"case: Madelung term {name}")
+    Phi = basis.eval_basis(w)
+    dV = grid.dvol(w.lattice, w.mesh)
+    S = basis.overlap(Phi, dV)
+    C = ri.lowdin(ri.random_coefficients(w), S)
+    M = madelung.madelung(w.lattice)
+    with lib.Context.from_workload(w, seed=w.sketch_seed()) as ctx:
+        assert abs(ctx.info()["madelung"] - M) < 1e-13 * M
+        K, E = ctx.build(C)
+        Kc, Ec = ctx.madelung_correct(C, K, E)
+        Kref, Eref = madelung.correct(K, E, C, S, M)
+        # a second call, device pointers, in place (the overlap formed by the first is kept)
+        Cd = torch.from_numpy(C).cuda()
+        Kd = torch.from_numpy(K).cuda()
+        ed = torch.tensor([E], dtype=torch.float64, device="cuda")
+        ctx.madelung_correct(Cd, Kd, ed)
+        torch.cuda.synchronize()
+        Kd1, ed1 = Kd.cpu().numpy(), float(ed[0])
+    _say(f"  M={M:.10f} dE={Ec - Eref:.3e} dK={np.abs(Kc - Kref).max() / np.abs(Kref).max():.3e}")
+    assert abs(Ec - Eref) < 1e-12 * abs(Eref)
+    assert np.abs(Kc - Kref).max() < 1e-12 * np.abs(Kref).max()
+    assert abs((E - Ec) - C.shape[1] * M) < 1e-10
+    assert np.array_equal(Kd1, Kc) and ed1 == Ec
+

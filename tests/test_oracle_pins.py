@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import rps_inputs as ri
-from oracle import basis, brute, conventional, coulomb, grid, isdf, rng, rps
+from oracle import basis, brute, conventional, coulomb, grid, isdf, madelung, rng, rps
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -456,3 +456,70 @@ def test_coulomb_invariants():
     J2, _, _ = coulomb.build_j(Phi, C[:, 1:], w.lattice, w.mesh)
     np.testing.assert_allclose(J1 + J2, J, atol=1e-13 * np.abs(J).max())
     assert abs(E - np.trace(C.T @ J @ C)) < 1e-13 * abs(E) and E > 0 and abs(EQ - E) < 1e-13 * E
+
+
+# ---------------------------------------------------------------- Madelung term (Sec. 4.5)
+def _lattice(kind, unit=1.0):
+    if kind == "sc":
+        return np.eye(3) * unit
+    if kind == "bcc":
+        return np.array([[-.5, .5, .5], [.5, -.5, .5], [.5, .5, -.5]]) * unit
+    return np.array([[0, .5, .5], [.5, 0, .5], [.5, .5, 0]]) * unit
+
+
+def test_madelung_published_constants():
+    """Wigner-lattice constants from the literature (tests/golden/madelung_constants.txt)."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "madelung_constants.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for kind, unit, val in rows:
+        lat = _lattice(kind, 1.7)
+        om = abs(np.linalg.det(lat))
+        length = 1.7 if unit == "L" else (3 * om / (4 * math.pi)) ** (1 / 3)
+        assert abs(madelung.madelung(lat) * length - float(val)) < 2e-9
+
+
+@pytest.mark.parametrize("kind", ["sc", "fcc", "skew"])
+def test_madelung_independent_of_splitting(kind):
+    lat = _lattice(kind, 5.0) if kind != "skew" else np.array([[6.0, 0, 0], [0.8, 5.5, 0], [0.3, 0.2, 6.2]])
+    om = abs(np.linalg.det(lat))
+    ref = madelung.madelung(lat)
+    for f in (0.4, 0.7, 1.5, 2.5):
+        assert abs(madelung.madelung(lat, eta=f * math.sqrt(math.pi) / om ** (1 / 3)) - ref) < 1e-12 * abs(ref)
+
+
+def test_madelung_from_grid_potential():
+    """The G = 0-free grid potential of a periodized normalised Gaussian charge
+    (exponent a) at its centre is -M + 2 sqrt(a/pi) + pi/(a Omega) when the
+    images are far apart (Ewald's identity with the splitting at sqrt(a))."""
+    lat = np.array([[4.0, 0, 0], [0.5, 4.2, 0], [0.2, -0.3, 4.4]])
+    mesh = (48, 50, 52)
+    a = 3.0
+    R = grid.grid_points(lat, mesh)
+    f = (R @ np.linalg.inv(lat))
+    rho = np.zeros(len(R))
+    for i in (-1, 0, 1):
+        for j in (-1, 0, 1):
+            for k in (-1, 0, 1):
+                d = (f - np.round(f) + np.array([i, j, k])) @ lat
+                rho += (a / math.pi) ** 1.5 * np.exp(-a * np.einsum("ij,ij->i", d, d))
+    v0 = grid.poisson(rho, lat, mesh)[0]          # grid point 0 is the charge centre
+    om = abs(np.linalg.det(lat))
+    ref = -madelung.madelung(lat) + 2 * math.sqrt(a / math.pi) + math.pi / (a * om)
+    assert abs(v0 - ref) < 1e-10 * abs(ref)
+
+
+def test_madelung_correction_shifts():
+    """For S-orthonormal C the energy drops by n_occ M (= nM/2 for n = 2 n_occ
+    electrons) and K_occ gains M S C."""
+    w = ri.tiny_s_cell(5, 6, 4.0, 2, 8, lmax=1)
+    Phi = basis.eval_basis(w)
+    dV = grid.dvol(w.lattice, w.mesh)
+    S = basis.overlap(Phi, dV)
+    C = ri.lowdin(ri.random_coefficients(w), S)
+    K, E = conventional.exchange_occ(Phi, C, w.lattice, w.mesh)
+    M = madelung.madelung(w.lattice)
+    K2, E2 = madelung.correct(K, E, C, S, M)
+    assert abs((E - E2) - C.shape[1] * M) < 1e-12
+    np.testing.assert_allclose(K2 - K, M * S @ C, atol=1e-14)
+
