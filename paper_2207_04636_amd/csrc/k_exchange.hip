@@ -699,7 +699,9 @@ template <int NMY>
 __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
   constexpr int NW = 8;
   constexpr int NP = 16;
-  constexpr int LDU = NP + 1;
+  constexpr int LDU = NP + 1;              // sU pitch (floats): rows 4 j + c read across j
+  constexpr int LDM = NP + 4;              // sU2 / sUg pitch: rows 4 lq + r read across lq
+  constexpr int RP = NP + 1;               // M1 partial pitch
   constexpr int SL = T + 4;                // FP32 slab pitch (floats)
   extern __shared__ double smem[];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -717,9 +719,10 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
   const int64_t rt1 = (rt0 + a.rtiles < rtiles_valid) ? rt0 + a.rtiles : rtiles_valid;
 
   // LDS (bytes): area0 | sPhi [T][PP] f32 | sC [Np][16] f64 | m1s [T][16] f64 | sU [T][LDU] f32
-  //              | sUg [gper*16][LDU] f32
+  //              | sU2 [T][LDM] f32 | sUg [gper*16][LDM] f32
   // area0 holds, one after another within a tile: the U partials [2][T][16] f64,
-  // the waves' A slabs [NW][16][SL] f32, the M1 partials [NW][T][16] f32.
+  // the waves' A slabs [NW][16][SL] f32, the M1 partials [NW][T][RP] f32.  The pitches
+  // keep the lanes of each access pattern on distinct banks.
   constexpr int AREA0 = NW * 16 * SL * 4;
   char* base = reinterpret_cast<char*>(smem);
   double* upart = reinterpret_cast<double*>(base);
@@ -729,7 +732,8 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
   double* sC = reinterpret_cast<double*>(base + AREA0 + (int64_t)T * PP * 4);
   double* m1s = sC + Np * NP;
   float* sU = reinterpret_cast<float*>(m1s + T * NP);
-  float* sUg = sU + T * LDU;
+  float* sU2 = sU + T * LDU;
+  float* sUg = sU2 + T * LDM;
 
   const int nmy = (gs1 - gs0 > w) ? (int)((gs1 - gs0 - w + NW - 1) / NW) : 0;   // <= NMY (host check)
 
@@ -738,7 +742,7 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
     sC[e] = (r < a.N && c < a.n) ? a.Cm[(int64_t)r * a.n + c] : 0.0;
   }
   for (int64_t e = tid; e < (gs1 - gs0) * 16 * NP; e += NW * 64)
-    sUg[(e / NP) * LDU + (e % NP)] = (float)a.Ug[gs0 * 16 * NP + e];
+    sUg[(e / NP) * LDM + (e % NP)] = (float)a.Ug[gs0 * 16 * NP + e];
 
   // V fragment of step (tile rt, subtile si): lane holds V[g0 + 4lq + r][R0 + 4 l16 + c]
   float vb[2][4][4];
@@ -771,30 +775,32 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
   // pieces are requested into registers while the current tile runs.
   constexpr int PFJ = 4;                   // pieces per thread: T * 128 / 4 / 512
   const int nq = Np / 4;
-  int pf_lds[PFJ];
-#pragma unroll
-  for (int j = 0; j < PFJ; ++j) {
+  static_assert(PFJ == 4, "four named prefetch registers");
+  auto lds_of = [&](int j) {
     const int q = tid + 512 * j;
-    pf_lds[j] = (q < T * nq) ? (q / nq) * PP + 4 * (q % nq) : -1;
-  }
-  float4 pf[PFJ];
+    return (q < T * nq) ? (q / nq) * PP + 4 * (q % nq) : -1;
+  };
+  const int pl0 = lds_of(0), pl1 = lds_of(1), pl2 = lds_of(2), pl3 = lds_of(3);
+  // named registers, not an array: an array captured by the lambdas ends up in scratch
+  float4 pf0, pf1, pf2, pf3;
+  const int qlast = T * nq - 1;
   auto fetch_phi = [&](int64_t rt) {
+    // unconditional loads (pieces past the tile re-read its last one)
     const float4* src = reinterpret_cast<const float4*>(a.Phi32 + rt * T * Np);
-#pragma unroll
-    for (int j = 0; j < PFJ; ++j)
-      if (pf_lds[j] >= 0) pf[j] = src[tid + 512 * j];
+    pf0 = src[min(tid, qlast)];
+    pf1 = src[min(tid + 512, qlast)];
+    pf2 = src[min(tid + 1024, qlast)];
+    pf3 = src[min(tid + 1536, qlast)];
   };
   if (rt0 < rt1) fetch_phi(rt0);
 
   auto tile = [&](auto tau, int64_t rt) {
     constexpr int TAU = decltype(tau)::value;
     __syncthreads();   // the previous tile is done with sPhi, m1s and area0
-#pragma unroll
-    for (int j = 0; j < PFJ; ++j)
-      if (pf_lds[j] >= 0) {
-        float* d = sPhi + pf_lds[j];
-        d[0] = pf[j].x; d[1] = pf[j].y; d[2] = pf[j].z; d[3] = pf[j].w;
-      }
+    if (pl0 >= 0) *reinterpret_cast<float4*>(sPhi + pl0) = pf0;
+    if (pl1 >= 0) *reinterpret_cast<float4*>(sPhi + pl1) = pf1;
+    if (pl2 >= 0) *reinterpret_cast<float4*>(sPhi + pl2) = pf2;
+    if (pl3 >= 0) *reinterpret_cast<float4*>(sPhi + pl3) = pf3;
     __syncthreads();
     if (rt + 1 < rt1) fetch_phi(rt + 1);
     {
@@ -810,7 +816,11 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
       for (int r = 0; r < 4; ++r) up[4 * r * NP] = acc[r];
     }
     __syncthreads();
-    for (int e = tid; e < T * NP; e += NW * 64) sU[(e / NP) * LDU + (e % NP)] = (float)(upart[e] + upart[T * NP + e]);
+    for (int e = tid; e < T * NP; e += NW * 64) {
+      const float u = (float)(upart[e] + upart[T * NP + e]);
+      sU[(e / NP) * LDU + (e % NP)] = u;
+      sU2[(e / NP) * LDM + (e % NP)] = u;
+    }
     __syncthreads();
     // U operands of the tile's products (column position p = 16 c + j is row 4 j + c):
     // P = U_g U^T: B[k = i][n = p]; M2 = A U: B[k = p][n = i], in registers when room
@@ -823,7 +833,7 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
     auto bm_row = [&](int kk) { return 4 * ((4 * kk + lq) & 15) + (kk >> 2); };
     if (BMREG)
 #pragma unroll
-      for (int kk = 0; kk < 16; ++kk) bM[kk] = sU[bm_row(kk) * LDU + l16];
+      for (int kk = 0; kk < 16; ++kk) bM[kk] = sU2[bm_row(kk) * LDM + l16];
 
     f4_t m1[4];
 #pragma unroll
@@ -850,9 +860,9 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
         const int gl = (w + si * NW) * 16;     // local row of the subtile in sUg
         float ugA[4], ugB[4];
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) ugA[kk] = sUg[(gl + l16) * LDU + 4 * kk + lq];
+        for (int kk = 0; kk < 4; ++kk) ugA[kk] = sUg[(gl + l16) * LDM + 4 * kk + lq];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) ugB[r] = sUg[(gl + 4 * lq + r) * LDU + l16];
+        for (int r = 0; r < 4; ++r) ugB[r] = sUg[(gl + 4 * lq + r) * LDM + l16];
         f4_t p[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) p[c] = zero_f4();
@@ -875,7 +885,7 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
         f4_t m2 = zero_f4();
 #pragma unroll
         for (int kk = 0; kk < 16; ++kk)
-          m2 = mfma_f32(slab[l16 * SL + 4 * kk + lq], BMREG ? bM[kk] : sU[bm_row(kk) * LDU + l16], m2);
+          m2 = mfma_f32(slab[l16 * SL + 4 * kk + lq], BMREG ? bM[kk] : sU2[bm_row(kk) * LDM + l16], m2);
 #pragma unroll
         for (int r = 0; r < 4; ++r) m2acc[si][r] += (double)m2[r];
         __builtin_amdgcn_wave_barrier();
@@ -887,14 +897,14 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) red[(w * 64 + 16 * lq + 4 * r + c) * 16 + l16] = m1[c][r];
+      for (int r = 0; r < 4; ++r) red[(w * 64 + 16 * lq + 4 * r + c) * RP + l16] = m1[c][r];
     __syncthreads();
     if (w < 4) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         double s = 0.0;
 #pragma unroll
-        for (int ww = 0; ww < NW; ++ww) s += (double)red[(ww * 64 + 16 * w + 4 * r + lq) * 16 + l16];
+        for (int ww = 0; ww < NW; ++ww) s += (double)red[(ww * 64 + 16 * w + 4 * r + lq) * RP + l16];
         m1s[(16 * w + 4 * r + lq) * 16 + l16] = s;
       }
     }
@@ -1237,7 +1247,7 @@ hipError_t launch_f32(const FusedArgs& a, int blocks, hipStream_t s) {
 // LDS bytes of fused_f32u_kernel (8 waves) for gper g subtiles per workgroup
 int64_t f32u_lds_bytes(int Np, int64_t gper) {
   return (int64_t)8 * 16 * (T + 4) * 4 + (int64_t)T * (Np + 4) * 4 + (int64_t)Np * 16 * 8 + (int64_t)T * 16 * 8 +
-         (int64_t)T * 17 * 4 + gper * 16 * 17 * 4;
+         (int64_t)T * 17 * 4 + (int64_t)T * 20 * 4 + gper * 16 * 20 * 4;
 }
 
 template <int NMY>
