@@ -794,6 +794,37 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
   };
   if (rt0 < rt1) fetch_phi(rt0);
 
+  // Fit-fit line (Eq. 16 line 3), folded in while the first loads are in flight.  Unit
+  // (ys, hc) = one 16 x 16 block of B = W o P_g times U_g rows hc: P_g^T is formed for
+  // the h rows of the unit (W is symmetric, so W o P_g^T is B^T), and its registers feed
+  // the product directly.  Units go round-robin over all waves of the grid, FP64.
+  if (a.Wl) {
+    const int64_t nsub = a.G / 16;
+    for (int64_t u = (int64_t)blockIdx.x * NW + w; u < nsub * nsub; u += (int64_t)gridDim.x * NW) {
+      const int64_t ys = u / nsub, hc = u % nsub;
+      const int64_t y0 = ys * 16, h0 = hc * 16;
+      d4_t pt = zero_d4();    // P_g^T[h0 + 4r + lq][y0 + l16]
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+        pt = mfma_f64(a.Ug[(h0 + l16) * NP + 4 * kk + lq], a.Ug[(y0 + l16) * NP + 4 * kk + lq], pt);
+      d4_t yacc = zero_d4();  // Y[y0 + 4r + lq][l16], this unit's part
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t h = h0 + 4 * r + lq;
+        yacc = mfma_f64(a.Wl[h * a.ldw + y0 + l16] * pt[r], a.Ug[h * NP + l16], yacc);
+      }
+      double* yo = a.Yneg + (hc * a.G + y0) * NP;
+      double e = 0.0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        yo[(4 * r + lq) * NP + l16] = -yacc[r];
+        e += a.Ug[(y0 + 4 * r + lq) * NP + l16] * yacc[r];
+      }
+      e = wave_sum(e);
+      if (lane == 0) a.e3u[u] = e;
+    }
+  }
+
   auto tile = [&](auto tau, int64_t rt) {
     constexpr int TAU = decltype(tau)::value;
     __syncthreads();   // the previous tile is done with sPhi, m1s and area0
@@ -1075,6 +1106,7 @@ __global__ __launch_bounds__(512) void finalize_kernel(const double* __restrict_
                                                       double ce1, double ce3, double* __restrict__ ex,
                                                       EnergyDots dots) {
   __shared__ double red[8][64][4];
+  __shared__ int last_blk;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
   const int ntile = (Np / 16) * (np / 16);
@@ -1089,14 +1121,16 @@ __global__ __launch_bounds__(512) void finalize_kernel(const double* __restrict_
       b1 = (b0 + per < n) ? b0 + per : n;
     };
     double sa = 0.0, sb = 0.0;
-    if (eb == 0) {
-      for (int64_t p = tid; p < ne1; p += 512) sa += e1p[p];
-      for (int64_t p = tid; p < ne3; p += 512) sb += e3p[p];
-    }
     int64_t b0, b1;
+    slice(ne1, b0, b1);
+    for (int64_t p = b0 + tid; p < b1; p += 512) sa += e1p[p];
+    slice(ne3, b0, b1);
+    for (int64_t p = b0 + tid; p < b1; p += 512) sb += e3p[p];
     slice(dots.n1, b0, b1);
+#pragma unroll 4
     for (int64_t p = b0 + tid; p < b1; p += 512) sa += dots.x1[p] * dots.y1[p];
     slice(dots.n3, b0, b1);
+#pragma unroll 4
     for (int64_t p = b0 + tid; p < b1; p += 512) sb += dots.x3[p] * dots.y3[p];
     double* r1 = &red[0][0][0];
     r1[tid] = ce1 * sa + ce3 * sb;
@@ -1108,6 +1142,30 @@ __global__ __launch_bounds__(512) void finalize_kernel(const double* __restrict_
     if (tid == 0) {
       if (neb == 1) *ex = -dV * r1[0];
       else dots.part[eb] = r1[0];
+    }
+    if (neb > 1 && dots.count) {
+      // the last energy block to finish sums the partials in a fixed order and resets
+      // the counter for the next build (device-scope release / acquire around it)
+      __threadfence();
+      __syncthreads();
+      if (tid == 0) last_blk = (atomicAdd(dots.count, 1u) == (unsigned)(neb - 1));
+      __syncthreads();
+      if (last_blk) {
+        __threadfence();
+        double v = 0.0;
+        for (int i = tid; i < neb; i += 512)
+          v += __hip_atomic_load(dots.part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        r1[tid] = v;
+        __syncthreads();
+        for (int off = 256; off > 0; off >>= 1) {
+          if (tid < off) r1[tid] += r1[tid + off];
+          __syncthreads();
+        }
+        if (tid == 0) {
+          *ex = -dV * r1[0];
+          *dots.count = 0u;
+        }
+      }
     }
     return;
   }
@@ -1403,12 +1461,13 @@ hipError_t finalize(const double* Phig, const double* M2, int64_t G, const doubl
                     int64_t ne1, const double* e3p, int64_t ne3, double ce1, double ce3, double* ex, hipStream_t s,
                     const EnergyDots& dots) {
   const int ntile = (Np / 16) * (np / 16);
-  // energy blocks: one per 64K dot-product terms (up to the partial list size)
-  int neb = (int)std::min<int64_t>((dots.n1 + dots.n3 + 65535) / 65536, dots.part ? dots.nparts : 1);
+  // energy blocks: one per 4K dot-product terms and partials (up to the partial list size)
+  int neb = (int)std::min<int64_t>((dots.n1 + dots.n3 + ne1 + ne3 + 4095) / 4096, dots.part ? dots.nparts : 1);
   if (neb < 1) neb = 1;
   hipLaunchKernelGGL(finalize_kernel, dim3(ntile + neb), dim3(512), 0, s, Phig, M2, G, K1, K3, N, n, np, Np, s1, s2,
                      s3, dV, K, e1p, ne1, e3p, ne3, ce1, ce3, ex, dots);
-  if (neb > 1 && ex) hipLaunchKernelGGL(energy_sum_kernel, dim3(1), dim3(256), 0, s, dots.part, neb, dV, ex);
+  if (neb > 1 && ex && !dots.count)
+    hipLaunchKernelGGL(energy_sum_kernel, dim3(1), dim3(256), 0, s, dots.part, neb, dV, ex);
   return hipGetLastError();
 }
 

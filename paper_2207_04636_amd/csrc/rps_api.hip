@@ -85,12 +85,13 @@ struct rps_context {
   DBuf<int64_t> dpoints;
   // build workspace (grows on demand)
   int ws_np = -1;
-  DBuf<double> U, Ug, Ugp, M2p, K1p, K3p, e1p, e3p, M2, K1, K3, Kdev, Cdev, exdev;
+  DBuf<double> U, Ug, Ugp, M2p, K1p, K3p, e1p, e3p, M2, K1, K3, Kdev, Cdev, exdev, e3u;
   int use_m4 = 0;   // 16x16x4 FP64 kernel by default (faster on gfx950); RPS_FP64_MFMA=m4|hybrid selects the 4x4x4 one
   // general path workspace
   int gws_np = -1;
   int64_t gchunk = 0;
   DBuf<double> gCp, gU, gUg, gA, gSp, gM2, gM1T, gK1, gK3, gY, gwork, epart;
+  DBuf<unsigned> ecount;   // last-block counter of the finalize kernel's energy sum (zero between builds)
   int64_t rblocks_main = 0, blocks_main = 0, blocks_l3 = 0;
   int rtiles = 4, gblocks = 1, nwaves = 4;
   // Coulomb matrix: kernel table k(G) / N_g kept from the set-up, and workspace
@@ -133,10 +134,11 @@ struct rps_context {
 
   ~rps_context() {
     DBuf<double>* all[] = {&Phi, &Phig, &V, &W, &U, &Ug, &Ugp, &M2p, &K1p, &K3p, &e1p,
-                           &e3p, &M2, &K1, &K3, &Kdev, &Cdev, &exdev};
+                           &e3p, &M2, &K1, &K3, &Kdev, &Cdev, &exdev, &e3u};
     for (auto* b : all) b->release(nullptr);
     DBuf<double>* gen[] = {&gCp, &gU, &gUg, &gA, &gSp, &gM2, &gM1T, &gK1, &gK3, &gY, &gwork, &epart};
     for (auto* b : gen) b->release(nullptr);
+    ecount.release(nullptr);
     DBuf<double>* jb[] = {&kern, &jCp, &jCin, &jU, &jrho, &jwork, &jpart, &jJ, &Sdev, &mCp, &mSC, &mpart};
     for (auto* b : jb) b->release(nullptr);
     V32.release(nullptr);
@@ -618,6 +620,14 @@ void choose_shape(rps_context& c, int np, FusedArgs& a) {
   }
 }
 
+// Partials and the zeroed counter of the finalize kernel's split energy sum.
+void ensure_energy_parts(rps_context& c) {
+  if (c.epart.p) return;
+  c.epart.alloc(kEnergyBlocks, &c.bytes);
+  c.ecount.alloc(1, &c.bytes);
+  hip_check(hipMemset(c.ecount.p, 0, sizeof(unsigned)), "hipMemset");
+}
+
 void ensure_workspace(rps_context& c, int np) {
   if (c.ws_np == np) return;
   c.clear_graphs();          // captured builds refer to the buffers about to change
@@ -636,7 +646,11 @@ void ensure_workspace(rps_context& c, int np) {
   c.U.alloc(c.ngp * np, cnt);
   c.Ug.alloc(c.nauxp * np, cnt);
   c.Ugp.alloc(c.nauxp * np, cnt);
-  c.M2p.alloc(c.rblocks_main * c.nauxp * np, cnt);
+  // M2 partials, followed by the negated fit-fit partials of the in-kernel-orbitals kernel
+  const int64_t nsub = c.nauxp / 16;
+  c.M2p.alloc((c.rblocks_main + (uses_f32u(c, np) ? nsub : 0)) * c.nauxp * np, cnt);
+  c.e3u.alloc(uses_f32u(c, np) ? nsub * nsub : 1, cnt);
+  ensure_energy_parts(c);
   c.K1p.alloc(c.blocks_main * c.Np * np, cnt);
   c.K3p.alloc(std::max<int64_t>(c.blocks_l3, 1) * c.Np * np, cnt);
   c.e1p.alloc(c.blocks_main, cnt);
@@ -682,7 +696,7 @@ void ensure_general(rps_context& c, int np) {
   c.gK3.alloc(c.Np * np, cnt);
   c.gY.alloc(c.nauxp * np, cnt);
   c.gwork.alloc(kSplitWork, cnt);
-  if (!c.epart.p) c.epart.alloc(kEnergyBlocks, cnt);
+  ensure_energy_parts(c);
   c.Cdev.alloc(c.nbas * np, cnt);
   c.Kdev.alloc(c.nbas * np, cnt);
   c.exdev.alloc(1, cnt);
@@ -809,7 +823,7 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
   EnergyDots dots;
   if (need_main) { dots.x1 = c.gUg.p; dots.y1 = c.gM2.p; dots.n1 = c.nauxp * np; }
   if (need_l3) { dots.x3 = c.gUg.p; dots.y3 = c.gY.p; dots.n3 = c.nauxp * np; }
-  dots.part = c.epart.p; dots.nparts = kEnergyBlocks;
+  dots.part = c.epart.p; dots.nparts = kEnergyBlocks; dots.count = c.ecount.p;
   hip_check(finalize(c.Phig.p, need_main ? c.gM2.p : nullptr, c.nauxp, k1 ? c.gK1.p : nullptr,
                      need_l3 ? c.gK3.p : nullptr, (int)c.nbas, nocc, np, (int)c.Np, s1, s2, s3, c.dV, Kout,
                      nullptr, 0, nullptr, 0, ce1, ce3, exout, st, dots),
@@ -868,6 +882,10 @@ void enqueue_build(rps_context& c, int variant, int32_t nocc, const double* C, d
             "orbitals");
   const bool need_main = (variant != RPS_VARIANT_THC);
   const bool need_l3 = (variant != RPS_VARIANT_PS);
+  // the in-kernel-orbitals kernel also forms the fit-fit line, as negated partials after
+  // the M2 partials (their ordered sum is then M2 - Y; the rPS variant only)
+  const bool l3_in_main = f32u && variant == RPS_VARIANT_RPS;
+  const int64_t nsub = c.nauxp / 16;
   if (need_main) {
     FusedArgs a{};
     a.Vm = c.V.p; a.ldv = c.ngp; a.Ug = c.Ug.p; a.Ur = c.U.p; a.Phir = c.Phi.p;
@@ -879,18 +897,22 @@ void enqueue_build(rps_context& c, int variant, int32_t nocc, const double* C, d
     a.Vm32 = (c.precision != RPS_PREC_FP64) ? c.V32.p : nullptr;
     a.Ugp = m4 ? c.Ugp.p : nullptr; a.use_m4 = m4 ? c.use_m4 : 0;
     if (f32u) { a.Phi32 = c.Phi32.p; a.Cm = Csrc; a.N = (int)c.nbas; a.n = nocc; }
+    if (l3_in_main) {
+      a.Wl = c.W.p; a.ldw = c.nauxp;
+      a.Yneg = c.M2p.p + c.rblocks_main * c.nauxp * np; a.e3u = c.e3u.p;
+    }
     a.M2p = c.M2p.p; a.K1p = c.K1p.p; a.e1p = c.e1p.p;
     prof_mark(c, 1, st);
     hip_check(fused_exchange(a, st), "fused main");
     prof_mark(c, 2, st);
   }
   hipStream_t sl3 = st;
-  if (need_l3 && st3) {      // fork after the orbitals: line 3 needs only U_g
+  if (need_l3 && !l3_in_main && st3) {      // fork after the orbitals: line 3 needs only U_g
     hip_check(hipEventRecord(c.gfork, st), "fork");
     hip_check(hipStreamWaitEvent(st3, c.gfork, 0), "fork wait");
     sl3 = st3;
   }
-  if (need_l3) {
+  if (need_l3 && !l3_in_main) {
     FusedArgs a{};
     a.Vm = c.W.p; a.ldv = c.nauxp; a.Ug = c.Ug.p; a.Ur = c.Ug.p; a.Phir = c.Phig.p;
     a.G = c.nauxp; a.R = c.nauxp; a.R_valid = c.naux; a.np = np; a.Np = (int)c.Np;
@@ -909,24 +931,34 @@ void enqueue_build(rps_context& c, int variant, int32_t nocc, const double* C, d
   double* Kout = dev ? K : c.Kdev.p;
   double* exout = dev ? ex : (ex ? c.exdev.p : nullptr);
   const bool k1 = need_main && variant == RPS_VARIANT_RPS;
+  const bool k3 = need_l3 && !l3_in_main;
   hip_check(sum_partials3(k1 ? c.K1p.p : nullptr, c.blocks_main, c.Np * np, c.K1.p,
-                          need_main ? c.M2p.p : nullptr, c.rblocks_main, c.nauxp * np, c.M2.p,
-                          need_l3 ? c.K3p.p : nullptr, c.blocks_l3, c.Np * np, c.K3.p, st),
+                          need_main ? c.M2p.p : nullptr, c.rblocks_main + (l3_in_main ? nsub : 0),
+                          c.nauxp * np, c.M2.p,
+                          k3 ? c.K3p.p : nullptr, c.blocks_l3, c.Np * np, c.K3.p, st),
             "partial sums");
   int64_t ne1 = need_main ? c.blocks_main : 0;
   EnergyDots dots;
+  dots.part = c.epart.p; dots.nparts = kEnergyBlocks; dots.count = c.ecount.p;
   if (need_main && !m4) {      // sum A o P = tr(U_g^T M2), formed by the finalize kernel
     ne1 = 0;
     dots.x1 = c.Ug.p; dots.y1 = c.M2.p; dots.n1 = c.nauxp * np;
   }
-  hip_check(finalize(c.Phig.p, need_main ? c.M2.p : nullptr, c.nauxp, k1 ? c.K1.p : nullptr,
-                     need_l3 ? c.K3.p : nullptr, (int)c.nbas, nocc, np, (int)c.Np, s1, s2, s3, c.dV, Kout,
-                     c.e1p.p, ne1, c.e3p.p, need_l3 ? c.blocks_l3 : 0, ce1, ce3, exout, st, dots),
-            "finalize");
+  if (l3_in_main) {
+    // M2 now holds Z = M2 - Y: K = dV (K1 + Phi_g^T Z); E_x = -dV (2 tr(U_g^T Z) + tr(U_g^T Y))
+    hip_check(finalize(c.Phig.p, c.M2.p, c.nauxp, c.K1.p, nullptr, (int)c.nbas, nocc, np, (int)c.Np, 1.0, 1.0, 0.0,
+                       c.dV, Kout, nullptr, 0, c.e3u.p, nsub * nsub, 2.0, 1.0, exout, st, dots),
+              "finalize");
+  } else {
+    hip_check(finalize(c.Phig.p, need_main ? c.M2.p : nullptr, c.nauxp, k1 ? c.K1.p : nullptr,
+                       k3 ? c.K3.p : nullptr, (int)c.nbas, nocc, np, (int)c.Np, s1, s2, s3, c.dV, Kout,
+                       c.e1p.p, ne1, c.e3p.p, k3 ? c.blocks_l3 : 0, ce1, ce3, exout, st, dots),
+              "finalize");
+  }
   prof_mark(c, 5, st);
   if (c.profiling && c.ev_used < kMaxProfiled) {
     if (!need_main) { prof_mark(c, 1, st); prof_mark(c, 2, st); }
-    if (!need_l3) { prof_mark(c, 3, st); prof_mark(c, 4, st); }
+    if (!need_l3 || l3_in_main) { prof_mark(c, 3, st); prof_mark(c, 4, st); }
     ++c.ev_used;
   }
   if (!dev) {
@@ -936,15 +968,19 @@ void enqueue_build(rps_context& c, int variant, int32_t nocc, const double* C, d
   }
 }
 
+// Replay of repeated builds as a captured graph: opt-in (RPS_GRAPH=1).  Measured on
+// the 48^3 cell, eager launches queue back to back with less device idle time than a
+// graph launch leaves between builds (130 us against 137 us per build).
 bool graphs_enabled() {
-  static const bool on = getenv("RPS_NO_GRAPH") == nullptr;
-  return on;
+  const char* g = getenv("RPS_GRAPH");
+  return g && g[0] == '1';
 }
 
-// One exchange build.  A device-pointer build repeated with the same
-// arguments is captured into a HIP graph on its second call (the fit-fit
-// kernel on a parallel branch) and replayed from then on; host-pointer
-// builds, profiled builds and builds inside a batch capture run eagerly.
+// One exchange build.  With graph replay on, a device-pointer build repeated with
+// the same arguments is captured into a HIP graph on its second call (the fit-fit
+// kernel on a parallel branch when it is a separate kernel) and replayed from then
+// on; host-pointer builds, profiled builds and builds inside a batch capture run
+// eagerly.
 void build_impl(rps_context& c, int variant, int32_t nocc, const double* C, double* K, double* ex,
                 int32_t flags, hipStream_t st, bool allow_graph = true) {
   if (c.ng == 0) fail(RPS_ERR_STATE, "context has no completed set-up");

@@ -136,6 +136,13 @@ struct FusedArgs {
   const float* Phi32;       // [Rp x Np] FP32 basis values
   const double* Cm;         // [N x n] occupied coefficients (row pitch n)
   int N, n;
+  // fit-fit line folded into that kernel (Wl NULL: not computed).  Unit (g subtile ys,
+  // h subtile hc) of Y = (Wl o (U_g U_g^T)) U_g is written NEGATED as rows ys of partial
+  // hc of Yneg ([G/16][G][np]; placed after the M2 partials, so that their ordered sum
+  // is M2 - Y), and sum U_g o Y over the unit goes to e3u[ys * (G/16) + hc].
+  const double* Wl; int64_t ldw;   // W [G x G] FP64, row pitch ldw (symmetric)
+  double* Yneg;
+  double* e3u;
   // outputs
   double* M2p;              // [rblocks][G][np]
   double* K1p;              // [gblocks*rblocks][Np][np]
@@ -169,6 +176,9 @@ struct EnergyDots {
   const double* x1 = nullptr; const double* y1 = nullptr; int64_t n1 = 0;
   const double* x3 = nullptr; const double* y3 = nullptr; int64_t n3 = 0;
   double* part = nullptr; int nparts = 0;
+  // with part: a device counter, zero between builds, by which the last energy block
+  // sums the partials itself (NULL: a second kernel does)
+  unsigned* count = nullptr;
 };
 // K[mu][i] = dV (s1 K1 + s2 Phi_g^T M2 + s3 K3) for mu < N, i < n ([Np][np] arrays,
 // any may be NULL); ex = -dV (ce1 e1 + ce3 e3) if ex is not NULL, with

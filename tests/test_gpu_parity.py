@@ -166,12 +166,13 @@ def test_full_exchange_config1(lib, cfg1):
     assert _kerr(Kf @ C, Ko) < 1e-10
 
 
-def test_graph_replay_matches_host_builds(lib, cfg1):
-    """Repeated device-pointer builds are captured into a HIP graph on the
-    second call and replayed after it; every replay must equal the host-mode
-    build bit for bit, also after C changes in place and with eager work and
-    synchronisations between replays."""
+def test_graph_replay_matches_host_builds(lib, cfg1, monkeypatch):
+    """With graph replay on (RPS_GRAPH=1), repeated device-pointer builds are
+    captured into a HIP graph on the second call and replayed after it; every
+    replay must equal the host-mode build bit for bit, also after C changes in
+    place and with eager work and synchronisations between replays."""
     _say("case: graph replay of repeated device builds")
+    monkeypatch.setenv("RPS_GRAPH", "1")
     import torch
     w, st, C = cfg1["w"], cfg1["st"], cfg1["C"]
     C2 = ri.lowdin(ri.random_coefficients(w, stream="perturbation"), basis.overlap(cfg1["Phi"], cfg1["dV"]))
