@@ -746,8 +746,11 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
 
   // V fragment of step (tile rt, subtile si): lane holds V[g0 + 4lq + r][R0 + 4 l16 + c]
   float vb[2][4][4];
+  // Loads are issued unconditionally (a step that does not exist re-reads V row 0 of
+  // the first tile), so that the wait before each use counts only older loads.
   auto load_v = [&](float (&dst)[4][4], int64_t rt, int si) {
-    const int64_t R0 = rt * T, g0 = (gs0 + w + (int64_t)si * NW) * 16;
+    const bool ok = rt < rt1 && si < nmy;
+    const int64_t R0 = (ok ? rt : rt0) * T, g0 = ok ? (gs0 + w + (int64_t)si * NW) * 16 : 0;
     const float* src = a.Vm32 + (g0 + 4 * lq) * a.ldv + R0 + 4 * l16;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -756,11 +759,7 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
     }
   };
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const int64_t rt = rt0 + s / NMY;
-    const int si = s % NMY;
-    if (rt < rt1 && si < nmy) load_v(vb[s & 1], rt, si);
-  }
+  for (int s = 0; s < 2; ++s) load_v(vb[s & 1], rt0 + s / NMY, s % NMY);
 
   double m2acc[NMY][4];
 #pragma unroll
@@ -792,7 +791,7 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
     pf2 = src[min(tid + 1024, qlast)];
     pf3 = src[min(tid + 1536, qlast)];
   };
-  if (rt0 < rt1) fetch_phi(rt0);
+  fetch_phi(rt0);
 
   // Fit-fit line (Eq. 16 line 3), folded in while the first loads are in flight.  Unit
   // (ys, hc) = one 16 x 16 block of B = W o P_g times U_g rows hc: P_g^T is formed for
@@ -833,7 +832,7 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
     if (pl2 >= 0) *reinterpret_cast<float4*>(sPhi + pl2) = pf2;
     if (pl3 >= 0) *reinterpret_cast<float4*>(sPhi + pl3) = pf3;
     __syncthreads();
-    if (rt + 1 < rt1) fetch_phi(rt + 1);
+    fetch_phi(rt + 1 < rt1 ? rt + 1 : rt);   // unconditional (the last tile re-reads itself)
     {
       // U partials: wave w -> rows 16 (w % 4) .. +15, basis functions of half w / 4
       const int sub = w & 3, half = w >> 2;
@@ -874,19 +873,12 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
     for (int si = 0; si < NMY; ++si) {
       const int b = (TAU * NMY + si) & 1;
       float v[4][4];
-      if (si < nmy) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < 4; ++r)
 #pragma unroll
-          for (int c = 0; c < 4; ++c) v[r][c] = vb[b][r][c];
-      }
-      {
-        // request the V fragment two steps ahead into the buffer just read
-        const int tg = si + 2;
-        const int64_t trt = rt + tg / NMY;
-        const int tsi = tg % NMY;
-        if (trt < rt1 && tsi < nmy) load_v(vb[b], trt, tsi);
-      }
+        for (int c = 0; c < 4; ++c) v[r][c] = vb[b][r][c];
+      // request the V fragment two steps ahead into the buffer just read
+      load_v(vb[b], rt + (si + 2) / NMY, (si + 2) % NMY);
       if (si < nmy) {
         const int gl = (w + si * NW) * 16;     // local row of the subtile in sUg
         float ugA[4], ugB[4];
@@ -901,22 +893,32 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
         for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
           for (int c = 0; c < 4; ++c) p[c] = mfma_f32(ugA[kk], bP[kk][c], p[c]);
+        // A to the slab, arranged for the M2 operand: row g holds position p = 4 kk + q
+        // at chunk (q, kk / 4) of four floats, chunk index XORed with (g / 4) % 4 in its
+        // low bits (conflict-free writes; each reader lane gets four 16-byte chunks)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           f4_t av;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             av[r] = v[r][c] * p[c][r];
-            slab[(4 * lq + r) * SL + 16 * c + l16] = av[r];
+            slab[(4 * lq + r) * SL + 4 * ((l16 & 3) * 4 + (c ^ lq)) + (l16 >> 2)] = av[r];
           }
 #pragma unroll
           for (int r = 0; r < 4; ++r) m1[c] = mfma_f32(av[r], ugB[r], m1[c]);
         }
         __builtin_amdgcn_wave_barrier();
+        float4 ach[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          ach[j] = *reinterpret_cast<const float4*>(slab + l16 * SL + 4 * (lq * 4 + (j ^ ((l16 >> 2) & 3))));
         f4_t m2 = zero_f4();
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk)
-          m2 = mfma_f32(slab[l16 * SL + 4 * kk + lq], BMREG ? bM[kk] : sU2[bm_row(kk) * LDM + l16], m2);
+        for (int kk = 0; kk < 16; ++kk) {
+          const float4 q = ach[kk >> 2];
+          const float av = (kk & 3) == 0 ? q.x : (kk & 3) == 1 ? q.y : (kk & 3) == 2 ? q.z : q.w;
+          m2 = mfma_f32(av, BMREG ? bM[kk] : sU2[bm_row(kk) * LDM + l16], m2);
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r) m2acc[si][r] += (double)m2[r];
         __builtin_amdgcn_wave_barrier();

@@ -590,8 +590,8 @@ void choose_shape(rps_context& c, int np, FusedArgs& a) {
   // wave); the others hold this workgroup's M2 block in LDS
   a.Np = (int)c.Np;
   auto fits = [&](const FusedArgs& t) {
-    // (the in-kernel-orbitals kernel stays within its registers up to 6 subtiles per wave)
-    return f32u ? (fused_f32u_nmy(t) <= 6 && fused_f32u_lds(t) <= lds_cap) : fused_lds_bytes(t) <= lds_cap;
+    // (the in-kernel-orbitals kernel stays within its registers up to 5 subtiles per wave)
+    return f32u ? (fused_f32u_nmy(t) <= 5 && fused_f32u_lds(t) <= lds_cap) : fused_lds_bytes(t) <= lds_cap;
   };
   a.gblocks = 1;
   a.rtiles = 1;
