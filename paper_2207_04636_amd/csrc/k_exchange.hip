@@ -737,12 +737,41 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
 
   const int nmy = (gs1 - gs0 > w) ? (int)((gs1 - gs0 - w + NW - 1) / NW) : 0;   // <= NMY (host check)
 
+  // operands of this wave's first fit-fit unit (see below), requested before anything else
+  const int64_t nsub3 = a.Wl ? a.G / 16 : 0, n3 = nsub3 * nsub3;
+  int64_t u3 = (int64_t)blockIdx.x * NW + w;
+  double l3ha[4], l3ya[4], l3w[4], l3hb[4], l3yr[4];
+  auto l3_load = [&](int64_t u) {
+    const int64_t y0 = (u / nsub3) * 16, h0 = (u % nsub3) * 16;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      l3ha[q] = a.Ug[(h0 + l16) * NP + 4 * q + lq];
+      l3ya[q] = a.Ug[(y0 + l16) * NP + 4 * q + lq];
+      l3w[q] = a.Wl[(h0 + 4 * q + lq) * a.ldw + y0 + l16];
+      l3hb[q] = a.Ug[(h0 + 4 * q + lq) * NP + l16];
+      l3yr[q] = a.Ug[(y0 + 4 * q + lq) * NP + l16];
+    }
+  };
+  if (u3 < n3) l3_load(u3);
+
+  // staging loops unrolled so that their global loads are in flight together
+#pragma unroll 4
   for (int e = tid; e < Np * NP; e += NW * 64) {
     const int r = e / NP, c = e % NP;
     sC[e] = (r < a.N && c < a.n) ? a.Cm[(int64_t)r * a.n + c] : 0.0;
   }
-  for (int64_t e = tid; e < (gs1 - gs0) * 16 * NP; e += NW * 64)
-    sUg[(e / NP) * LDM + (e % NP)] = (float)a.Ug[gs0 * 16 * NP + e];
+  {
+    // U_g rows of the workgroup, two doubles per load
+    const double2* ug2 = reinterpret_cast<const double2*>(a.Ug + gs0 * 16 * NP);
+    const int n2 = (int)((gs1 - gs0) * 16 * NP / 2);
+#pragma unroll 8
+    for (int e = tid; e < n2; e += NW * 64) {
+      const double2 v = ug2[e];
+      float* d = sUg + ((2 * e) / NP) * LDM + (2 * e) % NP;
+      d[0] = (float)v.x;
+      d[1] = (float)v.y;
+    }
+  }
 
   // V fragment of step (tile rt, subtile si): lane holds V[g0 + 4lq + r][R0 + 4 l16 + c]
   float vb[2][4][4];
@@ -796,32 +825,27 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
   // Fit-fit line (Eq. 16 line 3), folded in while the first loads are in flight.  Unit
   // (ys, hc) = one 16 x 16 block of B = W o P_g times U_g rows hc: P_g^T is formed for
   // the h rows of the unit (W is symmetric, so W o P_g^T is B^T), and its registers feed
-  // the product directly.  Units go round-robin over all waves of the grid, FP64.
-  if (a.Wl) {
-    const int64_t nsub = a.G / 16;
-    for (int64_t u = (int64_t)blockIdx.x * NW + w; u < nsub * nsub; u += (int64_t)gridDim.x * NW) {
-      const int64_t ys = u / nsub, hc = u % nsub;
-      const int64_t y0 = ys * 16, h0 = hc * 16;
-      d4_t pt = zero_d4();    // P_g^T[h0 + 4r + lq][y0 + l16]
+  // the product directly.  Units go round-robin over all waves of the grid, FP64; the
+  // operands of a wave's first unit were requested at the top of the kernel.
+  for (; u3 < n3; u3 += (int64_t)gridDim.x * NW) {
+    const int64_t ys = u3 / nsub3, hc = u3 % nsub3;
+    const int64_t y0 = ys * 16;
+    d4_t pt = zero_d4();    // P_g^T[h0 + 4r + lq][y0 + l16]
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
-        pt = mfma_f64(a.Ug[(h0 + l16) * NP + 4 * kk + lq], a.Ug[(y0 + l16) * NP + 4 * kk + lq], pt);
-      d4_t yacc = zero_d4();  // Y[y0 + 4r + lq][l16], this unit's part
+    for (int kk = 0; kk < 4; ++kk) pt = mfma_f64(l3ha[kk], l3ya[kk], pt);
+    d4_t yacc = zero_d4();  // Y[y0 + 4r + lq][l16], this unit's part
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t h = h0 + 4 * r + lq;
-        yacc = mfma_f64(a.Wl[h * a.ldw + y0 + l16] * pt[r], a.Ug[h * NP + l16], yacc);
-      }
-      double* yo = a.Yneg + (hc * a.G + y0) * NP;
-      double e = 0.0;
+    for (int r = 0; r < 4; ++r) yacc = mfma_f64(l3w[r] * pt[r], l3hb[r], yacc);
+    double* yo = a.Yneg + (hc * a.G + y0) * NP;
+    double e = 0.0;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        yo[(4 * r + lq) * NP + l16] = -yacc[r];
-        e += a.Ug[(y0 + 4 * r + lq) * NP + l16] * yacc[r];
-      }
-      e = wave_sum(e);
-      if (lane == 0) a.e3u[u] = e;
+    for (int r = 0; r < 4; ++r) {
+      yo[(4 * r + lq) * NP + l16] = -yacc[r];
+      e += l3yr[r] * yacc[r];
     }
+    e = wave_sum(e);
+    if (lane == 0) a.e3u[u3] = e;
+    if (u3 + (int64_t)gridDim.x * NW < n3) l3_load(u3 + (int64_t)gridDim.x * NW);
   }
 
   auto tile = [&](auto tau, int64_t rt) {
@@ -839,11 +863,16 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
       const int kh = Np / 8;                 // k steps of 4 per half
       const float* pa = sPhi + (16 * sub + l16) * PP + half * (Np / 2) + lq;
       const double* pb = sC + (half * (Np / 2) + lq) * NP + l16;
-      d4_t acc = zero_d4();
-      for (int kk = 0; kk < kh; ++kk) acc = mfma_f64((double)pa[4 * kk], pb[4 * kk * NP], acc);
+      // two independent accumulator chains (kh is even since Np % 16 == 0)
+      d4_t acc0 = zero_d4(), acc1 = zero_d4();
+#pragma unroll 2
+      for (int kk = 0; kk < kh; kk += 2) {
+        acc0 = mfma_f64((double)pa[4 * kk], pb[4 * kk * NP], acc0);
+        acc1 = mfma_f64((double)pa[4 * kk + 4], pb[(4 * kk + 4) * NP], acc1);
+      }
       double* up = upart + half * T * NP + (16 * sub + lq) * NP + l16;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) up[4 * r * NP] = acc[r];
+      for (int r = 0; r < 4; ++r) up[4 * r * NP] = acc0[r] + acc1[r];
     }
     __syncthreads();
     for (int e = tid; e < T * NP; e += NW * 64) {
@@ -932,23 +961,28 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) red[(w * 64 + 16 * lq + 4 * r + c) * RP + l16] = m1[c][r];
     __syncthreads();
-    if (w < 4) {
+    // the eight partials summed in FP64, two elements of the 64 x 16 block per thread
+    for (int e = tid; e < T * NP; e += NW * 64) {
+      const int row = e / NP, col = e % NP;
+      double sm = 0.0;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        double s = 0.0;
-#pragma unroll
-        for (int ww = 0; ww < NW; ++ww) s += (double)red[(ww * 64 + 16 * w + 4 * r + lq) * RP + l16];
-        m1s[(16 * w + 4 * r + lq) * 16 + l16] = s;
-      }
+      for (int ww = 0; ww < NW; ++ww) sm += (double)red[(ww * 64 + row) * RP + col];
+      m1s[e] = sm;
     }
     __syncthreads();
     if (a.want_k1 && w < mt) {
+      // K1 += Phi^T M1^T over the tile's 64 rows in two independent chains
       const float* ph = sPhi + lq * PP + 16 * w + l16;
+      d4_t t0 = zero_d4();
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          k1 = mfma_f64((double)ph[(16 * q + 4 * r) * PP], m1s[(16 * q + 4 * r + lq) * 16 + l16], k1);
+        for (int r = 0; r < 4; ++r) {
+          t0 = mfma_f64((double)ph[(16 * q + 4 * r) * PP], m1s[(16 * q + 4 * r + lq) * 16 + l16], t0);
+          k1 = mfma_f64((double)ph[(16 * q + 32 + 4 * r) * PP], m1s[(16 * q + 32 + 4 * r + lq) * 16 + l16], k1);
+        }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) k1[r] += t0[r];
     }
   };
 
