@@ -883,7 +883,7 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
     __syncthreads();
     // U operands of the tile's products (column position p = 16 c + j is row 4 j + c):
     // P = U_g U^T: B[k = i][n = p]; M2 = A U: B[k = p][n = i], in registers when room
-    constexpr bool BMREG = (NMY <= 4);
+    constexpr bool BMREG = (NMY <= 5);
     float bP[4][4], bM[16];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk)
@@ -901,13 +901,7 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
 #pragma unroll
     for (int si = 0; si < NMY; ++si) {
       const int b = (TAU * NMY + si) & 1;
-      float v[4][4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) v[r][c] = vb[b][r][c];
-      // request the V fragment two steps ahead into the buffer just read
-      load_v(vb[b], rt + (si + 2) / NMY, (si + 2) % NMY);
+      float (&v)[4][4] = vb[b];
       if (si < nmy) {
         const int gl = (w + si * NW) * 16;     // local row of the subtile in sUg
         float ugA[4], ugB[4];
@@ -952,6 +946,8 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
         for (int r = 0; r < 4; ++r) m2acc[si][r] += (double)m2[r];
         __builtin_amdgcn_wave_barrier();
       }
+      // request the V fragment two steps ahead into the buffer just used
+      load_v(vb[b], rt + (si + 2) / NMY, (si + 2) % NMY);
     }
 
     __syncthreads();
