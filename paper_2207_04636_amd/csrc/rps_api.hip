@@ -97,6 +97,7 @@ struct rps_context {
   // Coulomb matrix: kernel table k(G) / N_g kept from the set-up, and workspace
   DBuf<double> kern;
   int jws_np = -1;
+  bool jws_small = false;
   int64_t jchunk = 0;
   DBuf<double> jCp, jCin, jU, jrho, jwork, jpart, jJ;
   // Madelung term: S = dV Phi^T Phi (kept once formed) and workspace
@@ -1143,17 +1144,26 @@ int coulomb_splits(const rps_context& c) {
   return (int)z;
 }
 
+// Small-basis Coulomb path (one pass over Phi per step, U never stored): N <= 128, n <= 64.
+bool coulomb_small_path(const rps_context& c, int np) {
+  const char* e = getenv("RPS_COULOMB_GEMM");
+  return c.Np <= 128 && np <= 64 && !(e && e[0] == '1');
+}
+
 void ensure_coulomb(rps_context& c, int np) {
-  if (c.jws_np == np) return;
+  const bool small = coulomb_small_path(c, np);
+  if (c.jws_np == np && c.jws_small == small) return;
   int64_t* cnt = &c.bytes;
   c.jchunk = std::min<int64_t>(c.ngp, std::max<int64_t>(64, kCoulombChunk / np / 64 * 64));
   c.jCp.alloc(c.Np * np, cnt);
   c.jCin.alloc(c.nbas * np, cnt);
-  c.jU.alloc(c.jchunk * np, cnt);
+  if (small) c.jU.release(cnt); else c.jU.alloc(c.jchunk * np, cnt);
   if (!c.jrho.p) c.jrho.alloc(3 * c.ngp, cnt);
-  if (!c.jwork.p) c.jwork.alloc(std::max(1, coulomb_splits(c)) * c.Np * c.Np, cnt);
+  const int64_t nw = std::max<int64_t>({1, coulomb_splits(c), small ? coulomb_small_blocks(c.ngp) : 1});
+  if (c.jwork.n < nw * c.Np * c.Np) c.jwork.alloc(nw * c.Np * c.Np, cnt);
   if (!c.jpart.p) c.jpart.alloc(kCoulombParts, cnt);
   c.jws_np = np;
+  c.jws_small = small;
 }
 
 // J = dV Phi^T diag(Vc rho) Phi, rho(R) = sum_i U(R, i)^2, U = Phi C (Sec. 2.3, steps 1-4);
@@ -1175,9 +1185,13 @@ void build_coulomb_impl(rps_context& c, int32_t nocc, const double* C, double* J
     Csrc = c.jCin.p;
     if (!c.jJ.p) c.jJ.alloc(N * N, &c.bytes);
   }
-  hip_check(pack_matrix(Csrc, N, nocc, nocc, c.jCp.p, Np, np, st), "pack C");
+  const bool small = coulomb_small_path(c, np);
+  if (small)   // step 1 in one pass: U = Phi C and rho = sum U^2 per 16-row subtile, U never stored
+    hip_check(density_small(c.Phi.p, R, (int)Np, Csrc, (int)N, nocc, np, c.jrho.p, R, st), "density");
+  else
+    hip_check(pack_matrix(Csrc, N, nocc, nocc, c.jCp.p, Np, np, st), "pack C");
   // step 1: density, one chunk of grid rows at a time (rows past N_g have Phi = 0, so rho = 0)
-  for (int64_t r0 = 0; r0 < R; r0 += c.jchunk) {
+  for (int64_t r0 = 0; !small && r0 < R; r0 += c.jchunk) {
     const int64_t m = std::min(c.jchunk, R - r0);
     Gemm g;   // U = Phi[r0:r0+m] C
     g.M = m; g.N = np; g.K = Np;
@@ -1193,20 +1207,25 @@ void build_coulomb_impl(rps_context& c, int32_t nocc, const double* C, double* J
     hip_check(dot_scaled(c.jrho.p, c.jrho.p + 2 * R, R, c.dV, c.jpart.p, kCoulombParts - 1, exout, st), "E_J");
   }
   // step 4: lower tiles of Phi^T diag(V_H) Phi, split over the grid, mirrored and scaled by dV
-  Gemm g;
-  g.M = Np; g.N = Np; g.K = R;
-  g.A = c.Phi.p; g.lda = Np; g.transA = true; g.B = c.Phi.p; g.ldb = Np;
-  g.kscale = c.jrho.p; g.lower_only = true;
-  g.splitk = coulomb_splits(c);
-  if (g.splitk > 1) {
-    g.work = c.jwork.p;
-    g.keep_partials = true;
-  } else {
-    g.C = c.jwork.p; g.ldc = Np;
-  }
-  hip_check(gemm_f64(g, st), "Phi^T diag(V_H) Phi");
   double* Jout = dev ? J : c.jJ.p;
-  hip_check(sym_from_lower(c.jwork.p, g.splitk, Np, N, c.dV, Jout, st), "J");
+  if (small) {
+    hip_check(coulomb_small(c.Phi.p, R, (int)Np, c.jrho.p, c.jwork.p, st), "Phi^T diag(V_H) Phi");
+    hip_check(sym_from_lower(c.jwork.p, coulomb_small_blocks(R), Np, N, c.dV, Jout, st), "J");
+  } else {
+    Gemm g;
+    g.M = Np; g.N = Np; g.K = R;
+    g.A = c.Phi.p; g.lda = Np; g.transA = true; g.B = c.Phi.p; g.ldb = Np;
+    g.kscale = c.jrho.p; g.lower_only = true;
+    g.splitk = coulomb_splits(c);
+    if (g.splitk > 1) {
+      g.work = c.jwork.p;
+      g.keep_partials = true;
+    } else {
+      g.C = c.jwork.p; g.ldc = Np;
+    }
+    hip_check(gemm_f64(g, st), "Phi^T diag(V_H) Phi");
+    hip_check(sym_from_lower(c.jwork.p, g.splitk, Np, N, c.dV, Jout, st), "J");
+  }
   if (!dev) {
     hip_check(hipMemcpyAsync(J, c.jJ.p, (size_t)N * N * 8, hipMemcpyDeviceToHost, st), "copy J");
     if (ej) hip_check(hipMemcpyAsync(ej, exout, 8, hipMemcpyDeviceToHost, st), "copy E_J");

@@ -105,6 +105,15 @@ hipError_t dot_scaled(const double* x, const double* y, int64_t n, double scale,
 hipError_t sym_from_lower(const double* work, int nz, int64_t Np, int64_t N, double scale, double* J,
                           hipStream_t s);
 
+// Small-basis Coulomb path (Np <= 128): rho of rows [0, rows) of Phi [rows][Np] with
+// U = Phi C (np <= 64) written as density_rows does; and the lower 16 x 16 tiles of the
+// partials part[b][Np][Np] = sum over workgroup b's 64-row chunks of v[R] phi[R] phi[R]^T
+// (rows % 64 == 0; coulomb_small_blocks(rows) partials).
+hipError_t density_small(const double* Phi, int64_t rows, int Np, const double* C, int N, int n, int np,
+                         double* out, int64_t ld, hipStream_t s);
+int coulomb_small_blocks(int64_t rows);
+hipError_t coulomb_small(const double* Phi, int64_t rows, int Np, const double* v, double* part, hipStream_t s);
+
 // Madelung term: K[mu][i] += M SC[mu][i] (K, C: [N][n]; SC pitch ldsc) and, if ex,
 // *ex -= M sum C o SC, summed over nparts (<= 256) blocks in a fixed order (part: workspace).
 hipError_t madelung_apply(const double* SC, int64_t ldsc, const double* C, int64_t N, int64_t n, double M,

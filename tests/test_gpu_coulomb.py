@@ -47,8 +47,13 @@ def _rel(J, Jref):
     return float(np.abs(J - Jref).max() / np.abs(Jref).max())
 
 
-@pytest.mark.parametrize("name", list(_cases()))
-def test_coulomb_against_oracle(lib, name):
+@pytest.mark.parametrize("name", list(_cases()) + ["config2-c4-gemm"])
+def test_coulomb_against_oracle(lib, name, monkeypatch):
+    """Bases with N <= 128 and n <= 64 take the one-pass small-basis kernels; the
+    others (and "-gemm", forced) the chunked GEMM path."""
+    if name.endswith("-gemm"):
+        monkeypatch.setenv("RPS_COULOMB_GEMM", "1")
+        name = name[: -len("-gemm")]
     w, nocc = _cases()[name]
     if nocc is not None:
         w = dataclasses.replace(w, nocc=nocc)
