@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void sum_scaled_kernel(const double* __restric
 // J[i][j] = J[j][i] = scale * sum_z work[z][i][j] for j <= i < N.  Block (64, ZG):
 // 64 consecutive elements of the [Np][Np] partials, ZG interleaved groups of z
 // summed separately, then combined in a fixed order.
-constexpr int ZG = 4;
+constexpr int ZG = 16;
 __global__ __launch_bounds__(64 * ZG) void sym_from_lower_kernel(const double* __restrict__ work, int nz, int64_t Np,
                                                                  int64_t N, double scale, double* __restrict__ J) {
   __shared__ double red[ZG][64];

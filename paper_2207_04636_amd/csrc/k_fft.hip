@@ -22,12 +22,12 @@
 namespace rps {
 namespace {
 
-constexpr int PEN = 16;      // pencils per workgroup
 constexpr int LMAX = 128;    // longest supported axis
 
 // Pencil p (of outer*inner) starts at o*L*inner + i with o = p / inner, i = p % inner;
-// element j of it is at start + j*inner.
-template <int MODE>   // 0: forward, 1: inverse, 2: forward, multiply by kern, inverse
+// element j of it is at start + j*inner.  PEN pencils per workgroup: 16 for the
+// set-up's many rows, 4 when a single row pair would leave most CUs idle.
+template <int MODE, int PEN>   // 0: forward, 1: inverse, 2: forward, multiply by kern, inverse
 __global__ __launch_bounds__(256) void dft_axis_kernel(double* __restrict__ V, int64_t ld, int L,
                                                       int64_t inner, int64_t npencil,
                                                       const double* __restrict__ kern) {
@@ -123,13 +123,25 @@ hipError_t poisson_rows(double* V, int64_t nrows, int64_t ld, const int mesh[3],
     auto launch = [&](int axis, int mode) {
       const int L = mesh[axis];
       const int64_t np = ng / L;
-      dim3 grid((unsigned)((np + PEN - 1) / PEN), (unsigned)cn);
-      if (mode == 0)
-        hipLaunchKernelGGL(dft_axis_kernel<0>, grid, dim3(256), 0, s, Vc, ld, L, inner[axis], np, kern);
-      else if (mode == 1)
-        hipLaunchKernelGGL(dft_axis_kernel<1>, grid, dim3(256), 0, s, Vc, ld, L, inner[axis], np, kern);
-      else
-        hipLaunchKernelGGL(dft_axis_kernel<2>, grid, dim3(256), 0, s, Vc, ld, L, inner[axis], np, kern);
+      if ((np + 15) / 16 * cn >= 1024) {
+        constexpr int PEN = 16;
+        dim3 grid((unsigned)((np + PEN - 1) / PEN), (unsigned)cn);
+        if (mode == 0)
+          hipLaunchKernelGGL((dft_axis_kernel<0, PEN>), grid, dim3(256), 0, s, Vc, ld, L, inner[axis], np, kern);
+        else if (mode == 1)
+          hipLaunchKernelGGL((dft_axis_kernel<1, PEN>), grid, dim3(256), 0, s, Vc, ld, L, inner[axis], np, kern);
+        else
+          hipLaunchKernelGGL((dft_axis_kernel<2, PEN>), grid, dim3(256), 0, s, Vc, ld, L, inner[axis], np, kern);
+      } else {
+        constexpr int PEN = 4;
+        dim3 grid((unsigned)((np + PEN - 1) / PEN), (unsigned)cn);
+        if (mode == 0)
+          hipLaunchKernelGGL((dft_axis_kernel<0, PEN>), grid, dim3(256), 0, s, Vc, ld, L, inner[axis], np, kern);
+        else if (mode == 1)
+          hipLaunchKernelGGL((dft_axis_kernel<1, PEN>), grid, dim3(256), 0, s, Vc, ld, L, inner[axis], np, kern);
+        else
+          hipLaunchKernelGGL((dft_axis_kernel<2, PEN>), grid, dim3(256), 0, s, Vc, ld, L, inner[axis], np, kern);
+      }
     };
     launch(2, 0);
     launch(1, 0);
