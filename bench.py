@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix = vector)
 PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 matrix
-PEAK_BF16X3_TFLOPS = 2500.0 / 3.0   # dense BF16 matrix peak over the three products of a split-BF16 product
+PEAK_BF16X3_TFLOPS = 2500.0 / 6.0   # dense BF16 matrix peak over the six BF16 products of a split-BF16 product
 PEAK_HBM_GBS = 8000.0
 
 
