@@ -787,9 +787,6 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
       dst[r][0] = q.x; dst[r][1] = q.y; dst[r][2] = q.z; dst[r][3] = q.w;
     }
   };
-#pragma unroll
-  for (int s = 0; s < 2; ++s) load_v(vb[s & 1], rt0 + s / NMY, s % NMY);
-
   double m2acc[NMY][4];
 #pragma unroll
   for (int si = 0; si < NMY; ++si)
@@ -804,9 +801,11 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
   constexpr int PFJ = 4;                   // pieces per thread: T * 128 / 4 / 512
   const int nq = Np / 4;
   static_assert(PFJ == 4, "four named prefetch registers");
+  // pieces past the tile go to the pad columns [Np, Np + 4) of a row (never read), so
+  // that every store is unconditional and the wait before it counts the loads exactly
   auto lds_of = [&](int j) {
     const int q = tid + 512 * j;
-    return (q < T * nq) ? (q / nq) * PP + 4 * (q % nq) : -1;
+    return (q < T * nq) ? (q / nq) * PP + 4 * (q % nq) : (tid & 63) * PP + Np;
   };
   const int pl0 = lds_of(0), pl1 = lds_of(1), pl2 = lds_of(2), pl3 = lds_of(3);
   // named registers, not an array: an array captured by the lambdas ends up in scratch
@@ -820,7 +819,13 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
     pf2 = src[min(tid + 1024, qlast)];
     pf3 = src[min(tid + 1536, qlast)];
   };
+  // The first tile's basis rows go out before its first two V fragments: at the head
+  // of the tile loop the basis registers are then older than the last eight loads on
+  // every path into it (as after a tile, where the next tile's first two fragments are
+  // the most recent loads), so the wait for them never waits for V.
   fetch_phi(rt0);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) load_v(vb[s & 1], rt0 + s / NMY, s % NMY);
 
   // Fit-fit line (Eq. 16 line 3), folded in while the first loads are in flight.  Unit
   // (ys, hc) = one 16 x 16 block of B = W o P_g times U_g rows hc: P_g^T is formed for
@@ -851,10 +856,10 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
   auto tile = [&](auto tau, int64_t rt) {
     constexpr int TAU = decltype(tau)::value;
     __syncthreads();   // the previous tile is done with sPhi, m1s and area0
-    if (pl0 >= 0) *reinterpret_cast<float4*>(sPhi + pl0) = pf0;
-    if (pl1 >= 0) *reinterpret_cast<float4*>(sPhi + pl1) = pf1;
-    if (pl2 >= 0) *reinterpret_cast<float4*>(sPhi + pl2) = pf2;
-    if (pl3 >= 0) *reinterpret_cast<float4*>(sPhi + pl3) = pf3;
+    *reinterpret_cast<float4*>(sPhi + pl0) = pf0;
+    *reinterpret_cast<float4*>(sPhi + pl1) = pf1;
+    *reinterpret_cast<float4*>(sPhi + pl2) = pf2;
+    *reinterpret_cast<float4*>(sPhi + pl3) = pf3;
     __syncthreads();
     fetch_phi(rt + 1 < rt1 ? rt + 1 : rt);   // unconditional (the last tile re-reads itself)
     {
