@@ -296,10 +296,12 @@ def main():
     vbytes = (4.0 if mixed else 8.0) * naux * ng
     fused_s = run["fused_s"]
     achieved = flops / fused_s / 1e12
-    bf = args.precision == "bf16x3" and args.workload != "diamond1x1x1"
+    general = args.workload != "diamond1x1x1"
+    gemm_form = general and (n + 15) // 16 * 16 > 128     # padded n above the streaming form
+    # the GEMM form runs its products on the FP32 matrix cores in either precision form
+    bf = args.precision == "bf16x3" and general and not gemm_form
     peak = PEAK_BF16X3_TFLOPS if bf else (PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS)
     tag = ("fused_f32u" if mixed else "fused_f64") + f"_diamond1x1x1_c{args.c:g}"
-    general = args.workload != "diamond1x1x1"
     traffic = _traffic(tag) if args.workload == "diamond1x1x1" else None
     out = {
         "metric": "exchange builds/s (K_occ + E_x)",
@@ -315,7 +317,9 @@ def main():
         "dtype": ("bf16x3" if bf else "f32") if mixed else "f64",
         "data": "synthetic (seeded diamond-like cell, random S-orthonormal occupied coefficients)",
         "config": {"workload": f"{w.name}: {ng} grid points, N={N}, n_occ={n}, N_aux={naux}, rPS occ-RI, "
-                               + (("mixed: V FP32, split-BF16 MFMA products (hi*hi + hi*lo + lo*hi), FP32 in "
+                               + (("mixed: V, U, A in FP32, FP32 MFMA chunk products, FP32 sums over 64 terms, "
+                                   "FP64 beyond and in K") if mixed and gemm_form else
+                                  ("mixed: V FP32, split-BF16 MFMA products (hi*hi + hi*lo + lo*hi), FP32 in "
                                    "tile, FP64 across tiles and in K") if bf else
                                   ("mixed: V FP32, FP32 MFMA in-tile products, FP64 across tiles and in K")
                                   if mixed else "FP64"),
@@ -323,9 +327,11 @@ def main():
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": None if traffic is None else round(traffic),
-                     "kernel": ("stream_kernel passes" if general else
-                                ("fused_f32u_kernel" if mixed else "fused_f64_kernel")) + " (Eq. 16 lines 1-2 streaming V"
-                                + (", with U = Phi C, K1 and line 3 folded in)" if mixed and not general else ")"),
+                     "kernel": (("GEMM-form chunk products A_c = V o P, M1^T, M2 (Eq. 16 lines 1-2, "
+                                 + ("FP32" if mixed else "FP64") + " matrix cores)") if gemm_form else
+                                (("stream_kernel passes" if general else
+                                  ("fused_f32u_kernel" if mixed else "fused_f64_kernel")) + " (Eq. 16 lines 1-2 streaming V"
+                                 + (", with U = Phi C, K1 and line 3 folded in)" if mixed and not general else ")"))),
                      "kernel_avg_us": round(fused_s * 1e6, 3),
                      "algorithmic_flops_per_launch": flops,
                      "algorithmic_V_bytes_per_launch": vbytes,

@@ -242,6 +242,166 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(Gemm g) {
       }
 }
 
+// FP32 operands on the FP32 matrix cores (v_mfma_f32_16x16x4_f32), the
+// products of the precision form's GEMM form.  Tiling as gemm_big_kernel:
+// 2 x 2 waves of (16*TM) x (16*TN), BK = 16, double-buffered LDS with the next
+// step's operands prefetched into registers.  The LDS pitch BM + 16 puts the
+// four k rows of an operand fetch on disjoint banks.  Outputs:
+//   OUT32: C32 = D32 o (alpha * AB), FP32 (the A = V o P chunk, short K);
+//   else   C = alpha * AB + beta * C in FP64, or FP64 partials per K split,
+//          with the FP32 sums moved into FP64 registers every 64 terms of K.
+template <int TM, int TN, bool TA, bool TB, bool OUT32>
+__global__ __launch_bounds__(256, 2) void gemm32_kernel(Gemm32 g) {
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  constexpr int PA = BM * BK / 256, PB = BN * BK / 256;
+  constexpr int LA = BM + 16, LB = BN + 16;
+  __shared__ float As[2][BK * LA];
+  __shared__ float Bs[2][BK * LB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int bz = blockIdx.z;
+  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+
+  int64_t kbeg = 0, kend = g.K;
+  if (g.splitk > 1) {
+    const int64_t per = ((g.K + g.splitk - 1) / g.splitk + BK - 1) / BK * BK;
+    kbeg = (int64_t)bz * per;
+    kend = (kbeg + per < g.K) ? kbeg + per : g.K;
+  }
+  const int64_t nk = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
+
+  const bool interior = (m0 + BM <= g.M) && (n0 + BN <= g.N);
+  const int lda = (int)g.lda, ldb = (int)g.ldb;
+  float ra[PA], rb[PB];
+  auto load = [&](int64_t k0) {
+    const bool full = interior && (k0 + BK <= kend);
+    const int64_t kc = (k0 < kend) ? k0 : kbeg;   // keeps the base in bounds past the last step
+    const float* ba = g.A + (TA ? kc * g.lda + m0 : m0 * g.lda + kc);
+    const float* bb = g.B + (TB ? n0 * g.ldb + kc : kc * g.ldb + n0);
+    if (full) {
+#pragma unroll
+      for (int i = 0; i < PA; ++i) {
+        const int e = tid + 256 * i;
+        const int m = TA ? e % BM : e / BK, k = TA ? e / BM : e % BK;
+        ra[i] = ba[TA ? k * lda + m : m * lda + k];
+      }
+#pragma unroll
+      for (int i = 0; i < PB; ++i) {
+        const int e = tid + 256 * i;
+        const int n = TB ? e / BK : e % BN, k = TB ? e % BK : e / BN;
+        rb[i] = bb[TB ? n * ldb + k : k * ldb + n];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < PA; ++i) {
+        const int e = tid + 256 * i;
+        const int m = TA ? e % BM : e / BK, k = TA ? e / BM : e % BK;
+        ra[i] = (m0 + m < g.M && k0 + k < kend) ? ba[TA ? k * lda + m : m * lda + k] : 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < PB; ++i) {
+        const int e = tid + 256 * i;
+        const int n = TB ? e / BK : e % BN, k = TB ? e % BK : e / BN;
+        rb[i] = (n0 + n < g.N && k0 + k < kend) ? bb[TB ? n * ldb + k : k * ldb + n] : 0.f;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < PA; ++i) {
+      const int e = tid + 256 * i;
+      const int m = TA ? e % BM : e / BK, k = TA ? e / BM : e % BK;
+      As[buf][k * LA + m] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < PB; ++i) {
+      const int e = tid + 256 * i;
+      const int n = TB ? e / BK : e % BN, k = TB ? e % BK : e / BN;
+      Bs[buf][k * LB + n] = rb[i];
+    }
+  };
+
+  f4_t acc[TM][TN];
+  // FP64 output: the FP32 sums cover FLUSH K steps (64 terms), then go into FP64
+  // registers, so rounding does not grow with the length of K
+  constexpr int FLUSH = OUT32 ? (1 << 30) : 4;
+  double acc64[OUT32 ? 1 : TM][OUT32 ? 1 : TN][4];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = zero_f4();
+  if constexpr (!OUT32) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
+  }
+
+  if (nk > 0) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t t0 = 0; t0 < nk; t0 += FLUSH) {
+    const int64_t t1 = (t0 + FLUSH < nk) ? t0 + FLUSH : nk;
+    for (int64_t t = t0; t < t1; ++t) {
+      load(kbeg + (t + 1) * BK);
+      const float* as = As[t & 1] + lq * LA + wm * 16 * TM + l16;
+      const float* bs = Bs[t & 1] + lq * LB + wn * 16 * TN + l16;
+#pragma unroll
+      for (int kk = 0; kk < BK / 4; ++kk) {
+        float a[TM], b[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) a[i] = as[4 * kk * LA + 16 * i];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) b[j] = bs[4 * kk * LB + 16 * j];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = mfma_f32(a[i], b[j], acc[i][j]);
+      }
+      store((t + 1) & 1);
+      __syncthreads();
+    }
+    if constexpr (!OUT32) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[i][j][r];
+          acc[i][j] = zero_f4();
+        }
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = m0 + wm * 16 * TM + i * 16 + d32_row(lane, r);
+        const int64_t gn = n0 + wn * 16 * TN + j * 16 + l16;
+        if (gm < g.M && gn < g.N) {
+          if constexpr (OUT32) {
+            g.C32[gm * g.ldc + gn] = g.D32[gm * g.ldd + gn] * ((float)g.alpha * acc[i][j][r]);
+          } else {
+            const double v = g.alpha * acc64[i][j][r];
+            if (g.splitk > 1) {
+              g.work[((int64_t)bz * g.M + gm) * g.N + gn] = v;
+              continue;
+            }
+            double* c = g.C + gm * g.ldc + gn;
+            *c = (g.beta == 0.0) ? v : v + g.beta * *c;
+          }
+        }
+      }
+}
+
 // C = alpha * sum_z work[z] + beta * C (fixed order over z)
 __global__ void splitk_reduce_kernel(const double* __restrict__ work, int splitk, int64_t M, int64_t N,
                                      double* __restrict__ C, int64_t ldc, double beta) {
@@ -299,6 +459,60 @@ hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
                        g.splitk, g.M, g.N, g.C, g.ldc, g.beta);
   }
   return hipGetLastError();
+}
+
+namespace {
+template <int TN, bool OUT32>
+void launch32(const Gemm32& g, dim3 grid, hipStream_t s) {
+  if (!g.transA && !g.transB) hipLaunchKernelGGL((gemm32_kernel<4, TN, false, false, OUT32>), grid, dim3(256), 0, s, g);
+  else if (g.transA && !g.transB) hipLaunchKernelGGL((gemm32_kernel<4, TN, true, false, OUT32>), grid, dim3(256), 0, s, g);
+  else if (!g.transA && g.transB) hipLaunchKernelGGL((gemm32_kernel<4, TN, false, true, OUT32>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((gemm32_kernel<4, TN, true, true, OUT32>), grid, dim3(256), 0, s, g);
+}
+}  // namespace
+
+int gemm32_tile_n(int64_t N) {
+  // 128-wide output tiles unless 64-wide ones pad N less (N = 432: 448 against 512)
+  const int64_t p128 = (N + 127) / 128 * 128, p64 = (N + 63) / 64 * 64;
+  return (p64 < p128) ? 64 : 128;
+}
+
+hipError_t gemm_f32(const Gemm32& g0, hipStream_t s) {
+  Gemm32 g = g0;
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  const bool out32 = g.C32 != nullptr;
+  if (out32 && (!g.D32 || g.splitk > 1)) return hipErrorInvalidValue;
+  if (!out32 && !g.C) return hipErrorInvalidValue;
+  if (g.splitk > 1 && !g.work) return hipErrorInvalidValue;
+  if (g.splitk < 1) g.splitk = 1;
+  // 32-bit per-lane offsets inside a tile (at most 128 rows of either operand)
+  if (g.lda > INT32_MAX / 128 || g.ldb > INT32_MAX / 128) return hipErrorInvalidValue;
+  const int bn = out32 ? gemm32_tile_n(g.N) : 64;
+  dim3 grid((unsigned)((g.N + bn - 1) / bn), (unsigned)((g.M + 127) / 128), (unsigned)g.splitk);
+  if (grid.y > 65535u) return hipErrorInvalidValue;
+  if (bn == 64) {
+    if (out32) launch32<2, true>(g, grid, s); else launch32<2, false>(g, grid, s);
+  } else {
+    launch32<4, true>(g, grid, s);
+  }
+  if (g.splitk > 1) {
+    const int64_t cnt = g.M * g.N;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, g.work,
+                       g.splitk, g.M, g.N, g.C, g.ldc, g.beta);
+  }
+  return hipGetLastError();
+}
+
+int gemm32_splitk_for(int64_t M, int64_t N, int64_t K, int64_t kmax, int64_t work_cap_doubles) {
+  // K per split at most kmax, then >= 1024 workgroups while each split keeps
+  // >= 1024 of K, within the workspace (FP64-output tiles are 128 x 64)
+  const int bn = 64;
+  const int64_t tiles = ((M + 127) / 128) * ((N + bn - 1) / bn);
+  int64_t z = 1;
+  while ((K + z - 1) / z > kmax) ++z;
+  while (tiles * z < 1024 && K / (z + 1) >= 1024) ++z;
+  while (z > 1 && z * M * N > work_cap_doubles) --z;
+  return (int)z;
 }
 
 int gemm_splitk_for(int64_t M, int64_t N, int64_t K, int64_t work_cap_doubles) {

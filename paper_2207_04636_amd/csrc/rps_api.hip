@@ -91,6 +91,7 @@ struct rps_context {
   int gws_np = -1;
   int64_t gchunk = 0;
   DBuf<double> gCp, gU, gUg, gA, gSp, gM2, gM1T, gK1, gK3, gY, gwork, epart;
+  DBuf<float> gU32, gUg32, gA32;   // precision form of the GEMM form: FP32 operands and A chunk
   DBuf<unsigned> ecount;   // last-block counter of the finalize kernel's energy sum (zero between builds)
   int64_t rblocks_main = 0, blocks_main = 0, blocks_l3 = 0;
   int rtiles = 4, gblocks = 1, nwaves = 4;
@@ -139,6 +140,9 @@ struct rps_context {
     for (auto* b : all) b->release(nullptr);
     DBuf<double>* gen[] = {&gCp, &gU, &gUg, &gA, &gSp, &gM2, &gM1T, &gK1, &gK3, &gY, &gwork, &epart};
     for (auto* b : gen) b->release(nullptr);
+    gU32.release(nullptr);
+    gUg32.release(nullptr);
+    gA32.release(nullptr);
     ecount.release(nullptr);
     DBuf<double>* jb[] = {&kern, &jCp, &jCin, &jU, &jrho, &jwork, &jpart, &jJ, &Sdev, &mCp, &mSC, &mpart};
     for (auto* b : jb) b->release(nullptr);
@@ -666,27 +670,44 @@ void ensure_workspace(rps_context& c, int np) {
 }
 
 // ------------------------------------------------------------------ general path
-// Any N and n.  For chunks of Gc interpolation points (rows of V):
-//   A_c = V_c o (U_g[c] U^T)              (product whose epilogue multiplies by V)
-//   M2[c] = A_c U                          (long inner dimension, split over workgroups)
-//   M1^T += A_c^T U_g[c]
+// Any N and n.  The GEMM form (padded n above the streaming form's limit) takes
+// the grid in chunks c of R_c columns of V:
+//   A_c = V[:, c] o (U_g U[c]^T)          (N_aux x R_c; the epilogue multiplies by V)
+//   M1^T[c] = A_c^T U_g                    (rows c of M1^T, written once)
+//   M2 += A_c U[c]                         (N_aux x n, accumulated over the chunks)
 // then K1 = Phi^T M1^T, K2 = Phi_g^T M2, B = W o (U_g U_g^T), Y = B U_g,
-// K3 = Phi_g^T Y, e1 = tr(U_g^T M2), e3 = tr(U_g^T Y)  (Eq. 16).
+// K3 = Phi_g^T Y, e1 = tr(U_g^T M2), e3 = tr(U_g^T Y)  (Eq. 16).  In the
+// precision form the three chunk products run on the FP32 matrix cores with V,
+// U and U_g in FP32 and A_c stored in FP32; the products into M1^T and M2 sum 64
+// terms at a time in FP32 and everything beyond (longer sums, splits, chunks, K)
+// in FP64.
 
 void ensure_general(rps_context& c, int np) {
   if (c.gws_np == np) return;
   c.clear_graphs();
   int64_t* cnt = &c.bytes;
-  const int64_t budget = 2000000000ll / 8;     // A chunk: about 2 GB
-  int64_t gc = std::max<int64_t>(64, budget / c.ngp / 64 * 64);
-  gc = std::min(gc, c.nauxp);
-  c.gchunk = gc;
+  const bool f32 = c.precision != RPS_PREC_FP64;
+  const int64_t budget = 2000000000ll / (f32 ? 4 : 8);     // A chunk: about 2 GB
+  int64_t rc = std::max<int64_t>(128, budget / c.nauxp / 128 * 128);
+  if (const char* e = getenv("RPS_GEMM_RCHUNK")) rc = std::max<int64_t>(1, atoll(e));   // tests: ragged chunks
+  rc = std::min(rc, c.ngp);
+  c.gchunk = rc;
   c.gCp.alloc(c.Np * np, cnt);
   c.gU.alloc(c.ngp * np, cnt);
   c.gUg.alloc(c.nauxp * np, cnt);
+  c.gU32.release(cnt);
+  c.gUg32.release(cnt);
+  c.gA32.release(cnt);
   if (np > kStreamMaxNp || getenv("RPS_GENERAL_GEMM")) {
     c.gSp.release(cnt);
-    c.gA.alloc(std::max(gc * c.ngp, c.nauxp * c.nauxp), cnt);
+    if (f32) {
+      c.gA.alloc(c.nauxp * c.nauxp, cnt);      // B of the fit-fit line (FP64)
+      c.gA32.alloc(c.nauxp * rc, cnt);
+      c.gU32.alloc(c.ngp * np, cnt);
+      c.gUg32.alloc(c.nauxp * np, cnt);
+    } else {
+      c.gA.alloc(std::max(c.nauxp * rc, c.nauxp * c.nauxp), cnt);
+    }
   } else {
     c.gA.release(cnt);
     c.gSp.alloc(kStreamPartRows * np, cnt);    // split partials of the streaming form
@@ -774,25 +795,52 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
     }
   } else if (need_main) {
     prof_mark(c, 1, st);
-    for (int64_t g0 = 0; g0 < c.nauxp; g0 += c.gchunk) {
-      const int64_t gc = std::min(c.gchunk, c.nauxp - g0);
-      Gemm a;   // A_c = V_c o (U_g[c] U^T)
-      a.M = gc; a.N = c.ngp; a.K = np;
-      a.A = c.gUg.p + g0 * np; a.lda = np; a.B = c.gU.p; a.ldb = np; a.transB = true;
-      a.C = c.gA.p; a.ldc = c.ngp; a.epi = EPI_HADAMARD_SRC; a.ldd = c.ngp;
-      if (c.V.p) a.D = c.V.p + g0 * c.ngp;
-      else a.D32 = c.V32.p + g0 * c.ngp;      // precision form: V held in FP32, products in FP64
-      gemm_run(a, c, st, "A chunk", false);
-      Gemm m2;  // M2[c] = A_c U
-      m2.M = gc; m2.N = np; m2.K = c.ngp;
-      m2.A = c.gA.p; m2.lda = c.ngp; m2.B = c.gU.p; m2.ldb = np; m2.C = c.gM2.p + g0 * np; m2.ldc = np;
-      gemm_run(m2, c, st, "M2", true);
-      if (k1) {
-        Gemm m1;  // M1^T += A_c^T U_g[c]
-        m1.M = c.ngp; m1.N = np; m1.K = gc;
-        m1.A = c.gA.p; m1.lda = c.ngp; m1.transA = true; m1.B = c.gUg.p + g0 * np; m1.ldb = np;
-        m1.C = c.gM1T.p; m1.ldc = np; m1.beta = (g0 == 0) ? 0.0 : 1.0;
-        gemm_run(m1, c, st, "M1", false);
+    const bool f32 = c.gA32.p != nullptr;
+    if (f32) {
+      hip_check(to_f32(c.gU.p, c.ngp * np, c.gU32.p, st), "U to f32");
+      hip_check(to_f32(c.gUg.p, c.nauxp * np, c.gUg32.p, st), "U_g to f32");
+    }
+    constexpr int64_t kF32Terms = 1ll << 40;   // split for parallelism only (FP32 sums are short)
+    for (int64_t r0 = 0; r0 < c.ngp; r0 += c.gchunk) {
+      const int64_t rc = std::min(c.gchunk, c.ngp - r0);
+      if (f32) {
+        Gemm32 a;   // A_c = V[:, c] o (U_g U[c]^T), FP32
+        a.M = c.nauxp; a.N = rc; a.K = np;
+        a.A = c.gUg32.p; a.lda = np; a.B = c.gU32.p + r0 * np; a.ldb = np; a.transB = true;
+        a.C32 = c.gA32.p; a.ldc = rc; a.D32 = c.V32.p + r0; a.ldd = c.ngp;
+        hip_check(gemm_f32(a, st), "A chunk");
+        if (k1) {
+          Gemm32 m1;   // M1^T[c] = A_c^T U_g
+          m1.M = rc; m1.N = np; m1.K = c.nauxp;
+          m1.A = c.gA32.p; m1.lda = rc; m1.transA = true; m1.B = c.gUg32.p; m1.ldb = np;
+          m1.C = c.gM1T.p + r0 * np; m1.ldc = np;
+          m1.splitk = gemm32_splitk_for(m1.M, m1.N, m1.K, kF32Terms, kSplitWork); m1.work = c.gwork.p;
+          hip_check(gemm_f32(m1, st), "M1");
+        }
+        Gemm32 m2;     // M2 += A_c U[c]
+        m2.M = c.nauxp; m2.N = np; m2.K = rc;
+        m2.A = c.gA32.p; m2.lda = rc; m2.B = c.gU32.p + r0 * np; m2.ldb = np;
+        m2.C = c.gM2.p; m2.ldc = np; m2.beta = (r0 == 0) ? 0.0 : 1.0;
+        m2.splitk = gemm32_splitk_for(m2.M, m2.N, m2.K, kF32Terms, kSplitWork); m2.work = c.gwork.p;
+        hip_check(gemm_f32(m2, st), "M2");
+      } else {
+        Gemm a;     // A_c = V[:, c] o (U_g U[c]^T)
+        a.M = c.nauxp; a.N = rc; a.K = np;
+        a.A = c.gUg.p; a.lda = np; a.B = c.gU.p + r0 * np; a.ldb = np; a.transB = true;
+        a.C = c.gA.p; a.ldc = rc; a.epi = EPI_HADAMARD_SRC; a.D = c.V.p + r0; a.ldd = c.ngp;
+        gemm_run(a, c, st, "A chunk", false);
+        if (k1) {
+          Gemm m1;  // M1^T[c] = A_c^T U_g
+          m1.M = rc; m1.N = np; m1.K = c.nauxp;
+          m1.A = c.gA.p; m1.lda = rc; m1.transA = true; m1.B = c.gUg.p; m1.ldb = np;
+          m1.C = c.gM1T.p + r0 * np; m1.ldc = np;
+          gemm_run(m1, c, st, "M1", true);
+        }
+        Gemm m2;    // M2 += A_c U[c]
+        m2.M = c.nauxp; m2.N = np; m2.K = rc;
+        m2.A = c.gA.p; m2.lda = rc; m2.B = c.gU.p + r0 * np; m2.ldb = np;
+        m2.C = c.gM2.p; m2.ldc = np; m2.beta = (r0 == 0) ? 0.0 : 1.0;
+        gemm_run(m2, c, st, "M2", true);
       }
     }
     prof_mark(c, 2, st);

@@ -34,6 +34,27 @@ hipError_t gemm_f64(const Gemm& g, hipStream_t s);
 // Split count giving enough workgroups for a long-K product within work_cap doubles.
 int gemm_splitk_for(int64_t M, int64_t N, int64_t K, int64_t work_cap_doubles);
 
+// FP32 operands on the FP32 matrix cores:
+//   C32 != NULL: C32[M x N] (ldc) = D32 o (alpha * op(A) op(B)), FP32 sums (no split)
+//   else:        C[M x N] (ldc, FP64) = alpha * op(A) op(B) + beta * C; FP32 sums over
+//                64 terms of K at a time, FP64 beyond, the K splits summed in FP64 in a
+//                fixed order (partials in work, splitk * M * N)
+struct Gemm32 {
+  int64_t M = 0, N = 0, K = 0;
+  const float* A = nullptr; int64_t lda = 0; bool transA = false;
+  const float* B = nullptr; int64_t ldb = 0; bool transB = false;
+  double* C = nullptr; int64_t ldc = 0;
+  double alpha = 1.0, beta = 0.0;
+  float* C32 = nullptr;
+  const float* D32 = nullptr; int64_t ldd = 0;
+  int splitk = 1;
+  double* work = nullptr;
+};
+hipError_t gemm_f32(const Gemm32& g, hipStream_t s);
+// Split count with at most kmax of K per split and enough workgroups, within work_cap doubles
+// (a split count whose K range exceeds kmax is returned when the workspace allows no more).
+int gemm32_splitk_for(int64_t M, int64_t N, int64_t K, int64_t kmax, int64_t work_cap_doubles);
+
 // ---------------------------------------------------------------- basis / grid
 struct ShellDev {        // one Gaussian shell, device copy
   double cx, cy, cz;     // centre wrapped into the cell

@@ -100,11 +100,11 @@ def test_supercell_2x2x2_coulomb_against_oracle(lib):
 
 
 def test_supercell_3x3x3_scf_steps(lib):
-    """Config 4: FP64 GEMM form, then the precision form (FP32 V) on the same
-    points, over SCF-like steps.  The two contexts live one after the other
-    (FP64 V alone is 121 GB)."""
+    """Config 4: FP64 GEMM form, then the precision form (FP32 V and FP32
+    matrix-core products) on the same points, over SCF-like steps.  The two
+    contexts live one after the other (FP64 V alone is 121 GB)."""
     w = ri.diamond_3x3x3()
-    _say(f"case: {w.name} FP64 then FP32 V, 3 SCF-like steps")
+    _say(f"case: {w.name} FP64 then FP32 form, 3 SCF-like steps")
     with lib.Context.from_workload(w, seed=w.sketch_seed()) as ctx:
         pts = ctx.points()
         S = ctx.overlap()
@@ -134,6 +134,6 @@ def test_supercell_3x3x3_scf_steps(lib):
         for s, Cs in enumerate(steps):
             K, E = ctx.build(Cs)
             dk = np.abs(K - ref[s][0]).max() / np.abs(ref[s][0]).max()
-            _say(f"  FP32-V step {s}: dE={E - ref[s][1]:.3e} dK={dk:.3e}")
+            _say(f"  FP32 step {s}: dE={E - ref[s][1]:.3e} dK={dk:.3e}")
             assert abs(E - ref[s][1]) < 1e-6
             assert dk < 1e-4

@@ -6,7 +6,8 @@ n <= 128, and the GEMM form (A = V o P materialised in chunks) above it.  The
 cases below are diamond-like supercells on coarse grids, sized so the oracle
 finishes in seconds while the GPU kernels see several workgroups, ragged x
 blocks (N_aux and N_g not multiples of the 128-row block), ragged n (padding
-to 16) and every orbital block count used by configs 3 and 5.
+to 16), every orbital block count used by configs 3 and 5, and n above the
+streaming form's limit (the GEMM form of config 4).
 
 Bars with shared interpolation points: FP64 |dE_x| < 1e-8 Ha and
 max|dK|/max|K| < 1e-7; FP32 form |dE_x| < 1e-6 Ha with the K error reported
@@ -35,6 +36,8 @@ CASES = {
     "2x1x1-n40": dict(rep=(2, 1, 1), mesh_per_cell=20, nocc_per_atom=2, c=5.0, cid=62, nocc=40),
     # N = 416, n = 128 (eight blocks, the config-3 shape), N_g = 32 x 32 x 16
     "2x2x1-n128": dict(rep=(2, 2, 1), mesh_per_cell=16, nocc_per_atom=4, c=4.0, cid=63),
+    # N = 208, n = 150 (padded to 160, above the streaming form: the GEMM form, as config 4)
+    "2x1x1-n150": dict(rep=(2, 1, 1), mesh_per_cell=20, nocc_per_atom=2, c=4.0, cid=64, nocc=150),
 }
 
 
@@ -143,20 +146,28 @@ def test_full_exchange_general(lib):
     assert _kerr(Kf @ cs["C"], Ko) < 1e-10
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_gemm_form(lib, monkeypatch, prec):
-    """The chunked GEMM form (used for padded n > 128) on the same case; in the
-    precision form it reads V from its FP32 copy (products stay FP64)."""
-    _say(f"case: general GEMM form 2x1x1-n32 {prec}")
+@pytest.mark.parametrize("name,prec,rchunk", [
+    ("2x1x1-n32", "fp64", None), ("2x1x1-n32", "fp32", None), ("2x1x1-n32", "bf16x3", None),
+    ("2x1x1-n40", "fp64", 1000), ("2x1x1-n40", "fp32", 1000), ("2x1x1-n150", "fp32", 3333),
+])
+def test_gemm_form(lib, monkeypatch, name, prec, rchunk):
+    """The GEMM form (used for padded n > 128) forced onto smaller n, and with
+    grid chunks that do not divide N_g (rchunk columns, last chunk ragged).  The
+    precision forms run its three chunk products on the FP32 matrix cores."""
+    _say(f"case: general GEMM form {name} {prec} chunk={rchunk}")
     monkeypatch.setenv("RPS_GENERAL_GEMM", "1")
-    cs = _case("2x1x1-n32")
-    p = lib.PREC_FP64 if prec == "fp64" else lib.PREC_FP32
+    if rchunk is not None:
+        monkeypatch.setenv("RPS_GEMM_RCHUNK", str(rchunk))
+    cs = _case(name)
+    p = {"fp64": lib.PREC_FP64, "fp32": lib.PREC_FP32, "bf16x3": lib.PREC_BF16X3}[prec]
     with lib.Context.from_workload(cs["w"], points=cs["points"], precision=p) as ctx:
         K, E = ctx.build(cs["C"])
+        K2, E2 = ctx.build(cs["C"])
     tol_e, tol_k = (1e-8, 1e-7) if prec == "fp64" else (1e-6, 1e-4)
     _say(f"  dE={E - cs['E']:.3e} dK={_kerr(K, cs['K']):.3e}")
     assert abs(E - cs["E"]) < tol_e
     assert _kerr(K, cs["K"]) < tol_k
+    assert np.array_equal(K, K2) and E == E2
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
