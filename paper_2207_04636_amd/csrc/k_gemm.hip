@@ -508,11 +508,20 @@ int gemm32_splitk_for(int64_t M, int64_t N, int64_t K, int64_t kmax, int64_t wor
   // >= 1024 of K, within the workspace (FP64-output tiles are 128 x 64)
   const int bn = 64;
   const int64_t tiles = ((M + 127) / 128) * ((N + bn - 1) / bn);
-  int64_t z = 1;
-  while ((K + z - 1) / z > kmax) ++z;
-  while (tiles * z < 1024 && K / (z + 1) >= 1024) ++z;
-  while (z > 1 && z * M * N > work_cap_doubles) --z;
-  return (int)z;
+  // among the split counts that keep >= 1024 of K per split, the one whose workgroups
+  // fill the last round of 512 (two per CU) best, the smaller on a tie
+  int64_t z0 = 1;
+  while ((K + z0 - 1) / z0 > kmax) ++z0;
+  int64_t best = z0;
+  double best_fill = -1.0;
+  for (int64_t z = z0; z <= z0 + 7; ++z) {
+    if (z > z0 && K / z < 1024) break;
+    if (z > 1 && z * M * N > work_cap_doubles) break;
+    const int64_t wgs = tiles * z, rounds = (wgs + 511) / 512;
+    const double fill = (double)wgs / (double)(rounds * 512) + (rounds > 1 ? 0.0 : -0.5);
+    if (fill > best_fill + 1e-9) { best_fill = fill; best = z; }
+  }
+  return (int)best;
 }
 
 int gemm_splitk_for(int64_t M, int64_t N, int64_t K, int64_t work_cap_doubles) {

@@ -187,35 +187,45 @@ hipError_t cholesky_lower(double* A, int64_t n, int64_t lda, int32_t* status, hi
   return hipGetLastError();
 }
 
+// Two-level blocked solve.  Outer blocks of NB2 rows: the block is solved 64 rows
+// at a time (the 64 x 64 triangle in LDS, one thread per right-hand side, and
+// rank-64 updates confined to the block's rows), then the rest of B takes one
+// rank-NB2 update.  The updates that sweep all of B are therefore NB2 deep, so B
+// streams through HBM n / NB2 times instead of n / 64 times.
 hipError_t tri_solve_lower(const double* L, int64_t n, int64_t ldl, double* B, int64_t ncols,
                            int64_t ldb, bool trans, hipStream_t s) {
-  const int64_t nb = n / NB;
-  for (int64_t q = 0; q < nb; ++q) {
-    const int64_t b = trans ? (nb - 1 - q) : q;
-    const int64_t k0 = b * NB;
-    if (!trans)
-      hipLaunchKernelGGL(tri64_kernel<false>, dim3(nblk(ncols, 256)), dim3(256), 0, s,
-                         L + k0 * ldl + k0, ldl, B + k0 * ldb, (int64_t)1, ldb, ncols);
-    else
-      hipLaunchKernelGGL(tri64_kernel<true>, dim3(nblk(ncols, 256)), dim3(256), 0, s,
-                         L + k0 * ldl + k0, ldl, B + k0 * ldb, (int64_t)1, ldb, ncols);
+  constexpr int64_t NB2 = 512;
+  if (n % NB != 0) return hipErrorInvalidValue;
+  const int64_t nout = (n + NB2 - 1) / NB2;
+  auto update = [&](int64_t r0, int64_t r1, int64_t k0, int64_t kb) -> hipError_t {
+    // rows [r0, r1) of B minus the contribution of the solved rows [k0, k0 + kb)
+    if (r1 <= r0) return hipSuccess;
     Gemm g;
-    g.N = ncols; g.K = NB;
+    g.M = r1 - r0; g.N = ncols; g.K = kb;
     g.B = B + k0 * ldb; g.ldb = ldb;
+    g.C = B + r0 * ldb; g.ldc = ldb;
     g.alpha = -1.0; g.beta = 1.0;
-    if (!trans) {            // rows below: B[k0+NB:] -= L[k0+NB:, k0:k0+NB] X_b
-      g.M = n - k0 - NB;
-      g.A = L + (k0 + NB) * ldl + k0; g.lda = ldl;
-      g.C = B + (k0 + NB) * ldb; g.ldc = ldb;
-    } else {                 // rows above: B[:k0] -= L[k0:k0+NB, :k0]^T X_b
-      g.M = k0;
-      g.A = L + k0 * ldl; g.lda = ldl; g.transA = true;
-      g.C = B; g.ldc = ldb;
-    }
-    if (g.M > 0) {
-      hipError_t e = gemm_f64(g, s);
+    if (!trans) { g.A = L + r0 * ldl + k0; g.lda = ldl; }                     // L[r0:r1, k0:k0+kb]
+    else { g.A = L + k0 * ldl + r0; g.lda = ldl; g.transA = true; }           // L[k0:k0+kb, r0:r1]^T
+    return gemm_f64(g, s);
+  };
+  for (int64_t oq = 0; oq < nout; ++oq) {
+    const int64_t ob = trans ? (nout - 1 - oq) : oq;
+    const int64_t o0 = ob * NB2, o1 = (o0 + NB2 < n) ? o0 + NB2 : n;
+    const int64_t nin = (o1 - o0) / NB;
+    for (int64_t q = 0; q < nin; ++q) {
+      const int64_t k0 = o0 + (trans ? (nin - 1 - q) : q) * NB;
+      if (!trans)
+        hipLaunchKernelGGL(tri64_kernel<false>, dim3(nblk(ncols, 256)), dim3(256), 0, s,
+                           L + k0 * ldl + k0, ldl, B + k0 * ldb, (int64_t)1, ldb, ncols);
+      else
+        hipLaunchKernelGGL(tri64_kernel<true>, dim3(nblk(ncols, 256)), dim3(256), 0, s,
+                           L + k0 * ldl + k0, ldl, B + k0 * ldb, (int64_t)1, ldb, ncols);
+      const hipError_t e = trans ? update(o0, k0, k0, NB) : update(k0 + NB, o1, k0, NB);
       if (e != hipSuccess) return e;
     }
+    const hipError_t e = trans ? update(0, o0, o0, o1 - o0) : update(o1, n, o0, o1 - o0);
+    if (e != hipSuccess) return e;
   }
   return hipGetLastError();
 }

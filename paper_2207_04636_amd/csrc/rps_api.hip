@@ -176,6 +176,8 @@ struct StageLog {
 constexpr int64_t kSplitWork = 64ll << 20;   // doubles of split-K partials (512 MB)
 constexpr int kEnergyBlocks = 256;            // most blocks the energy dot products are split over
 constexpr int kStreamMaxNp = 128;             // largest padded n of the streaming form
+constexpr int64_t kChiPanel = 32768;          // grid columns per fitting-function panel (set-up)
+constexpr int64_t kWBlock = 8192;             // grid columns per block of the W product (set-up)
 constexpr int kStreamBlocks = 512;            // workgroups aimed at per streaming launch (default)
 constexpr int kStreamMaxTarget = 1024;        // largest target the tuner tries
 constexpr int64_t kStreamPartRows = (int64_t)kStreamMaxTarget * 128;   // rows of split partials
@@ -381,8 +383,7 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
                                   (double)c.nauxp * c.nauxp) +
                            ((prec != RPS_PREC_FP64) ? 4.0 * (double)c.nauxp * c.ngp : 0.0);
     const double xgg = 8.0 * 3.0 * (double)c.nauxp * c.nauxp;   // L, T and its transpose
-    const int64_t bc = 8192;
-    const double xblk = 8.0 * (double)c.nauxp * bc;
+    const double xblk = 8.0 * (double)c.nauxp * (double)kWBlock;
     double selb = 0.0;
     if (!points_in && !c.exact) {
       const double ncand = (mode == RPS_SELECT_GLOBAL) ? (double)c.ng : (double)c.naux + 10.0 * c.natom + 64;
@@ -484,26 +485,21 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
     }
     (void)hipFree(dstatus);
     stage("fitting metric and Cholesky", st);
-    // ---- chi = X_gg^-1 X_gR in column panels: X_gR = (Phi_g Phi^T)^2 for the panel,
-    //      two triangular solves on the panel (its working set stays on chip), copy into V
+    // ---- chi = X_gg^-1 X_gR in column panels, in place in V: X_gR = (Phi_g Phi^T)^2 for
+    //      the panel, then the two triangular solves on it
     {
-      const int64_t pw = 8192;
-      DBuf<double> Xp;
-      Xp.alloc(c.nauxp * pw, &tmpb);
+      const int64_t pw = std::min(kChiPanel, c.ngp);
       for (int64_t r0 = 0; r0 < c.ngp; r0 += pw) {
         const int64_t nc = std::min(pw, c.ngp - r0);
         Gemm g;
         g.M = c.nauxp; g.N = nc; g.K = c.Np;
         g.A = c.Phig.p; g.lda = c.Np; g.B = c.Phi.p + r0 * c.Np; g.ldb = c.Np; g.transB = true;
-        g.C = Xp.p; g.ldc = pw; g.epi = EPI_SQUARE;
+        g.C = c.V.p + r0; g.ldc = c.ngp; g.epi = EPI_SQUARE;
         hip_check(gemm_f64(g, st), "X_gR panel");
-        hip_check(tri_solve_lower(L.p, c.nauxp, c.nauxp, Xp.p, nc, pw, false, st), "solve L");
-        hip_check(tri_solve_lower(L.p, c.nauxp, c.nauxp, Xp.p, nc, pw, true, st), "solve L^T");
-        hip_check(hipMemcpy2DAsync(c.V.p + r0, c.ngp * 8, Xp.p, pw * 8, nc * 8, c.nauxp, hipMemcpyDeviceToDevice, st),
-                  "panel copy");
+        hip_check(tri_solve_lower(L.p, c.nauxp, c.nauxp, c.V.p + r0, nc, c.ngp, false, st), "solve L");
+        hip_check(tri_solve_lower(L.p, c.nauxp, c.nauxp, c.V.p + r0, nc, c.ngp, true, st), "solve L^T");
       }
       hip_check(hipStreamSynchronize(st), "sync");
-      Xp.release(nullptr);
     }
     stage("fitting functions chi", st);
     // ---- V = Vc chi (Sec. 3.2)
@@ -511,7 +507,7 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
     stage("potentials V", st);
     // ---- W = V chi^T = (V X_gR^T) X_gg^-1  (Eq. 14), X_gR recomputed in column blocks
     {
-      const int64_t bc = 8192;
+      const int64_t bc = kWBlock;
       DBuf<double> T, Xb;
       T.alloc(c.nauxp * c.nauxp, &tmpb);
       Xb.alloc(c.nauxp * bc, &tmpb);
