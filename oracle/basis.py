@@ -126,3 +126,17 @@ def voronoi(w) -> np.ndarray:
 def overlap(Phi: np.ndarray, dV: float) -> np.ndarray:
     """Grid overlap S = dV Phi^T Phi (the metric used to orthonormalise C)."""
     return dV * (Phi.T @ Phi)
+
+
+def screen(Phi: np.ndarray, eps: float, dV: float) -> np.ndarray:
+    """Screened basis of Sec. 4.1: per atom the stored values on its Voronoi set
+    are those of the pSinc coefficients phi~ = sqrt(dV) phi above eps1 in
+    magnitude; everything else is dropped.  The Voronoi sets partition the grid,
+    so as a matrix this is Phi with the entries sqrt(dV) |phi| < eps set to zero
+    (eps = 0 keeps everything).  The storage layout (one dense block per atom)
+    does not change any value."""
+    if eps <= 0.0:
+        return Phi.copy()
+    out = Phi.copy()
+    out[np.sqrt(dV) * np.abs(Phi) < eps] = 0.0
+    return out

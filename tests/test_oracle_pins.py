@@ -2,6 +2,7 @@
 published test vectors, closed forms, brute-force sums without FFTs, exact
 algebraic identities of the rPS derivation (Sec. 3.2), special cases and
 invariants.  All CPU; no GPU code is involved."""
+import dataclasses
 import math
 import os
 
@@ -523,3 +524,46 @@ def test_madelung_correction_shifts():
     assert abs((E - E2) - C.shape[1] * M) < 1e-12
     np.testing.assert_allclose(K2 - K, M * S @ C, atol=1e-14)
 
+
+
+# ---------------------------------------------------------------- screened basis (Sec. 4.1)
+def test_screen_s_function_radius():
+    """One normalised s Gaussian in a large cubic cell (images below 1e-30): the
+    kept points are exactly those inside the radius where sqrt(dV) N e^(-a r^2)
+    equals eps, a closed form independent of the screening code."""
+    L, m, a, eps = 24.0, 48, 0.7, 1e-6
+    w = ri.tiny_s_cell(1, m, L, 1, 1, lmax=0)
+    w = dataclasses.replace(w, atoms=np.array([[L / 2, L / 2, L / 2]]), shell_exp=np.array([a]))
+    Phi = basis.eval_basis(w)
+    dV = grid.dvol(w.lattice, w.mesh)
+    Ps = basis.screen(Phi, eps, dV)
+    ns = (2.0 * a / math.pi) ** 0.75
+    rstar2 = math.log(math.sqrt(dV) * ns / eps) / a
+    pts = grid.grid_points(w.lattice, w.mesh)
+    r2 = np.sum((pts - L / 2) ** 2, axis=1)
+    inside = r2 <= rstar2
+    assert np.array_equal(Ps[:, 0] != 0.0, inside)
+    assert np.array_equal(Ps[inside, 0], Phi[inside, 0])
+    assert 0 < inside.sum() < len(inside)
+
+
+def test_screen_monotone_and_identity(cfg1):
+    w, Phi, dV, *_ = cfg1
+    assert np.array_equal(basis.screen(Phi, 0.0, dV), Phi)
+    a, b = basis.screen(Phi, 1e-6, dV), basis.screen(Phi, 1e-3, dV)
+    assert np.all((b != 0) <= (a != 0))          # a larger eps keeps a subset
+    kept = b != 0
+    assert np.array_equal(b[kept], Phi[kept])    # kept values are untouched
+
+
+def test_screen_at_paper_eps_leaves_exchange(cfg1):
+    """At eps1 = 1e-8 the screened exchange (same points, V and W from the
+    screened basis) differs from the unscreened one far below the fit error."""
+    w, Phi, dV, C, Kc, Ec, _ = cfg1
+    Ps = basis.screen(Phi, 1e-8, dV)
+    st = isdf.setup(w, Phi)
+    K0, E0, _ = rps.build_occ(Phi, st["points"], st["V"], st["W"], C, dV)
+    st2 = isdf.setup(w, Ps, points=st["points"])
+    K1, E1, _ = rps.build_occ(Ps, st2["points"], st2["V"], st2["W"], C, dV)
+    assert abs(E1 - E0) < 1e-7 * abs(E0)
+    assert np.abs(K1 - K0).max() < 1e-6 * np.abs(K0).max()
