@@ -105,6 +105,8 @@ typedef struct {
     int32_t precision;
     int32_t exact;        /* 1 if n_aux == N_g (chi = identity) */
     double madelung;      /* Madelung constant M of the cell (see rps_madelung_constant) */
+    double basis_fill;    /* screened set-up: fraction of the N_g x N basis values held in the
+                             atom blocks (1.0 without screening) */
 } rps_info;
 
 /*
@@ -131,6 +133,26 @@ typedef struct {
 rps_status rps_setup_isdf(const rps_cell *cell, const rps_basis *basis, int64_t n_aux,
                           uint64_t seed, int32_t select_mode, int32_t precision,
                           const int64_t *points_in, void *hip_stream, rps_context **out);
+
+/*
+ * rps_setup_isdf with the screened basis of Sec. 4.1: every basis value whose
+ * pSinc coefficient sqrt(dV) |phi_mu(R)| is below basis_eps (the paper's
+ * eps1, 1e-8 there) is dropped before anything reads the basis, so the set-up
+ * (points, chi, V, W) and every build use the screened values.  Each atom I
+ * then holds one dense block: the grid points of its Voronoi set times the
+ * basis functions not all zero there.  The general-size build (N > 128, or n
+ * above the fused kernels' limit) forms U = Phi C and K1 = Phi^T M1^T from
+ * these blocks, and rps_build_coulomb forms the density and J from them
+ * (bases with N > 128 or n > 64); the fused kernels for small bases read the
+ * screened values in dense form.  Sums over the atoms holding a function run
+ * in a fixed order, so results are deterministic.  basis_eps = 0 is exactly
+ * rps_setup_isdf.  rps_info.basis_fill reports the fraction of values held.
+ * Errors: as rps_setup_isdf; RPS_ERR_ARG for a negative or non-finite basis_eps.
+ */
+rps_status rps_setup_isdf_screened(const rps_cell *cell, const rps_basis *basis, int64_t n_aux,
+                                   uint64_t seed, int32_t select_mode, int32_t precision,
+                                   const int64_t *points_in, double basis_eps, void *hip_stream,
+                                   rps_context **out);
 
 /*
  * One exchange build, Eq. 16 (Sec. 3.3) with the contraction order of

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "RPS_OK", 1: "RPS_ERR_ARG", 2: "RPS_ERR_SHAPE", 3: "RPS_ERR_N
                 4: "RPS_ERR_NOT_PD", 5: "RPS_ERR_DEVICE", 6: "RPS_ERR_STATE"}
 
 # every symbol declared in include/rps.h
-EXPORTS = ("rps_setup_isdf", "rps_build_exchange_occRI", "rps_build_exchange_variant",
+EXPORTS = ("rps_setup_isdf", "rps_setup_isdf_screened", "rps_build_exchange_occRI", "rps_build_exchange_variant",
            "rps_build_exchange_full", "rps_build_coulomb", "rps_madelung_constant", "rps_madelung_correct",
            "rps_build_exchange_occRI_batched",
            "rps_exchange_energy",
@@ -60,7 +60,8 @@ class Info(ct.Structure):
                 ("ngrid_pad", ct.c_int64), ("nbas_pad", ct.c_int64), ("naux_pad", ct.c_int64),
                 ("n_candidates", ct.c_int64), ("dvol", ct.c_double), ("chol_shift", ct.c_double),
                 ("setup_seconds", ct.c_double), ("device_bytes", ct.c_int64),
-                ("precision", ct.c_int32), ("exact", ct.c_int32), ("madelung", ct.c_double)]
+                ("precision", ct.c_int32), ("exact", ct.c_int32), ("madelung", ct.c_double),
+                ("basis_fill", ct.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -88,6 +89,8 @@ def load(path: str = LIB_PATH):
     P, I32, I64, U64, D = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_uint64, ct.c_double
     lib.rps_setup_isdf.argtypes = [ct.POINTER(Cell), ct.POINTER(Basis), I64, U64, I32, I32,
                                    ct.POINTER(ct.c_int64), P, ct.POINTER(P)]
+    lib.rps_setup_isdf_screened.argtypes = [ct.POINTER(Cell), ct.POINTER(Basis), I64, U64, I32, I32,
+                                            ct.POINTER(ct.c_int64), D, P, ct.POINTER(P)]
     lib.rps_build_exchange_occRI.argtypes = [P, I32, P, P, P, I32, P]
     lib.rps_build_exchange_variant.argtypes = [P, I32, I32, P, P, P, I32, P]
     lib.rps_build_exchange_full.argtypes = [P, I32, P, P, I32, P]
@@ -162,7 +165,7 @@ class Context:
 
     def __init__(self, lattice, mesh, atoms, shell_atom, shell_l, shell_exp, naux: int,
                  seed: int = 0, select: int = SELECT_VORONOI, precision: int = PREC_FP64,
-                 points=None, stream=None):
+                 points=None, stream=None, basis_eps: float = 0.0):
         lib = load()
         self._lib = lib
         cell = Cell()
@@ -183,8 +186,9 @@ class Context:
             self._pts_in = np.ascontiguousarray(np.asarray(points, dtype=np.int64))
             pts = self._pts_in.ctypes.data_as(ct.POINTER(ct.c_int64))
         h = ct.c_void_p()
-        _check(lib.rps_setup_isdf(ct.byref(cell), ct.byref(b), int(naux), ct.c_uint64(int(seed) & (2**64 - 1)),
-                                  int(select), int(precision), pts, _stream_handle(stream), ct.byref(h)))
+        _check(lib.rps_setup_isdf_screened(ct.byref(cell), ct.byref(b), int(naux),
+                                           ct.c_uint64(int(seed) & (2**64 - 1)), int(select), int(precision),
+                                           pts, float(basis_eps), _stream_handle(stream), ct.byref(h)))
         self._h = h
         inf = self.info()
         self.nbas, self.naux, self.ngrid = int(inf["nbas"]), int(inf["naux"]), int(inf["ngrid"])

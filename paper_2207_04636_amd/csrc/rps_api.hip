@@ -83,6 +83,17 @@ struct rps_context {
   DBuf<float> V32;
   DBuf<float> Phi32;   // precision form, N <= 128: FP32 basis for the in-kernel orbitals
   DBuf<int64_t> dpoints;
+  // Voronoi-screened basis (Sec. 4.1; set up when eps1 > 0): atom I holds grid rows
+  // perm[vofs[I] .. vofs[I+1]) and functions fun[fofs[I] .. fofs[I+1]) (ascending); its
+  // block Phi_I sits at pofs[I] in sPhi (row-major, pitch n_I) and its J block at qofs[I]
+  double basis_eps = 0.0;
+  bool sparse = false;
+  std::vector<int64_t> vofs, fofs, pofs, qofs;
+  DBuf<int64_t> sperm, sinv, sfun, smu_ofs, smu_rows, sqofs, sfofs;
+  DBuf<int32_t> spos, smu_atom;   // pos[I][mu] (-1 if absent); atom of each CSR entry
+  DBuf<double> sPhi;
+  int sws_np = -1, sjws_np = -1;
+  DBuf<double> sCg, sUv, sK1p, sQ, svv, sjwork, sUj;
   // build workspace (grows on demand)
   int ws_np = -1;
   DBuf<double> U, Ug, Ugp, M2p, K1p, K3p, e1p, e3p, M2, K1, K3, Kdev, Cdev, exdev, e3u;
@@ -149,6 +160,12 @@ struct rps_context {
     V32.release(nullptr);
     Phi32.release(nullptr);
     dpoints.release(nullptr);
+    DBuf<int64_t>* si[] = {&sperm, &sinv, &sfun, &smu_ofs, &smu_rows, &sqofs, &sfofs};
+    for (auto* b : si) b->release(nullptr);
+    spos.release(nullptr);
+    smu_atom.release(nullptr);
+    DBuf<double>* sd[] = {&sPhi, &sCg, &sUv, &sK1p, &sQ, &svv, &sjwork, &sUj};
+    for (auto* b : sd) b->release(nullptr);
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     clear_graphs();
     if (gfork) (void)hipEventDestroy(gfork);
@@ -283,6 +300,105 @@ std::vector<int64_t> select_pivots(rps_context& c, const std::vector<int64_t>& c
   return out;
 }
 
+// Voronoi owner of every grid point (Sec. 4.1), kept on the host
+void compute_owners(rps_context& c, const double* atoms, hipStream_t st) {
+  if ((int64_t)c.owner_host.size() == c.ng) return;
+  DBuf<int32_t> own;
+  int64_t tmpb = 0;
+  own.alloc(c.ng, &tmpb);
+  DBuf<double> datoms;
+  datoms.alloc(3 * (int64_t)c.natom, &tmpb);
+  hip_check(hipMemcpyAsync(datoms.p, atoms, 3 * c.natom * 8, hipMemcpyHostToDevice, st), "copy atoms");
+  hip_check(voronoi_assign(make_cell(c), datoms.p, c.natom, c.ng, own.p, st), "voronoi");
+  c.owner_host.resize(c.ng);
+  hip_check(hipMemcpyAsync(c.owner_host.data(), own.p, c.ng * 4, hipMemcpyDeviceToHost, st), "copy owner");
+  hip_check(hipStreamSynchronize(st), "sync");
+  own.release(nullptr);
+  datoms.release(nullptr);
+}
+
+// Atom blocks of the screened basis: grid rows of each Voronoi set, the functions not
+// all zero there, the packed blocks and the maps of the fixed-order sums over atoms.
+void build_screened_blocks(rps_context& c, const double* atoms, hipStream_t st) {
+  compute_owners(c, atoms, st);
+  const int N = (int)c.nbas, natom = c.natom;
+  int64_t tmp = 0;
+  DBuf<int32_t> own, flags;
+  own.alloc(c.ng, &tmp);
+  flags.alloc((int64_t)natom * N, &tmp);
+  hip_check(hipMemcpyAsync(own.p, c.owner_host.data(), c.ng * 4, hipMemcpyHostToDevice, st), "copy owner");
+  hip_check(hipMemsetAsync(flags.p, 0, (size_t)natom * N * 4, st), "clear flags");
+  hip_check(basis_flags(c.Phi.p, c.ng, (int)c.Np, N, own.p, flags.p, st), "flags");
+  std::vector<int32_t> fl((size_t)natom * N);
+  hip_check(hipMemcpyAsync(fl.data(), flags.p, fl.size() * 4, hipMemcpyDeviceToHost, st), "copy flags");
+  hip_check(hipStreamSynchronize(st), "sync");
+  own.release(nullptr);
+  flags.release(nullptr);
+
+  std::vector<std::vector<int64_t>> kap(natom);
+  for (int64_t R = 0; R < c.ng; ++R) kap[c.owner_host[R]].push_back(R);
+  std::vector<int64_t> perm, inv(c.ng), fun;
+  std::vector<int32_t> pos((size_t)natom * N, -1);
+  c.vofs.assign(natom + 1, 0);
+  c.fofs.assign(natom + 1, 0);
+  c.pofs.assign(natom + 1, 0);
+  c.qofs.assign(natom + 1, 0);
+  for (int I = 0; I < natom; ++I) {
+    for (int64_t R : kap[I]) {
+      inv[R] = (int64_t)perm.size();
+      perm.push_back(R);
+    }
+    int k = 0;
+    for (int mu = 0; mu < N; ++mu)
+      if (fl[(size_t)I * N + mu]) {
+        pos[(size_t)I * N + mu] = k++;
+        fun.push_back(mu);
+      }
+    c.vofs[I + 1] = (int64_t)perm.size();
+    c.fofs[I + 1] = (int64_t)fun.size();
+    c.pofs[I + 1] = c.pofs[I] + (int64_t)kap[I].size() * k;
+    c.qofs[I + 1] = c.qofs[I] + (int64_t)k * k;
+  }
+  // for every function, the atoms holding it (ascending) and its packed row there
+  std::vector<int64_t> mofs(N + 1, 0), mrows;
+  std::vector<int32_t> matom;
+  for (int mu = 0; mu < N; ++mu) {
+    for (int I = 0; I < natom; ++I) {
+      const int p = pos[(size_t)I * N + mu];
+      if (p < 0) continue;
+      mrows.push_back(c.fofs[I] + p);
+      matom.push_back(I);
+    }
+    mofs[mu + 1] = (int64_t)mrows.size();
+  }
+  auto up64 = [&](DBuf<int64_t>& d, const std::vector<int64_t>& h) {
+    d.alloc(std::max<int64_t>((int64_t)h.size(), 1), &c.bytes);
+    if (!h.empty()) hip_check(hipMemcpyAsync(d.p, h.data(), h.size() * 8, hipMemcpyHostToDevice, st), "copy map");
+  };
+  auto up32 = [&](DBuf<int32_t>& d, const std::vector<int32_t>& h) {
+    d.alloc(std::max<int64_t>((int64_t)h.size(), 1), &c.bytes);
+    if (!h.empty()) hip_check(hipMemcpyAsync(d.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, st), "copy map");
+  };
+  up64(c.sperm, perm);
+  up64(c.sinv, inv);
+  up64(c.sfun, fun);
+  up64(c.smu_ofs, mofs);
+  up64(c.smu_rows, mrows);
+  up64(c.sqofs, c.qofs);
+  up64(c.sfofs, c.fofs);
+  up32(c.spos, pos);
+  up32(c.smu_atom, matom);
+  c.sPhi.alloc(std::max<int64_t>(c.pofs[natom], 1), &c.bytes);
+  for (int I = 0; I < natom; ++I) {
+    const int64_t nr = c.vofs[I + 1] - c.vofs[I];
+    const int nc = (int)(c.fofs[I + 1] - c.fofs[I]);
+    hip_check(pack_block(c.Phi.p, (int)c.Np, c.sperm.p + c.vofs[I], nr, c.sfun.p + c.fofs[I], nc,
+                         c.sPhi.p + c.pofs[I], st), "pack");
+  }
+  hip_check(hipStreamSynchronize(st), "sync");
+  c.sparse = true;
+}
+
 void select_points(rps_context& c, int mode, uint64_t seed, const std::vector<int>& nfunc_atom,
                    const double* atoms, hipStream_t st) {
   const int64_t global_limit = 16384;   // Gram of all grid points must stay small
@@ -300,18 +416,7 @@ void select_points(rps_context& c, int mode, uint64_t seed, const std::vector<in
     return;
   }
   // Voronoi sets (Sec. 4.1)
-  DBuf<int32_t> own;
-  int64_t tmpb = 0;
-  own.alloc(c.ng, &tmpb);
-  DBuf<double> datoms;
-  datoms.alloc(3 * (int64_t)c.natom, &tmpb);
-  hip_check(hipMemcpyAsync(datoms.p, atoms, 3 * c.natom * 8, hipMemcpyHostToDevice, st), "copy atoms");
-  hip_check(voronoi_assign(make_cell(c), datoms.p, c.natom, c.ng, own.p, st), "voronoi");
-  c.owner_host.resize(c.ng);
-  hip_check(hipMemcpyAsync(c.owner_host.data(), own.p, c.ng * 4, hipMemcpyDeviceToHost, st), "copy owner");
-  hip_check(hipStreamSynchronize(st), "sync");
-  own.release(nullptr);
-  datoms.release(nullptr);
+  compute_owners(c, atoms, st);
   std::vector<std::vector<int64_t>> kappa(c.natom);
   for (int64_t R = 0; R < c.ng; ++R) kappa[c.owner_host[R]].push_back(R);
   const double cfac = (double)c.naux / (double)c.nbas;
@@ -332,7 +437,7 @@ void select_points(rps_context& c, int mode, uint64_t seed, const std::vector<in
 }
 
 void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_t n_aux, uint64_t seed,
-                int32_t mode, int32_t prec, const int64_t* points_in, hipStream_t st) {
+                int32_t mode, int32_t prec, const int64_t* points_in, double basis_eps, hipStream_t st) {
   auto t0 = std::chrono::steady_clock::now();
   StageLog stage;
   // ---- validation
@@ -341,6 +446,8 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
     fail(RPS_ERR_ARG, "basis needs natom >= 1, nshell >= 1 and non-NULL arrays");
   if (prec < RPS_PREC_FP64 || prec > RPS_PREC_BF16X3) fail(RPS_ERR_ARG, "unknown precision");
   if (mode != RPS_SELECT_VORONOI && mode != RPS_SELECT_GLOBAL) fail(RPS_ERR_ARG, "unknown selection mode");
+  if (!(basis_eps >= 0.0) || !std::isfinite(basis_eps)) fail(RPS_ERR_ARG, "basis_eps must be finite and >= 0");
+  c.basis_eps = basis_eps;
   memcpy(c.lat, cell->lattice, sizeof c.lat);
   const double vol = fabs(det3(c.lat));
   if (!(vol > 1e-10) || !inv3(c.lat, c.ainv)) fail(RPS_ERR_ARG, "lattice is singular");
@@ -410,6 +517,9 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
     hip_check(hipMemcpyAsync(dsh.p, shells.data(), sizeof(ShellDev) * shells.size(), hipMemcpyHostToDevice, st),
               "copy shells");
     hip_check(basis_eval(make_cell(c), dsh.p, (int)shells.size(), c.ng, c.Phi.p, c.Np, st), "basis");
+    // screened basis (Sec. 4.1): pSinc coefficients sqrt(dV) |phi| below eps1 are dropped,
+    // before anything else reads Phi
+    if (basis_eps > 0.0) hip_check(screen_basis(c.Phi.p, c.ngp * c.Np, basis_eps / sqrt(c.dV), st), "screen");
     hip_check(hipStreamSynchronize(st), "sync");
     (void)hipFree(dsh.p);
     dsh.p = nullptr;
@@ -549,6 +659,10 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
       hip_check(hipStreamSynchronize(st), "sync");
     }
   }
+  if (basis_eps > 0.0) {
+    build_screened_blocks(c, b->atom_xyz, st);
+    stage("screened basis blocks", st);
+  }
   c.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
@@ -678,7 +792,18 @@ void ensure_workspace(rps_context& c, int np) {
 // terms at a time in FP32 and everything beyond (longer sums, splits, chunks, K)
 // in FP64.
 
+// workspace of the products with the screened basis's atom blocks
+void ensure_sparse_ws(rps_context& c, int np) {
+  if (c.sws_np == np) return;
+  c.clear_graphs();
+  c.sCg.alloc(std::max<int64_t>(c.fofs[c.natom], 1) * np, &c.bytes);
+  c.sK1p.alloc(std::max<int64_t>(c.fofs[c.natom], 1) * np, &c.bytes);
+  c.sUv.alloc(c.ng * np, &c.bytes);
+  c.sws_np = np;
+}
+
 void ensure_general(rps_context& c, int np) {
+  if (c.sparse) ensure_sparse_ws(c, np);
   if (c.gws_np == np) return;
   c.clear_graphs();
   int64_t* cnt = &c.bytes;
@@ -729,12 +854,55 @@ void gemm_run(Gemm g, rps_context& c, hipStream_t st, const char* what, bool all
   hip_check(gemm_f64(g, st), what);
 }
 
+// ---- products with the screened basis (atom blocks; see k_sparse.hip)
+// U (ngp x np, grid order) = Phi C from the atom blocks; Cp is C packed [Np][np]
+void sparse_u(rps_context& c, const double* Cp, int np, double* U, hipStream_t st) {
+  ensure_sparse_ws(c, np);
+  const int64_t F = c.fofs[c.natom];
+  if (F > 0) hip_check(gather_rows(Cp, np, c.sfun.p, F, F, np, c.sCg.p, np, st), "C rows");
+  for (int I = 0; I < c.natom; ++I) {
+    const int64_t nr = c.vofs[I + 1] - c.vofs[I], nc = c.fofs[I + 1] - c.fofs[I];
+    if (nr == 0) continue;
+    if (nc == 0) {
+      hip_check(fill(c.sUv.p + c.vofs[I] * np, nr * np, 0.0, st), "U block");
+      continue;
+    }
+    Gemm g;   // U[kappa_I] = Phi_I C[S_I]
+    g.M = nr; g.N = np; g.K = nc;
+    g.A = c.sPhi.p + c.pofs[I]; g.lda = nc; g.B = c.sCg.p + c.fofs[I] * np; g.ldb = np;
+    g.C = c.sUv.p + c.vofs[I] * np; g.ldc = np;
+    hip_check(gemm_f64(g, st), "U block");
+  }
+  hip_check(gather_rows(c.sUv.p, np, c.sinv.p, c.ng, c.ngp, np, U, np, st), "U rows");
+}
+
+// K1 (Np x np) = Phi^T M1T from the atom blocks (M1T: ngp x np, grid order); split-K
+// partials go to c.gwork
+void sparse_k1(rps_context& c, const double* M1T, int np, double* K1, hipStream_t st) {
+  ensure_sparse_ws(c, np);
+  hip_check(gather_rows(M1T, np, c.sperm.p, c.ng, c.ng, np, c.sUv.p, np, st), "M1 rows");
+  for (int I = 0; I < c.natom; ++I) {
+    const int64_t nr = c.vofs[I + 1] - c.vofs[I], nc = c.fofs[I + 1] - c.fofs[I];
+    if (nc == 0) continue;
+    Gemm g;   // partial K1 rows of atom I: Phi_I^T M1T[kappa_I]
+    g.M = nc; g.N = np; g.K = nr;
+    g.A = c.sPhi.p + c.pofs[I]; g.lda = nc; g.transA = true; g.B = c.sUv.p + c.vofs[I] * np; g.ldb = np;
+    g.C = c.sK1p.p + c.fofs[I] * np; g.ldc = np;
+    g.splitk = gemm_splitk_for(g.M, g.N, g.K, kSplitWork);
+    g.work = c.gwork.p;
+    hip_check(gemm_f64(g, st), "K1 block");
+  }
+  hip_check(csr_rowsum(c.sK1p.p, np, c.smu_ofs.p, c.smu_rows.p, (int)c.nbas, (int)c.Np, K1, st), "K1 sums");
+}
+
 void build_general(rps_context& c, int variant, int nocc, const double* Csrc, double* Kout, double* exout,
                    hipStream_t st, double s1, double s2, double s3, double ce1, double ce3) {
   const int np = (int)round_up(nocc, 16);
   ensure_general(c, np);
   hip_check(pack_matrix(Csrc, c.nbas, nocc, nocc, c.gCp.p, c.Np, np, st), "pack C");
-  {
+  if (c.sparse) {
+    sparse_u(c, c.gCp.p, np, c.gU.p, st);
+  } else {
     Gemm g;   // U = Phi C
     g.M = c.ngp; g.N = np; g.K = c.Np;
     g.A = c.Phi.p; g.lda = c.Np; g.B = c.gCp.p; g.ldb = np; g.C = c.gU.p; g.ldc = np;
@@ -766,7 +934,9 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
         hip_check(stream_product(m1, prec, 1, st), "stream M1");
       }
       prof_mark(c, 2, st);
-      if (k1) {
+      if (k1 && c.sparse) {
+        sparse_k1(c, c.gM1T.p, np, c.gK1.p, st);
+      } else if (k1) {
         Gemm g;   // K1 = Phi^T M1^T
         g.M = c.Np; g.N = np; g.K = c.ngp;
         g.A = c.Phi.p; g.lda = c.Np; g.transA = true; g.B = c.gM1T.p; g.ldb = np; g.C = c.gK1.p; g.ldc = np;
@@ -840,7 +1010,9 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
       }
     }
     prof_mark(c, 2, st);
-    if (k1) {
+    if (k1 && c.sparse) {
+      sparse_k1(c, c.gM1T.p, np, c.gK1.p, st);
+    } else if (k1) {
       Gemm g;   // K1 = Phi^T M1^T
       g.M = c.Np; g.N = np; g.K = c.ngp;
       g.A = c.Phi.p; g.lda = c.Np; g.transA = true; g.B = c.gM1T.p; g.ldb = np; g.C = c.gK1.p; g.ldc = np;
@@ -1212,6 +1384,32 @@ void ensure_coulomb(rps_context& c, int np) {
 
 // J = dV Phi^T diag(Vc rho) Phi, rho(R) = sum_i U(R, i)^2, U = Phi C (Sec. 2.3, steps 1-4);
 // ej = dV sum_R rho V_H.  All steps run on st in FP64.
+constexpr int64_t kSparseJWork = 16ll << 20;   // doubles of split partials per atom J block
+
+// Lower triangles of the atom J blocks Phi_I^T diag(v) Phi_I, then J = dV sum over atoms
+void sparse_j(rps_context& c, const double* vh, double* J, hipStream_t st) {
+  if (!c.sQ.p) {
+    c.sQ.alloc(std::max<int64_t>(c.qofs[c.natom], 1), &c.bytes);
+    c.svv.alloc(c.ng, &c.bytes);
+    c.sjwork.alloc(kSparseJWork, &c.bytes);
+  }
+  hip_check(gather_rows(vh, 1, c.sperm.p, c.ng, c.ng, 1, c.svv.p, 1, st), "V_H rows");
+  for (int I = 0; I < c.natom; ++I) {
+    const int64_t nr = c.vofs[I + 1] - c.vofs[I], nc = c.fofs[I + 1] - c.fofs[I];
+    if (nc == 0) continue;
+    Gemm g;
+    g.M = nc; g.N = nc; g.K = nr;
+    g.A = c.sPhi.p + c.pofs[I]; g.lda = nc; g.transA = true; g.B = c.sPhi.p + c.pofs[I]; g.ldb = nc;
+    g.kscale = c.svv.p + c.vofs[I]; g.lower_only = true;
+    g.C = c.sQ.p + c.qofs[I]; g.ldc = nc;
+    g.splitk = gemm_splitk_for(g.M, g.N, g.K, kSparseJWork);
+    g.work = c.sjwork.p;
+    hip_check(gemm_f64(g, st), "J block");
+  }
+  hip_check(j_reduce(c.sQ.p, c.sqofs.p, c.sfofs.p, c.spos.p, c.smu_ofs.p, c.smu_atom.p, (int)c.nbas, c.dV, J, st),
+            "J sums");
+}
+
 void build_coulomb_impl(rps_context& c, int32_t nocc, const double* C, double* J, double* ej, int32_t flags,
                         hipStream_t st) {
   if (c.ng == 0) fail(RPS_ERR_STATE, "context has no completed set-up");
@@ -1234,8 +1432,17 @@ void build_coulomb_impl(rps_context& c, int32_t nocc, const double* C, double* J
     hip_check(density_small(c.Phi.p, R, (int)Np, Csrc, (int)N, nocc, np, c.jrho.p, R, st), "density");
   else
     hip_check(pack_matrix(Csrc, N, nocc, nocc, c.jCp.p, Np, np, st), "pack C");
+  if (!small && c.sparse) {
+    // step 1 from the atom blocks of the screened basis: U in grid order, then rho
+    if (c.sjws_np != np) {
+      c.sUj.alloc(R * np, &c.bytes);
+      c.sjws_np = np;
+    }
+    sparse_u(c, c.jCp.p, np, c.sUj.p, st);
+    hip_check(density_rows(c.sUj.p, R, np, c.jrho.p, R, st), "density");
+  }
   // step 1: density, one chunk of grid rows at a time (rows past N_g have Phi = 0, so rho = 0)
-  for (int64_t r0 = 0; !small && r0 < R; r0 += c.jchunk) {
+  for (int64_t r0 = 0; !small && !c.sparse && r0 < R; r0 += c.jchunk) {
     const int64_t m = std::min(c.jchunk, R - r0);
     Gemm g;   // U = Phi[r0:r0+m] C
     g.M = m; g.N = np; g.K = Np;
@@ -1255,6 +1462,8 @@ void build_coulomb_impl(rps_context& c, int32_t nocc, const double* C, double* J
   if (small) {
     hip_check(coulomb_small(c.Phi.p, R, (int)Np, c.jrho.p, c.jwork.p, st), "Phi^T diag(V_H) Phi");
     hip_check(sym_from_lower(c.jwork.p, coulomb_small_blocks(R), Np, N, c.dV, Jout, st), "J");
+  } else if (c.sparse) {
+    sparse_j(c, c.jrho.p, Jout, st);
   } else {
     Gemm g;
     g.M = Np; g.N = Np; g.K = R;
@@ -1545,20 +1754,28 @@ int32_t rps_abi_version(void) { return 1; }
 
 const char* rps_last_error(void) { return g_err.c_str(); }
 
-rps_status rps_setup_isdf(const rps_cell* cell, const rps_basis* basis, int64_t n_aux, uint64_t seed,
-                          int32_t select_mode, int32_t precision, const int64_t* points_in, void* hip_stream,
-                          rps_context** out) {
+rps_status rps_setup_isdf_screened(const rps_cell* cell, const rps_basis* basis, int64_t n_aux, uint64_t seed,
+                                   int32_t select_mode, int32_t precision, const int64_t* points_in,
+                                   double basis_eps, void* hip_stream, rps_context** out) {
   return guarded([&] {
     if (!out) fail(RPS_ERR_ARG, "out must not be NULL");
     rps_context* c = new rps_context();
     try {
-      setup_impl(*c, cell, basis, n_aux, seed, select_mode, precision, points_in, (hipStream_t)hip_stream);
+      setup_impl(*c, cell, basis, n_aux, seed, select_mode, precision, points_in, basis_eps,
+                 (hipStream_t)hip_stream);
     } catch (...) {
       delete c;
       throw;
     }
     *out = c;
   });
+}
+
+rps_status rps_setup_isdf(const rps_cell* cell, const rps_basis* basis, int64_t n_aux, uint64_t seed,
+                          int32_t select_mode, int32_t precision, const int64_t* points_in, void* hip_stream,
+                          rps_context** out) {
+  return rps_setup_isdf_screened(cell, basis, n_aux, seed, select_mode, precision, points_in, 0.0, hip_stream,
+                                 out);
 }
 
 rps_status rps_build_exchange_occRI(rps_context* ctx, int32_t nocc, const double* C, double* K, double* ex,
@@ -1755,6 +1972,7 @@ rps_status rps_get_info(const rps_context* ctx, rps_info* info) {
     info->n_candidates = c.ncand; info->dvol = c.dV; info->chol_shift = c.shift;
     info->setup_seconds = c.setup_seconds; info->device_bytes = c.bytes;
     info->precision = c.precision; info->exact = c.exact; info->madelung = c.madelung;
+    info->basis_fill = c.sparse ? (double)c.pofs[c.natom] / ((double)c.ng * (double)c.nbas) : 1.0;
   });
 }
 

@@ -55,6 +55,22 @@ hipError_t gemm_f32(const Gemm32& g, hipStream_t s);
 // (a split count whose K range exceeds kmax is returned when the workspace allows no more).
 int gemm32_splitk_for(int64_t M, int64_t N, int64_t K, int64_t kmax, int64_t work_cap_doubles);
 
+// ---------------------------------------------------------------- screened basis (k_sparse.hip)
+// Phi[i] = 0 where |Phi[i]| < thr (i < count)
+hipError_t screen_basis(double* Phi, int64_t count, double thr, hipStream_t s);
+// flags[owner[R] * N + mu] = 1 where Phi[R][mu] != 0 (flags zeroed by the caller)
+hipError_t basis_flags(const double* Phi, int64_t ng, int Np, int N, const int32_t* owner, int32_t* flags,
+                       hipStream_t s);
+// dst[r][c] = Phi[rows[r]][cols[c]] (dst row-major, pitch nc)
+hipError_t pack_block(const double* Phi, int Np, const int64_t* rows, int64_t nr, const int64_t* cols, int nc,
+                      double* dst, hipStream_t s);
+// out[mu][i] = sum_{e in [ofs[mu], ofs[mu+1])} part[rows[e]][i], in order (mu < N; rows N..Np-1 zero)
+hipError_t csr_rowsum(const double* part, int np, const int64_t* ofs, const int64_t* rows, int N, int Np,
+                      double* out, hipStream_t s);
+// J[mu][nu] = J[nu][mu] = scale * sum_{e in ofs[mu]..} Q_atom[e][pos(mu)][pos(nu)] (lower triangles read)
+hipError_t j_reduce(const double* Q, const int64_t* qofs, const int64_t* fofs, const int32_t* pos,
+                    const int64_t* ofs, const int32_t* atom, int N, double scale, double* J, hipStream_t s);
+
 // ---------------------------------------------------------------- basis / grid
 struct ShellDev {        // one Gaussian shell, device copy
   double cx, cy, cz;     // centre wrapped into the cell

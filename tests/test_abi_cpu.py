@@ -70,8 +70,12 @@ def _setup_status(**over):
         pts = np.asarray(pts, dtype=np.int64)
         pp = pts.ctypes.data_as(ct.POINTER(ct.c_int64))
     h = ct.c_void_p()
-    st = lib.rps_setup_isdf(ct.byref(cell), ct.byref(b), naux, 1, over.get("mode", 0), over.get("prec", 0), pp,
-                            None, ct.byref(h))
+    if "eps" in over:
+        st = lib.rps_setup_isdf_screened(ct.byref(cell), ct.byref(b), naux, 1, over.get("mode", 0),
+                                         over.get("prec", 0), pp, over["eps"], None, ct.byref(h))
+    else:
+        st = lib.rps_setup_isdf(ct.byref(cell), ct.byref(b), naux, 1, over.get("mode", 0), over.get("prec", 0), pp,
+                                None, ct.byref(h))
     return st, lib.rps_last_error().decode(), h
 
 
@@ -88,6 +92,9 @@ def _setup_status(**over):
     (dict(naux=3, points=[1, 2, 512]), B.RPS_ERR_SHAPE),
     (dict(prec=7), B.RPS_ERR_ARG),
     (dict(mode=5), B.RPS_ERR_ARG),
+    (dict(eps=-1e-8), B.RPS_ERR_ARG),
+    (dict(eps=float("nan")), B.RPS_ERR_ARG),
+    (dict(eps=float("inf")), B.RPS_ERR_ARG),
 ])
 def test_setup_rejects_bad_arguments(over, status):
     st, msg, h = _setup_status(**over)
