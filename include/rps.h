@@ -107,6 +107,8 @@ typedef struct {
     double madelung;      /* Madelung constant M of the cell (see rps_madelung_constant) */
     double basis_fill;    /* screened set-up: fraction of the N_g x N basis values held in the
                              atom blocks (1.0 without screening) */
+    double basis_pair_fill; /* screened set-up: sum over atoms of |kappa_I| n_I^2 / (N_g N^2),
+                               the fraction of the dense J product's work (1.0 without) */
 } rps_info;
 
 /*

@@ -61,7 +61,7 @@ class Info(ct.Structure):
                 ("n_candidates", ct.c_int64), ("dvol", ct.c_double), ("chol_shift", ct.c_double),
                 ("setup_seconds", ct.c_double), ("device_bytes", ct.c_int64),
                 ("precision", ct.c_int32), ("exact", ct.c_int32), ("madelung", ct.c_double),
-                ("basis_fill", ct.c_double)]
+                ("basis_fill", ct.c_double), ("basis_pair_fill", ct.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -105,9 +105,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(Gemm g) {
 // Large tiles: 4 waves in 2 x 2, each wave (16*TM) x (16*TN) of C, BK = 16,
 // operands prefetched into registers while the matrix cores work on the
 // current LDS buffer (two buffers, one barrier per K step).  KS: row k of
-// op(B) is scaled by kscale[k] as it is loaded.
-template <int TM, int TN, bool TA, bool TB, bool KS = false>
-__global__ __launch_bounds__(256, 2) void gemm_big_kernel(Gemm g) {
+// op(B) is scaled by kscale[k] as it is loaded.  The body computes the output
+// tile at (m0, n0) of K split bz; gemm_big_kernel and the grouped kernel below
+// differ only in how they pick the tile and the operands.
+template <int TM, int TN, bool TA, bool TB, bool KS>
+__device__ __forceinline__ void gemm_big_body(const Gemm& g, int64_t m0, int64_t n0, int bz) {
   constexpr int BM = 32 * TM, BN = 32 * TN;
   constexpr int PA = BM * BK / 256, PB = BN * BK / 256;
   constexpr int LA = BM + 1, LB = BN + 1;
@@ -116,8 +118,6 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(Gemm g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int l16 = lane & 15, lq = lane >> 4;
-  const int bz = blockIdx.z;
-  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
   if (g.lower_only && n0 > m0 + BM - 1) return;
 
   int64_t kbeg = 0, kend = g.K;
@@ -402,6 +402,27 @@ __global__ __launch_bounds__(256, 2) void gemm32_kernel(Gemm32 g) {
       }
 }
 
+template <int TM, int TN, bool TA, bool TB, bool KS = false>
+__global__ __launch_bounds__(256, 2) void gemm_big_kernel(Gemm g) {
+  gemm_big_body<TM, TN, TA, TB, KS>(g, (int64_t)blockIdx.y * 32 * TM, (int64_t)blockIdx.x * 32 * TN, blockIdx.z);
+}
+
+// Many independent products in one launch: item blockIdx.z takes the base operands
+// at its own offsets, sizes and pitches (no K split).
+template <int TM, int TN, bool TA, bool TB, bool KS>
+__global__ __launch_bounds__(256, 2) void gemm_grouped_kernel(Gemm base, const GemmItem* __restrict__ items) {
+  const GemmItem it = items[blockIdx.z];
+  const int64_t m0 = (int64_t)blockIdx.y * 32 * TM, n0 = (int64_t)blockIdx.x * 32 * TN;
+  if (m0 >= it.M || n0 >= it.N) return;
+  Gemm g = base;
+  g.M = it.M; g.N = it.N; g.K = it.K;
+  g.lda = it.lda; g.ldb = it.ldb; g.ldc = it.ldc;
+  g.A = base.A + it.aofs; g.B = base.B + it.bofs; g.C = base.C + it.cofs;
+  if (KS) g.kscale = base.kscale + it.kofs;
+  g.splitk = 1;
+  gemm_big_body<TM, TN, TA, TB, KS>(g, m0, n0, 0);
+}
+
 // C = alpha * sum_z work[z] + beta * C (fixed order over z)
 __global__ void splitk_reduce_kernel(const double* __restrict__ work, int splitk, int64_t M, int64_t N,
                                      double* __restrict__ C, int64_t ldc, double beta) {
@@ -522,6 +543,33 @@ int gemm32_splitk_for(int64_t M, int64_t N, int64_t K, int64_t kmax, int64_t wor
     if (fill > best_fill + 1e-9) { best_fill = fill; best = z; }
   }
   return (int)best;
+}
+
+namespace {
+template <int TN>
+void launch_grouped(const Gemm& g, const GemmItem* items, dim3 grid, hipStream_t s) {
+  if (g.kscale) hipLaunchKernelGGL((gemm_grouped_kernel<4, TN, true, false, true>), grid, dim3(256), 0, s, g, items);
+  else if (!g.transA && !g.transB)
+    hipLaunchKernelGGL((gemm_grouped_kernel<4, TN, false, false, false>), grid, dim3(256), 0, s, g, items);
+  else if (g.transA && !g.transB)
+    hipLaunchKernelGGL((gemm_grouped_kernel<4, TN, true, false, false>), grid, dim3(256), 0, s, g, items);
+  else if (!g.transA && g.transB)
+    hipLaunchKernelGGL((gemm_grouped_kernel<4, TN, false, true, false>), grid, dim3(256), 0, s, g, items);
+  else hipLaunchKernelGGL((gemm_grouped_kernel<4, TN, true, true, false>), grid, dim3(256), 0, s, g, items);
+}
+}  // namespace
+
+hipError_t gemm_f64_grouped(const Gemm& base, const GemmItem* items, int nitems, int64_t maxM, int64_t maxN,
+                            hipStream_t s) {
+  if (nitems <= 0 || maxM <= 0 || maxN <= 0) return hipSuccess;
+  if (nitems > 65535 || base.splitk > 1 || base.epi != EPI_AXPBY) return hipErrorInvalidValue;
+  if (base.kscale && !(base.transA && !base.transB)) return hipErrorInvalidValue;
+  const int bn = (maxN <= 64) ? 64 : 128;
+  dim3 grid((unsigned)((maxN + bn - 1) / bn), (unsigned)((maxM + 127) / 128), (unsigned)nitems);
+  if (grid.y > 65535u) return hipErrorInvalidValue;
+  if (bn == 64) launch_grouped<2>(base, items, grid, s);
+  else launch_grouped<4>(base, items, grid, s);
+  return hipGetLastError();
 }
 
 int gemm_splitk_for(int64_t M, int64_t N, int64_t K, int64_t work_cap_doubles) {

@@ -93,7 +93,9 @@ struct rps_context {
   DBuf<int32_t> spos, smu_atom;   // pos[I][mu] (-1 if absent); atom of each CSR entry
   DBuf<double> sPhi;
   int sws_np = -1, sjws_np = -1;
-  DBuf<double> sCg, sUv, sK1p, sQ, svv, sjwork, sUj;
+  DBuf<double> sCg, sUv, sK1p, sQ, svv, sUj;
+  DBuf<GemmItem> sitU, sitK1, sitJ;   // per-atom products of one grouped launch each
+  int64_t smaxr = 0, smaxc = 0;       // largest Voronoi set, largest function list
   // build workspace (grows on demand)
   int ws_np = -1;
   DBuf<double> U, Ug, Ugp, M2p, K1p, K3p, e1p, e3p, M2, K1, K3, Kdev, Cdev, exdev, e3u;
@@ -164,8 +166,11 @@ struct rps_context {
     for (auto* b : si) b->release(nullptr);
     spos.release(nullptr);
     smu_atom.release(nullptr);
-    DBuf<double>* sd[] = {&sPhi, &sCg, &sUv, &sK1p, &sQ, &svv, &sjwork, &sUj};
+    DBuf<double>* sd[] = {&sPhi, &sCg, &sUv, &sK1p, &sQ, &svv, &sUj};
     for (auto* b : sd) b->release(nullptr);
+    sitU.release(nullptr);
+    sitK1.release(nullptr);
+    sitJ.release(nullptr);
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     clear_graphs();
     if (gfork) (void)hipEventDestroy(gfork);
@@ -395,6 +400,20 @@ void build_screened_blocks(rps_context& c, const double* atoms, hipStream_t st) 
     hip_check(pack_block(c.Phi.p, (int)c.Np, c.sperm.p + c.vofs[I], nr, c.sfun.p + c.fofs[I], nc,
                          c.sPhi.p + c.pofs[I], st), "pack");
   }
+  // J blocks: lower triangles of Phi_I^T diag(v[kappa_I]) Phi_I, one grouped launch
+  std::vector<GemmItem> jt;
+  c.smaxr = c.smaxc = 0;
+  for (int I = 0; I < natom; ++I) {
+    const int64_t nr = c.vofs[I + 1] - c.vofs[I], nc = c.fofs[I + 1] - c.fofs[I];
+    c.smaxr = std::max(c.smaxr, nr);
+    c.smaxc = std::max(c.smaxc, nc);
+    if (nc == 0) continue;
+    jt.push_back(GemmItem{nc, nc, nr, nc, nc, nc, c.pofs[I], c.pofs[I], c.qofs[I], c.vofs[I]});
+  }
+  c.sitJ.alloc(std::max<int64_t>((int64_t)jt.size(), 1), &c.bytes);
+  if (!jt.empty())
+    hip_check(hipMemcpyAsync(c.sitJ.p, jt.data(), jt.size() * sizeof(GemmItem), hipMemcpyHostToDevice, st), "items");
+  c.sitJ.n = (int64_t)jt.size();
   hip_check(hipStreamSynchronize(st), "sync");
   c.sparse = true;
 }
@@ -799,6 +818,22 @@ void ensure_sparse_ws(rps_context& c, int np) {
   c.sCg.alloc(std::max<int64_t>(c.fofs[c.natom], 1) * np, &c.bytes);
   c.sK1p.alloc(std::max<int64_t>(c.fofs[c.natom], 1) * np, &c.bytes);
   c.sUv.alloc(c.ng * np, &c.bytes);
+  // U rows of atom I = Phi_I C[S_I] (an empty function list gives zero rows: K = 0);
+  // K1 partial rows of atom I = Phi_I^T M1T[kappa_I]
+  std::vector<GemmItem> ut, kt;
+  for (int I = 0; I < c.natom; ++I) {
+    const int64_t nr = c.vofs[I + 1] - c.vofs[I], nc = c.fofs[I + 1] - c.fofs[I];
+    if (nr > 0) ut.push_back(GemmItem{nr, np, nc, std::max<int64_t>(nc, 1), np, np, c.pofs[I], c.fofs[I] * np,
+                                      c.vofs[I] * np, 0});
+    if (nc > 0) kt.push_back(GemmItem{nc, np, nr, nc, np, np, c.pofs[I], c.vofs[I] * np, c.fofs[I] * np, 0});
+  }
+  auto up = [&](DBuf<GemmItem>& d, const std::vector<GemmItem>& h) {
+    d.alloc(std::max<int64_t>((int64_t)h.size(), 1), &c.bytes);
+    if (!h.empty()) hip_check(hipMemcpy(d.p, h.data(), h.size() * sizeof(GemmItem), hipMemcpyHostToDevice), "items");
+    d.n = (int64_t)h.size();
+  };
+  up(c.sitU, ut);
+  up(c.sitK1, kt);
   c.sws_np = np;
 }
 
@@ -860,38 +895,19 @@ void sparse_u(rps_context& c, const double* Cp, int np, double* U, hipStream_t s
   ensure_sparse_ws(c, np);
   const int64_t F = c.fofs[c.natom];
   if (F > 0) hip_check(gather_rows(Cp, np, c.sfun.p, F, F, np, c.sCg.p, np, st), "C rows");
-  for (int I = 0; I < c.natom; ++I) {
-    const int64_t nr = c.vofs[I + 1] - c.vofs[I], nc = c.fofs[I + 1] - c.fofs[I];
-    if (nr == 0) continue;
-    if (nc == 0) {
-      hip_check(fill(c.sUv.p + c.vofs[I] * np, nr * np, 0.0, st), "U block");
-      continue;
-    }
-    Gemm g;   // U[kappa_I] = Phi_I C[S_I]
-    g.M = nr; g.N = np; g.K = nc;
-    g.A = c.sPhi.p + c.pofs[I]; g.lda = nc; g.B = c.sCg.p + c.fofs[I] * np; g.ldb = np;
-    g.C = c.sUv.p + c.vofs[I] * np; g.ldc = np;
-    hip_check(gemm_f64(g, st), "U block");
-  }
+  Gemm g;   // U[kappa_I] = Phi_I C[S_I] for every atom
+  g.A = c.sPhi.p; g.B = c.sCg.p; g.C = c.sUv.p;
+  hip_check(gemm_f64_grouped(g, c.sitU.p, (int)c.sitU.n, c.smaxr, np, st), "U blocks");
   hip_check(gather_rows(c.sUv.p, np, c.sinv.p, c.ng, c.ngp, np, U, np, st), "U rows");
 }
 
-// K1 (Np x np) = Phi^T M1T from the atom blocks (M1T: ngp x np, grid order); split-K
-// partials go to c.gwork
+// K1 (Np x np) = Phi^T M1T from the atom blocks (M1T: ngp x np, grid order)
 void sparse_k1(rps_context& c, const double* M1T, int np, double* K1, hipStream_t st) {
   ensure_sparse_ws(c, np);
   hip_check(gather_rows(M1T, np, c.sperm.p, c.ng, c.ng, np, c.sUv.p, np, st), "M1 rows");
-  for (int I = 0; I < c.natom; ++I) {
-    const int64_t nr = c.vofs[I + 1] - c.vofs[I], nc = c.fofs[I + 1] - c.fofs[I];
-    if (nc == 0) continue;
-    Gemm g;   // partial K1 rows of atom I: Phi_I^T M1T[kappa_I]
-    g.M = nc; g.N = np; g.K = nr;
-    g.A = c.sPhi.p + c.pofs[I]; g.lda = nc; g.transA = true; g.B = c.sUv.p + c.vofs[I] * np; g.ldb = np;
-    g.C = c.sK1p.p + c.fofs[I] * np; g.ldc = np;
-    g.splitk = gemm_splitk_for(g.M, g.N, g.K, kSplitWork);
-    g.work = c.gwork.p;
-    hip_check(gemm_f64(g, st), "K1 block");
-  }
+  Gemm g;   // partial K1 rows of every atom: Phi_I^T M1T[kappa_I]
+  g.A = c.sPhi.p; g.transA = true; g.B = c.sUv.p; g.C = c.sK1p.p;
+  hip_check(gemm_f64_grouped(g, c.sitK1.p, (int)c.sitK1.n, c.smaxc, np, st), "K1 blocks");
   hip_check(csr_rowsum(c.sK1p.p, np, c.smu_ofs.p, c.smu_rows.p, (int)c.nbas, (int)c.Np, K1, st), "K1 sums");
 }
 
@@ -1384,28 +1400,17 @@ void ensure_coulomb(rps_context& c, int np) {
 
 // J = dV Phi^T diag(Vc rho) Phi, rho(R) = sum_i U(R, i)^2, U = Phi C (Sec. 2.3, steps 1-4);
 // ej = dV sum_R rho V_H.  All steps run on st in FP64.
-constexpr int64_t kSparseJWork = 16ll << 20;   // doubles of split partials per atom J block
-
 // Lower triangles of the atom J blocks Phi_I^T diag(v) Phi_I, then J = dV sum over atoms
 void sparse_j(rps_context& c, const double* vh, double* J, hipStream_t st) {
   if (!c.sQ.p) {
     c.sQ.alloc(std::max<int64_t>(c.qofs[c.natom], 1), &c.bytes);
     c.svv.alloc(c.ng, &c.bytes);
-    c.sjwork.alloc(kSparseJWork, &c.bytes);
   }
   hip_check(gather_rows(vh, 1, c.sperm.p, c.ng, c.ng, 1, c.svv.p, 1, st), "V_H rows");
-  for (int I = 0; I < c.natom; ++I) {
-    const int64_t nr = c.vofs[I + 1] - c.vofs[I], nc = c.fofs[I + 1] - c.fofs[I];
-    if (nc == 0) continue;
-    Gemm g;
-    g.M = nc; g.N = nc; g.K = nr;
-    g.A = c.sPhi.p + c.pofs[I]; g.lda = nc; g.transA = true; g.B = c.sPhi.p + c.pofs[I]; g.ldb = nc;
-    g.kscale = c.svv.p + c.vofs[I]; g.lower_only = true;
-    g.C = c.sQ.p + c.qofs[I]; g.ldc = nc;
-    g.splitk = gemm_splitk_for(g.M, g.N, g.K, kSparseJWork);
-    g.work = c.sjwork.p;
-    hip_check(gemm_f64(g, st), "J block");
-  }
+  Gemm g;
+  g.A = c.sPhi.p; g.transA = true; g.B = c.sPhi.p; g.C = c.sQ.p;
+  g.kscale = c.svv.p; g.lower_only = true;
+  hip_check(gemm_f64_grouped(g, c.sitJ.p, (int)c.sitJ.n, c.smaxc, c.smaxc, st), "J blocks");
   hip_check(j_reduce(c.sQ.p, c.sqofs.p, c.sfofs.p, c.spos.p, c.smu_ofs.p, c.smu_atom.p, (int)c.nbas, c.dV, J, st),
             "J sums");
 }
@@ -1973,6 +1978,12 @@ rps_status rps_get_info(const rps_context* ctx, rps_info* info) {
     info->setup_seconds = c.setup_seconds; info->device_bytes = c.bytes;
     info->precision = c.precision; info->exact = c.exact; info->madelung = c.madelung;
     info->basis_fill = c.sparse ? (double)c.pofs[c.natom] / ((double)c.ng * (double)c.nbas) : 1.0;
+    double pair = 0.0;
+    for (int I = 0; c.sparse && I < c.natom; ++I) {
+      const double nc = (double)(c.fofs[I + 1] - c.fofs[I]);
+      pair += (double)(c.vofs[I + 1] - c.vofs[I]) * nc * nc;
+    }
+    info->basis_pair_fill = c.sparse ? pair / ((double)c.ng * (double)c.nbas * (double)c.nbas) : 1.0;
   });
 }
 

@@ -31,6 +31,15 @@ struct Gemm {
   const double* kscale = nullptr;      // op(B)[k][n] *= kscale[k] (transA && !transB, or N <= 16)
 };
 hipError_t gemm_f64(const Gemm& g, hipStream_t s);
+// One launch of many independent products: item i computes C_i = alpha op(A_i) op(B_i)
+// + beta C_i with A_i = base.A + aofs etc. (its own sizes and pitches), and with
+// base.kscale + kofs as the row scale when base.kscale is set (transA only).  Items
+// live in device memory; maxM / maxN bound their sizes.  No K split; EPI_AXPBY only.
+struct GemmItem {
+  int64_t M, N, K, lda, ldb, ldc, aofs, bofs, cofs, kofs;
+};
+hipError_t gemm_f64_grouped(const Gemm& base, const GemmItem* items, int nitems, int64_t maxM, int64_t maxN,
+                            hipStream_t s);
 // Split count giving enough workgroups for a long-K product within work_cap doubles.
 int gemm_splitk_for(int64_t M, int64_t N, int64_t K, int64_t work_cap_doubles);
 

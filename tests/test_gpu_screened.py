@@ -61,14 +61,16 @@ def _kerr(K, Kref):
 
 
 def _fill(w, Ps):
-    """Fraction of the N_g x N values inside the atom blocks (Voronoi sets times the
-    functions not all zero there)."""
+    """Fractions of the N_g x N values inside the atom blocks (Voronoi sets times the
+    functions not all zero there) and of the N_g N^2 work of the dense J product."""
     own = basis.voronoi(w)
-    tot = 0
+    tot = pair = 0
     for I in range(len(w.atoms)):
         rows = own == I
-        tot += int(rows.sum()) * int(np.count_nonzero(np.any(Ps[rows] != 0.0, axis=0)))
-    return tot / Ps.size
+        nI = int(np.count_nonzero(np.any(Ps[rows] != 0.0, axis=0)))
+        tot += int(rows.sum()) * nI
+        pair += int(rows.sum()) * nI * nI
+    return tot / Ps.size, pair / (Ps.size * Ps.shape[1])
 
 
 @pytest.mark.parametrize("name,eps,prec,gemm", [
@@ -87,7 +89,7 @@ def test_screened_exchange_against_oracle(lib, monkeypatch, name, eps, prec, gem
     _say(f"case: screened exchange {name} eps={eps:g} {prec} gemm={gemm}")
     p = lib.PREC_FP64 if prec == "fp64" else lib.PREC_FP32
     with lib.Context.from_workload(w, points=cs["points"], precision=p, basis_eps=eps) as ctx:
-        fill = ctx.info()["basis_fill"]
+        fill, pfill = ctx.info()["basis_fill"], ctx.info()["basis_pair_fill"]
         K, E = ctx.build(cs["C"])
         K2, E2 = ctx.build(cs["C"])
     dk = _kerr(K, cs["K"])
@@ -96,7 +98,8 @@ def test_screened_exchange_against_oracle(lib, monkeypatch, name, eps, prec, gem
     assert abs(E - cs["E"]) < tol_e
     assert dk < tol_k
     assert np.array_equal(K, K2) and E == E2
-    assert abs(fill - _fill(w, cs["Ps"])) < 2e-3
+    ref_fill, ref_pfill = _fill(w, cs["Ps"])
+    assert abs(fill - ref_fill) < 2e-3 and abs(pfill - ref_pfill) < 2e-3
     if eps >= 1e-4:
         assert fill < 0.9
 
@@ -123,4 +126,4 @@ def test_zero_eps_keeps_every_value(lib):
     w = ri.tiny_cell()
     _say("case: basis_eps = 0, config 1")
     with lib.Context.from_workload(w, seed=w.sketch_seed(), basis_eps=0.0) as ctx:
-        assert ctx.info()["basis_fill"] == 1.0
+        assert ctx.info()["basis_fill"] == 1.0 and ctx.info()["basis_pair_fill"] == 1.0
