@@ -678,7 +678,8 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
       hip_check(hipStreamSynchronize(st), "sync");
     }
   }
-  if (basis_eps > 0.0) {
+  const char* sb = getenv("RPS_SCREENED_BLOCKS");   // "0": screened values in dense form only (tests)
+  if (basis_eps > 0.0 && !(sb && sb[0] == '0')) {
     build_screened_blocks(c, b->atom_xyz, st);
     stage("screened basis blocks", st);
   }

@@ -137,3 +137,29 @@ def test_supercell_3x3x3_scf_steps(lib):
             _say(f"  FP32 step {s}: dE={E - ref[s][1]:.3e} dK={dk:.3e}")
             assert abs(E - ref[s][1]) < 1e-6
             assert dk < 1e-4
+
+
+def test_supercell_2x2x2_screened_blocks_against_dense(lib, monkeypatch):
+    """Config 3 with the screened basis at the paper's eps1 = 1e-8: the atom-block
+    products (U, K1, J) against the same screened values in dense form
+    (RPS_SCREENED_BLOCKS=0), same points and C.  Both compute the same sums in FP64
+    in a different order, so the bars are rounding-level."""
+    w = ri.diamond_2x2x2()
+    _say(f"case: {w.name} screened eps1=1e-8, atom blocks vs dense")
+    with lib.Context.from_workload(w, seed=w.sketch_seed(), basis_eps=1e-8) as ctx:
+        fill = ctx.info()["basis_fill"]
+        pts = ctx.points()
+        C = ri.lowdin(ri.random_coefficients(w), ctx.overlap())
+        K, E = ctx.build(C)
+        J, EJ = ctx.build_coulomb(C)
+    monkeypatch.setenv("RPS_SCREENED_BLOCKS", "0")
+    with lib.Context.from_workload(w, points=pts, basis_eps=1e-8) as ctx:
+        assert ctx.info()["basis_fill"] == 1.0
+        Kd, Ed = ctx.build(C)
+        Jd, EJd = ctx.build_coulomb(C)
+    dk = np.abs(K - Kd).max() / np.abs(Kd).max()
+    dj = np.abs(J - Jd).max() / np.abs(Jd).max()
+    _say(f"  fill={fill:.4f} dE={E - Ed:.3e} dK={dk:.3e} dE_J={EJ - EJd:.3e} dJ={dj:.3e}")
+    assert fill < 0.6
+    assert abs(E - Ed) < 1e-10 * abs(Ed) and dk < 1e-10
+    assert abs(EJ - EJd) < 1e-11 * abs(EJd) and dj < 1e-11
