@@ -50,9 +50,12 @@ struct Frag<float> {
   static __device__ __forceinline__ acc mma(float a, float b, acc c) { return mfma_f32(a, b, c); }
 };
 
+// Y tile pitch.  FP32: 16 NC + 4 = 4 x odd, so the two read patterns of a wave
+// (row l16 at column 4 j + lq, and row 4 lq + r at column l16 + 16 cb) fall on
+// 64 distinct banks.
 template <typename TM, int NC>
 __host__ __device__ constexpr int stream_ldy() {
-  return 16 * NC + 1;
+  return std::is_same<TM, float>::value ? 16 * NC + 4 : 16 * NC + 1;
 }
 
 template <typename TM, int NC, int TRANS, int NW>
@@ -111,52 +114,71 @@ __global__ __launch_bounds__(NW * 64) void stream_kernel(StreamArgs a) {
   // S operand row of the P^T product for lane l16 (see the header)
   const int yrowA = F64 ? 4 * (l16 & 3) + (l16 >> 2) : l16;
 
+  // S values of a tile: lane holds S[x0 + l16][y] for y = tile + 16 sb + 4 lq + r
+  TM vv[2][4], vn[2][4];
+  auto load_s = [&](int64_t t, TM (&d)[2][4]) {
+    const int64_t yb = ys + ((t < ntile) ? t : ntile - 1) * BY;   // past the last tile: re-read it
+#pragma unroll
+    for (int sb = 0; sb < 2; ++sb) {
+      const int64_t y0 = yb + 16 * sb + 4 * lq;
+      if constexpr (TRANS == 0) {
+        if constexpr (F64) {
+          const double* p = a.V + (x0 + l16) * a.ldv + y0;
+          const double2 u0 = *reinterpret_cast<const double2*>(p);
+          const double2 u1 = *reinterpret_cast<const double2*>(p + 2);
+          d[sb][0] = u0.x; d[sb][1] = u0.y; d[sb][2] = u1.x; d[sb][3] = u1.y;
+        } else {
+          const float4 u = *reinterpret_cast<const float4*>(a.V32 + (x0 + l16) * a.ldv + y0);
+          d[sb][0] = u.x; d[sb][1] = u.y; d[sb][2] = u.z; d[sb][3] = u.w;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if constexpr (F64) d[sb][r] = a.V[(y0 + r) * a.ldv + x0 + l16];
+          else d[sb][r] = a.V32[(y0 + r) * a.ldv + x0 + l16];
+        }
+      }
+    }
+  };
+
   if (ntile > 0) {
     stage_load(0);
     stage_store(0);
+    if (xvalid) load_s(0, vv);
   }
   __syncthreads();
   for (int64_t t = 0; t < ntile; ++t) {
     if (t + 1 < ntile) stage_load(t + 1);
     const TM* sy = sY + (t & 1) * BY * LDY;
-    const int64_t yb = ys + t * BY;
     if (xvalid) {
-      TM vv[2][4];
+      load_s(t + 1, vn);    // the next tile's S values, a tile ahead
 #pragma unroll
       for (int sb = 0; sb < 2; ++sb) {
-        const int64_t y0 = yb + 16 * sb + 4 * lq;
-        if constexpr (TRANS == 0) {
-          if constexpr (F64) {
-            const double* p = a.V + (x0 + l16) * a.ldv + y0;
-            const double2 u0 = *reinterpret_cast<const double2*>(p);
-            const double2 u1 = *reinterpret_cast<const double2*>(p + 2);
-            vv[sb][0] = u0.x; vv[sb][1] = u0.y; vv[sb][2] = u1.x; vv[sb][3] = u1.y;
-          } else {
-            const float4 u = *reinterpret_cast<const float4*>(a.V32 + (x0 + l16) * a.ldv + y0);
-            vv[sb][0] = u.x; vv[sb][1] = u.y; vv[sb][2] = u.z; vv[sb][3] = u.w;
-          }
-        } else {
+        // operands of the two products read from LDS into registers first, so that
+        // the reads are in flight together instead of one per matrix-core step
+        const TM* ya = sy + (16 * sb + yrowA) * LDY + lq;
+        const TM* yb_ = sy + (16 * sb + 4 * lq) * LDY + l16;
+        TM pa[NK], ob[4][NC];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            if constexpr (F64) vv[sb][r] = a.V[(y0 + r) * a.ldv + x0 + l16];
-            else vv[sb][r] = a.V32[(y0 + r) * a.ldv + x0 + l16];
-          }
-        }
-      }
+        for (int j = 0; j < NK; ++j) pa[j] = ya[4 * j];
 #pragma unroll
-      for (int sb = 0; sb < 2; ++sb) {
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int cb = 0; cb < NC; ++cb) ob[r][cb] = yb_[r * LDY + 16 * cb];
+        // FP32: keep the reads above the products (the scheduler otherwise interleaves
+        // one read and its full wait per two matrix-core steps); the FP64 operands would
+        // not fit in registers together
+        if constexpr (!F64) __builtin_amdgcn_sched_barrier(0);
         // P^T[y][x] = sum_d Y[y][d] X[x][d]
         acc_t s = F::zero();
-        const TM* ya = sy + (16 * sb + yrowA) * LDY + lq;
 #pragma unroll
-        for (int j = 0; j < NK; ++j) s = F::mma(ya[4 * j], xr[j], s);
+        for (int j = 0; j < NK; ++j) s = F::mma(pa[j], xr[j], s);
         // A = S o P, straight into the O product (k-step r <-> y = 4 lq + r)
-        const TM* yb_ = sy + (16 * sb + 4 * lq) * LDY + l16;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const TM av = s[r] * vv[sb][r];
 #pragma unroll
-          for (int cb = 0; cb < NC; ++cb) o[cb] = F::mma(av, yb_[r * LDY + 16 * cb], o[cb]);
+          for (int cb = 0; cb < NC; ++cb) o[cb] = F::mma(av, ob[r][cb], o[cb]);
         }
       }
       if constexpr (!F64) {
@@ -167,6 +189,10 @@ __global__ __launch_bounds__(NW * 64) void stream_kernel(StreamArgs a) {
           o[cb] = F::zero();
         }
       }
+#pragma unroll
+      for (int sb = 0; sb < 2; ++sb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) vv[sb][r] = vn[sb][r];
     }
     if (t + 1 < ntile) stage_store((t + 1) & 1);
     __syncthreads();
