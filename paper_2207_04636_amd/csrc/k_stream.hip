@@ -75,6 +75,7 @@ __global__ __launch_bounds__(NW * 64) void stream_kernel(StreamArgs a) {
   const int l16 = lane & 15, lq = lane >> 4;
   const int64_t x0 = ((int64_t)blockIdx.x * NW + w) * 16;
   const bool xvalid = x0 < a.nx;
+  const int64_t xrow = xvalid ? x0 : a.nx - 16;   // rows read by a wave past the end (discarded)
   const int64_t ys = (int64_t)blockIdx.y * a.ysplit;
   const int64_t ye = (ys + a.ysplit < a.ny) ? ys + a.ysplit : a.ny;
   const int64_t ntile = (ye > ys) ? (ye - ys) / BY : 0;
@@ -123,19 +124,19 @@ __global__ __launch_bounds__(NW * 64) void stream_kernel(StreamArgs a) {
       const int64_t y0 = yb + 16 * sb + 4 * lq;
       if constexpr (TRANS == 0) {
         if constexpr (F64) {
-          const double* p = a.V + (x0 + l16) * a.ldv + y0;
+          const double* p = a.V + (xrow + l16) * a.ldv + y0;
           const double2 u0 = *reinterpret_cast<const double2*>(p);
           const double2 u1 = *reinterpret_cast<const double2*>(p + 2);
           d[sb][0] = u0.x; d[sb][1] = u0.y; d[sb][2] = u1.x; d[sb][3] = u1.y;
         } else {
-          const float4 u = *reinterpret_cast<const float4*>(a.V32 + (x0 + l16) * a.ldv + y0);
+          const float4 u = *reinterpret_cast<const float4*>(a.V32 + (xrow + l16) * a.ldv + y0);
           d[sb][0] = u.x; d[sb][1] = u.y; d[sb][2] = u.z; d[sb][3] = u.w;
         }
       } else {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          if constexpr (F64) d[sb][r] = a.V[(y0 + r) * a.ldv + x0 + l16];
-          else d[sb][r] = a.V32[(y0 + r) * a.ldv + x0 + l16];
+          if constexpr (F64) d[sb][r] = a.V[(y0 + r) * a.ldv + xrow + l16];
+          else d[sb][r] = a.V32[(y0 + r) * a.ldv + xrow + l16];
         }
       }
     }
@@ -144,14 +145,17 @@ __global__ __launch_bounds__(NW * 64) void stream_kernel(StreamArgs a) {
   if (ntile > 0) {
     stage_load(0);
     stage_store(0);
-    if (xvalid) load_s(0, vv);
+    load_s(0, vv);
   }
   __syncthreads();
+  // Every load of the loop is unconditional (past the last tile the last one is re-read
+  // and staged into the idle buffer), so the wait before each use counts the loads
+  // exactly instead of falling back to waiting for all of them.
   for (int64_t t = 0; t < ntile; ++t) {
-    if (t + 1 < ntile) stage_load(t + 1);
+    stage_load(t + 1 < ntile ? t + 1 : t);
+    load_s(t + 1, vn);    // the next tile's S values, a tile ahead
     const TM* sy = sY + (t & 1) * BY * LDY;
     if (xvalid) {
-      load_s(t + 1, vn);    // the next tile's S values, a tile ahead
 #pragma unroll
       for (int sb = 0; sb < 2; ++sb) {
         // operands of the two products read from LDS into registers first, so that
@@ -189,12 +193,12 @@ __global__ __launch_bounds__(NW * 64) void stream_kernel(StreamArgs a) {
           o[cb] = F::zero();
         }
       }
-#pragma unroll
-      for (int sb = 0; sb < 2; ++sb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) vv[sb][r] = vn[sb][r];
     }
-    if (t + 1 < ntile) stage_store((t + 1) & 1);
+#pragma unroll
+    for (int sb = 0; sb < 2; ++sb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) vv[sb][r] = vn[sb][r];
+    stage_store((t + 1) & 1);
     __syncthreads();
   }
 
@@ -264,6 +268,7 @@ __global__ __launch_bounds__(NW * 64) void stream_bf16x3_kernel(StreamArgs a) {
   const int l16 = lane & 15, lq = lane >> 4;
   const int64_t x0 = ((int64_t)blockIdx.x * NW + w) * 16;
   const bool xvalid = x0 < a.nx;
+  const int64_t xrow = xvalid ? x0 : a.nx - 16;   // rows read by a wave past the end (discarded)
   const int64_t ys = (int64_t)blockIdx.y * a.ysplit;
   const int64_t ye = (ys + a.ysplit < a.ny) ? ys + a.ysplit : a.ny;
   const int64_t ntile = (ye > ys) ? (ye - ys) / BY : 0;
@@ -325,31 +330,37 @@ __global__ __launch_bounds__(NW * 64) void stream_bf16x3_kernel(StreamArgs a) {
     }
   };
 
+  // S values at (x0 + l16, tile + y(e)), y(e) = 4 lq + e (e < 4), 16 + 4 lq + e - 4 (e >= 4)
+  float vv[8], vn[8];
+  auto load_s = [&](int64_t t, float (&d)[8]) {
+    const int64_t yb = ys + ((t < ntile) ? t : ntile - 1) * BY;   // past the last tile: re-read it
+    if constexpr (TRANS == 0) {
+      const float* p = a.V32 + (xrow + l16) * a.ldv + yb + 4 * lq;
+      const float4 u0 = *reinterpret_cast<const float4*>(p);
+      const float4 u1 = *reinterpret_cast<const float4*>(p + 16);
+      d[0] = u0.x; d[1] = u0.y; d[2] = u0.z; d[3] = u0.w;
+      d[4] = u1.x; d[5] = u1.y; d[6] = u1.z; d[7] = u1.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t y = yb + ((e < 4) ? 4 * lq + e : 16 + 4 * lq + e - 4);
+        d[e] = a.V32[y * a.ldv + xrow + l16];
+      }
+    }
+  };
+
   if (ntile > 0) {
     stage_load(0);
     stage_store(0);
+    load_s(0, vv);
   }
   __syncthreads();
+  // unconditional loads, as in the FP64/FP32 kernel
   for (int64_t t = 0; t < ntile; ++t) {
-    if (t + 1 < ntile) stage_load(t + 1);
+    stage_load(t + 1 < ntile ? t + 1 : t);
+    load_s(t + 1, vn);    // the next tile's S values, a tile ahead
     const __bf16* b = sm + (t & 1) * L::BUF;
-    const int64_t yb = ys + t * BY;
     if (xvalid) {
-      // S values at (x0 + l16, yb + y(e)), y(e) = 4 lq + e (e < 4), 16 + 4 lq + e - 4 (e >= 4)
-      float vv[8];
-      if constexpr (TRANS == 0) {
-        const float* p = a.V32 + (x0 + l16) * a.ldv + yb + 4 * lq;
-        const float4 u0 = *reinterpret_cast<const float4*>(p);
-        const float4 u1 = *reinterpret_cast<const float4*>(p + 16);
-        vv[0] = u0.x; vv[1] = u0.y; vv[2] = u0.z; vv[3] = u0.w;
-        vv[4] = u1.x; vv[5] = u1.y; vv[6] = u1.z; vv[7] = u1.w;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int64_t y = yb + ((e < 4) ? 4 * lq + e : 16 + 4 * lq + e - 4);
-          vv[e] = a.V32[y * a.ldv + x0 + l16];
-        }
-      }
       // P^T tiles of the two 16-row halves: reg r <-> y = 16 sb + 4 lq + r, x = l16
       f4_t sp[2];
 #pragma unroll
@@ -407,7 +418,9 @@ __global__ __launch_bounds__(NW * 64) void stream_bf16x3_kernel(StreamArgs a) {
         }
       }
     }
-    if (t + 1 < ntile) stage_store((t + 1) & 1);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) vv[e] = vn[e];
+    stage_store((t + 1) & 1);
     __syncthreads();
   }
 
