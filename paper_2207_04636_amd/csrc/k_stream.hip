@@ -96,12 +96,19 @@ __global__ __launch_bounds__(NW * 64) void stream_kernel(StreamArgs a) {
       for (int r = 0; r < 4; ++r) od[cb][r] = 0.0;
   }
 
-  // Y tile staging (rows are contiguous: ldy == np)
-  double ystage[PER];
+  // Y tile staging (rows are contiguous: ldy == np); the FP32 form reads the FP32
+  // copy of Y (Y is re-read by every x block, so this halves the dominant traffic)
+  TM ystage[PER];
   auto stage_load = [&](int64_t t) {
-    const double* src = a.Y + (ys + t * BY) * a.ldy;
+    if constexpr (F64) {
+      const double* src = a.Y + (ys + t * BY) * a.ldy;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) ystage[k] = src[tid + k * NW * 64];
+      for (int k = 0; k < PER; ++k) ystage[k] = src[tid + k * NW * 64];
+    } else {
+      const float* src = a.Y32 + (ys + t * BY) * a.ldy;
+#pragma unroll
+      for (int k = 0; k < PER; ++k) ystage[k] = src[tid + k * NW * 64];
+    }
   };
   auto stage_store = [&](int buf) {
     TM* dst = sY + buf * BY * LDY;
@@ -307,9 +314,9 @@ __global__ __launch_bounds__(NW * 64) void stream_bf16x3_kernel(StreamArgs a) {
     for (int r = 0; r < 4; ++r) od[cb][r] = 0.0;
   }
 
-  double ystage[PER];
+  float ystage[PER];   // from the FP32 copy of Y (the split keeps 24 bits anyway)
   auto stage_load = [&](int64_t t) {
-    const double* src = a.Y + (ys + t * BY) * a.ldy;
+    const float* src = a.Y32 + (ys + t * BY) * a.ldy;
 #pragma unroll
     for (int k = 0; k < PER; ++k) ystage[k] = src[tid + k * NW * 64];
   };
@@ -320,7 +327,7 @@ __global__ __launch_bounds__(NW * 64) void stream_bf16x3_kernel(StreamArgs a) {
       const int e = tid + k * NW * 64;
       const int r = e / NP, c = e % NP;
       __bf16 h, m, l;
-      split3_bf16((float)ystage[k], h, m, l);
+      split3_bf16(ystage[k], h, m, l);
       b[r * LR + c] = h;
       b[SZR + r * LR + c] = m;
       b[2 * SZR + r * LR + c] = l;
@@ -509,11 +516,11 @@ hipError_t stream_product(const StreamArgs& a, int prec, int nsplit, hipStream_t
   const int64_t tiles = a.ny / BY;
   b.ysplit = ((tiles + nsplit - 1) / nsplit) * BY;
   if (prec == 2) {
-    if (!a.V32) return hipErrorInvalidValue;
+    if (!a.V32 || !a.Y32) return hipErrorInvalidValue;
     return a.trans ? dispatch_bf16x3<1>(b, nsplit, s) : dispatch_bf16x3<0>(b, nsplit, s);
   }
   if (prec == 1) {
-    if (!a.V32) return hipErrorInvalidValue;
+    if (!a.V32 || !a.Y32) return hipErrorInvalidValue;
     return a.trans ? dispatch_nc<float, 1>(b, nsplit, s) : dispatch_nc<float, 0>(b, nsplit, s);
   }
   if (!a.V) return hipErrorInvalidValue;

@@ -868,6 +868,10 @@ void ensure_general(rps_context& c, int np) {
   } else {
     c.gA.release(cnt);
     c.gSp.alloc(kStreamPartRows * np, cnt);    // split partials of the streaming form
+    if (f32) {                                  // FP32 copies of the Y operands of the passes
+      c.gU32.alloc(c.ngp * np, cnt);
+      c.gUg32.alloc(c.nauxp * np, cnt);
+    }
   }
   c.gM2.alloc(c.nauxp * np, cnt);
   c.gM1T.alloc(c.ngp * np, cnt);
@@ -935,9 +939,13 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
     const int prec = c.precision;
     if (need_main) {
       prof_mark(c, 1, st);
+      if (prec != RPS_PREC_FP64) {
+        hip_check(to_f32(c.gU.p, c.ngp * np, c.gU32.p, st), "U to f32");
+        hip_check(to_f32(c.gUg.p, c.nauxp * np, c.gUg32.p, st), "U_g to f32");
+      }
       StreamArgs m2;   // M2 = (V o P) U, x = interpolation points
       m2.V = c.V.p; m2.V32 = c.V32.p; m2.ldv = c.ngp; m2.trans = 0;
-      m2.X = c.gUg.p; m2.ldx = np; m2.Y = c.gU.p; m2.ldy = np;
+      m2.X = c.gUg.p; m2.ldx = np; m2.Y = c.gU.p; m2.Y32 = c.gU32.p; m2.ldy = np;
       m2.nx = c.nauxp; m2.ny = c.ngp; m2.np = np; m2.out = c.gSp.p;
       const int sp = stream_splits(m2.nx, m2.ny, c.tune_target > 0 ? c.tune_target : kStreamBlocks);
       hip_check(stream_product(m2, prec, sp, st), "stream M2");
@@ -946,7 +954,7 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
       if (k1) {
         StreamArgs m1;  // M1^T = (V o P)^T U_g, x = grid points
         m1.V = c.V.p; m1.V32 = c.V32.p; m1.ldv = c.ngp; m1.trans = 1;
-        m1.X = c.gU.p; m1.ldx = np; m1.Y = c.gUg.p; m1.ldy = np;
+        m1.X = c.gU.p; m1.ldx = np; m1.Y = c.gUg.p; m1.Y32 = c.gUg32.p; m1.ldy = np;
         m1.nx = c.ngp; m1.ny = c.nauxp; m1.np = np; m1.out = c.gM1T.p;
         hip_check(stream_product(m1, prec, 1, st), "stream M1");
       }

@@ -261,6 +261,7 @@ struct StreamArgs {
   int trans = 0;
   const double* X = nullptr; int64_t ldx = 0;
   const double* Y = nullptr; int64_t ldy = 0;
+  const float* Y32 = nullptr;  // FP32 copy of Y (same pitch), read by the FP32 and split-BF16 forms
   int64_t nx = 0, ny = 0;
   int64_t ysplit = 0;       // set by stream_product
   int np = 0;
