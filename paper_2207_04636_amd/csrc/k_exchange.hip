@@ -720,12 +720,11 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
 
   // LDS (bytes): area0 | sPhi [T][PP] f32 | sC [Np][16] f64 | m1s [T][16] f64 | sU [T][LDU] f32
   //              | sU2 [T][LDM] f32 | sUg [gper*16][LDM] f32
-  // area0 holds, one after another within a tile: the U partials [2][T][16] f64,
-  // the waves' A slabs [NW][16][SL] f32, the M1 partials [NW][T][RP] f32.  The pitches
-  // keep the lanes of each access pattern on distinct banks.
+  // area0 holds, one after another within a tile: the waves' A slabs [NW][16][SL] f32,
+  // the M1 partials [NW][T][RP] f32.  The pitches keep the lanes of each access pattern
+  // on distinct banks.
   constexpr int AREA0 = NW * 16 * SL * 4;
   char* base = reinterpret_cast<char*>(smem);
-  double* upart = reinterpret_cast<double*>(base);
   float* slab = reinterpret_cast<float*>(base) + w * 16 * SL;
   float* red = reinterpret_cast<float*>(base);
   float* sPhi = reinterpret_cast<float*>(base + AREA0);
@@ -862,28 +861,27 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
     *reinterpret_cast<float4*>(sPhi + pl3) = pf3;
     __syncthreads();
     fetch_phi(rt + 1 < rt1 ? rt + 1 : rt);   // unconditional (the last tile re-reads itself)
-    {
-      // U partials: wave w -> rows 16 (w % 4) .. +15, basis functions of half w / 4
-      const int sub = w & 3, half = w >> 2;
-      const int kh = Np / 8;                 // k steps of 4 per half
-      const float* pa = sPhi + (16 * sub + l16) * PP + half * (Np / 2) + lq;
-      const double* pb = sC + (half * (Np / 2) + lq) * NP + l16;
-      // two independent accumulator chains (kh is even since Np % 16 == 0)
+    if (w < 4) {
+      // U rows 16 w .. 16 w + 15 over all basis functions on the FP64 matrix cores (two
+      // accumulator chains), rounded to FP32 straight into sU / sU2.  Waves 4-7 have no
+      // share: split over eight waves the halves would need a sum through LDS and one more
+      // barrier, while the matrix cores of each SIMD do the same work either way.
+      const int ksteps = Np / 4;             // even, since Np % 16 == 0
+      const float* pa = sPhi + (16 * w + l16) * PP + lq;
+      const double* pb = sC + lq * NP + l16;
       d4_t acc0 = zero_d4(), acc1 = zero_d4();
-#pragma unroll 2
-      for (int kk = 0; kk < kh; kk += 2) {
+#pragma unroll 4
+      for (int kk = 0; kk < ksteps; kk += 2) {
         acc0 = mfma_f64((double)pa[4 * kk], pb[4 * kk * NP], acc0);
         acc1 = mfma_f64((double)pa[4 * kk + 4], pb[(4 * kk + 4) * NP], acc1);
       }
-      double* up = upart + half * T * NP + (16 * sub + lq) * NP + l16;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) up[4 * r * NP] = acc0[r] + acc1[r];
-    }
-    __syncthreads();
-    for (int e = tid; e < T * NP; e += NW * 64) {
-      const float u = (float)(upart[e] + upart[T * NP + e]);
-      sU[(e / NP) * LDU + (e % NP)] = u;
-      sU2[(e / NP) * LDM + (e % NP)] = u;
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * w + 4 * r + lq;
+        const float u = (float)(acc0[r] + acc1[r]);
+        sU[row * LDU + l16] = u;
+        sU2[row * LDM + l16] = u;
+      }
     }
     __syncthreads();
     // U operands of the tile's products (column position p = 16 c + j is row 4 j + c):
