@@ -462,7 +462,11 @@ hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
   if (g.splitk > 1 && (!g.work || g.epi != EPI_AXPBY)) return hipErrorInvalidValue;
   if (g.epi == EPI_HADAMARD_SRC && !g.D && !g.D32) return hipErrorInvalidValue;
   if (g.splitk < 1) g.splitk = 1;
-  const int bn = gemm_tile_n(g.M, g.N);
+  int bn = gemm_tile_n(g.M, g.N);
+  if (g.tile_n) {
+    if ((g.tile_n != 64 && g.tile_n != 128) || g.N <= 16) return hipErrorInvalidValue;
+    bn = g.tile_n;
+  }
   if (g.kscale && bn != 16 && !(g.transA && !g.transB)) return hipErrorInvalidValue;
   if (bn == 16) {
     dim3 grid((unsigned)((g.N + 15) / 16), (unsigned)((g.M + 127) / 128), (unsigned)g.splitk);
@@ -570,6 +574,30 @@ hipError_t gemm_f64_grouped(const Gemm& base, const GemmItem* items, int nitems,
   if (bn == 64) launch_grouped<2>(base, items, grid, s);
   else launch_grouped<4>(base, items, grid, s);
   return hipGetLastError();
+}
+
+void gemm_plan(Gemm& g, int64_t work_cap_doubles) {
+  g.tile_n = 0;
+  g.splitk = 1;
+  if (g.epi != EPI_AXPBY || g.kscale || g.N <= 64) {
+    g.splitk = gemm_splitk_for(g.M, g.N, g.K, work_cap_doubles);
+    return;
+  }
+  double best = -1.0;
+  for (int bn = 128; bn >= 64; bn -= 64) {
+    const int64_t padn = (g.N + bn - 1) / bn * bn;
+    const int64_t tiles = ((g.M + 127) / 128) * (padn / bn);
+    for (int64_t z = 1; z <= 64; ++z) {
+      if (z > 1 && (g.K / z < 256 || z * g.M * g.N > work_cap_doubles)) break;
+      const int64_t wgs = tiles * z, rounds = (wgs + 511) / 512;
+      const double score = (double)g.N / (double)padn * (double)wgs / (double)(rounds * 512);
+      if (score > best + 1e-9) {
+        best = score;
+        g.tile_n = bn;
+        g.splitk = (int)z;
+      }
+    }
+  }
 }
 
 int gemm_splitk_for(int64_t M, int64_t N, int64_t K, int64_t work_cap_doubles) {

@@ -888,8 +888,10 @@ void ensure_general(rps_context& c, int np) {
 
 void gemm_run(Gemm g, rps_context& c, hipStream_t st, const char* what, bool allow_split) {
   if (allow_split && g.epi == EPI_AXPBY) {
-    g.splitk = gemm_splitk_for(g.M, g.N, g.K, kSplitWork);
+    gemm_plan(g, kSplitWork);
     g.work = c.gwork.p;
+  } else if (!g.kscale && g.N > 64) {
+    g.tile_n = ((g.N + 63) / 64 * 64 < (g.N + 127) / 128 * 128) ? 64 : 128;   // less padding
   }
   hip_check(gemm_f64(g, st), what);
 }

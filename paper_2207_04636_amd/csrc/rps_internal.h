@@ -29,8 +29,13 @@ struct Gemm {
   double* work = nullptr;    // splitk * M * N doubles
   bool keep_partials = false;          // splitk > 1: leave the partials in work, no reduction
   const double* kscale = nullptr;      // op(B)[k][n] *= kscale[k] (transA && !transB, or N <= 16)
+  int tile_n = 0;                      // output tile width 64 or 128 (0: chosen from N)
 };
 hipError_t gemm_f64(const Gemm& g, hipStream_t s);
+// Split count and tile width of an AXPBY product together: the pair whose workgroups fill
+// their last round (two per CU) best, weighted by the share of the tile columns that
+// are not padding; splits keep >= 256 of K and fit work_cap doubles.
+void gemm_plan(Gemm& g, int64_t work_cap_doubles);
 // One launch of many independent products: item i computes C_i = alpha op(A_i) op(B_i)
 // + beta C_i with A_i = base.A + aofs etc. (its own sizes and pitches), and with
 // base.kscale + kofs as the row scale when base.kscale is set (transA only).  Items
