@@ -397,24 +397,45 @@ __global__ __launch_bounds__(NW * 64) void stream_bf16x3_kernel(StreamArgs a) {
         am[e] = m;
         al[e] = l;
       }
-      // O[x][c] += A[x][y] Y[y][c]
+      // O[x][c] += A[x][y] Y[y][c], column blocks in pairs: the pair's operands are read
+      // together ahead of its products, and the two accumulation chains alternate
       const __bf16* yt = b + 3 * SZR + l16 * LT + 4 * lq;
 #pragma unroll
-      for (int cb = 0; cb < NC; ++cb) {
-        const __bf16* ph = yt + 16 * cb * LT;
-        bf8_t bt[3];
+      for (int c0 = 0; c0 < NC; c0 += 2) {
+        const int npair = (c0 + 1 < NC) ? 2 : 1;
+        bf8_t bt[2][3];
 #pragma unroll
-        for (int pl = 0; pl < 3; ++pl) {
-          const bf4_t v0 = *reinterpret_cast<const bf4_t*>(ph + pl * SZT);
-          const bf4_t v1 = *reinterpret_cast<const bf4_t*>(ph + pl * SZT + 16);
-          bt[pl] = bf8_t{v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
+        for (int u = 0; u < 2; ++u) {
+          if (u < npair) {
+            const __bf16* ph = yt + 16 * (c0 + u) * LT;
+#pragma unroll
+            for (int pl = 0; pl < 3; ++pl) {
+              const bf4_t v0 = *reinterpret_cast<const bf4_t*>(ph + pl * SZT);
+              const bf4_t v1 = *reinterpret_cast<const bf4_t*>(ph + pl * SZT + 16);
+              bt[u][pl] = bf8_t{v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
+            }
+          }
         }
-        o[cb] = mfma_bf16(al, bt[0], o[cb]);     // smallest terms first
-        o[cb] = mfma_bf16(ah, bt[2], o[cb]);
-        o[cb] = mfma_bf16(am, bt[1], o[cb]);
-        o[cb] = mfma_bf16(am, bt[0], o[cb]);
-        o[cb] = mfma_bf16(ah, bt[1], o[cb]);
-        o[cb] = mfma_bf16(ah, bt[0], o[cb]);
+        __builtin_amdgcn_sched_barrier(0);
+        // smallest terms first
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+          if (u < npair) o[c0 + u] = mfma_bf16(al, bt[u][0], o[c0 + u]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+          if (u < npair) o[c0 + u] = mfma_bf16(ah, bt[u][2], o[c0 + u]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+          if (u < npair) o[c0 + u] = mfma_bf16(am, bt[u][1], o[c0 + u]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+          if (u < npair) o[c0 + u] = mfma_bf16(am, bt[u][0], o[c0 + u]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+          if (u < npair) o[c0 + u] = mfma_bf16(ah, bt[u][1], o[c0 + u]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+          if (u < npair) o[c0 + u] = mfma_bf16(ah, bt[u][0], o[c0 + u]);
       }
       if ((t & 1) || t + 1 == ntile) {
 #pragma unroll
