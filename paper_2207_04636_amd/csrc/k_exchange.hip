@@ -1207,22 +1207,21 @@ __global__ __launch_bounds__(512) void finalize_kernel(const double* __restrict_
   const int m = blockIdx.x / (np / 16), j = blockIdx.x % (np / 16);
   d4_t acc = zero_d4();
   if (M2) {
-    const int64_t nsl = G / 4;
-    int64_t sl = w;
-    for (; sl + 56 < nsl; sl += 64) {
-      double a[8], b[8];
+    // wave w takes the k slices sl = w + 8 q (G is a multiple of 64), sixteen at a time
+    // with all their loads in flight together (clamped, unconditional; slices past the
+    // end contribute zero)
+    const int64_t per = G / 32;
+    for (int64_t q0 = 0; q0 < per; q0 += 16) {
+      double a[16], b[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int64_t g = 4 * (sl + 8 * u) + lq;
+      for (int u = 0; u < 16; ++u) {
+        const int64_t q = (q0 + u < per) ? q0 + u : per - 1;
+        const int64_t g = 4 * (w + 8 * q) + lq;
         a[u] = Phig[g * Np + 16 * m + l16];
         b[u] = M2[g * np + 16 * j + l16];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc = mfma_f64(a[u], b[u], acc);
-    }
-    for (; sl < nsl; sl += 8) {
-      const int64_t g = 4 * sl + lq;
-      acc = mfma_f64(Phig[g * Np + 16 * m + l16], M2[g * np + 16 * j + l16], acc);
+      for (int u = 0; u < 16; ++u) acc = mfma_f64(a[u], (q0 + u < per) ? b[u] : 0.0, acc);
     }
   }
 #pragma unroll
@@ -1495,6 +1494,7 @@ hipError_t finalize(const double* Phig, const double* M2, int64_t G, const doubl
                     int n, int np, int Np, double s1, double s2, double s3, double dV, double* K, const double* e1p,
                     int64_t ne1, const double* e3p, int64_t ne3, double ce1, double ce3, double* ex, hipStream_t s,
                     const EnergyDots& dots) {
+  if (G % 64) return hipErrorInvalidValue;   // the K2 tiles take G in slices of 8 x 4 rows
   const int ntile = (Np / 16) * (np / 16);
   // energy blocks: one per 4K dot-product terms and partials (up to the partial list size)
   int neb = (int)std::min<int64_t>((dots.n1 + dots.n3 + ne1 + ne3 + 4095) / 4096, dots.part ? dots.nparts : 1);
