@@ -1088,9 +1088,9 @@ __global__ __launch_bounds__(256) void orbitals_kernel(const double* __restrict_
 }
 
 // Deterministic sums over partials for up to three segments in one launch:
-// out_s[i] = sum_p in_s[p * count_s + i].  A block owns 64 outputs of one
-// segment; its 4 partial lanes take p = q, q + 4, ... with 8 loads in flight,
-// and are combined in a fixed order.
+// out_s[i] = sum_p in_s[p * count_s + i].  A block owns 16 outputs of one
+// segment; its 16 partial lanes per output take p = q, q + 16, ... with 8 loads
+// in flight, and are combined in a fixed order.
 struct ReduceSeg {
   const double* in;
   int64_t nparts, count;
@@ -1103,28 +1103,35 @@ struct ReduceArgs {
 };
 
 __global__ __launch_bounds__(256) void reduce_partials_kernel(ReduceArgs ra) {
-  __shared__ double red[4][64];
+  // 16 outputs per block, 16 partial lanes per output (lane q takes p = q, q + 16, ...,
+  // eight loads in flight), lanes combined in a fixed order
+  __shared__ double red[16][17];
   int si = 0;
   for (int k = 1; k < ra.nseg; ++k)
     if ((int64_t)blockIdx.x >= ra.seg[k].block0) si = k;
   const ReduceSeg sg = ra.seg[si];
-  const int x = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const int64_t i = ((int64_t)blockIdx.x - sg.block0) * 64 + x;
+  const int x = threadIdx.x & 15, q = threadIdx.x >> 4;
+  const int64_t i = ((int64_t)blockIdx.x - sg.block0) * 16 + x;
   double s = 0.0;
   if (i < sg.count) {
     int64_t p = q;
-    for (; p + 28 < sg.nparts; p += 32) {
+    for (; p + 112 < sg.nparts; p += 128) {
       double v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = sg.in[(p + 4 * u) * sg.count + i];
+      for (int u = 0; u < 8; ++u) v[u] = sg.in[(p + 16 * u) * sg.count + i];
 #pragma unroll
       for (int u = 0; u < 8; ++u) s += v[u];
     }
-    for (; p < sg.nparts; p += 4) s += sg.in[p * sg.count + i];
+    for (; p < sg.nparts; p += 16) s += sg.in[p * sg.count + i];
   }
   red[q][x] = s;
   __syncthreads();
-  if (q == 0 && i < sg.count) sg.out[i] = ((red[0][x] + red[1][x]) + red[2][x]) + red[3][x];
+  if (q == 0 && i < sg.count) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) t += red[k][x];
+    sg.out[i] = t;
+  }
 }
 
 // Final step of a build.  Workgroup (m, j) owns the 16 x 16 output tile
@@ -1448,7 +1455,7 @@ hipError_t sum_partials3(const double* in0, int64_t n0, int64_t c0, double* o0, 
     if (!ins[k] || ns[k] <= 0 || cs[k] <= 0) continue;
     ReduceSeg& g = ra.seg[ra.nseg++];
     g.in = ins[k]; g.nparts = ns[k]; g.count = cs[k]; g.out = outs[k]; g.block0 = blocks;
-    blocks += (cs[k] + 63) / 64;
+    blocks += (cs[k] + 15) / 16;
   }
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)blocks), dim3(256), 0, s, ra);
