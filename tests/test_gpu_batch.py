@@ -1,10 +1,12 @@
 """GPU tests of the batching form (rps_batch_*) and the autotuner.
 
-A batch of uneven cells (fast-path and general-path sizes, FP64 and the FP32
-form) is captured into one HIP graph.  Every replay must reproduce, bit for
+A batch of uneven cells (fast-path and general-path sizes, the GEMM form,
+FP64, FP32 and split-BF16, dense and screened basis) is captured into one HIP
+graph.  Every replay must reproduce, bit for
 bit, the eager builds of the same contexts (same tuned launch parameters, no
 atomics anywhere), also with eager work and synchronisations between replays;
 the config-1 cell is also checked against the FP64 oracle."""
+import dataclasses
 import sys
 
 import numpy as np
@@ -29,11 +31,16 @@ def lib():
 
 
 def _cells():
+    """(workload, precision 0 FP64 / 1 FP32 / 2 split-BF16, eps1 of the screened basis)"""
     cfg1 = ri.tiny_cell()
     c2 = ri.diamond_cell(4.0)
     g1 = ri.diamond_supercell(rep=(2, 1, 1), mesh_per_cell=20, nocc_per_atom=2, c=4.0, cid=61)
     g2 = ri.diamond_supercell(rep=(1, 1, 2), mesh_per_cell=16, nocc_per_atom=3, c=3.0, cid=64)
-    return [(cfg1, 0), (cfg1, 1), (c2, 0), (c2, 1), (g1, 0), (g1, 1), (g2, 0)]
+    # n = 150 (padded 160): the GEMM form inside the graph
+    g3 = dataclasses.replace(ri.diamond_supercell(rep=(2, 1, 1), mesh_per_cell=20, nocc_per_atom=2, c=4.0,
+                                                  cid=65), nocc=150)
+    return [(cfg1, 0, 0.0), (cfg1, 1, 0.0), (c2, 0, 0.0), (c2, 1, 0.0), (g1, 0, 0.0), (g1, 1, 0.0),
+            (g2, 0, 0.0), (g1, 2, 1e-4), (g3, 1, 1e-8)]
 
 
 @pytest.fixture(scope="module")
@@ -42,8 +49,8 @@ def batch_setup(lib):
     cells = _cells()
     ctxs, Cs, refs = [], [], []
     pts1 = None
-    for w, prec in cells:
-        kw = dict(precision=lib.PREC_FP64 if prec == 0 else lib.PREC_FP32)
+    for w, prec, eps in cells:
+        kw = dict(precision=[lib.PREC_FP64, lib.PREC_FP32, lib.PREC_BF16X3][prec], basis_eps=eps)
         if w.name == cells[0][0].name:
             if pts1 is None:
                 Phi = basis.eval_basis(w)
@@ -57,7 +64,7 @@ def batch_setup(lib):
         ctxs.append(ctx)
         Cs.append(torch.from_numpy(C).cuda())
         refs.append(C)
-    Ks = [torch.empty((w.nbas, w.nocc), dtype=torch.float64, device="cuda") for w, _ in cells]
+    Ks = [torch.empty((w.nbas, w.nocc), dtype=torch.float64, device="cuda") for w, _, _ in cells]
     ex = torch.zeros(len(cells), dtype=torch.float64, device="cuda")
     yield dict(cells=cells, ctxs=ctxs, Cs=Cs, Ks=Ks, ex=ex, Chost=refs, pts1=pts1)
     for c in ctxs:

@@ -127,3 +127,26 @@ def test_zero_eps_keeps_every_value(lib):
     _say("case: basis_eps = 0, config 1")
     with lib.Context.from_workload(w, seed=w.sketch_seed(), basis_eps=0.0) as ctx:
         assert ctx.info()["basis_fill"] == 1.0 and ctx.info()["basis_pair_fill"] == 1.0
+
+
+def test_screened_gemm_form_graph_replay(lib, monkeypatch):
+    """Graph replay (RPS_GRAPH=1) of the GEMM form with the screened basis (grouped
+    per-atom launches, FP32 chunk products): every replay equals the host-mode build
+    bit for bit, with eager work between replays."""
+    import torch
+    monkeypatch.setenv("RPS_GRAPH", "1")
+    cs = _case("2x1x1-n150", 1e-4)
+    w = cs["w"]
+    _say("case: screened GEMM form 2x1x1-n150, graph replay vs host builds")
+    with lib.Context.from_workload(w, points=cs["points"], precision=lib.PREC_FP32, basis_eps=1e-4) as ctx:
+        Kh, Eh = ctx.build(cs["C"])
+        Cd = torch.from_numpy(cs["C"]).cuda()
+        K = torch.empty((w.nbas, w.nocc), dtype=torch.float64, device="cuda")
+        ex = torch.zeros(1, dtype=torch.float64, device="cuda")
+        for it in range(4):          # eager, capture + launch, then replays
+            K.fill_(float("nan"))
+            ctx.build(Cd, K, ex)
+            torch.cuda.synchronize()
+            assert np.array_equal(K.cpu().numpy(), Kh), it
+            assert float(ex.item()) == Eh, it
+            ctx.build(cs["C"])       # eager host-mode work between replays
