@@ -1169,7 +1169,7 @@ __global__ __launch_bounds__(512) void finalize_kernel(const double* __restrict_
     slice(ne3, b0, b1);
     for (int64_t p = b0 + tid; p < b1; p += 512) sb += e3p[p];
     slice(dots.n1, b0, b1);
-#pragma unroll 4
+#pragma unroll 8
     for (int64_t p = b0 + tid; p < b1; p += 512) sa += dots.x1[p] * dots.y1[p];
     slice(dots.n3, b0, b1);
 #pragma unroll 4
@@ -1504,7 +1504,9 @@ hipError_t finalize(const double* Phig, const double* M2, int64_t G, const doubl
   if (G % 64) return hipErrorInvalidValue;   // the K2 tiles take G in slices of 8 x 4 rows
   const int ntile = (Np / 16) * (np / 16);
   // energy blocks: one per 4K dot-product terms and partials (up to the partial list size)
-  int neb = (int)std::min<int64_t>((dots.n1 + dots.n3 + ne1 + ne3 + 4095) / 4096, dots.part ? dots.nparts : 1);
+  // (up to 16K terms one block does it all: no device-scope fence, no counter)
+  const int64_t nterms = dots.n1 + dots.n3 + ne1 + ne3;
+  int neb = (nterms <= 16384) ? 1 : (int)std::min<int64_t>((nterms + 4095) / 4096, dots.part ? dots.nparts : 1);
   if (neb < 1) neb = 1;
   hipLaunchKernelGGL(finalize_kernel, dim3(ntile + neb), dim3(512), 0, s, Phig, M2, G, K1, K3, N, n, np, Np, s1, s2,
                      s3, dV, K, e1p, ne1, e3p, ne3, ce1, ce3, ex, dots);
