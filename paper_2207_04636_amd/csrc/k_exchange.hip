@@ -1026,11 +1026,6 @@ __global__ __launch_bounds__(256) void orbitals_kernel(const double* __restrict_
   const int l16 = lane & 15, lq = lane >> 4;
   constexpr int ldb = NPK + 1;
   double* sB = lds + NPK * NP + w * 16 * ldb;  // this wave's 16 x Np block, pitch Np + 1
-  for (int e = tid; e < NPK * NP; e += 256) {
-    const int r = e / NP, c = e % NP;
-    sC[e] = (r < N && c < n) ? C[(int64_t)r * n + c] : 0.0;
-  }
-  __syncthreads();
   const int64_t nsub = (R + G) / 16;
   constexpr int nvec = 16 * NPK / 2;           // 16-byte pieces of a 16-row block
   constexpr int NQ = (nvec + 63) / 64;
@@ -1048,7 +1043,13 @@ __global__ __launch_bounds__(256) void orbitals_kernel(const double* __restrict_
     }
   };
   const int64_t sfirst = (int64_t)blockIdx.x * 4 + w, sstep = (int64_t)gridDim.x * 4;
+  // the first block of basis values is in flight while C is staged
   if (sfirst < nsub) fetch(sfirst);
+  for (int e = tid; e < NPK * NP; e += 256) {
+    const int r = e / NP, c = e % NP;
+    sC[e] = (r < N && c < n) ? C[(int64_t)r * n + c] : 0.0;
+  }
+  __syncthreads();
   for (int64_t sidx = sfirst; sidx < nsub; sidx += sstep) {
     const int64_t row0 = sidx * 16;
     double* dst = (row0 < R) ? U + row0 * NP : Ug + (row0 - R) * NP;
