@@ -754,10 +754,11 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
   if (u3 < n3) l3_load(u3);
 
   // staging loops unrolled so that their global loads are in flight together
+  float* sCf = reinterpret_cast<float*>(sC);   // C rounded to FP32 (first half of its area)
 #pragma unroll 4
   for (int e = tid; e < Np * NP; e += NW * 64) {
     const int r = e / NP, c = e % NP;
-    sC[e] = (r < a.N && c < a.n) ? a.Cm[(int64_t)r * a.n + c] : 0.0;
+    sCf[e] = (r < a.N && c < a.n) ? (float)a.Cm[(int64_t)r * a.n + c] : 0.0f;
   }
   {
     // U_g rows of the workgroup, two doubles per load
@@ -862,23 +863,23 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
     __syncthreads();
     fetch_phi(rt + 1 < rt1 ? rt + 1 : rt);   // unconditional (the last tile re-reads itself)
     if (w < 4) {
-      // U rows 16 w .. 16 w + 15 over all basis functions on the FP64 matrix cores (two
-      // accumulator chains), rounded to FP32 straight into sU / sU2.  Waves 4-7 have no
+      // U rows 16 w .. 16 w + 15 over all basis functions on the FP32 matrix cores (two
+      // accumulator chains, C rounded to FP32), straight into sU / sU2.  Waves 4-7 have no
       // share: split over eight waves the halves would need a sum through LDS and one more
       // barrier, while the matrix cores of each SIMD do the same work either way.
       const int ksteps = Np / 4;             // even, since Np % 16 == 0
       const float* pa = sPhi + (16 * w + l16) * PP + lq;
-      const double* pb = sC + lq * NP + l16;
-      d4_t acc0 = zero_d4(), acc1 = zero_d4();
+      const float* pb = sCf + lq * NP + l16;
+      f4_t acc0 = zero_f4(), acc1 = zero_f4();
 #pragma unroll 4
       for (int kk = 0; kk < ksteps; kk += 2) {
-        acc0 = mfma_f64((double)pa[4 * kk], pb[4 * kk * NP], acc0);
-        acc1 = mfma_f64((double)pa[4 * kk + 4], pb[(4 * kk + 4) * NP], acc1);
+        acc0 = mfma_f32(pa[4 * kk], pb[4 * kk * NP], acc0);
+        acc1 = mfma_f32(pa[4 * kk + 4], pb[(4 * kk + 4) * NP], acc1);
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = 16 * w + 4 * r + lq;
-        const float u = (float)(acc0[r] + acc1[r]);
+        const int row = 16 * w + 4 * lq + r;
+        const float u = acc0[r] + acc1[r];
         sU[row * LDU + l16] = u;
         sU2[row * LDM + l16] = u;
       }
