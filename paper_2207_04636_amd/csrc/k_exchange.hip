@@ -792,7 +792,7 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
   for (int si = 0; si < NMY; ++si)
 #pragma unroll
     for (int r = 0; r < 4; ++r) m2acc[si][r] = 0.0;
-  d4_t k1 = zero_d4();
+  double k1[4] = {0.0, 0.0, 0.0, 0.0};   // K1[16 w + 4 lq + r][l16], summed over the tiles in FP64
   const int mt = Np / 16;
 
   // Basis rows of a tile (T x Np floats, contiguous): float4 piece q = tid + 512 j of
@@ -961,28 +961,31 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) red[(w * 64 + 16 * lq + 4 * r + c) * RP + l16] = m1[c][r];
     __syncthreads();
-    // the eight partials summed in FP64, two elements of the 64 x 16 block per thread
+    // the eight partials summed in FP64 and rounded to FP32, two elements of the 64 x 16
+    // block per thread
+    float* m1f = reinterpret_cast<float*>(m1s);
     for (int e = tid; e < T * NP; e += NW * 64) {
       const int row = e / NP, col = e % NP;
       double sm = 0.0;
 #pragma unroll
       for (int ww = 0; ww < NW; ++ww) sm += (double)red[(ww * 64 + row) * RP + col];
-      m1s[e] = sm;
+      m1f[e] = (float)sm;
     }
     __syncthreads();
     if (a.want_k1 && w < mt) {
-      // K1 += Phi^T M1^T over the tile's 64 rows in two independent chains
+      // K1 += Phi^T M1^T over the tile's 64 rows on the FP32 matrix cores in two
+      // independent chains of 32 rows, added to the FP64 sum of the tiles
       const float* ph = sPhi + lq * PP + 16 * w + l16;
-      d4_t t0 = zero_d4();
+      f4_t t0 = zero_f4(), t1 = zero_f4();
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          t0 = mfma_f64((double)ph[(16 * q + 4 * r) * PP], m1s[(16 * q + 4 * r + lq) * 16 + l16], t0);
-          k1 = mfma_f64((double)ph[(16 * q + 32 + 4 * r) * PP], m1s[(16 * q + 32 + 4 * r + lq) * 16 + l16], k1);
+          t0 = mfma_f32(ph[(16 * q + 4 * r) * PP], m1f[(16 * q + 4 * r + lq) * 16 + l16], t0);
+          t1 = mfma_f32(ph[(16 * q + 32 + 4 * r) * PP], m1f[(16 * q + 32 + 4 * r + lq) * 16 + l16], t1);
         }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) k1[r] += t0[r];
+      for (int r = 0; r < 4; ++r) k1[r] += (double)t0[r] + (double)t1[r];
     }
   };
 
@@ -995,7 +998,7 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
   if (a.want_k1 && w < mt) {
     double* out = a.K1p + (int64_t)wg * a.Np * NP;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) out[(int64_t)(16 * w + 4 * r + lq) * NP + l16] = k1[r];
+    for (int r = 0; r < 4; ++r) out[(int64_t)(16 * w + 4 * lq + r) * NP + l16] = k1[r];
   }
   // M2 rows of the wave's subtiles: M2[g0 + 4lq + r][l16]
   double* out = a.M2p + (int64_t)rb * a.G * NP;
