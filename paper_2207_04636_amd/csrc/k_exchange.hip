@@ -961,15 +961,15 @@ __global__ __launch_bounds__(512) void fused_f32u_kernel(FusedArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) red[(w * 64 + 16 * lq + 4 * r + c) * RP + l16] = m1[c][r];
     __syncthreads();
-    // the eight partials summed in FP64 and rounded to FP32, two elements of the 64 x 16
-    // block per thread
+    // the eight partials summed in FP32 (the sum feeds the FP32 K1 product), two elements
+    // of the 64 x 16 block per thread
     float* m1f = reinterpret_cast<float*>(m1s);
     for (int e = tid; e < T * NP; e += NW * 64) {
       const int row = e / NP, col = e % NP;
-      double sm = 0.0;
+      float sm = 0.0f;
 #pragma unroll
-      for (int ww = 0; ww < NW; ++ww) sm += (double)red[(ww * 64 + row) * RP + col];
-      m1f[e] = (float)sm;
+      for (int ww = 0; ww < NW; ++ww) sm += red[(ww * 64 + row) * RP + col];
+      m1f[e] = sm;
     }
     __syncthreads();
     if (a.want_k1 && w < mt) {
