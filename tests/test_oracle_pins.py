@@ -235,6 +235,92 @@ def test_rps_error_identities(tiny, naux):
     assert abs(E - Etr) < 1e-13
 
 
+@pytest.mark.parametrize("naux", [10, 18, 30])
+def test_ps_and_thc_error_identities(tiny, naux):
+    """Sec. 3.2's expansion of the exact integral around the fit, for the two
+    one-line approximations.  With rho_ab = u_a u_b, its fit rhobar_ab =
+    sum_g rho_ab(R_g) chi_g and delta_ab = rho_ab - rhobar_ab (all computed
+    here by FFT, not by the oracle's build):
+      PS  (fitted pair times exact pair):  (mu i|i j) = dV <rhobar_mu i, Vc rho_ij>
+          E_PS  - E_conv = + dV sum_ij <delta_ij, Vc rho_ij>
+          K_PS  - K_conv = - dV sum_i <delta_mu i, Vc rho_ij>
+      THC (fit times fit):                 (mu i|i j) = dV <rhobar_mu i, Vc rhobar_ij>
+          E_THC - E_conv = + dV sum_ij (2 <delta_ij, Vc rho_ij> - <delta_ij, Vc delta_ij>)
+          K_THC - K_conv = dV sum_i (<delta_mu i, Vc delta_ij> - <delta_mu i, Vc rho_ij>
+                                     - <rho_mu i, Vc delta_ij>)
+    A dropped term, a wrong sign, the wrong side fitted or a transposed
+    operand in ps_occ / thc_occ breaks one of these."""
+    w, Phi, dV, C, Kc, Ec = tiny
+    st = isdf.setup(w.with_naux(naux), Phi, mode="global")
+    pts, chi = st["points"], st["chi"]
+    args = (Phi, pts, st["V"], st["W"], C, dV)
+    Kps, Eps = rps.ps_occ(*args)
+    Kthc, Ethc = rps.thc_occ(*args)
+    U = Phi @ C
+    n = U.shape[1]
+    rho = np.stack([U[:, i] * U[:, j] for i in range(n) for j in range(n)])
+    dlt = _delta(rho, pts, chi)
+    vrho = grid.poisson(rho, w.lattice, w.mesh)
+    vdlt = grid.poisson(dlt, w.lattice, w.mesh)
+    d_r = dV * np.sum(dlt * vrho)          # sum_ij <delta_ij, Vc rho_ij>
+    d_d = dV * np.sum(dlt * vdlt)          # sum_ij <delta_ij, Vc delta_ij>
+    scale = max(1.0, abs(Ec))
+    assert abs((Eps - Ec) - d_r) < 1e-13 * scale
+    assert abs((Ethc - Ec) - (2.0 * d_r - d_d)) < 1e-13 * scale
+    assert d_d > 0                          # the G != 0 Coulomb kernel is positive definite
+    dps = np.zeros_like(Kc)
+    dthc = np.zeros_like(Kc)
+    for i in range(n):
+        r_mu = (Phi * U[:, i][:, None]).T                             # rho_{mu i}, (N, N_g)
+        d_mu = _delta(r_mu, pts, chi)
+        for j in range(n):
+            k = i * n + j
+            dps[:, j] -= dV * d_mu @ vrho[k]
+            dthc[:, j] += dV * (d_mu @ vdlt[k] - d_mu @ vrho[k] - r_mu @ vdlt[k])
+    np.testing.assert_allclose(Kps - Kc, dps, atol=1e-13)
+    np.testing.assert_allclose(Kthc - Kc, dthc, atol=1e-13)
+
+
+def test_cholesky_shift_retry_rank_deficient_metric():
+    """Sec. 4.3 solves the fit with a Cholesky factorisation of X_gg and names
+    no regularisation.  X_gg = (Phi_g Phi_g^T)^2 has rank at most N(N+1)/2
+    (the pair space), so with more points than that it is singular and the
+    plain factorisation fails; the oracle then retries once with the shift
+    lambda = 1e-13 max diag(X_gg) (reading of the paper).  Pinned here:
+    numpy's own Cholesky rejects X_gg, the shifted factor reproduces
+    X_gg + lambda I, and the fit made with it still obeys the exact rPS error
+    identity (which holds for any chi with V = Vc chi and W = V chi^T)."""
+    w = ri.tiny_s_cell(3, 8, 4.0, 2, 24, cid=91)        # 3 s functions: pair rank 6
+    Phi = basis.eval_basis(w)
+    dV = grid.dvol(w.lattice, w.mesh)
+    C = ri.lowdin(ri.random_coefficients(w), basis.overlap(Phi, dV))
+    Kc, Ec = conventional.exchange_occ(Phi, C, w.lattice, w.mesh)
+    pts = np.random.default_rng(3).choice(w.ngrid, 24, replace=False)
+    X = isdf.fitting_metric(Phi[pts])
+    assert np.linalg.matrix_rank(X, tol=1e-10 * np.abs(X).max()) <= 6
+    with pytest.raises(np.linalg.LinAlgError):
+        np.linalg.cholesky(X)
+    L, lam = isdf.cholesky_with_shift(X)
+    assert lam == pytest.approx(1e-13 * float(np.max(np.diag(X))), rel=1e-15)
+    np.testing.assert_allclose(L @ L.T, X + lam * np.eye(len(pts)), atol=1e-12 * np.abs(X).max())
+    st = isdf.setup(w, Phi, points=pts)
+    assert st["shift"] == lam
+    K, E, Etr = rps.build_occ(Phi, pts, st["V"], st["W"], C, dV)
+    U = Phi @ C
+    dij = np.stack([_delta(U[:, i] * U[:, j], pts, st["chi"]) for i in range(2) for j in range(2)])
+    eref = dV * np.sum(dij * grid.poisson(dij, w.lattice, w.mesh))
+    assert abs((E - Ec) - eref) < 1e-12 * max(1.0, abs(Ec))
+    assert abs(E - Etr) < 1e-12
+
+
+def test_cholesky_fails_when_metric_vanishes():
+    """A metric with zero diagonal (every basis value at the points zero) gets
+    a zero shift and stays singular: the oracle raises, as the library returns
+    its not-positive-definite error."""
+    with pytest.raises(np.linalg.LinAlgError):
+        isdf.cholesky_with_shift(np.zeros((8, 8)))
+
+
 def test_rps_exact_with_all_points(tiny):
     """N_chi = N_g: chi is the identity and rPS reproduces exact exchange."""
     w, Phi, dV, C, Kc, Ec = tiny
