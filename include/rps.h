@@ -109,6 +109,11 @@ typedef struct {
                              atom blocks (1.0 without screening) */
     double basis_pair_fill; /* screened set-up: sum over atoms of |kappa_I| n_I^2 / (N_g N^2),
                                the fraction of the dense J product's work (1.0 without) */
+    int32_t build_arith;  /* arithmetic the last exchange build used for its V products, as an
+                             rps_precision value (-1 before the first build).  RPS_PREC_BF16X3
+                             contexts report RPS_PREC_FP32 where that form runs FP32 products:
+                             the fused kernels for n_occ <= 16 and N <= 128, and the GEMM form
+                             for n_occ > 128 */
 } rps_info;
 
 /*
@@ -278,6 +283,10 @@ rps_status rps_autotune(rps_context *ctx, int32_t nocc, const double *C, double 
  *                          1, 2 and 4 and keeping the fastest.
  * A context may appear once per batch and must not be used by other builds
  * while a replay of the batch runs (the builds share its workspace).
+ * The graph holds the addresses of each context's build workspace: after
+ * rps_autotune on one of its contexts, or a build there with another number of
+ * occupied orbitals (either may reallocate that workspace), rps_batch_run
+ * returns RPS_ERR_STATE without launching; destroy and recreate the batch.
  * Destroy the batch before any of its contexts.
  * rps_batch_info: nbranch, and seconds[3] = {create (tuning + capture),
  * last capture, mean replay measured at creation}.

@@ -61,7 +61,8 @@ class Info(ct.Structure):
                 ("n_candidates", ct.c_int64), ("dvol", ct.c_double), ("chol_shift", ct.c_double),
                 ("setup_seconds", ct.c_double), ("device_bytes", ct.c_int64),
                 ("precision", ct.c_int32), ("exact", ct.c_int32), ("madelung", ct.c_double),
-                ("basis_fill", ct.c_double), ("basis_pair_fill", ct.c_double)]
+                ("basis_fill", ct.c_double), ("basis_pair_fill", ct.c_double),
+                ("build_arith", ct.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -148,6 +149,53 @@ def _is_device(x) -> bool:
     return not isinstance(x, np.ndarray) and getattr(x, "is_cuda", False)
 
 
+def _check_array(x, shape, name, device=None):
+    """Raise ValueError unless x is a C-contiguous float64 array of the given
+    shape (a numpy array, or a torch tensor on `device` when that is given).
+    The library reads and writes exactly these extents through raw pointers,
+    so a wrong shape would mean out-of-bounds accesses there."""
+    shape = tuple(int(s) for s in shape)
+    if isinstance(x, np.ndarray):
+        if device is not None:
+            raise ValueError(f"{name} must be a device tensor like the other operands, got a numpy array")
+        ok = x.dtype == np.float64 and x.flags.c_contiguous
+        dtype = x.dtype
+    else:
+        if not hasattr(x, "data_ptr"):
+            raise ValueError(f"{name} must be a numpy array or a torch tensor, got {type(x).__name__}")
+        import torch
+        ok = x.dtype == torch.float64 and x.is_contiguous()
+        dtype = x.dtype
+        if device is not None and x.device != device:
+            raise ValueError(f"{name} is on {x.device}, expected {device}")
+        if device is None and getattr(x, "is_cuda", False):
+            raise ValueError(f"{name} is a device tensor but the other operands are host arrays")
+    if not ok:
+        raise ValueError(f"{name} must be a C-contiguous float64 array (got dtype {dtype})")
+    if tuple(x.shape) != shape:
+        raise ValueError(f"{name} has shape {tuple(x.shape)}, expected {shape}")
+
+
+def _check_scalar_out(x, name, device, count=1):
+    """ex / ej outputs of device calls: a float64 tensor of >= count elements on device."""
+    if x is None:
+        return
+    import torch
+    if not hasattr(x, "data_ptr") or x.dtype != torch.float64 or not x.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 tensor")
+    if x.device != device:
+        raise ValueError(f"{name} is on {x.device}, expected {device}")
+    if x.numel() < count:
+        raise ValueError(f"{name} needs at least {count} element(s), has {x.numel()}")
+
+
+def _coef_cols(C, nbas, name="C") -> int:
+    """Number of occupied orbitals of a coefficient matrix with nbas rows."""
+    if getattr(C, "ndim", None) != 2 or int(C.shape[0]) != int(nbas) or int(C.shape[1]) < 1:
+        raise ValueError(f"{name} must have shape ({nbas}, n_occ) with n_occ >= 1, got {tuple(getattr(C, 'shape', ()))}")
+    return int(C.shape[1])
+
+
 def _stream_handle(stream) -> Optional[int]:
     if stream is None:
         try:
@@ -208,17 +256,18 @@ class Context:
         1-element float64 tensor) and returning them."""
         if _is_device(C):
             import torch
-            if C.dtype != torch.float64 or not C.is_contiguous():
-                raise ValueError("C must be a contiguous float64 tensor")
-            n = int(C.shape[1])
+            n = _coef_cols(C, self.nbas)
+            _check_array(C, (self.nbas, n), "C", C.device)
             if K is None:
                 K = torch.empty((self.nbas, n), dtype=torch.float64, device=C.device)
+            _check_array(K, (self.nbas, n), "K", C.device)
+            _check_scalar_out(ex, "ex", C.device)
             exp_ = 0 if ex is None else _ptr(ex)
             _check(self._lib.rps_build_exchange_variant(self._h, int(variant), n, _ptr(C), _ptr(K), exp_ or None,
                                                         PTRS_DEVICE, _stream_handle(stream)))
             return K, ex
         C = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
-        n = int(C.shape[1])
+        n = _coef_cols(C, self.nbas)
         Kh = np.empty((self.nbas, n))
         e = ct.c_double(0.0)
         _check(self._lib.rps_build_exchange_variant(self._h, int(variant), n, C.ctypes.data, Kh.ctypes.data,
@@ -227,6 +276,7 @@ class Context:
 
     def build_full(self, C):
         C = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
+        _coef_cols(C, self.nbas)
         Kh = np.empty((self.nbas, self.nbas))
         _check(self._lib.rps_build_exchange_full(self._h, int(C.shape[1]), C.ctypes.data, Kh.ctypes.data,
                                                  PTRS_HOST, None))
@@ -238,15 +288,18 @@ class Context:
         call writing J (and ej, a 1-element float64 tensor) and returning them."""
         if _is_device(C):
             import torch
-            if C.dtype != torch.float64 or not C.is_contiguous():
-                raise ValueError("C must be a contiguous float64 tensor")
+            n = _coef_cols(C, self.nbas)
+            _check_array(C, (self.nbas, n), "C", C.device)
             if J is None:
                 J = torch.empty((self.nbas, self.nbas), dtype=torch.float64, device=C.device)
+            _check_array(J, (self.nbas, self.nbas), "J", C.device)
+            _check_scalar_out(ej, "ej", C.device)
             _check(self._lib.rps_build_coulomb(self._h, int(C.shape[1]), _ptr(C), _ptr(J),
                                                None if ej is None else _ptr(ej), PTRS_DEVICE,
                                                _stream_handle(stream)))
             return J, ej
         C = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
+        _coef_cols(C, self.nbas)
         Jh = np.empty((self.nbas, self.nbas))
         e = ct.c_double(0.0)
         _check(self._lib.rps_build_coulomb(self._h, int(C.shape[1]), C.ctypes.data, Jh.ctypes.data,
@@ -258,12 +311,18 @@ class Context:
         (K + M S C, E - M tr(C^T S C)) with E = ex (a float, or None); torch
         CUDA C, K (and ex, a 1-element float64 tensor): stream-ordered, returns (K, ex)."""
         if _is_device(C):
+            n = _coef_cols(C, self.nbas)
+            _check_array(C, (self.nbas, n), "C", C.device)
+            _check_array(K, (self.nbas, n), "K", C.device)
+            _check_scalar_out(ex, "ex", C.device)
             _check(self._lib.rps_madelung_correct(self._h, int(C.shape[1]), _ptr(C), _ptr(K),
                                                   None if ex is None else _ptr(ex), PTRS_DEVICE,
                                                   _stream_handle(stream)))
             return K, ex
         C = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
+        n = _coef_cols(C, self.nbas)
         Kh = np.array(K, dtype=np.float64, order="C", copy=True)
+        _check_array(Kh, (self.nbas, n), "K")
         e = ct.c_double(0.0 if ex is None else float(ex))
         _check(self._lib.rps_madelung_correct(self._h, int(C.shape[1]), C.ctypes.data, Kh.ctypes.data,
                                               None if ex is None else ct.addressof(e), PTRS_HOST, None))
@@ -298,6 +357,12 @@ class Context:
     def autotune(self, C, K, ex=None, stream=None) -> float:
         """Tune this context's launch parameters on device tensors C, K (and ex);
         returns the best mean build time in ms (see rps_autotune)."""
+        if not _is_device(C):
+            raise ValueError("autotune takes device tensors C, K (and ex)")
+        n = _coef_cols(C, self.nbas)
+        _check_array(C, (self.nbas, n), "C", C.device)
+        _check_array(K, (self.nbas, n), "K", C.device)
+        _check_scalar_out(ex, "ex", C.device)
         best = ct.c_double(0.0)
         _check(self._lib.rps_autotune(self._h, int(C.shape[1]), _ptr(C), _ptr(K), None if ex is None else _ptr(ex),
                                       _stream_handle(stream), ct.byref(best)))
@@ -335,20 +400,49 @@ def exchange_energy(C: np.ndarray, K: np.ndarray) -> float:
     lib = load()
     C = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
     K = np.ascontiguousarray(np.asarray(K, dtype=np.float64))
+    if C.ndim != 2 or K.shape != C.shape:
+        raise ValueError(f"C and K must be 2-D arrays of one shape, got {C.shape} and {K.shape}")
     e = ct.c_double(0.0)
     _check(lib.rps_exchange_energy(int(C.shape[0]), int(C.shape[1]), C.ctypes.data, K.ctypes.data, ct.byref(e)))
     return e.value
 
 
+def _check_batch(ctxs, Cs, Ks, ex, device_only):
+    """Per-cell checks of a batch: C[b], K[b] of shape (N_b, n_b), all host
+    arrays or all device tensors on one device; ex of >= len(ctxs) elements."""
+    nb = len(ctxs)
+    if len(Cs) != nb or len(Ks) != nb:
+        raise ValueError(f"{nb} contexts need {nb} C and K arrays, got {len(Cs)} and {len(Ks)}")
+    if nb == 0:
+        return False
+    dev = _is_device(Cs[0])
+    if device_only and not dev:
+        raise ValueError("the batching form takes device tensors")
+    device = Cs[0].device if dev else None
+    for b, (c, C, K) in enumerate(zip(ctxs, Cs, Ks)):
+        n = _coef_cols(C, c.nbas, f"C[{b}]")
+        _check_array(C, (c.nbas, n), f"C[{b}]", device)
+        _check_array(K, (c.nbas, n), f"K[{b}]", device)
+    if ex is not None:
+        if dev:
+            _check_scalar_out(ex, "ex", device, nb)
+        elif not (isinstance(ex, np.ndarray) and ex.dtype == np.float64 and ex.flags.c_contiguous
+                  and ex.size >= nb):
+            raise ValueError(f"ex must be a contiguous float64 array of >= {nb} elements")
+    return dev
+
+
 def build_batched(ctxs, Cs, Ks, ex=None, stream=None):
-    """Batched builds over several contexts (device tensors)."""
+    """Batched builds over several contexts (all host arrays or all device
+    tensors; rps_build_exchange_occRI_batched).  ex: float64 array of
+    len(ctxs) elements or None."""
     lib = load()
+    dev = _check_batch(ctxs, Cs, Ks, ex, device_only=False)
     nb = len(ctxs)
     H = (ct.c_void_p * nb)(*[c._h.value for c in ctxs])
     nocc = (ct.c_int32 * nb)(*[int(C.shape[1]) for C in Cs])
     Cp = (ct.c_void_p * nb)(*[_ptr(C) for C in Cs])
     Kp = (ct.c_void_p * nb)(*[_ptr(K) for K in Ks])
-    dev = _is_device(Cs[0]) if nb else False
     _check(lib.rps_build_exchange_occRI_batched(H, nb, nocc, Cp, Kp, None if ex is None else _ptr(ex),
                                                 PTRS_DEVICE if dev else PTRS_HOST, _stream_handle(stream)))
 
@@ -362,6 +456,7 @@ class Batch:
     def __init__(self, ctxs, Cs, Ks, ex=None, autotune: bool = True, branches: int = 0, stream=None):
         lib = load()
         self._lib = lib
+        _check_batch(ctxs, Cs, Ks, ex, device_only=True)
         self._keep = (list(ctxs), list(Cs), list(Ks), ex)
         nb = len(ctxs)
         H = (ct.c_void_p * nb)(*[c._h.value for c in ctxs])

@@ -120,6 +120,7 @@ struct rps_context {
   int tune_target = 0;                      // streaming form: workgroups aimed at per launch
   int tune_rtiles = 0, tune_gblocks = 0;    // fused kernel: R tiles per workgroup, g blocks
   double tune_ms = 0.0;                     // best build time the tuner measured
+  int last_arith = -1;                      // arithmetic of the last build's V products (rps_info.build_arith)
   // replay of repeated device-pointer builds as a captured HIP graph
   struct GraphEntry {
     int variant, nocc;
@@ -133,7 +134,12 @@ struct rps_context {
   GraphEntry last_call{-1, 0, nullptr, nullptr, nullptr, nullptr, nullptr};
   hipStream_t gstream = nullptr, gbranch = nullptr;   // capture stream and the line-3 branch
   hipEvent_t gfork = nullptr, gjoin = nullptr;
+  // Generation of the build workspace: bumped whenever buffers that captured builds
+  // refer to may be reallocated (every such change goes through clear_graphs), so a
+  // batch graph captured earlier can tell that its baked-in pointers are stale.
+  uint64_t ws_gen = 0;
   void clear_graphs() {
+    ++ws_gen;
     for (auto& e : graphs) {
       (void)hipGraphExecDestroy(e.exec);
       (void)hipGraphDestroy(e.graph);
@@ -936,6 +942,9 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
   const bool need_l3 = (variant != RPS_VARIANT_PS);
   const bool k1 = need_main && variant == RPS_VARIANT_RPS;
   const bool stream = c.gSp.p != nullptr && np <= kStreamMaxNp;
+  // the streaming passes run the context's precision; the GEMM form runs FP32
+  // products for either precision form
+  c.last_arith = stream ? c.precision : (c.gA32.p != nullptr ? RPS_PREC_FP32 : RPS_PREC_FP64);
   if (stream) {
     // streaming form: O never materialises A = V o P (see k_stream.hip)
     const int prec = c.precision;
@@ -1121,6 +1130,7 @@ void enqueue_build(rps_context& c, int variant, int32_t nocc, const double* C, d
   // in-kernel-orbitals precision kernel needs U_g only
   const bool m4 = (np == 16) && c.use_m4;
   const bool f32u = uses_f32u(c, np);
+  c.last_arith = (c.precision == RPS_PREC_FP64) ? RPS_PREC_FP64 : RPS_PREC_FP32;   // fused kernels: FP32 products
   hip_check(orbitals(c.Phi.p, f32u ? 0 : c.ngp, c.Phig.p, c.nauxp, (int)c.Np, Csrc, (int)c.nbas, nocc, np, c.U.p,
                      c.Ug.p, m4 ? c.Ugp.p : nullptr, st),
             "orbitals");
@@ -1659,6 +1669,7 @@ rps_status guarded(F&& f) {
 // A captured batch of exchange builds over many contexts (the batching form).
 struct rps_batch {
   std::vector<rps_context*> ctx;
+  std::vector<uint64_t> gen;           // workspace generation of each context at capture
   std::vector<int32_t> nocc;
   std::vector<const double*> C;
   std::vector<double*> K;
@@ -1741,6 +1752,8 @@ void capture_batch(rps_batch& b, int nbranch, hipStream_t origin) {
   }
   hip_check(hipStreamEndCapture(origin, &b.graph), "hipStreamEndCapture");
   hip_check(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  b.gen.resize(nb);
+  for (int i = 0; i < nb; ++i) b.gen[i] = b.ctx[i]->ws_gen;
   b.capture_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   b.nbranch = nbranch;
   for (int i = 0; i < nb; ++i) b.ctx[i]->profiling = prof[i];
@@ -1922,6 +1935,12 @@ rps_status rps_batch_create(rps_context* const* ctx, int32_t nbatch, const int32
 rps_status rps_batch_run(rps_batch* b, void* hip_stream) {
   return guarded([&] {
     if (!b || !b->exec) fail(RPS_ERR_ARG, "NULL or empty batch");
+    // the graph holds the workspace addresses of its contexts as they were at capture
+    for (size_t i = 0; i < b->ctx.size(); ++i)
+      if (b->ctx[i]->ws_gen != b->gen[i])
+        fail(RPS_ERR_STATE, "the workspace of context " + std::to_string(i) +
+                                " changed after the batch was captured (autotune, or a build with another "
+                                "number of occupied orbitals); destroy and recreate the batch");
     hip_check(hipGraphLaunch(b->exec, (hipStream_t)hip_stream), "hipGraphLaunch");
   });
 }
@@ -1995,6 +2014,7 @@ rps_status rps_get_info(const rps_context* ctx, rps_info* info) {
       pair += (double)(c.vofs[I + 1] - c.vofs[I]) * nc * nc;
     }
     info->basis_pair_fill = c.sparse ? pair / ((double)c.ng * (double)c.nbas * (double)c.nbas) : 1.0;
+    info->build_arith = c.last_arith;
   });
 }
 

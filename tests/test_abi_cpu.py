@@ -150,3 +150,70 @@ def test_madelung_constant_host():
     with pytest.raises(P.RpsError):
         P.madelung_constant(np.array([[1.0, 0, 0], [2.0, 0, 0], [0, 0, 1.0]]))
 
+
+
+class _NoLib:
+    """Stands in for the library: any call into it fails the test, so the
+    binding's argument checks must raise first."""
+    def __getattr__(self, name):
+        raise AssertionError(f"library function {name} called with invalid arguments")
+
+
+def _fake_context(nbas=5):
+    ctx = object.__new__(B.Context)
+    ctx._lib = _NoLib()
+    ctx._h = ct.c_void_p(0)
+    ctx.nbas, ctx.naux, ctx.ngrid, ctx.dvol = nbas, 10, 512, 0.1
+    return ctx
+
+
+@pytest.mark.parametrize("C", [np.zeros((4, 2)), np.zeros((6, 2)), np.zeros((5, 0)), np.zeros(5),
+                               np.zeros((5, 2, 1))])
+def test_binding_rejects_bad_coefficient_shapes(C):
+    """The library reads N x n_occ doubles from C through a raw pointer: a C
+    with another number of rows would be read out of bounds, so the binding
+    refuses it before any library call."""
+    ctx = _fake_context(5)
+    with pytest.raises(ValueError):
+        ctx.build(C)
+    with pytest.raises(ValueError):
+        ctx.build_coulomb(C)
+    with pytest.raises(ValueError):
+        ctx.build_full(C)
+
+
+def test_binding_rejects_bad_outputs_and_batches():
+    ctx = _fake_context(5)
+    C = np.zeros((5, 2))
+    with pytest.raises(ValueError):
+        ctx.madelung_correct(C, np.zeros((5, 3)))
+    with pytest.raises(ValueError):
+        ctx.autotune(C, np.zeros((5, 2)))             # host arrays: the tuner takes device tensors
+    with pytest.raises(ValueError):
+        P.exchange_energy(np.zeros((5, 2)), np.zeros((5, 3)))
+    other = _fake_context(7)
+    with pytest.raises(ValueError):                   # C[1] has the rows of the first context
+        B.build_batched([ctx, other], [C, C], [C, np.zeros((7, 2))])
+    with pytest.raises(ValueError):                   # lists of different lengths
+        B.build_batched([ctx, other], [C], [C])
+    with pytest.raises(ValueError):                   # ex too short for two cells
+        B.build_batched([ctx, ctx], [C, C], [np.zeros((5, 2)), np.zeros((5, 2))], ex=np.zeros(1))
+    with pytest.raises(ValueError):                   # integer K
+        B.build_batched([ctx], [C], [np.zeros((5, 2), dtype=np.int64)])
+    with pytest.raises(ValueError):                   # the graph-captured batch takes device tensors
+        B.Batch([ctx], [C], [np.zeros((5, 2))])
+
+
+def test_binding_checks_torch_tensors():
+    torch = pytest.importorskip("torch")
+    ctx = _fake_context(5)
+    K = np.zeros((5, 2))
+    with pytest.raises(ValueError):                   # non-contiguous
+        B._check_array(torch.zeros((2, 5), dtype=torch.float64).t(), (5, 2), "C")
+    with pytest.raises(ValueError):                   # float32
+        B._check_array(torch.zeros((5, 2), dtype=torch.float32), (5, 2), "C")
+    with pytest.raises(ValueError):                   # wrong shape
+        B._check_array(torch.zeros((5, 3), dtype=torch.float64), (5, 2), "K")
+    B._check_array(torch.zeros((5, 2), dtype=torch.float64), (5, 2), "C")
+    with pytest.raises(ValueError):                   # a host array where a device tensor is needed
+        B._check_array(K, (5, 2), "K", torch.device("cpu"))
