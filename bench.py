@@ -1,27 +1,28 @@
 #!/usr/bin/env python3
 """Exchange builds per second of the rPS occ-RI exchange on one MI355X.
 
-One step = one exchange build (K_occ and E_x, Eq. 16 of the paper): U_g = Phi_g C,
-the fused V-streaming kernel (which also forms U = Phi C tile by tile, K1 and
-the fit-fit line in the timed mixed form), the ordered reductions and the final
-combine, launched eagerly; kernel times come from a separate profiled pass.  The ISDF set-up (points, V, W) runs once
-before the timed region and is reported separately.  Inputs (C) are resident
-in device memory when the timed region starts.  The Coulomb matrix build (J,
-E_J; Sec. 2.3) is timed after it on the FP64 context and reported with the
-paper's cost ratio K / J.
+One step = one exchange build (K_occ and E_x, Eq. 16 of the paper) from
+occupied coefficients already resident in device memory.  The ISDF set-up
+(points, V, W) runs once before the timed region and is reported separately.
 
-Default workload: the 8-atom diamond-like cell (L = 6.74 bohr, 48^3 grid,
-N = 104, n_occ = 16) with N_aux = 6N = 624.  The timed path (`value`) is the
-mixed-precision form; the FP64 path is timed beside it on the same points and
-coefficients, and the energy difference between the two is reported against
-the 1e-6 Ha bar.  --precision fp64 times the FP64 path alone.  --c selects
-another N_aux/N of the convergence sweep (4, 6, 8, 10).
+Default workload: the 3x3x3 diamond-like supercell (216 atoms, L = 20.22 bohr,
+108^3 grid, N = 2808, n_occ = 432, N_aux = 12000).  Ten SCF-like coefficient
+sets (occupied-virtual rotations of angle 0.01, re-orthonormalised) are built
+in turn.  The timed path (`value`) is the mixed-precision form (V stored FP32,
+FP32 matrix-core products summed in FP64 beyond 64 terms); the FP64 path is
+timed beside it on the same points and coefficient sets, and the energy
+difference of every set is reported against the 1e-6 Ha bar.  Steps are timed
+one by one with HIP events (median and min reported) and as a whole between
+two device synchronisations (`value`, `ms_per_step`).
 
-Prints one JSON line.  The roofline block refers to the fused V-streaming
-kernel of the timed path, timed with HIP events recorded by the library on
-its own stream; its algorithmic work per launch is 6 n N_aux N_g flops
-(P = U_g U^T, M1 = A^T U_g, M2 = A U, each 2 n N_aux N_g) on s_V N_aux N_g
-bytes of V (s_V = 4 mixed, 8 FP64).
+Other workloads (--workload): diamond2x2x2 (the 2x2x2 supercell, the same
+protocol), diamond1x1x1 (the 8-atom cell, c = N_aux/N from --c), batch64 (the
+batching form over 64 uneven cells).
+
+Prints one JSON line.  The roofline block refers to the main phase of the
+timed path (the V-streaming products of Eq. 16 lines 1-2), timed with HIP
+events the library records on its own stream; its algorithmic work per build
+is 6 n N_aux N_g flops (P = U_g U^T, M1 = A^T U_g, M2 = A U, each 2 n N_aux N_g).
 """
 from __future__ import annotations
 
@@ -122,6 +123,216 @@ def _time_path(P, w, prec, points, C, steps, warmup, coulomb=False, basis_eps=0.
         res["E_J"] = float(ej.item())
     ctx.close()
     return res
+
+
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [os.cpu_count() or 1])
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline_sliced(w, slices=(16384, 32768)):
+    """The FP64 oracle's rPS build (oracle.rps.build_occ) on grid slices of the
+    workload's shapes, for cells whose full V does not fit host memory
+    (12000 x 1259712 doubles is 121 GB at the 3x3x3 cell).  The oracle runs
+    unchanged on Phi [s x N], V [N_aux x s], W [N_aux x N_aux], C [N x n] with
+    the N_aux points inside the slice (seeded arrays; the cost does not depend
+    on the values).  Its time is a + b s (every term of Eq. 16 is linear in
+    the grid size except the N_aux^2 fit-fit products), so two slice sizes fix
+    a and b, and the full build is a + b N_g."""
+    import numpy as np
+    from oracle import rps as orps
+    rng = np.random.default_rng(7)
+    dV = w.volume / w.ngrid
+    W = rng.random((w.naux, w.naux))
+    W = 0.5 * (W + W.T)
+    C = rng.random((w.nbas, w.nocc))
+    times = []
+    for i, sl in enumerate(slices):
+        Phi = rng.random((sl, w.nbas))
+        V = rng.random((w.naux, sl))
+        pts = np.sort(rng.choice(sl, w.naux, replace=False))
+        if i == 0:
+            orps.build_occ(Phi, pts, V, W, C, dV)        # warm-up
+        t0 = time.perf_counter()
+        orps.build_occ(Phi, pts, V, W, C, dV)
+        times.append(time.perf_counter() - t0)
+        del Phi, V
+    b = (times[1] - times[0]) / (slices[1] - slices[0])
+    a = times[0] - b * slices[0]
+    full = a + b * w.ngrid
+    return {"value": round(1.0 / full, 6), "unit": "builds/s", "cores": int(_blas_threads()), "kind": "oracle",
+            "sample": f"oracle rps.build_occ at the {w.name} shapes on grid slices of {slices[0]} and {slices[1]} "
+                      f"points (seeded arrays, one build each after a warm-up): {times[0]:.2f} s and "
+                      f"{times[1]:.2f} s; time linear in the slice, extrapolated to N_g = {w.ngrid}: "
+                      f"{full:.1f} s per build"}
+
+
+def scf_bench(args, w):
+    """Supercell protocol: FP64 context (library point selection) and the
+    mixed context on the same points; ten SCF-like coefficient sets built in
+    turn on each; per-set |dE_x| of mixed against FP64."""
+    import numpy as np
+    import torch
+    import paper_2207_04636_amd as P
+    import rps_inputs as ri
+    dev = torch.device("cuda:0")
+    nsets = 10
+    mprec = {"fp32": P.PREC_FP32, "bf16x3": P.PREC_BF16X3, "fp64": P.PREC_FP64}[args.precision]
+    mixed = mprec != P.PREC_FP64
+    say = lambda m: print(f"[bench {w.name}] {m}", file=sys.stderr, flush=True)
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def run_steps(ctx, Cd, Kd, exd, nsteps):
+        """nsteps builds, step s on coefficient set s % nsets; per-step events
+        and the whole between two synchronisations."""
+        evs = [(ev(), ev()) for _ in range(nsteps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(nsteps):
+            k = s % nsets
+            evs[s][0].record()
+            ctx.build(Cd[k], Kd[k], exd[k:k + 1])
+            evs[s][1].record()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        per = np.array([a.elapsed_time(b) for a, b in evs])
+        return dt, per
+
+    def profile(ctx, Cd, Kd, exd, nb):
+        ctx.set_profiling(True)
+        for s in range(nb):
+            ctx.build(Cd[s % nsets], Kd[s % nsets], exd[s % nsets:s % nsets + 1])
+        prof = ctx.profile()
+        ctx.set_profiling(False)
+        n = max(prof["builds"], 1)
+        return prof["fused_ms"] / n, prof["line3_ms"] / n, prof["build_ms"] / n
+
+    # ---- FP64 path (library-selected points; the mixed context reuses them)
+    t0 = time.perf_counter()
+    ctx = P.Context.from_workload(w, seed=w.sketch_seed(), basis_eps=args.basis_eps)
+    setup64 = time.perf_counter() - t0
+    say(f"FP64 set-up {setup64:.1f} s")
+    points = ctx.points()
+    S = ctx.overlap()
+    C0 = ri.lowdin(ri.random_coefficients(w), S)
+    Cs = [C0]
+    for k in range(1, nsets):
+        Cs.append(ri.perturbed(Cs[-1], S, k, angle=0.01, w=w))
+    Cd = [torch.from_numpy(C).to(dev) for C in Cs]
+    Kd = [torch.empty((w.nbas, w.nocc), dtype=torch.float64, device=dev) for _ in range(nsets)]
+    exd = torch.zeros(nsets, dtype=torch.float64, device=dev)
+    ctx.build(Cd[0], Kd[0], exd[0:1])                      # warm-up (sizes the workspace)
+    dt64, per64 = run_steps(ctx, Cd, Kd, exd, nsets)
+    E64 = exd.cpu().numpy().copy()
+    K64 = [k.cpu().numpy() for k in Kd]
+    f64_ms, _, b64_ms = profile(ctx, Cd, Kd, exd, 2)
+    say(f"FP64 {nsets / dt64:.3f} builds/s")
+    J = torch.empty((w.nbas, w.nbas), dtype=torch.float64, device=dev)
+    ej = torch.zeros(1, dtype=torch.float64, device=dev)
+    ctx.build_coulomb(Cd[0], J, ej)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        ctx.build_coulomb(Cd[0], J, ej)
+    torch.cuda.synchronize()
+    j_ms = (time.perf_counter() - t0) / 3 * 1e3
+    EJ = float(ej.item())
+    info64 = ctx.info()
+    ctx.close()
+    del J
+    # ---- timed path
+    t0 = time.perf_counter()
+    ctx = (P.Context.from_workload(w, points=points, precision=mprec, basis_eps=args.basis_eps)
+           if mixed else P.Context.from_workload(w, points=points, basis_eps=args.basis_eps))
+    setupm = time.perf_counter() - t0
+    say(f"timed-path set-up {setupm:.1f} s")
+    for s in range(args.warmup):
+        ctx.build(Cd[s % nsets], Kd[s % nsets], exd[s % nsets:s % nsets + 1])
+    dt, per = run_steps(ctx, Cd, Kd, exd, args.steps)
+    say(f"timed {args.steps} builds: {args.steps / dt:.3f} builds/s")
+    # energies and K of every set from this context (the first nsets timed steps cover them all)
+    if args.steps < nsets:
+        run_steps(ctx, Cd, Kd, exd, nsets)
+    Em = exd.cpu().numpy().copy()
+    dK = max(float(np.abs(Kd[k].cpu().numpy() - K64[k]).max() / np.abs(K64[k]).max()) for k in range(nsets))
+    main_ms, l3_ms, build_ms = profile(ctx, Cd, Kd, exd, 3)
+    info = ctx.info()
+    ctx.close()
+
+    n, naux, ng, N = w.nocc, w.naux, w.ngrid, w.nbas
+    flops = 6.0 * n * naux * ng
+    np_ = (n + 15) // 16 * 16
+    gemm_form = np_ > 128
+    arith = int(info["build_arith"])
+    peak = {P.PREC_FP64: PEAK_FP64_TFLOPS, P.PREC_FP32: PEAK_FP32_TFLOPS, P.PREC_BF16X3: PEAK_BF16X3_TFLOPS}[arith]
+    achieved = flops / (main_ms * 1e-3) / 1e12
+    dE = Em - E64
+    F_all = 6.0 * n * naux * ng + 4.0 * n * ng * N + 4.0 * n * naux ** 2 + 4.0 * n * naux * N
+    vbytes = (8.0 if arith == P.PREC_FP64 else 4.0) * naux * ng
+    out = {
+        "metric": "exchange builds/s (K_occ + E_x)",
+        "value": round(args.steps / dt, 4),
+        "unit": "builds/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {P.PREC_FP64: "f64", P.PREC_FP32: "f32", P.PREC_BF16X3: "bf16x3"}[arith],
+        "data": "synthetic (seeded diamond-like supercell, random S-orthonormal occupied coefficients, "
+                "10 SCF-like occupied-virtual rotations of angle 0.01)",
+        "config": {"workload": f"{w.name}: {ng} grid points, N={N}, n_occ={n}, N_aux={naux}, rPS occ-RI, "
+                               + (f"screened basis eps1={args.basis_eps:g}, " if args.basis_eps > 0 else "")
+                               + ("mixed: V, U, U_g and A in FP32, FP32 MFMA chunk products with FP32 sums over "
+                                  "64 terms and FP64 beyond; U = Phi C, K1, K2, K3, line 3 and E_x in FP64"
+                                  if mixed and gemm_form and arith == P.PREC_FP32 else
+                                  "mixed: V FP32, split-BF16 MFMA streaming products, FP32 in tile, FP64 across"
+                                  if arith == P.PREC_BF16X3 else
+                                  "mixed: V FP32, FP32 MFMA streaming products, FP64 across tiles"
+                                  if mixed else "FP64"),
+                   "global_batch": 1, "parallelism": "single GPU"},
+        "step_ms": {"median": round(float(np.median(per)), 3), "min": round(float(per.min()), 3),
+                    "max": round(float(per.max()), 3)},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": ("gemm32_kernel chunk products of the GEMM form (A_c = V o (U_g U_c^T), "
+                                "M1^T_c = A_c^T U_g, M2 += A_c U_c; Eq. 16 lines 1-2) with their split-K "
+                                "reductions, per build" if gemm_form else
+                                "stream_kernel passes (Eq. 16 lines 1-2), per build"),
+                     "kernel_avg_us": round(main_ms * 1e3, 1),
+                     "algorithmic_flops_per_launch": flops,
+                     "algorithmic_V_bytes_per_launch": vbytes,
+                     "hbm_view_GBs": round(vbytes / (main_ms * 1e-3) / 1e9, 1)},
+        "whole_build_roofline": {"flops": F_all, "achieved_tflops": round(F_all / (dt / args.steps) / 1e12, 3),
+                                 "frac": round(F_all / (dt / args.steps) / 1e12 / peak, 4)},
+        "build_ms_events": round(build_ms, 3),
+        "line3_ms": round(l3_ms, 3),
+        "setup_s": {"fp64_context": round(setup64, 2), "timed_context": round(setupm, 2),
+                    "library_fp64": round(float(info64["setup_seconds"]), 2)},
+        "E_x": float(Em[0]),
+        "fp64_path": {"builds_per_s": round(nsets / dt64, 4), "ms_per_step": round(dt64 / nsets * 1e3, 3),
+                      "step_ms_median": round(float(np.median(per64)), 3), "main_phase_ms": round(f64_ms, 3),
+                      "main_phase_frac_fp64_peak": round(flops / (f64_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+                      "build_ms_events": round(b64_ms, 3), "E_x": float(E64[0])},
+        "mixed_vs_fp64": {"speedup": round((args.steps / dt) / (nsets / dt64), 4),
+                          "dE_x_per_set": [float(x) for x in dE], "max_abs_dE_x": float(np.abs(dE).max()),
+                          "max_dK_over_max_K": dK, "dE_x_bar": 1e-6,
+                          "within_bar": bool(np.abs(dE).max() < 1e-6)},
+        "coulomb": {"build_ms": round(j_ms, 2), "E_J": EJ,
+                    "k_over_j_fp64": round(dt64 / nsets * 1e3 / j_ms, 3),
+                    "k_over_j_timed_path": round(dt / args.steps * 1e3 / j_ms, 3)},
+    }
+    if not args.no_cpu_baseline:
+        say("oracle CPU baseline")
+        out["cpu_baseline"] = cpu_baseline_sliced(w) if ng > 500000 else cpu_baseline(w, nrep=1)
+    print(json.dumps(out), flush=True)
 
 
 def _traffic(kernel_tag):
@@ -237,8 +448,8 @@ def batch_bench(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--c", type=float, default=6.0, help="N_aux / N (4, 6, 8 or 10)")
     ap.add_argument("--precision", choices=["fp32", "bf16x3", "fp64"], default="fp32",
                     help="fp32 (default): the mixed form (V stored FP32, FP32 in-tile products, FP64 across "
@@ -246,9 +457,11 @@ def main():
                          "split-BF16 products on the streaming passes (general sizes; n <= 16 uses the FP32 "
                          "kernel); fp64: the FP64 path only")
     ap.add_argument("--workload", choices=["diamond1x1x1", "diamond2x2x2", "diamond3x3x3", "batch64"],
-                    default="diamond1x1x1",
-                    help="diamond1x1x1 (default, the headline line); diamond2x2x2 / diamond3x3x3: the precision "
-                         "form on the supercells (few steps); batch64: the batching form over 64 uneven cells")
+                    default="diamond3x3x3",
+                    help="diamond3x3x3 (default, the headline line: the 3x3x3 supercell, mixed against FP64 over "
+                         "10 SCF-like coefficient sets); diamond2x2x2: the same on the 2x2x2 supercell; "
+                         "diamond1x1x1: the 8-atom cell (use --steps 2000 --warmup 50); batch64: the batching "
+                         "form over 64 uneven cells")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--basis-eps", type=float, default=0.0,
                     help="screened basis (Sec. 4.1): drop pSinc coefficients below this eps1 (0 = dense)")
@@ -277,12 +490,10 @@ def main():
 
     if args.workload == "batch64":
         return batch_bench(args)
-    if args.workload != "diamond1x1x1":
-        if args.steps == ap.get_default("steps"):
-            args.steps, args.warmup = 5, 1
-        args.no_cpu_baseline = True
-    w = {"diamond1x1x1": lambda: ri.diamond_cell(args.c), "diamond2x2x2": ri.diamond_2x2x2,
-         "diamond3x3x3": ri.diamond_3x3x3}[args.workload]()
+    if args.workload in ("diamond2x2x2", "diamond3x3x3"):
+        w = ri.diamond_2x2x2() if args.workload == "diamond2x2x2" else ri.diamond_3x3x3()
+        return scf_bench(args, w)
+    w = ri.diamond_cell(args.c)
     # interpolation points and the orthonormal occupied coefficients, shared by both paths
     t0 = time.perf_counter()
     with P.Context.from_workload(w, seed=w.sketch_seed(), basis_eps=args.basis_eps) as sel:

@@ -326,8 +326,10 @@ rps_status rps_get_array(const rps_context *ctx, int32_t which, int64_t row0, in
 
 /*
  * Kernel timing for measurement.  With enable = 1 every later build records
- * HIP events on its stream around the V-streaming kernel(s) (Eq. 16, lines 1-2),
- * around the fit-fit kernel (line 3) and around the whole build.
+ * HIP events on its stream around the V-streaming kernel(s) (Eq. 16, lines 1-2;
+ * in the GEMM form of n_occ > 128, the chunk products A_c = V o P, M1^T and M2
+ * with their split-K reductions), around the fit-fit kernel (line 3) and
+ * around the whole build.
  * rps_get_profile synchronises the stream of the last build, writes
  *   out[0] = builds timed, out[1] = total ms in the V-streaming kernel,
  *   out[2] = total ms in the fit-fit kernel, out[3] = total ms of whole builds,

@@ -38,11 +38,15 @@ void hip_check(hipError_t e, const char* what) {
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
-// Device buffer owned by a context.
+// Device buffer owned by a context (or by a set-up step; freed on every exit path).
 template <typename Tp>
 struct DBuf {
   Tp* p = nullptr;
   int64_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(nullptr); }
   void alloc(int64_t count, int64_t* counter) {
     release(counter);
     if (count <= 0) return;
@@ -996,12 +1000,12 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
       prof_mark(c, 4, st);
     }
   } else if (need_main) {
-    prof_mark(c, 1, st);
     const bool f32 = c.gA32.p != nullptr;
     if (f32) {
       hip_check(to_f32(c.gU.p, c.ngp * np, c.gU32.p, st), "U to f32");
       hip_check(to_f32(c.gUg.p, c.nauxp * np, c.gUg32.p, st), "U_g to f32");
     }
+    prof_mark(c, 1, st);     // the profiled main phase: the chunk products only
     constexpr int64_t kF32Terms = 1ll << 40;   // split for parallelism only (FP32 sums are short)
     for (int64_t r0 = 0; r0 < c.ngp; r0 += c.gchunk) {
       const int64_t rc = std::min(c.gchunk, c.ngp - r0);

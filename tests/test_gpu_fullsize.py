@@ -101,16 +101,17 @@ def test_supercell_2x2x2_coulomb_against_oracle(lib):
 
 def test_supercell_3x3x3_scf_steps(lib):
     """Config 4: FP64 GEMM form, then the precision form (FP32 V and FP32
-    matrix-core products) on the same points, over SCF-like steps.  The two
-    contexts live one after the other (FP64 V alone is 121 GB)."""
+    matrix-core products) on the same points, over 10 SCF-like builds
+    (occupied-virtual rotations of angle 0.01).  The two contexts live one
+    after the other (FP64 V alone is 121 GB)."""
     w = ri.diamond_3x3x3()
-    _say(f"case: {w.name} FP64 then FP32 form, 3 SCF-like steps")
+    _say(f"case: {w.name} FP64 then FP32 form, 10 SCF-like builds")
     with lib.Context.from_workload(w, seed=w.sketch_seed()) as ctx:
         pts = ctx.points()
         S = ctx.overlap()
         C = ri.lowdin(ri.random_coefficients(w), S)
         steps = [C]
-        for s in range(1, 3):
+        for s in range(1, 10):
             steps.append(ri.perturbed(steps[-1], S, s, angle=0.01, w=w))
         # Coulomb matrix at full size: exact symmetry, both energy routes, occupied rotation
         J, EJ = ctx.build_coulomb(C)
