@@ -773,40 +773,102 @@ void ensure_energy_parts(rps_context& c) {
   hip_check(hipMemset(c.ecount.p, 0, sizeof(unsigned)), "hipMemset");
 }
 
+// Launch shape and buffer sizes (in doubles) of the fused path's workspace for
+// padded n = np; the same plan serves the context's own buffers and the
+// no-allocation entry point's static scratch, so both give identical builds.
+struct FusedPlan {
+  int rtiles, gblocks, nwaves;
+  int64_t rblocks_main, blocks_main, blocks_l3;
+  bool f32u, m4;
+  int64_t nU, nUg, nUgp, nM2p, ne3u, nK1p, nK3p, ne1p, ne3p, nM2, nK1, nK3;
+};
+
+FusedPlan fused_plan(rps_context& c, int np) {
+  FusedPlan p{};
+  FusedArgs a{};
+  a.R_valid = c.ng;
+  choose_shape(c, np, a);
+  p.rtiles = a.rtiles;
+  p.gblocks = a.gblocks;
+  p.nwaves = a.nwaves;
+  p.rblocks_main = fused_rblocks(a);
+  p.blocks_main = p.rblocks_main * p.gblocks;
+  p.blocks_l3 = (c.nauxp / 64) * ((c.naux + 63) / 64);   // one 64 x 64 tile of W per workgroup
+  p.f32u = uses_f32u(c, np);
+  p.m4 = (np == 16) && c.use_m4;
+  const int64_t nsub = c.nauxp / 16;
+  p.nU = c.ngp * np;
+  p.nUg = c.nauxp * np;
+  p.nUgp = c.nauxp * np;
+  // M2 partials, followed by the negated fit-fit partials of the in-kernel-orbitals kernel
+  p.nM2p = (p.rblocks_main + (p.f32u ? nsub : 0)) * c.nauxp * np;
+  p.ne3u = p.f32u ? nsub * nsub : 1;
+  p.nK1p = p.blocks_main * c.Np * np;
+  p.nK3p = std::max<int64_t>(p.blocks_l3, 1) * c.Np * np;
+  p.ne1p = p.blocks_main;
+  p.ne3p = std::max<int64_t>(p.blocks_l3, 1);
+  p.nM2 = c.nauxp * np;
+  p.nK1 = c.Np * np;
+  p.nK3 = c.Np * np;
+  return p;
+}
+
+// Pointers of the fused path's workspace (the context's buffers, or carved
+// from the static scratch by the no-allocation entry point).
+struct FusedWs {
+  FusedPlan plan;
+  double *U = nullptr, *Ug = nullptr, *Ugp = nullptr, *M2p = nullptr, *e3u = nullptr, *K1p = nullptr,
+         *K3p = nullptr, *e1p = nullptr, *e3p = nullptr, *M2 = nullptr, *K1 = nullptr, *K3 = nullptr,
+         *epart = nullptr;
+  unsigned* ecount = nullptr;
+};
+
 void ensure_workspace(rps_context& c, int np) {
   if (c.ws_np == np) return;
   c.clear_graphs();          // captured builds refer to the buffers about to change
   int64_t* cnt = &c.bytes;
-  FusedArgs a{};
-  a.R_valid = c.ng;
-  choose_shape(c, np, a);
-  c.rtiles = a.rtiles;
-  c.gblocks = a.gblocks;
-  c.nwaves = a.nwaves;
   if (const char* m = getenv("RPS_FP64_MFMA"))
     c.use_m4 = (strcmp(m, "16x16x4") == 0) ? 0 : (strcmp(m, "hybrid") == 0) ? 2 : 1;
-  c.rblocks_main = fused_rblocks(a);
-  c.blocks_main = c.rblocks_main * c.gblocks;
-  c.blocks_l3 = (c.nauxp / 64) * ((c.naux + 63) / 64);   // one 64 x 64 tile of W per workgroup
-  c.U.alloc(c.ngp * np, cnt);
-  c.Ug.alloc(c.nauxp * np, cnt);
-  c.Ugp.alloc(c.nauxp * np, cnt);
-  // M2 partials, followed by the negated fit-fit partials of the in-kernel-orbitals kernel
-  const int64_t nsub = c.nauxp / 16;
-  c.M2p.alloc((c.rblocks_main + (uses_f32u(c, np) ? nsub : 0)) * c.nauxp * np, cnt);
-  c.e3u.alloc(uses_f32u(c, np) ? nsub * nsub : 1, cnt);
+  const FusedPlan p = fused_plan(c, np);
+  c.rtiles = p.rtiles;
+  c.gblocks = p.gblocks;
+  c.nwaves = p.nwaves;
+  c.rblocks_main = p.rblocks_main;
+  c.blocks_main = p.blocks_main;
+  c.blocks_l3 = p.blocks_l3;
+  c.U.alloc(p.nU, cnt);
+  c.Ug.alloc(p.nUg, cnt);
+  c.Ugp.alloc(p.nUgp, cnt);
+  c.M2p.alloc(p.nM2p, cnt);
+  c.e3u.alloc(p.ne3u, cnt);
   ensure_energy_parts(c);
-  c.K1p.alloc(c.blocks_main * c.Np * np, cnt);
-  c.K3p.alloc(std::max<int64_t>(c.blocks_l3, 1) * c.Np * np, cnt);
-  c.e1p.alloc(c.blocks_main, cnt);
-  c.e3p.alloc(std::max<int64_t>(c.blocks_l3, 1), cnt);
-  c.M2.alloc(c.nauxp * np, cnt);
-  c.K1.alloc(c.Np * np, cnt);
-  c.K3.alloc(c.Np * np, cnt);
+  c.K1p.alloc(p.nK1p, cnt);
+  c.K3p.alloc(p.nK3p, cnt);
+  c.e1p.alloc(p.ne1p, cnt);
+  c.e3p.alloc(p.ne3p, cnt);
+  c.M2.alloc(p.nM2, cnt);
+  c.K1.alloc(p.nK1, cnt);
+  c.K3.alloc(p.nK3, cnt);
   c.Cdev.alloc(c.nbas * np, cnt);
   c.Kdev.alloc(c.nbas * np, cnt);
   c.exdev.alloc(1, cnt);
   c.ws_np = np;
+}
+
+FusedWs context_ws(rps_context& c, int np) {
+  FusedWs w;
+  w.plan.f32u = uses_f32u(c, np);
+  w.plan.m4 = (np == 16) && c.use_m4;
+  w.plan.rtiles = c.rtiles;
+  w.plan.gblocks = c.gblocks;
+  w.plan.nwaves = c.nwaves;
+  w.plan.rblocks_main = c.rblocks_main;
+  w.plan.blocks_main = c.blocks_main;
+  w.plan.blocks_l3 = c.blocks_l3;
+  w.U = c.U.p; w.Ug = c.Ug.p; w.Ugp = c.Ugp.p; w.M2p = c.M2p.p; w.e3u = c.e3u.p; w.K1p = c.K1p.p;
+  w.K3p = c.K3p.p; w.e1p = c.e1p.p; w.e3p = c.e3p.p; w.M2 = c.M2.p; w.K1 = c.K1.p; w.K3 = c.K3.p;
+  w.epart = c.epart.p; w.ecount = c.ecount.p;
+  return w;
 }
 
 // ------------------------------------------------------------------ general path
@@ -1095,6 +1157,107 @@ bool uses_general(const rps_context& c, int np) {
   return general;
 }
 
+// The fused path of one build (N <= 128, n within the fused kernels' limits) on
+// the workspace w: orbitals, the V-streaming kernel (lines 1-2, and line 3 in
+// the in-kernel-orbitals form), the fit-fit kernel, the ordered partial sums and
+// the combine.  C, K and ex are device pointers.  prof: record the profiling
+// events (the no-allocation entry point passes false: events are created on
+// demand).
+void enqueue_fused(rps_context& c, const FusedWs& w, int variant, int32_t nocc, const double* Csrc, double* Kout,
+                   double* exout, hipStream_t st, hipStream_t st3, bool prof) {
+  const int np = (int)round_up(nocc, 16);
+  double s1 = 1, s2 = 1, s3 = -1, ce1 = 2, ce3 = -1;
+  if (variant == RPS_VARIANT_PS) { s1 = 0; s2 = 1; s3 = 0; ce1 = 1; ce3 = 0; }
+  if (variant == RPS_VARIANT_THC) { s1 = 0; s2 = 0; s3 = 1; ce1 = 0; ce3 = 1; }
+  // U = Phi C (orbitals on the grid) and U_g = Phi_g C (at the points); the
+  // in-kernel-orbitals precision kernel needs U_g only
+  const bool m4 = w.plan.m4;
+  const bool f32u = w.plan.f32u;
+  c.last_arith = (c.precision == RPS_PREC_FP64) ? RPS_PREC_FP64 : RPS_PREC_FP32;   // fused kernels: FP32 products
+  hip_check(orbitals(c.Phi.p, f32u ? 0 : c.ngp, c.Phig.p, c.nauxp, (int)c.Np, Csrc, (int)c.nbas, nocc, np, w.U,
+                     w.Ug, m4 ? w.Ugp : nullptr, st),
+            "orbitals");
+  const bool need_main = (variant != RPS_VARIANT_THC);
+  const bool need_l3 = (variant != RPS_VARIANT_PS);
+  // the in-kernel-orbitals kernel also forms the fit-fit line, as negated partials after
+  // the M2 partials (their ordered sum is then M2 - Y; the rPS variant only)
+  const bool l3_in_main = f32u && variant == RPS_VARIANT_RPS;
+  const int64_t nsub = c.nauxp / 16;
+  if (need_main) {
+    FusedArgs a{};
+    a.Vm = c.V.p; a.ldv = c.ngp; a.Ug = w.Ug; a.Ur = w.U; a.Phir = c.Phi.p;
+    a.G = c.nauxp; a.R = c.ngp; a.R_valid = c.ng; a.np = np; a.Np = (int)c.Np;
+    a.rtiles = w.plan.rtiles; a.gblocks = w.plan.gblocks; a.nwaves = w.plan.nwaves;
+    a.want_m2 = 1; a.want_k1 = (variant == RPS_VARIANT_RPS) ? 1 : 0; a.want_m1 = 0;
+    a.want_e = m4 ? 1 : 0;     // sum A o P = tr(U_g^T M2) is formed after the M2 reduction instead
+    a.prec = c.precision;
+    a.Vm32 = (c.precision != RPS_PREC_FP64) ? c.V32.p : nullptr;
+    a.Ugp = m4 ? w.Ugp : nullptr; a.use_m4 = m4 ? c.use_m4 : 0;
+    if (f32u) { a.Phi32 = c.Phi32.p; a.Cm = Csrc; a.N = (int)c.nbas; a.n = nocc; }
+    if (l3_in_main) {
+      a.Wl = c.W.p; a.ldw = c.nauxp;
+      a.Yneg = w.M2p + w.plan.rblocks_main * c.nauxp * np; a.e3u = w.e3u;
+    }
+    a.M2p = w.M2p; a.K1p = w.K1p; a.e1p = w.e1p;
+    if (prof) prof_mark(c, 1, st);
+    hip_check(fused_exchange(a, st), "fused main");
+    if (prof) prof_mark(c, 2, st);
+  }
+  hipStream_t sl3 = st;
+  if (need_l3 && !l3_in_main && st3) {      // fork after the orbitals: line 3 needs only U_g
+    hip_check(hipEventRecord(c.gfork, st), "fork");
+    hip_check(hipStreamWaitEvent(st3, c.gfork, 0), "fork wait");
+    sl3 = st3;
+  }
+  if (need_l3 && !l3_in_main) {
+    FusedArgs a{};
+    a.Vm = c.W.p; a.ldv = c.nauxp; a.Ug = w.Ug; a.Ur = w.Ug; a.Phir = c.Phig.p;
+    a.G = c.nauxp; a.R = c.nauxp; a.R_valid = c.naux; a.np = np; a.Np = (int)c.Np;
+    a.rtiles = 1; a.gblocks = (int)(c.nauxp / 64); a.nwaves = 4;
+    a.want_m2 = 0; a.want_k1 = 1; a.want_m1 = 0; a.want_e = 1; a.prec = RPS_PREC_FP64;
+    a.Ugp = m4 ? w.Ugp : nullptr; a.use_m4 = m4 ? c.use_m4 : 0;
+    a.K1p = w.K3p; a.e1p = w.e3p;
+    if (prof) prof_mark(c, 3, sl3);
+    hip_check(fused_exchange(a, sl3), "fused line 3");
+    if (prof) prof_mark(c, 4, sl3);
+  }
+  if (sl3 != st) {
+    hip_check(hipEventRecord(c.gjoin, sl3), "join");
+    hip_check(hipStreamWaitEvent(st, c.gjoin, 0), "join wait");
+  }
+  const bool k1 = need_main && variant == RPS_VARIANT_RPS;
+  const bool k3 = need_l3 && !l3_in_main;
+  hip_check(sum_partials3(k1 ? w.K1p : nullptr, w.plan.blocks_main, c.Np * np, w.K1,
+                          need_main ? w.M2p : nullptr, w.plan.rblocks_main + (l3_in_main ? nsub : 0),
+                          c.nauxp * np, w.M2,
+                          k3 ? w.K3p : nullptr, w.plan.blocks_l3, c.Np * np, w.K3, st),
+            "partial sums");
+  int64_t ne1 = need_main ? w.plan.blocks_main : 0;
+  EnergyDots dots;
+  dots.part = w.epart; dots.nparts = kEnergyBlocks; dots.count = w.ecount;
+  if (need_main && !m4) {      // sum A o P = tr(U_g^T M2), formed by the finalize kernel
+    ne1 = 0;
+    dots.x1 = w.Ug; dots.y1 = w.M2; dots.n1 = c.nauxp * np;
+  }
+  if (l3_in_main) {
+    // M2 now holds Z = M2 - Y: K = dV (K1 + Phi_g^T Z); E_x = -dV (2 tr(U_g^T Z) + tr(U_g^T Y))
+    hip_check(finalize(c.Phig.p, w.M2, c.nauxp, w.K1, nullptr, (int)c.nbas, nocc, np, (int)c.Np, 1.0, 1.0, 0.0,
+                       c.dV, Kout, nullptr, 0, w.e3u, nsub * nsub, 2.0, 1.0, exout, st, dots),
+              "finalize");
+  } else {
+    hip_check(finalize(c.Phig.p, need_main ? w.M2 : nullptr, c.nauxp, k1 ? w.K1 : nullptr,
+                       k3 ? w.K3 : nullptr, (int)c.nbas, nocc, np, (int)c.Np, s1, s2, s3, c.dV, Kout,
+                       w.e1p, ne1, w.e3p, k3 ? w.plan.blocks_l3 : 0, ce1, ce3, exout, st, dots),
+              "finalize");
+  }
+  if (prof) prof_mark(c, 5, st);
+  if (prof && c.profiling && c.ev_used < kMaxProfiled) {
+    if (!need_main) { prof_mark(c, 1, st); prof_mark(c, 2, st); }
+    if (!need_l3 || l3_in_main) { prof_mark(c, 3, st); prof_mark(c, 4, st); }
+    ++c.ev_used;
+  }
+}
+
 // variant coefficients: K = dV (s1 K1 + s2 K2 + s3 K3), E = -dV (ce1 e1 + ce3 e3)
 // Enqueue one build on st.  With st3 != NULL (graph capture only) the fit-fit
 // kernel of the fused path runs on st3, beside the V-streaming kernel.
@@ -1130,95 +1293,9 @@ void enqueue_build(rps_context& c, int variant, int32_t nocc, const double* C, d
     }
     return;
   }
-  // U = Phi C (orbitals on the grid) and U_g = Phi_g C (at the points); the
-  // in-kernel-orbitals precision kernel needs U_g only
-  const bool m4 = (np == 16) && c.use_m4;
-  const bool f32u = uses_f32u(c, np);
-  c.last_arith = (c.precision == RPS_PREC_FP64) ? RPS_PREC_FP64 : RPS_PREC_FP32;   // fused kernels: FP32 products
-  hip_check(orbitals(c.Phi.p, f32u ? 0 : c.ngp, c.Phig.p, c.nauxp, (int)c.Np, Csrc, (int)c.nbas, nocc, np, c.U.p,
-                     c.Ug.p, m4 ? c.Ugp.p : nullptr, st),
-            "orbitals");
-  const bool need_main = (variant != RPS_VARIANT_THC);
-  const bool need_l3 = (variant != RPS_VARIANT_PS);
-  // the in-kernel-orbitals kernel also forms the fit-fit line, as negated partials after
-  // the M2 partials (their ordered sum is then M2 - Y; the rPS variant only)
-  const bool l3_in_main = f32u && variant == RPS_VARIANT_RPS;
-  const int64_t nsub = c.nauxp / 16;
-  if (need_main) {
-    FusedArgs a{};
-    a.Vm = c.V.p; a.ldv = c.ngp; a.Ug = c.Ug.p; a.Ur = c.U.p; a.Phir = c.Phi.p;
-    a.G = c.nauxp; a.R = c.ngp; a.R_valid = c.ng; a.np = np; a.Np = (int)c.Np;
-    a.rtiles = c.rtiles; a.gblocks = c.gblocks; a.nwaves = c.nwaves;
-    a.want_m2 = 1; a.want_k1 = (variant == RPS_VARIANT_RPS) ? 1 : 0; a.want_m1 = 0;
-    a.want_e = m4 ? 1 : 0;     // sum A o P = tr(U_g^T M2) is formed after the M2 reduction instead
-    a.prec = c.precision;
-    a.Vm32 = (c.precision != RPS_PREC_FP64) ? c.V32.p : nullptr;
-    a.Ugp = m4 ? c.Ugp.p : nullptr; a.use_m4 = m4 ? c.use_m4 : 0;
-    if (f32u) { a.Phi32 = c.Phi32.p; a.Cm = Csrc; a.N = (int)c.nbas; a.n = nocc; }
-    if (l3_in_main) {
-      a.Wl = c.W.p; a.ldw = c.nauxp;
-      a.Yneg = c.M2p.p + c.rblocks_main * c.nauxp * np; a.e3u = c.e3u.p;
-    }
-    a.M2p = c.M2p.p; a.K1p = c.K1p.p; a.e1p = c.e1p.p;
-    prof_mark(c, 1, st);
-    hip_check(fused_exchange(a, st), "fused main");
-    prof_mark(c, 2, st);
-  }
-  hipStream_t sl3 = st;
-  if (need_l3 && !l3_in_main && st3) {      // fork after the orbitals: line 3 needs only U_g
-    hip_check(hipEventRecord(c.gfork, st), "fork");
-    hip_check(hipStreamWaitEvent(st3, c.gfork, 0), "fork wait");
-    sl3 = st3;
-  }
-  if (need_l3 && !l3_in_main) {
-    FusedArgs a{};
-    a.Vm = c.W.p; a.ldv = c.nauxp; a.Ug = c.Ug.p; a.Ur = c.Ug.p; a.Phir = c.Phig.p;
-    a.G = c.nauxp; a.R = c.nauxp; a.R_valid = c.naux; a.np = np; a.Np = (int)c.Np;
-    a.rtiles = 1; a.gblocks = (int)(c.nauxp / 64); a.nwaves = 4;
-    a.want_m2 = 0; a.want_k1 = 1; a.want_m1 = 0; a.want_e = 1; a.prec = RPS_PREC_FP64;
-    a.Ugp = m4 ? c.Ugp.p : nullptr; a.use_m4 = m4 ? c.use_m4 : 0;
-    a.K1p = c.K3p.p; a.e1p = c.e3p.p;
-    prof_mark(c, 3, sl3);
-    hip_check(fused_exchange(a, sl3), "fused line 3");
-    prof_mark(c, 4, sl3);
-  }
-  if (sl3 != st) {
-    hip_check(hipEventRecord(c.gjoin, sl3), "join");
-    hip_check(hipStreamWaitEvent(st, c.gjoin, 0), "join wait");
-  }
   double* Kout = dev ? K : c.Kdev.p;
   double* exout = dev ? ex : (ex ? c.exdev.p : nullptr);
-  const bool k1 = need_main && variant == RPS_VARIANT_RPS;
-  const bool k3 = need_l3 && !l3_in_main;
-  hip_check(sum_partials3(k1 ? c.K1p.p : nullptr, c.blocks_main, c.Np * np, c.K1.p,
-                          need_main ? c.M2p.p : nullptr, c.rblocks_main + (l3_in_main ? nsub : 0),
-                          c.nauxp * np, c.M2.p,
-                          k3 ? c.K3p.p : nullptr, c.blocks_l3, c.Np * np, c.K3.p, st),
-            "partial sums");
-  int64_t ne1 = need_main ? c.blocks_main : 0;
-  EnergyDots dots;
-  dots.part = c.epart.p; dots.nparts = kEnergyBlocks; dots.count = c.ecount.p;
-  if (need_main && !m4) {      // sum A o P = tr(U_g^T M2), formed by the finalize kernel
-    ne1 = 0;
-    dots.x1 = c.Ug.p; dots.y1 = c.M2.p; dots.n1 = c.nauxp * np;
-  }
-  if (l3_in_main) {
-    // M2 now holds Z = M2 - Y: K = dV (K1 + Phi_g^T Z); E_x = -dV (2 tr(U_g^T Z) + tr(U_g^T Y))
-    hip_check(finalize(c.Phig.p, c.M2.p, c.nauxp, c.K1.p, nullptr, (int)c.nbas, nocc, np, (int)c.Np, 1.0, 1.0, 0.0,
-                       c.dV, Kout, nullptr, 0, c.e3u.p, nsub * nsub, 2.0, 1.0, exout, st, dots),
-              "finalize");
-  } else {
-    hip_check(finalize(c.Phig.p, need_main ? c.M2.p : nullptr, c.nauxp, k1 ? c.K1.p : nullptr,
-                       k3 ? c.K3.p : nullptr, (int)c.nbas, nocc, np, (int)c.Np, s1, s2, s3, c.dV, Kout,
-                       c.e1p.p, ne1, c.e3p.p, k3 ? c.blocks_l3 : 0, ce1, ce3, exout, st, dots),
-              "finalize");
-  }
-  prof_mark(c, 5, st);
-  if (c.profiling && c.ev_used < kMaxProfiled) {
-    if (!need_main) { prof_mark(c, 1, st); prof_mark(c, 2, st); }
-    if (!need_l3 || l3_in_main) { prof_mark(c, 3, st); prof_mark(c, 4, st); }
-    ++c.ev_used;
-  }
+  enqueue_fused(c, context_ws(c, np), variant, nocc, Csrc, Kout, exout, st, st3, true);
   if (!dev) {
     hip_check(hipMemcpyAsync(K, c.Kdev.p, (size_t)c.nbas * nocc * 8, hipMemcpyDeviceToHost, st), "copy K");
     if (ex) hip_check(hipMemcpyAsync(ex, c.exdev.p, 8, hipMemcpyDeviceToHost, st), "copy ex");
