@@ -179,6 +179,26 @@ rps_status rps_build_exchange_occRI(rps_context *ctx, int32_t nocc, const double
                                     double *ex, int32_t flags, void *hip_stream);
 
 /*
+ * rps_build_exchange_occRI for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The call allocates nothing.  The build's workspace (orbitals at
+ * the points, the ordered partial sums of lines 1-3, the energy partials and
+ * counter) comes from a static device array of 64 MiB that the library holds
+ * on every device it runs on until the process ends; the caller passes only
+ * C, K and ex, all device pointers (stream-ordered on hip_stream, asynchronous).
+ * Results equal rps_build_exchange_occRI's on the same context.
+ * Limits: the fused path only (N <= 128 with n_occ <= 64 for FP64 contexts,
+ * n_occ <= 16 for the precision forms; about 38 MiB at most for the 8-atom
+ * 48^3 cell) and at most 64 MiB of workspace; anything else returns
+ * RPS_ERR_SHAPE before any launch.  All calls on one device share the array:
+ * calls that overlap on one device (two streams, two host threads) race and
+ * give wrong results; order them on one stream.
+ * Errors: RPS_ERR_ARG, RPS_ERR_STATE, RPS_ERR_SHAPE, RPS_ERR_DEVICE.
+ */
+rps_status rps_build_exchange_occRI_noalloc(rps_context *ctx, int32_t nocc, const double *C, double *K,
+                                            double *ex, void *hip_stream);
+
+/*
  * Same as rps_build_exchange_occRI for the PS and THC approximations
  * (variant = rps_variant; Sec. 3.2: PS keeps the first line of Eq. 13, THC the
  * third).  RPS_VARIANT_RPS gives exactly rps_build_exchange_occRI.

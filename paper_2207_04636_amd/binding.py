@@ -26,6 +26,7 @@ STATUS_NAMES = {0: "RPS_OK", 1: "RPS_ERR_ARG", 2: "RPS_ERR_SHAPE", 3: "RPS_ERR_N
 
 # every symbol declared in include/rps.h
 EXPORTS = ("rps_setup_isdf", "rps_setup_isdf_screened", "rps_build_exchange_occRI", "rps_build_exchange_variant",
+           "rps_build_exchange_occRI_noalloc",
            "rps_build_exchange_full", "rps_build_coulomb", "rps_madelung_constant", "rps_madelung_correct",
            "rps_build_exchange_occRI_batched",
            "rps_exchange_energy",
@@ -94,6 +95,7 @@ def load(path: str = LIB_PATH):
                                             ct.POINTER(ct.c_int64), D, P, ct.POINTER(P)]
     lib.rps_build_exchange_occRI.argtypes = [P, I32, P, P, P, I32, P]
     lib.rps_build_exchange_variant.argtypes = [P, I32, I32, P, P, P, I32, P]
+    lib.rps_build_exchange_occRI_noalloc.argtypes = [P, I32, P, P, P, P]
     lib.rps_build_exchange_full.argtypes = [P, I32, P, P, I32, P]
     lib.rps_build_coulomb.argtypes = [P, I32, P, P, P, I32, P]
     lib.rps_madelung_constant.argtypes = [P, ct.POINTER(D)]
@@ -273,6 +275,19 @@ class Context:
         _check(self._lib.rps_build_exchange_variant(self._h, int(variant), n, C.ctypes.data, Kh.ctypes.data,
                                                     ct.addressof(e), PTRS_HOST, None))
         return Kh, e.value
+
+    def build_noalloc(self, C, K, ex=None, stream=None):
+        """rps_build_exchange_occRI_noalloc: the build on the library's static
+        device scratch (no device allocation); C, K (and ex) device tensors."""
+        if not _is_device(C):
+            raise ValueError("the no-allocation build takes device tensors")
+        n = _coef_cols(C, self.nbas)
+        _check_array(C, (self.nbas, n), "C", C.device)
+        _check_array(K, (self.nbas, n), "K", C.device)
+        _check_scalar_out(ex, "ex", C.device)
+        _check(self._lib.rps_build_exchange_occRI_noalloc(self._h, n, _ptr(C), _ptr(K),
+                                                          None if ex is None else _ptr(ex), _stream_handle(stream)))
+        return K, ex
 
     def build_full(self, C):
         C = np.ascontiguousarray(np.asarray(C, dtype=np.float64))

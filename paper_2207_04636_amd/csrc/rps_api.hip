@@ -13,6 +13,7 @@
 #include <new>
 #include <string>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "../../include/rps.h"
@@ -465,6 +466,34 @@ void select_points(rps_context& c, int mode, uint64_t seed, const std::vector<in
   c.points = select_pivots(c, Rh, c.naux, seed, 0, 1, st);
 }
 
+// ------------------------------------------------------------------ no-allocation build
+// Static device scratch of the no-allocation entry point: the fused path's
+// workspace (orbitals at the points, M2 / K1 / fit-fit partials, their sums,
+// the energy partials and the energy counter) carved from one array per device.
+// The code object holds it on every device it is loaded on until the process
+// ends.  Host code must not use the array's name as an address: the device
+// address of each device's copy is taken once with hipGetSymbolAddress (with
+// that device current) and kept in g_scratch_ptr.
+constexpr int64_t kNoAllocScratchBytes = 64ll << 20;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / 8];
+
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;   // device address of `scratch` per device ordinal
+
+double* scratch_device_ptr() {
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!ptr) fail(RPS_ERR_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
 void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_t n_aux, uint64_t seed,
                 int32_t mode, int32_t prec, const int64_t* points_in, double basis_eps, hipStream_t st) {
   auto t0 = std::chrono::steady_clock::now();
@@ -693,6 +722,9 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
     build_screened_blocks(c, b->atom_xyz, st);
     stage("screened basis blocks", st);
   }
+  // device address of the no-allocation build's static scratch on this device, taken
+  // here so that loading the array happens at set-up, not inside that build
+  (void)scratch_device_ptr();
   c.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
@@ -1724,6 +1756,56 @@ void autotune(rps_context& c, int32_t nocc, const double* C, double* K, double* 
   c.profiling = saved_prof;
 }
 
+// ------------------------------------------------------------------ no-allocation build (continued)
+// Carve the workspace of plan p from base (256-byte aligned pieces); returns the
+// doubles used (the caller checks them against the scratch size before use).
+int64_t carve_fused_ws(const FusedPlan& p, double* base, FusedWs& w) {
+  int64_t off = 0;
+  auto take = [&](int64_t n) {
+    double* q = base ? base + off : nullptr;
+    off += (n + 31) / 32 * 32;
+    return q;
+  };
+  w.plan = p;
+  w.U = p.f32u ? nullptr : take(p.nU);      // the in-kernel-orbitals kernel forms U itself
+  w.Ug = take(p.nUg);
+  w.Ugp = p.m4 ? take(p.nUgp) : nullptr;
+  w.M2p = take(p.nM2p);
+  w.e3u = take(p.ne3u);
+  w.K1p = take(p.nK1p);
+  w.K3p = take(p.nK3p);
+  w.e1p = take(p.ne1p);
+  w.e3p = take(p.ne3p);
+  w.M2 = take(p.nM2);
+  w.K1 = take(p.nK1);
+  w.K3 = take(p.nK3);
+  w.epart = take(kEnergyBlocks);
+  w.ecount = reinterpret_cast<unsigned*>(take(32));
+  return off;
+}
+
+void build_noalloc_impl(rps_context& c, int32_t nocc, const double* C, double* K, double* ex, hipStream_t st) {
+  if (c.ng == 0) fail(RPS_ERR_STATE, "context has no completed set-up");
+  if (nocc < 1) fail(RPS_ERR_ARG, "nocc must be >= 1");
+  if (!C || !K) fail(RPS_ERR_ARG, "C and K must not be NULL");
+  const int np = (int)round_up(nocc, 16);
+  if (uses_general(c, np))
+    fail(RPS_ERR_SHAPE, "the no-allocation build covers the fused path only (N <= 128 with n_occ <= 64 in FP64 "
+                        "or n_occ <= 16 in the precision forms)");
+  FusedWs w;
+  const FusedPlan p = fused_plan(c, np);
+  const int64_t need = carve_fused_ws(p, nullptr, w);
+  if (need * 8 > kNoAllocScratchBytes)
+    fail(RPS_ERR_SHAPE, "the no-allocation build needs " + std::to_string(need * 8) + " bytes of scratch, " +
+                            "above its static maximum of " + std::to_string(kNoAllocScratchBytes) + " bytes");
+  double* base = scratch_device_ptr();
+  carve_fused_ws(p, base, w);
+  // the energy counter must start at zero (a fill kernel, no memset node if captured)
+  hip_check(fill(reinterpret_cast<double*>(w.ecount), 32, 0.0, st), "clear counter");
+  c.last_stream = st;
+  enqueue_fused(c, w, RPS_VARIANT_RPS, nocc, C, K, ex, st, nullptr, false);
+}
+
 template <typename F>
 rps_status guarded(F&& f) {
   try {
@@ -1893,6 +1975,14 @@ rps_status rps_build_exchange_occRI(rps_context* ctx, int32_t nocc, const double
   return guarded([&] {
     if (!ctx) fail(RPS_ERR_ARG, "ctx must not be NULL");
     build_impl(*ctx, RPS_VARIANT_RPS, nocc, C, K, ex, flags, (hipStream_t)hip_stream);
+  });
+}
+
+rps_status rps_build_exchange_occRI_noalloc(rps_context* ctx, int32_t nocc, const double* C, double* K,
+                                            double* ex, void* hip_stream) {
+  return guarded([&] {
+    if (!ctx) fail(RPS_ERR_ARG, "ctx must not be NULL");
+    build_noalloc_impl(*ctx, nocc, C, K, ex, (hipStream_t)hip_stream);
   });
 }
 
