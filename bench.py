@@ -212,6 +212,8 @@ def scf_bench(args, w):
         n = max(prof["builds"], 1)
         return prof["fused_ms"] / n, prof["line3_ms"] / n, prof["build_ms"] / n
 
+    if args.synthetic_potentials:
+        return synthetic_bench(args, w, mprec, run_steps, profile, nsets)
     # ---- FP64 path (library-selected points; the mixed context reuses them)
     t0 = time.perf_counter()
     ctx = P.Context.from_workload(w, seed=w.sketch_seed(), basis_eps=args.basis_eps)
@@ -332,6 +334,63 @@ def scf_bench(args, w):
     if not args.no_cpu_baseline:
         say("oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline_sliced(w) if ng > 500000 else cpu_baseline(w, nrep=1)
+    print(json.dumps(out), flush=True)
+
+
+def synthetic_bench(args, w, mprec, run_steps, profile, nsets):
+    """Build timing alone on seeded synthetic potentials (rps_setup_isdf_from_potentials):
+    random grid points, V uniform in [0, 1e-3) in the stored FP32 form, W a random
+    symmetric matrix.  The builds run the same kernels at the same launch shapes
+    as with the fitted potentials (their cost does not depend on the values),
+    without the point selection, fit and FFT of the set-up; energies are not
+    meaningful.  Used to profile the builds of the largest cell."""
+    import numpy as np
+    import torch
+    import paper_2207_04636_amd as P
+    import rps_inputs as ri
+    if mprec == P.PREC_FP64:
+        raise SystemExit("--synthetic-potentials times the precision forms only (FP32 V)")
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(11)
+    points = np.sort(rng.choice(w.ngrid, w.naux, replace=False)).astype(np.int64)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    V = torch.rand((w.naux, w.ngrid), dtype=torch.float32, device=dev, generator=gen) * 1e-3
+    Wh = rng.random((w.naux, w.naux))
+    W = torch.from_numpy(0.5 * (Wh + Wh.T)).to(dev)
+    t0 = time.perf_counter()
+    ctx = P.Context.from_potentials(w, points, V, W, precision=mprec)
+    setup_s = time.perf_counter() - t0
+    del V, W
+    torch.cuda.empty_cache()
+    S = ctx.overlap()
+    Cs = [ri.lowdin(ri.random_coefficients(w), S)]
+    for k in range(1, nsets):
+        Cs.append(ri.perturbed(Cs[-1], S, k, angle=0.01, w=w))
+    Cd = [torch.from_numpy(C).to(dev) for C in Cs]
+    Kd = [torch.empty((w.nbas, w.nocc), dtype=torch.float64, device=dev) for _ in range(nsets)]
+    exd = torch.zeros(nsets, dtype=torch.float64, device=dev)
+    for s in range(args.warmup):
+        ctx.build(Cd[s % nsets], Kd[s % nsets], exd[s % nsets:s % nsets + 1])
+    dt, per = run_steps(ctx, Cd, Kd, exd, args.steps)
+    main_ms, l3_ms, build_ms = profile(ctx, Cd, Kd, exd, 3)
+    info = ctx.info()
+    ctx.close()
+    flops = 6.0 * w.nocc * w.naux * w.ngrid
+    arith = int(info["build_arith"])
+    peak = PEAK_FP32_TFLOPS if arith == P.PREC_FP32 else PEAK_BF16X3_TFLOPS
+    out = {"metric": "exchange builds/s (K_occ + E_x)", "value": round(args.steps / dt, 4), "unit": "builds/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(dt / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32" if arith == P.PREC_FP32 else "bf16x3",
+           "data": "synthetic potentials (random points, V, W; energies not meaningful): build timing only",
+           "config": {"workload": f"{w.name}, synthetic potentials", "global_batch": 1,
+                      "parallelism": "single GPU"},
+           "step_ms": {"median": round(float(np.median(per)), 3), "min": round(float(per.min()), 3)},
+           "roofline": {"bound": "mfma", "achieved": round(flops / (main_ms * 1e-3) / 1e12, 3), "peak": peak,
+                        "unit": "TFLOP/s", "frac": round(flops / (main_ms * 1e-3) / 1e12 / peak, 4),
+                        "traffic": None, "kernel_avg_us": round(main_ms * 1e3, 1)},
+           "build_ms_events": round(build_ms, 3), "setup_s": round(setup_s, 2)}
     print(json.dumps(out), flush=True)
 
 
@@ -463,6 +522,9 @@ def main():
                          "diamond1x1x1: the 8-atom cell (use --steps 2000 --warmup 50); batch64: the batching "
                          "form over 64 uneven cells")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--synthetic-potentials", action="store_true",
+                    help="supercell workloads: time the builds on seeded synthetic potentials given to the library "
+                         "(no point selection, fit or FFT at set-up); for profiling the builds alone")
     ap.add_argument("--basis-eps", type=float, default=0.0,
                     help="screened basis (Sec. 4.1): drop pSinc coefficients below this eps1 (0 = dense)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",

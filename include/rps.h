@@ -162,6 +162,27 @@ rps_status rps_setup_isdf_screened(const rps_cell *cell, const rps_basis *basis,
                                    rps_context **out);
 
 /*
+ * Set-up from potentials computed elsewhere: the basis on the grid (Sec. 2.1.3)
+ * and Phi_g as in rps_setup_isdf, but the interpolation points, the potentials V
+ * of the fitting functions (Eq. 12) and W (Eq. 14) are the caller's; no point
+ * selection, fit or FFT runs.  For reusing set-up products across processes or
+ * codes (save them with rps_get_points and rps_get_array), and for timing builds
+ * apart from the fit.
+ * points   : host array of n_aux distinct grid indices (required)
+ * precision: rps_precision of later builds; it also fixes V's element type
+ * V        : [n_aux][ldv] row-major, ldv >= N_g: FP64 for RPS_PREC_FP64, FP32
+ *            (the stored form) for RPS_PREC_FP32 and RPS_PREC_BF16X3
+ * W        : [n_aux][ldw] FP64, ldw >= n_aux, symmetric
+ * flags    : RPS_PTRS_HOST or RPS_PTRS_DEVICE (V and W); the call is synchronous
+ * n_aux == N_g (the exact case) is refused: use rps_setup_isdf.
+ * Errors: RPS_ERR_ARG, RPS_ERR_SHAPE, RPS_ERR_NOMEM (before allocating), RPS_ERR_DEVICE.
+ */
+rps_status rps_setup_isdf_from_potentials(const rps_cell *cell, const rps_basis *basis, int64_t n_aux,
+                                          const int64_t *points, int32_t precision, const void *V, int64_t ldv,
+                                          const double *W, int64_t ldw, int32_t flags, void *hip_stream,
+                                          rps_context **out);
+
+/*
  * One exchange build, Eq. 16 (Sec. 3.3) with the contraction order of
  * Sec. 4.4 for the second line:
  *   U = Phi C, U_g = U[points], P = U_g U^T, A = V o P, P_g = U_g U_g^T,

@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "RPS_OK", 1: "RPS_ERR_ARG", 2: "RPS_ERR_SHAPE", 3: "RPS_ERR_N
                 4: "RPS_ERR_NOT_PD", 5: "RPS_ERR_DEVICE", 6: "RPS_ERR_STATE"}
 
 # every symbol declared in include/rps.h
-EXPORTS = ("rps_setup_isdf", "rps_setup_isdf_screened", "rps_build_exchange_occRI", "rps_build_exchange_variant",
+EXPORTS = ("rps_setup_isdf", "rps_setup_isdf_screened", "rps_setup_isdf_from_potentials",
+           "rps_build_exchange_occRI", "rps_build_exchange_variant",
            "rps_build_exchange_occRI_noalloc",
            "rps_build_exchange_full", "rps_build_coulomb", "rps_madelung_constant", "rps_madelung_correct",
            "rps_build_exchange_occRI_batched",
@@ -93,6 +94,8 @@ def load(path: str = LIB_PATH):
                                    ct.POINTER(ct.c_int64), P, ct.POINTER(P)]
     lib.rps_setup_isdf_screened.argtypes = [ct.POINTER(Cell), ct.POINTER(Basis), I64, U64, I32, I32,
                                             ct.POINTER(ct.c_int64), D, P, ct.POINTER(P)]
+    lib.rps_setup_isdf_from_potentials.argtypes = [ct.POINTER(Cell), ct.POINTER(Basis), I64, ct.POINTER(ct.c_int64),
+                                                   I32, P, I64, P, I64, I32, P, ct.POINTER(P)]
     lib.rps_build_exchange_occRI.argtypes = [P, I32, P, P, P, I32, P]
     lib.rps_build_exchange_variant.argtypes = [P, I32, I32, P, P, P, I32, P]
     lib.rps_build_exchange_occRI_noalloc.argtypes = [P, I32, P, P, P, P]
@@ -213,11 +216,7 @@ def _stream_handle(stream) -> Optional[int]:
 class Context:
     """An rPS set-up (points, V, W on the device) for one cell and basis."""
 
-    def __init__(self, lattice, mesh, atoms, shell_atom, shell_l, shell_exp, naux: int,
-                 seed: int = 0, select: int = SELECT_VORONOI, precision: int = PREC_FP64,
-                 points=None, stream=None, basis_eps: float = 0.0):
-        lib = load()
-        self._lib = lib
+    def _marshal(self, lattice, mesh, atoms, shell_atom, shell_l, shell_exp):
         cell = Cell()
         lat = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(9))
         cell.lattice[:] = list(lat)
@@ -231,6 +230,20 @@ class Context:
                   self._sa.ctypes.data_as(ct.POINTER(ct.c_int32)),
                   self._sl.ctypes.data_as(ct.POINTER(ct.c_int32)),
                   self._se.ctypes.data_as(ct.POINTER(ct.c_double)))
+        return cell, b
+
+    def _finish(self, h):
+        self._h = h
+        inf = self.info()
+        self.nbas, self.naux, self.ngrid = int(inf["nbas"]), int(inf["naux"]), int(inf["ngrid"])
+        self.dvol = float(inf["dvol"])
+
+    def __init__(self, lattice, mesh, atoms, shell_atom, shell_l, shell_exp, naux: int,
+                 seed: int = 0, select: int = SELECT_VORONOI, precision: int = PREC_FP64,
+                 points=None, stream=None, basis_eps: float = 0.0):
+        lib = load()
+        self._lib = lib
+        cell, b = self._marshal(lattice, mesh, atoms, shell_atom, shell_l, shell_exp)
         pts = None
         if points is not None:
             self._pts_in = np.ascontiguousarray(np.asarray(points, dtype=np.int64))
@@ -239,10 +252,31 @@ class Context:
         _check(lib.rps_setup_isdf_screened(ct.byref(cell), ct.byref(b), int(naux),
                                            ct.c_uint64(int(seed) & (2**64 - 1)), int(select), int(precision),
                                            pts, float(basis_eps), _stream_handle(stream), ct.byref(h)))
-        self._h = h
-        inf = self.info()
-        self.nbas, self.naux, self.ngrid = int(inf["nbas"]), int(inf["naux"]), int(inf["ngrid"])
-        self.dvol = float(inf["dvol"])
+        self._finish(h)
+
+    @classmethod
+    def from_potentials(cls, w, points, V, W, precision: int = PREC_FP64, stream=None):
+        """rps_setup_isdf_from_potentials: a context for workload w whose points,
+        V [N_aux x N_g] (float64 for FP64, float32 for the precision forms) and
+        W [N_aux x N_aux] (float64) are given (numpy arrays, or torch device tensors)."""
+        self = object.__new__(cls)
+        self._lib = load()
+        cell, b = self._marshal(w.lattice, w.mesh, w.atoms, w.shell_atom, w.shell_l, w.shell_exp)
+        self._pts_in = np.ascontiguousarray(np.asarray(points, dtype=np.int64))
+        naux, ng = len(self._pts_in), int(np.prod(w.mesh))
+        vdt = "float64" if precision == PREC_FP64 else "float32"
+        dev = _is_device(V)
+        for x, shape, name, dt in ((V, (naux, ng), "V", vdt), (W, (naux, naux), "W", "float64")):
+            if tuple(x.shape) != shape or str(x.dtype).split(".")[-1] != dt:
+                raise ValueError(f"{name} must be {dt} of shape {shape}, got {x.dtype} {tuple(x.shape)}")
+            if _is_device(x) != dev or not (x.flags.c_contiguous if isinstance(x, np.ndarray) else x.is_contiguous()):
+                raise ValueError(f"V and W must both be contiguous host arrays or both device tensors")
+        h = ct.c_void_p()
+        _check(self._lib.rps_setup_isdf_from_potentials(
+            ct.byref(cell), ct.byref(b), naux, self._pts_in.ctypes.data_as(ct.POINTER(ct.c_int64)), int(precision),
+            _ptr(V), ng, _ptr(W), naux, PTRS_DEVICE if dev else PTRS_HOST, _stream_handle(stream), ct.byref(h)))
+        self._finish(h)
+        return self
 
     @classmethod
     def from_workload(cls, w, **kw):

@@ -9,6 +9,8 @@
 // (64 x 64 tiles); products with at most 16 columns use 4 x 1 waves of 32 x 16.
 // K advances in steps of 16 through LDS, stored k-major so that both operand
 // fetches of the MFMA read consecutive addresses across the 16 lanes of a row.
+#include <stdlib.h>
+
 #include "mfma.h"
 #include "rps_internal.h"
 
@@ -402,6 +404,201 @@ __global__ __launch_bounds__(256, 2) void gemm32_kernel(Gemm32 g) {
       }
 }
 
+// FP32 products with 16-byte operand traffic.  Same outputs and tiling as
+// gemm32_kernel (2 x 2 waves of (16*TM) x (16*TN), FP32 sums over 64 terms of K
+// then FP64), but every operand moves in 16-byte pieces: float4 loads from global
+// memory, 16-byte LDS stores, and 16-byte LDS reads where K is the contiguous
+// dimension.  Each operand tile keeps the storage order it has in global memory:
+//   K-major  ([mn][k], pitch BK + 4): op(A) with TA = false, op(B) with TB = true;
+//   MN-major ([k][mn], pitch BMN + 4): op(A) with TA = true, op(B) with TB = false.
+// The matrix-core step kk (0..3) of a 16-wide K slice h takes from lane group
+// q = lane / 16 the element k = 16 h + 4 q + kk (a fixed permutation of K that
+// both operands share, so the products are the same sums), which makes the four
+// values a lane needs from a K-major tile one 16-byte read.  The pitches keep the
+// reads of a wave off shared banks: K-major rows are BK + 4 = 20 floats apart, so
+// eight consecutive rows cover the 32 banks once; MN-major row groups 4 rows apart
+// are 16 banks apart.  The 16-byte stores are conflict-free for MN-major tiles and
+// at most two-way for K-major ones.
+// Requires lda, ldb (and ldd for OUT32) multiples of 4 and 16-byte aligned bases.
+template <int TM, int TN, bool TA, bool TB, bool OUT32, int BK>
+__global__ __launch_bounds__(256, 2) void gemm32v_kernel(Gemm32 g) {
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  constexpr int PKM = BK + 4;                      // K-major pitch
+  constexpr int PAM = BM + 4, PBM = BN + 4;        // MN-major pitches
+  constexpr int ASZ = TA ? BK * PAM : BM * PKM;
+  constexpr int BSZ = TB ? BN * PKM : BK * PBM;
+  constexpr int NA4 = BM * BK / 4 / 256, NB4 = BN * BK / 4 / 256;   // float4 per thread per step
+  __shared__ __attribute__((aligned(16))) float As[2][ASZ];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BSZ];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int bz = blockIdx.z;
+  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+
+  int64_t kbeg = 0, kend = g.K;
+  if (g.splitk > 1) {
+    const int64_t per = ((g.K + g.splitk - 1) / g.splitk + BK - 1) / BK * BK;
+    kbeg = (int64_t)bz * per;
+    kend = (kbeg + per < g.K) ? kbeg + per : g.K;
+  }
+  const int64_t nk = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
+  const bool interior = (m0 + BM <= g.M) && (n0 + BN <= g.N);
+  const int lda = (int)g.lda, ldb = (int)g.ldb;
+
+  f4_t ra[NA4], rb[NB4];
+  // piece i of a thread: row r = e / (C / 4), 4 columns from c = 4 (e % (C / 4)),
+  // e = tid + 256 i, C the contiguous extent of the tile in global memory
+  auto load = [&](int64_t k0) {
+    const bool full = interior && (k0 + BK <= kend);
+    const int64_t kc = (k0 < kend) ? k0 : kbeg;       // keeps the base in bounds past the last step
+    const float* ba = g.A + (TA ? kc * g.lda + m0 : m0 * g.lda + kc);
+    const float* bb = g.B + (TB ? n0 * g.ldb + kc : kc * g.ldb + n0);
+#pragma unroll
+    for (int i = 0; i < NA4; ++i) {
+      const int e = tid + 256 * i;
+      constexpr int CW = (TA ? BM : BK) / 4;
+      const int r = e / CW, c = 4 * (e % CW);
+      const float* src = ba + r * lda + c;
+      if (full) {
+        ra[i] = *reinterpret_cast<const f4_t*>(src);
+      } else {
+        // rows: m (TA = false) or k (TA = true); columns: the other
+        const int64_t rm = TA ? k0 + r : m0 + r, rlim = TA ? kend : g.M;
+        const int64_t cm = TA ? m0 + c : k0 + c, clim = TA ? g.M : kend;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ra[i][j] = (rm < rlim && cm + j < clim) ? src[j] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB4; ++i) {
+      const int e = tid + 256 * i;
+      constexpr int CW = (TB ? BK : BN) / 4;
+      const int r = e / CW, c = 4 * (e % CW);
+      const float* src = bb + r * ldb + c;
+      if (full) {
+        rb[i] = *reinterpret_cast<const f4_t*>(src);
+      } else {
+        const int64_t rn = TB ? n0 + r : k0 + r, rlim = TB ? g.N : kend;
+        const int64_t cn = TB ? k0 + c : n0 + c, clim = TB ? kend : g.N;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) rb[i][j] = (rn < rlim && cn + j < clim) ? src[j] : 0.f;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < NA4; ++i) {
+      const int e = tid + 256 * i;
+      constexpr int CW = (TA ? BM : BK) / 4;
+      const int r = e / CW, c = 4 * (e % CW);
+      *reinterpret_cast<f4_t*>(&As[buf][r * (TA ? PAM : PKM) + c]) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NB4; ++i) {
+      const int e = tid + 256 * i;
+      constexpr int CW = (TB ? BK : BN) / 4;
+      const int r = e / CW, c = 4 * (e % CW);
+      *reinterpret_cast<f4_t*>(&Bs[buf][r * (TB ? PKM : PBM) + c]) = rb[i];
+    }
+  };
+
+  f4_t acc[TM][TN];
+  constexpr int FLUSH = OUT32 ? (1 << 30) : 64 / BK;   // FP64 output: FP32 sums over 64 terms of K
+  double acc64[OUT32 ? 1 : TM][OUT32 ? 1 : TN][4];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = zero_f4();
+  if constexpr (!OUT32) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
+  }
+
+  if (nk > 0) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t t0 = 0; t0 < nk; t0 += FLUSH) {
+    const int64_t t1 = (t0 + FLUSH < nk) ? t0 + FLUSH : nk;
+    for (int64_t t = t0; t < t1; ++t) {
+      load(kbeg + (t + 1) * BK);
+      const float* as = As[t & 1];
+      const float* bs = Bs[t & 1];
+#pragma unroll
+      for (int h = 0; h < BK / 16; ++h) {
+        f4_t a[TM], b[TN];      // a[i][kk]: operand of step kk for row block i
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          const int m = wm * 16 * TM + i * 16 + l16;
+          if constexpr (TA) {
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) a[i][kk] = as[(16 * h + 4 * lq + kk) * PAM + m];
+          } else {
+            a[i] = *reinterpret_cast<const f4_t*>(&as[m * PKM + 16 * h + 4 * lq]);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int n = wn * 16 * TN + j * 16 + l16;
+          if constexpr (TB) {
+            b[j] = *reinterpret_cast<const f4_t*>(&bs[n * PKM + 16 * h + 4 * lq]);
+          } else {
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) b[j][kk] = bs[(16 * h + 4 * lq + kk) * PBM + n];
+          }
+        }
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = mfma_f32(a[i][kk], b[j][kk], acc[i][j]);
+      }
+      store((t + 1) & 1);
+      __syncthreads();
+    }
+    if constexpr (!OUT32) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[i][j][r];
+          acc[i][j] = zero_f4();
+        }
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = m0 + wm * 16 * TM + i * 16 + d32_row(lane, r);
+        const int64_t gn = n0 + wn * 16 * TN + j * 16 + l16;
+        if (gm < g.M && gn < g.N) {
+          if constexpr (OUT32) {
+            g.C32[gm * g.ldc + gn] = g.D32[gm * g.ldd + gn] * ((float)g.alpha * acc[i][j][r]);
+          } else {
+            const double v = g.alpha * acc64[i][j][r];
+            if (g.splitk > 1) {
+              g.work[((int64_t)bz * g.M + gm) * g.N + gn] = v;
+              continue;
+            }
+            double* c = g.C + gm * g.ldc + gn;
+            *c = (g.beta == 0.0) ? v : v + g.beta * *c;
+          }
+        }
+      }
+}
+
 template <int TM, int TN, bool TA, bool TB, bool KS = false>
 __global__ __launch_bounds__(256, 2) void gemm_big_kernel(Gemm g) {
   gemm_big_body<TM, TN, TA, TB, KS>(g, (int64_t)blockIdx.y * 32 * TM, (int64_t)blockIdx.x * 32 * TN, blockIdx.z);
@@ -494,6 +691,27 @@ void launch32(const Gemm32& g, dim3 grid, hipStream_t s) {
   else if (!g.transA && g.transB) hipLaunchKernelGGL((gemm32_kernel<4, TN, false, true, OUT32>), grid, dim3(256), 0, s, g);
   else hipLaunchKernelGGL((gemm32_kernel<4, TN, true, true, OUT32>), grid, dim3(256), 0, s, g);
 }
+template <int TN, bool OUT32, int BK>
+void launch32v_bk(const Gemm32& g, dim3 grid, hipStream_t s) {
+  if (!g.transA && !g.transB) hipLaunchKernelGGL((gemm32v_kernel<4, TN, false, false, OUT32, BK>), grid, dim3(256), 0, s, g);
+  else if (g.transA && !g.transB) hipLaunchKernelGGL((gemm32v_kernel<4, TN, true, false, OUT32, BK>), grid, dim3(256), 0, s, g);
+  else if (!g.transA && g.transB) hipLaunchKernelGGL((gemm32v_kernel<4, TN, false, true, OUT32, BK>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((gemm32v_kernel<4, TN, true, true, OUT32, BK>), grid, dim3(256), 0, s, g);
+}
+// K steps of 16: at the 3x3x3 cell's chunk shapes they measured 102-110 TF/s against
+// 98-106 TF/s with steps of 32 (twice the LDS and prefetch registers per workgroup)
+template <int TN, bool OUT32>
+void launch32v(const Gemm32& g, dim3 grid, hipStream_t s) {
+  launch32v_bk<TN, OUT32, 16>(g, grid, s);
+}
+// 16-byte operand traffic needs 4-float aligned rows and bases
+bool vec4_ok(const Gemm32& g) {
+  auto al = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
+  if (g.lda % 4 || g.ldb % 4 || !al(g.A) || !al(g.B)) return false;
+  if (g.C32 && (g.ldd % 4 || !al(g.D32))) return false;
+  const char* v = getenv("RPS_GEMM32_SCALAR");     // comparison runs: the scalar-traffic kernel
+  return !(v && v[0] == '1');
+}
 }  // namespace
 
 int gemm32_tile_n(int64_t N) {
@@ -515,10 +733,12 @@ hipError_t gemm_f32(const Gemm32& g0, hipStream_t s) {
   const int bn = out32 ? gemm32_tile_n(g.N) : 64;
   dim3 grid((unsigned)((g.N + bn - 1) / bn), (unsigned)((g.M + 127) / 128), (unsigned)g.splitk);
   if (grid.y > 65535u) return hipErrorInvalidValue;
+  const bool vec = vec4_ok(g);
   if (bn == 64) {
-    if (out32) launch32<2, true>(g, grid, s); else launch32<2, false>(g, grid, s);
+    if (vec) { if (out32) launch32v<2, true>(g, grid, s); else launch32v<2, false>(g, grid, s); }
+    else { if (out32) launch32<2, true>(g, grid, s); else launch32<2, false>(g, grid, s); }
   } else {
-    launch32<4, true>(g, grid, s);
+    if (vec) launch32v<4, true>(g, grid, s); else launch32<4, true>(g, grid, s);
   }
   if (g.splitk > 1) {
     const int64_t cnt = g.M * g.N;

@@ -494,8 +494,20 @@ double* scratch_device_ptr() {
   return g_scratch_ptr[dev];
 }
 
+// Set-up products supplied by the caller (rps_setup_isdf_from_potentials): V in the
+// context's storage precision (FP64, or FP32 for the precision forms) and W, with
+// their row pitches, as host or device pointers.
+struct GivenFit {
+  const void* V = nullptr;
+  int64_t ldv = 0;
+  const double* W = nullptr;
+  int64_t ldw = 0;
+  bool device = false;
+};
+
 void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_t n_aux, uint64_t seed,
-                int32_t mode, int32_t prec, const int64_t* points_in, double basis_eps, hipStream_t st) {
+                int32_t mode, int32_t prec, const int64_t* points_in, double basis_eps, hipStream_t st,
+                const GivenFit* given = nullptr) {
   auto t0 = std::chrono::steady_clock::now();
   StageLog stage;
   // ---- validation
@@ -533,6 +545,12 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
   c.ngp = round_up(c.ng, 64);
   c.Np = round_up(c.nbas, 16);
   c.nauxp = round_up(c.naux, 64);
+  if (given) {
+    if (!points_in) fail(RPS_ERR_ARG, "set-up from given potentials needs points_in");
+    if (!given->V || !given->W) fail(RPS_ERR_ARG, "V and W must not be NULL");
+    if (given->ldv < c.ng || given->ldw < n_aux) fail(RPS_ERR_SHAPE, "ldv must be >= N_g and ldw >= n_aux");
+    if (c.exact) fail(RPS_ERR_SHAPE, "n_aux == N_g is the exact case (chi = identity); use rps_setup_isdf");
+  }
   if (points_in) {
     std::vector<char> seen(c.ng, 0);
     for (int64_t g = 0; g < n_aux; ++g) {
@@ -544,9 +562,9 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
   }
   // ---- memory estimate before any allocation
   {
-    const double persist = 8.0 * ((double)c.ngp * c.Np + (double)c.nauxp * c.Np + (double)c.nauxp * c.ngp +
-                                  (double)c.nauxp * c.nauxp) +
-                           ((prec != RPS_PREC_FP64) ? 4.0 * (double)c.nauxp * c.ngp : 0.0);
+    const double vbytes = (given && prec != RPS_PREC_FP64) ? 0.0 : 8.0 * (double)c.nauxp * c.ngp;
+    const double persist = 8.0 * ((double)c.ngp * c.Np + (double)c.nauxp * c.Np + (double)c.nauxp * c.nauxp) +
+                           vbytes + ((prec != RPS_PREC_FP64) ? 4.0 * (double)c.nauxp * c.ngp : 0.0);
     const double xgg = 8.0 * 3.0 * (double)c.nauxp * c.nauxp;   // L, T and its transpose
     const double xblk = 8.0 * (double)c.nauxp * (double)kWBlock;
     double selb = 0.0;
@@ -556,7 +574,7 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
       const double nmax = std::max(ncand, kap);
       selb = 8.0 * (nmax * nmax + nmax * (double)c.naux + nmax * (double)c.Np);
     }
-    const double need = persist + std::max(xgg + xblk, selb) + 64.0 * 1024 * 1024;
+    const double need = persist + (given ? 0.0 : std::max(xgg + xblk, selb)) + 64.0 * 1024 * 1024;
     size_t fr = 0, tot = 0;
     hip_check(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
     if (need > (double)fr)
@@ -597,8 +615,11 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
   hip_check(hipMemcpyAsync(c.dpoints.p, c.points.data(), c.naux * 8, hipMemcpyHostToDevice, st), "copy points");
   c.Phig.alloc(c.nauxp * c.Np, &c.bytes);
   hip_check(gather_rows(c.Phi.p, c.Np, c.dpoints.p, c.naux, c.nauxp, c.Np, c.Phig.p, c.Np, st), "gather");
-  c.V.alloc(c.nauxp * c.ngp, &c.bytes);
-  hip_check(fill(c.V.p, c.nauxp * c.ngp, 0.0, st), "fill");
+  const bool given32 = given && prec != RPS_PREC_FP64;   // caller's V goes straight into the FP32 store
+  if (!given32) {
+    c.V.alloc(c.nauxp * c.ngp, &c.bytes);
+    hip_check(fill(c.V.p, c.nauxp * c.ngp, 0.0, st), "fill");
+  }
   c.W.alloc(c.nauxp * c.nauxp, &c.bytes);
   hip_check(fill(c.W.p, c.nauxp * c.nauxp, 0.0, st), "fill");
   std::vector<double> kern = coulomb_kernel_table(c.lat, c.mesh);
@@ -607,7 +628,23 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
   int64_t tmpb = 0;
   hip_check(hipMemcpyAsync(c.kern.p, kern.data(), c.ng * 8, hipMemcpyHostToDevice, st), "copy kernel");
 
-  if (c.exact) {
+  if (given) {
+    // rows of the caller's V and W into the padded device arrays (padding stays zero)
+    const hipMemcpyKind kind = given->device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (given32) {
+      c.V32.alloc(c.nauxp * c.ngp, &c.bytes);
+      hip_check(hipMemsetAsync(c.V32.p, 0, (size_t)c.nauxp * c.ngp * 4, st), "clear V32");
+      hip_check(hipMemcpy2DAsync(c.V32.p, c.ngp * 4, given->V, given->ldv * 4, c.ng * 4, c.naux, kind, st),
+                "copy V");
+    } else {
+      hip_check(hipMemcpy2DAsync(c.V.p, c.ngp * 8, given->V, given->ldv * 8, c.ng * 8, c.naux, kind, st),
+                "copy V");
+    }
+    hip_check(hipMemcpy2DAsync(c.W.p, c.nauxp * 8, given->W, given->ldw * 8, c.naux * 8, c.naux, kind, st),
+              "copy W");
+    hip_check(hipStreamSynchronize(st), "sync");
+    stage("given potentials", st);
+  } else if (c.exact) {
     // chi = identity on the chosen order: V[g] = Vc e_{points[g]}, W[g][g'] = V[g][points[g']]
     hip_check(set_unit_rows(c.V.p, c.ngp, c.dpoints.p, c.naux, st), "unit rows");
     hip_check(poisson_rows(c.V.p, c.nauxp, c.ngp, c.mesh, dkern, st), "poisson");
@@ -706,10 +743,12 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
   }
   hip_check(hipStreamSynchronize(st), "sync");
   if (prec != RPS_PREC_FP64) {
-    c.V32.alloc(c.nauxp * c.ngp, &c.bytes);
-    hip_check(to_f32(c.V.p, c.nauxp * c.ngp, c.V32.p, st), "to f32");
-    hip_check(hipStreamSynchronize(st), "sync");
-    c.V.release(&c.bytes);      // the precision form keeps only the FP32 copy of V
+    if (!given32) {
+      c.V32.alloc(c.nauxp * c.ngp, &c.bytes);
+      hip_check(to_f32(c.V.p, c.nauxp * c.ngp, c.V32.p, st), "to f32");
+      hip_check(hipStreamSynchronize(st), "sync");
+      c.V.release(&c.bytes);      // the precision form keeps only the FP32 copy of V
+    }
     const char* fu = getenv("RPS_F32_FUSED_U");
     if (c.Np <= 128 && !(fu && fu[0] == '0')) {
       c.Phi32.alloc(c.ngp * c.Np, &c.bytes);
@@ -1955,6 +1994,26 @@ rps_status rps_setup_isdf_screened(const rps_cell* cell, const rps_basis* basis,
     try {
       setup_impl(*c, cell, basis, n_aux, seed, select_mode, precision, points_in, basis_eps,
                  (hipStream_t)hip_stream);
+    } catch (...) {
+      delete c;
+      throw;
+    }
+    *out = c;
+  });
+}
+
+rps_status rps_setup_isdf_from_potentials(const rps_cell* cell, const rps_basis* basis, int64_t n_aux,
+                                          const int64_t* points, int32_t precision, const void* V, int64_t ldv,
+                                          const double* W, int64_t ldw, int32_t flags, void* hip_stream,
+                                          rps_context** out) {
+  return guarded([&] {
+    if (!out) fail(RPS_ERR_ARG, "out must not be NULL");
+    if (flags != RPS_PTRS_HOST && flags != RPS_PTRS_DEVICE) fail(RPS_ERR_ARG, "flags must be RPS_PTRS_HOST or RPS_PTRS_DEVICE");
+    GivenFit gf;
+    gf.V = V; gf.ldv = ldv; gf.W = W; gf.ldw = ldw; gf.device = (flags == RPS_PTRS_DEVICE);
+    rps_context* c = new rps_context();
+    try {
+      setup_impl(*c, cell, basis, n_aux, 0, RPS_SELECT_VORONOI, precision, points, 0.0, (hipStream_t)hip_stream, &gf);
     } catch (...) {
       delete c;
       throw;

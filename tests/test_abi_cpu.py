@@ -217,3 +217,44 @@ def test_binding_checks_torch_tensors():
     B._check_array(torch.zeros((5, 2), dtype=torch.float64), (5, 2), "C")
     with pytest.raises(ValueError):                   # a host array where a device tensor is needed
         B._check_array(K, (5, 2), "K", torch.device("cpu"))
+
+
+def _from_pot_status(naux=10, points=True, ldv=None, ldw=None, V=True, W=True, flags=0, exact=False):
+    lib = P.load()
+    cell = B.Cell()
+    cell.lattice[:] = list(np.eye(3).reshape(9) * 5.0)
+    cell.mesh[:] = [8, 8, 8]
+    atoms = np.array([[0.0, 0, 0], [2.0, 2, 2]])
+    sa = np.array([0, 1], dtype=np.int32)
+    sl = np.array([0, 1], dtype=np.int32)
+    se = np.array([1.0, 0.7])
+    b = B.Basis(2, 2, atoms.ctypes.data_as(ct.POINTER(ct.c_double)), sa.ctypes.data_as(ct.POINTER(ct.c_int32)),
+                sl.ctypes.data_as(ct.POINTER(ct.c_int32)), se.ctypes.data_as(ct.POINTER(ct.c_double)))
+    if exact:
+        naux = 512
+    pts = np.arange(naux, dtype=np.int64)
+    Vh = np.zeros((naux, 512))
+    Wh = np.zeros((naux, naux))
+    h = ct.c_void_p()
+    st = lib.rps_setup_isdf_from_potentials(ct.byref(cell), ct.byref(b), naux,
+                                            pts.ctypes.data_as(ct.POINTER(ct.c_int64)) if points else None, 0,
+                                            Vh.ctypes.data if V else None, 512 if ldv is None else ldv,
+                                            Wh.ctypes.data if W else None, naux if ldw is None else ldw, flags, None,
+                                            ct.byref(h))
+    return st, lib.rps_last_error().decode(), h
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(points=False), B.RPS_ERR_ARG),
+    (dict(V=False), B.RPS_ERR_ARG),
+    (dict(W=False), B.RPS_ERR_ARG),
+    (dict(ldv=511), B.RPS_ERR_SHAPE),
+    (dict(ldw=9), B.RPS_ERR_SHAPE),
+    (dict(flags=5), B.RPS_ERR_ARG),
+    (dict(exact=True), B.RPS_ERR_SHAPE),
+])
+def test_setup_from_potentials_rejects_bad_arguments(kw, status):
+    """The set-up from given potentials checks its arguments before any device call."""
+    st, msg, h = _from_pot_status(**kw)
+    assert st == status, msg
+    assert msg and h.value is None

@@ -240,3 +240,29 @@ def test_build_arith_reported(lib, refs):
         K, E = ctx.build(C)
         assert ctx.info()["build_arith"] == lib.PREC_FP32
     assert abs(E - Eref) < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_setup_from_potentials_matches_setup(lib, refs, prec):
+    """rps_setup_isdf_from_potentials given the V and W a regular set-up made
+    (host arrays, then device tensors) builds exactly what that set-up builds;
+    the FP32 form is given V rounded to FP32 as its store holds it."""
+    import torch
+    w, pts, C, Kref, Eref = refs[0]
+    p = lib.PREC_FP64 if prec == "fp64" else lib.PREC_FP32
+    _say(f"case: set-up from given potentials, {prec}, {w.name}")
+    with lib.Context.from_workload(w, points=pts) as c64:
+        V = c64.array(1)
+        W = c64.array(2)
+    with lib.Context.from_workload(w, points=pts, precision=p) as ref:
+        K0, E0 = ref.build(C)
+    Vg = V if p == lib.PREC_FP64 else V.astype(np.float32)
+    for dev in (False, True):
+        Vin = torch.from_numpy(Vg).cuda() if dev else Vg
+        Win = torch.from_numpy(W).cuda() if dev else W
+        with lib.Context.from_potentials(w, pts, Vin, Win, precision=p) as ctx:
+            assert np.array_equal(ctx.points(), pts)
+            K1, E1 = ctx.build(C)
+        _say(f"  {'device' if dev else 'host'} inputs: dE={E1 - E0:.3e} dK={_kerr(K1, K0):.3e}")
+        assert np.array_equal(K1, K0) and E1 == E0
+    assert abs(E0 - Eref) < (1e-8 if p == lib.PREC_FP64 else 1e-6)
