@@ -433,14 +433,29 @@ __global__ __launch_bounds__(256, 2) void gemm32v_kernel(Gemm32 g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int l16 = lane & 15, lq = lane >> 4;
-  const int bz = blockIdx.z;
-  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+  // Tile order (1-D grid).  Workgroups go to the eight XCDs in turn (workgroup L to
+  // XCD L % 8), and each XCD has its own L2, so XCD j takes the contiguous range
+  // [j per, (j + 1) per) of the tile sequence; in that sequence the K splits are
+  // outermost and the output tiles run in groups of GROUP row panels, column by
+  // column, so that the tiles an XCD has in flight share their row panels (A) and
+  // column panels (B) in its L2.
+  const int64_t tiles_n = (g.N + BN - 1) / BN, tiles_m = (g.M + BM - 1) / BM;
+  const int64_t ntile = tiles_n * tiles_m * g.splitk;
+  const int64_t per = ((ntile + 7) / 8);
+  const int64_t T = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (T >= ntile) return;
+  constexpr int64_t GROUP = 8;
+  const int bz = (int)(T / (tiles_n * tiles_m));
+  const int64_t T2 = T % (tiles_n * tiles_m);
+  const int64_t grp = T2 / (GROUP * tiles_n), r2 = T2 % (GROUP * tiles_n);
+  const int64_t gh = (tiles_m - grp * GROUP < GROUP) ? tiles_m - grp * GROUP : GROUP;
+  const int64_t m0 = (grp * GROUP + r2 % gh) * BM, n0 = (r2 / gh) * BN;
 
   int64_t kbeg = 0, kend = g.K;
   if (g.splitk > 1) {
-    const int64_t per = ((g.K + g.splitk - 1) / g.splitk + BK - 1) / BK * BK;
-    kbeg = (int64_t)bz * per;
-    kend = (kbeg + per < g.K) ? kbeg + per : g.K;
+    const int64_t kper = ((g.K + g.splitk - 1) / g.splitk + BK - 1) / BK * BK;
+    kbeg = (int64_t)bz * kper;
+    kend = (kbeg + kper < g.K) ? kbeg + kper : g.K;
   }
   const int64_t nk = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
   const bool interior = (m0 + BM <= g.M) && (n0 + BN <= g.N);
@@ -734,11 +749,16 @@ hipError_t gemm_f32(const Gemm32& g0, hipStream_t s) {
   dim3 grid((unsigned)((g.N + bn - 1) / bn), (unsigned)((g.M + 127) / 128), (unsigned)g.splitk);
   if (grid.y > 65535u) return hipErrorInvalidValue;
   const bool vec = vec4_ok(g);
+  // the 16-byte kernel orders its tiles itself: one dimension, padded to whole rounds
+  // of the eight XCDs (the padding workgroups exit at once)
+  const int64_t ntile = (int64_t)grid.x * grid.y * grid.z;
+  const dim3 grid1((unsigned)((ntile + 7) / 8 * 8));
+  if (vec && ntile > (int64_t)UINT32_MAX - 8) return hipErrorInvalidValue;
   if (bn == 64) {
-    if (vec) { if (out32) launch32v<2, true>(g, grid, s); else launch32v<2, false>(g, grid, s); }
+    if (vec) { if (out32) launch32v<2, true>(g, grid1, s); else launch32v<2, false>(g, grid1, s); }
     else { if (out32) launch32<2, true>(g, grid, s); else launch32<2, false>(g, grid, s); }
   } else {
-    if (vec) launch32v<4, true>(g, grid, s); else launch32<4, true>(g, grid, s);
+    if (vec) launch32v<4, true>(g, grid1, s); else launch32<4, true>(g, grid, s);
   }
   if (g.splitk > 1) {
     const int64_t cnt = g.M * g.N;
