@@ -420,6 +420,18 @@ __global__ __launch_bounds__(256, 2) void gemm32_kernel(Gemm32 g) {
 // are 16 banks apart.  The 16-byte stores are conflict-free for MN-major tiles and
 // at most two-way for K-major ones.
 // Requires lda, ldb (and ldd for OUT32) multiples of 4 and 16-byte aligned bases.
+// Row of a K-major tile filled by piece row q.  With 16-wide K steps four
+// consecutive lanes fill one row (16 floats), so eight lanes fill two rows; rows
+// 4 apart sit 80 = 16 (mod 32) banks apart, so pairing q = 2t, 2t + 1 with rows
+// 4 apart puts the eight lanes' 16-byte stores on distinct banks (rows next to
+// each other would share four).  A bijection on every block of eight rows.
+template <int CW>
+__device__ __forceinline__ int kmajor_row(int q) {
+  if constexpr (CW != 4) return q;
+  const int t = q >> 1;
+  return ((t >> 2) << 3) + (t & 3) + ((q & 1) << 2);
+}
+
 template <int TM, int TN, bool TA, bool TB, bool OUT32, int BK>
 __global__ __launch_bounds__(256, 2) void gemm32v_kernel(Gemm32 g) {
   constexpr int BM = 32 * TM, BN = 32 * TN;
@@ -473,7 +485,7 @@ __global__ __launch_bounds__(256, 2) void gemm32v_kernel(Gemm32 g) {
     for (int i = 0; i < NA4; ++i) {
       const int e = tid + 256 * i;
       constexpr int CW = (TA ? BM : BK) / 4;
-      const int r = e / CW, c = 4 * (e % CW);
+      const int r = TA ? e / CW : kmajor_row<CW>(e / CW), c = 4 * (e % CW);
       const float* src = ba + r * lda + c;
       if (full) {
         ra[i] = *reinterpret_cast<const f4_t*>(src);
@@ -489,7 +501,7 @@ __global__ __launch_bounds__(256, 2) void gemm32v_kernel(Gemm32 g) {
     for (int i = 0; i < NB4; ++i) {
       const int e = tid + 256 * i;
       constexpr int CW = (TB ? BK : BN) / 4;
-      const int r = e / CW, c = 4 * (e % CW);
+      const int r = TB ? kmajor_row<CW>(e / CW) : e / CW, c = 4 * (e % CW);
       const float* src = bb + r * ldb + c;
       if (full) {
         rb[i] = *reinterpret_cast<const f4_t*>(src);
@@ -506,14 +518,14 @@ __global__ __launch_bounds__(256, 2) void gemm32v_kernel(Gemm32 g) {
     for (int i = 0; i < NA4; ++i) {
       const int e = tid + 256 * i;
       constexpr int CW = (TA ? BM : BK) / 4;
-      const int r = e / CW, c = 4 * (e % CW);
+      const int r = TA ? e / CW : kmajor_row<CW>(e / CW), c = 4 * (e % CW);
       *reinterpret_cast<f4_t*>(&As[buf][r * (TA ? PAM : PKM) + c]) = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < NB4; ++i) {
       const int e = tid + 256 * i;
       constexpr int CW = (TB ? BK : BN) / 4;
-      const int r = e / CW, c = 4 * (e % CW);
+      const int r = TB ? kmajor_row<CW>(e / CW) : e / CW, c = 4 * (e % CW);
       *reinterpret_cast<f4_t*>(&Bs[buf][r * (TB ? PKM : PBM) + c]) = rb[i];
     }
   };
