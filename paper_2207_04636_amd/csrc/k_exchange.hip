@@ -681,9 +681,10 @@ __global__ __launch_bounds__(NW * 64) void fused_f32_kernel(FusedArgs a) {
 // Precision form, n <= 16, with the orbitals formed tile by tile in the kernel.
 // Per R tile (64 grid rows) the FP32 basis rows are staged in LDS once and serve
 // both ends of the tile:
-//   start: U = Phi C on the FP64 matrix cores (FP32 basis values, FP64 C),
-//          rounded to FP32 for the in-tile products (as U is in the form above);
-//   end:   K1 += Phi^T M1^T in FP64.
+//   start: U = Phi C on the FP32 matrix cores (FP32 basis values, C rounded to
+//          FP32), the in-tile operand of the products below;
+//   end:   the eight waves' M1 partials summed in FP32, K1_tile = Phi^T M1^T on
+//          the FP32 matrix cores, added to an FP64 sum over the tiles.
 // The orbitals therefore never leave the chip and the basis is read once per
 // build in FP32.  Other choices, all for the latency of the V stream:
 //  * every wave steps through NMY g subtiles per tile (the workgroup's block of
