@@ -337,6 +337,62 @@ def scf_bench(args, w):
     print(json.dumps(out), flush=True)
 
 
+def cpu_table():
+    """The oracle timed on the host cores (no GPU): the rPS occ build (Eq. 16) at
+    the 24^3 cell, the 48^3 cell (c = 6), the 2x2x2 and 3x3x3 supercells, and
+    the conventional occ exchange (one Poisson solve per occupied pair, Sec. 2.4)
+    at the same cells.  rPS: full-shape seeded arrays where they fit (first two
+    cells; also on one core), grid slices extrapolated linearly beyond.
+    Conventional: the oracle run with 4 and 8 occupied orbitals (10 and 36 pair
+    solves) on the full grid, the time per pair from the difference, times
+    n (n + 1) / 2 pairs; the U = Phi C and K = Phi^T Y products it leaves out are
+    below 0.1% of the total at these sizes."""
+    import platform
+    import numpy as np
+    import rps_inputs as ri
+    from oracle import conventional
+    cpu = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    cells = [("24^3 cell (config 1)", ri.tiny_cell()), ("48^3 cell, c = 6 (config 2)", ri.diamond_cell(6.0)),
+             ("2x2x2 supercell (config 3)", ri.diamond_2x2x2()), ("3x3x3 supercell (config 4)", ri.diamond_3x3x3())]
+    out = {"cores": int(_blas_threads()), "cpu": cpu, "nproc": os.cpu_count(), "cells": []}
+    for name, w in cells:
+        print(f"[cpu-table] {name}", file=sys.stderr, flush=True)
+        row = {"cell": name, "workload": w.name}
+        if w.ngrid * w.naux <= 2e8:
+            row["rps"] = cpu_baseline(w, nrep=2)
+            if w.ngrid > 50000:
+                from threadpoolctl import threadpool_limits
+                with threadpool_limits(limits=1):
+                    one = cpu_baseline(w, nrep=1)
+                row["rps_one_core"] = {"value": one["value"], "unit": "builds/s"}
+        else:
+            row["rps"] = cpu_baseline_sliced(w)
+        rng = np.random.default_rng(5)
+        Phi = rng.random((w.ngrid, 8))
+        times = []
+        for nn in (4, 8):
+            C = rng.random((8, nn))
+            t0 = time.perf_counter()
+            conventional.exchange_occ(Phi, C, w.lattice, w.mesh)
+            times.append(time.perf_counter() - t0)
+        per_pair = (times[1] - times[0]) / (36 - 10)
+        npairs = w.nocc * (w.nocc + 1) // 2
+        full = per_pair * npairs
+        row["conventional"] = {"value": round(1.0 / full, 6), "unit": "builds/s", "seconds_per_build": round(full, 2),
+                               "pairs": npairs, "seconds_per_pair": round(per_pair, 5),
+                               "sample": f"oracle conventional.exchange_occ with 4 and 8 orbitals on the full "
+                                         f"{'x'.join(map(str, w.mesh))} grid: {times[0]:.2f} s and {times[1]:.2f} s"}
+        out["cells"].append(row)
+    print(json.dumps(out), flush=True)
+
+
 def synthetic_bench(args, w, mprec, run_steps, profile, nsets):
     """Build timing alone on seeded synthetic potentials (rps_setup_isdf_from_potentials):
     random grid points, V uniform in [0, 1e-3) in the stored FP32 form, W a random
@@ -527,10 +583,15 @@ def main():
                          "(no point selection, fit or FFT at set-up); for profiling the builds alone")
     ap.add_argument("--basis-eps", type=float, default=0.0,
                     help="screened basis (Sec. 4.1): drop pSinc coefficients below this eps1 (0 = dense)")
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="only time the oracle on the host cores (rPS build and conventional exchange at the "
+                         "24^3, 48^3, 2x2x2 and 3x3x3 cells) and print one JSON line; no GPU is used")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (three times) and exit: the reference "
                          "kernel that scales the HBM byte counters of a profiler run")
     args = ap.parse_args()
+    if args.cpu_table:
+        return cpu_table()
     if args.copy_calibration > 0:
         import torch
         nel = args.copy_calibration // 8
