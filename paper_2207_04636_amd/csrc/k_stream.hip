@@ -58,8 +58,9 @@ __host__ __device__ constexpr int stream_ldy() {
   return std::is_same<TM, float>::value ? 16 * NC + 4 : 16 * NC + 1;
 }
 
+// One work item of a pass: x block bx (16 NW rows) and y split by.
 template <typename TM, int NC, int TRANS, int NW>
-__global__ __launch_bounds__(NW * 64) void stream_kernel(StreamArgs a) {
+__device__ __forceinline__ void stream_body(const StreamArgs& a, int64_t bx, int64_t by, unsigned char* smem_raw) {
   using F = Frag<TM>;
   using acc_t = typename F::acc;
   constexpr bool F64 = std::is_same<TM, double>::value;
@@ -68,15 +69,14 @@ __global__ __launch_bounds__(NW * 64) void stream_kernel(StreamArgs a) {
   constexpr int LDY = stream_ldy<TM, NC>();
   constexpr int PER = BY * NP / (NW * 64);   // staged Y elements per thread
   static_assert(PER * NW * 64 == BY * NP, "tile split");
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   TM* sY = reinterpret_cast<TM*>(smem_raw);
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
-  const int64_t x0 = ((int64_t)blockIdx.x * NW + w) * 16;
+  const int64_t x0 = (bx * NW + w) * 16;
   const bool xvalid = x0 < a.nx;
   const int64_t xrow = xvalid ? x0 : a.nx - 16;   // rows read by a wave past the end (discarded)
-  const int64_t ys = (int64_t)blockIdx.y * a.ysplit;
+  const int64_t ys = by * a.ysplit;
   const int64_t ye = (ys + a.ysplit < a.ny) ? ys + a.ysplit : a.ny;
   const int64_t ntile = (ye > ys) ? (ye - ys) / BY : 0;
 
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(NW * 64) void stream_kernel(StreamArgs a) {
   }
 
   if (!xvalid) return;
-  double* out = a.out + ((int64_t)blockIdx.y * a.nx) * a.np;
+  double* out = a.out + (by * a.nx) * a.np;
 #pragma unroll
   for (int cb = 0; cb < NC; ++cb)
 #pragma unroll
@@ -221,6 +221,37 @@ __global__ __launch_bounds__(NW * 64) void stream_kernel(StreamArgs a) {
       else v = od[cb][r];
       out[x * a.np + 16 * cb + l16] = v;
     }
+}
+
+
+template <typename TM, int NC, int TRANS, int NW>
+__global__ __launch_bounds__(NW * 64) void stream_kernel(StreamArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  stream_body<TM, NC, TRANS, NW>(a, blockIdx.x, blockIdx.y, smem_raw);
+}
+
+// Persistent form for the batching form: the work items of one pass class
+// (precision, n, orientation) over many cells, taken from a device queue in
+// list order (longest first) until it runs dry; every workgroup ends when the
+// counter passes the last item.  items[i] = (cell, x block, y split) and
+// args[cell] the cell's pass; *counter is zero at launch.
+template <typename TM, int NC, int TRANS, int NW>
+__global__ __launch_bounds__(NW * 64) void stream_queue_kernel(const StreamArgs* __restrict__ args,
+                                                              const StreamItem* __restrict__ items, int nitems,
+                                                              unsigned* __restrict__ counter) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_item;
+  while (true) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int i = s_item;
+    __syncthreads();
+    if (i >= nitems) break;
+    const StreamItem it = items[i];
+    const StreamArgs a = args[it.cell];
+    stream_body<TM, NC, TRANS, NW>(a, it.bx, it.by, smem_raw);
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -262,21 +293,20 @@ struct Bf16Layout {
 };
 
 template <int NC, int TRANS, int NW>
-__global__ __launch_bounds__(NW * 64) void stream_bf16x3_kernel(StreamArgs a) {
+__device__ __forceinline__ void bf16x3_body(const StreamArgs& a, int64_t bx, int64_t by, unsigned char* smem_raw) {
   using L = Bf16Layout<NC>;
   constexpr int NP = L::NP, NKC = L::NKC, NPP = L::NPP, LR = L::LR, LT = L::LT;
   constexpr int SZR = L::SZR, SZT = L::SZT;
   constexpr int PER = BY * NP / (NW * 64);
   static_assert(PER * NW * 64 == BY * NP, "tile split");
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   __bf16* sm = reinterpret_cast<__bf16*>(smem_raw);
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
-  const int64_t x0 = ((int64_t)blockIdx.x * NW + w) * 16;
+  const int64_t x0 = (bx * NW + w) * 16;
   const bool xvalid = x0 < a.nx;
   const int64_t xrow = xvalid ? x0 : a.nx - 16;   // rows read by a wave past the end (discarded)
-  const int64_t ys = (int64_t)blockIdx.y * a.ysplit;
+  const int64_t ys = by * a.ysplit;
   const int64_t ye = (ys + a.ysplit < a.ny) ? ys + a.ysplit : a.ny;
   const int64_t ntile = (ye > ys) ? (ye - ys) / BY : 0;
 
@@ -453,11 +483,37 @@ __global__ __launch_bounds__(NW * 64) void stream_bf16x3_kernel(StreamArgs a) {
   }
 
   if (!xvalid) return;
-  double* out = a.out + ((int64_t)blockIdx.y * a.nx) * a.np;
+  double* out = a.out + (by * a.nx) * a.np;
 #pragma unroll
   for (int cb = 0; cb < NC; ++cb)
 #pragma unroll
     for (int r = 0; r < 4; ++r) out[(x0 + 4 * lq + r) * a.np + 16 * cb + l16] = od[cb][r];
+}
+
+template <int NC, int TRANS, int NW>
+__global__ __launch_bounds__(NW * 64) void stream_bf16x3_kernel(StreamArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  bf16x3_body<NC, TRANS, NW>(a, blockIdx.x, blockIdx.y, smem_raw);
+}
+
+// Persistent split-BF16 form (see stream_queue_kernel).
+template <int NC, int TRANS, int NW>
+__global__ __launch_bounds__(NW * 64) void bf16x3_queue_kernel(const StreamArgs* __restrict__ args,
+                                                              const StreamItem* __restrict__ items, int nitems,
+                                                              unsigned* __restrict__ counter) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_item;
+  while (true) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int i = s_item;
+    __syncthreads();
+    if (i >= nitems) break;
+    const StreamItem it = items[i];
+    const StreamArgs a = args[it.cell];
+    bf16x3_body<NC, TRANS, NW>(a, it.bx, it.by, smem_raw);
+    __syncthreads();
+  }
 }
 
 template <int NC, int TRANS>
@@ -529,13 +585,96 @@ int stream_splits(int64_t nx, int64_t ny, int target_blocks) {
   return (int)sp;
 }
 
-hipError_t stream_product(const StreamArgs& a, int prec, int nsplit, hipStream_t s) {
+hipError_t stream_prepare(const StreamArgs& a, int prec, int nsplit, StreamArgs& b) {
   if (a.np < 16 || a.np > 128 || a.np % 16 || a.nx % 16 || a.ny % BY || a.ldy != a.np) return hipErrorInvalidValue;
-  if (nsplit < 1) return hipErrorInvalidValue;
-  StreamArgs b = a;
+  if (nsplit < 1 || prec < 0 || prec > 2) return hipErrorInvalidValue;
+  if (prec == 0 ? !a.V : (!a.V32 || !a.Y32)) return hipErrorInvalidValue;
+  b = a;
   // y rows per split, a multiple of the tile
   const int64_t tiles = a.ny / BY;
   b.ysplit = ((tiles + nsplit - 1) / nsplit) * BY;
+  return hipSuccess;
+}
+
+int64_t stream_xblocks(int64_t nx) { return (nx + 127) / 128; }
+
+namespace {
+template <typename K>
+int resident_blocks(K kern, size_t lds) {
+  int per_cu = 0, dev = 0, cus = 0;
+  if (lds > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 512, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  return per_cu * cus;
+}
+
+template <typename TM, int NC, int TRANS>
+hipError_t queue_stream(const StreamArgs* args, const StreamItem* items, int nitems, unsigned* counter, int nblocks,
+                        hipStream_t s, int* resident) {
+  constexpr int NW = 8;
+  const size_t lds = (size_t)2 * BY * stream_ldy<TM, NC>() * sizeof(TM);
+  auto kern = stream_queue_kernel<TM, NC, TRANS, NW>;
+  if (resident) { *resident = resident_blocks(kern, lds); return hipSuccess; }
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(NW * 64), lds, s, args, items, nitems, counter);
+  return hipGetLastError();
+}
+
+template <int NC, int TRANS>
+hipError_t queue_bf16x3(const StreamArgs* args, const StreamItem* items, int nitems, unsigned* counter, int nblocks,
+                        hipStream_t s, int* resident) {
+  constexpr int NW = 8;
+  const size_t lds = (size_t)2 * Bf16Layout<NC>::BUF * 2;
+  auto kern = bf16x3_queue_kernel<NC, TRANS, NW>;
+  if (resident) { *resident = resident_blocks(kern, lds); return hipSuccess; }
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(NW * 64), lds, s, args, items, nitems, counter);
+  return hipGetLastError();
+}
+
+template <int TRANS>
+hipError_t queue_dispatch(int prec, int np, const StreamArgs* args, const StreamItem* items, int nitems,
+                          unsigned* counter, int nblocks, hipStream_t s, int* resident) {
+#define RPS_QCASE(NC_)                                                                                    \
+  case NC_:                                                                                               \
+    return prec == 0 ? queue_stream<double, NC_, TRANS>(args, items, nitems, counter, nblocks, s, resident) \
+         : prec == 1 ? queue_stream<float, NC_, TRANS>(args, items, nitems, counter, nblocks, s, resident)  \
+                     : queue_bf16x3<NC_, TRANS>(args, items, nitems, counter, nblocks, s, resident);
+  switch (np / 16) {
+    RPS_QCASE(1) RPS_QCASE(2) RPS_QCASE(3) RPS_QCASE(4) RPS_QCASE(5) RPS_QCASE(6) RPS_QCASE(7) RPS_QCASE(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef RPS_QCASE
+}
+}  // namespace
+
+int stream_queue_blocks(int prec, int np, int trans) {
+  int r = 0;
+  if (prec < 0 || prec > 2 || np < 16 || np > 128 || np % 16) return 0;
+  if (trans) (void)queue_dispatch<1>(prec, np, nullptr, nullptr, 0, nullptr, 0, nullptr, &r);
+  else (void)queue_dispatch<0>(prec, np, nullptr, nullptr, 0, nullptr, 0, nullptr, &r);
+  return r;
+}
+
+hipError_t stream_product_queue(const StreamArgs* args, const StreamItem* items, int nitems, int prec, int np,
+                                int trans, unsigned* counter, int nblocks, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  if (!args || !items || !counter || nblocks < 1 || prec < 0 || prec > 2) return hipErrorInvalidValue;
+  return trans ? queue_dispatch<1>(prec, np, args, items, nitems, counter, nblocks, s, nullptr)
+               : queue_dispatch<0>(prec, np, args, items, nitems, counter, nblocks, s, nullptr);
+}
+
+hipError_t stream_product(const StreamArgs& a, int prec, int nsplit, hipStream_t s) {
+  StreamArgs b;
+  const hipError_t pe = stream_prepare(a, prec, nsplit, b);
+  if (pe != hipSuccess) return pe;
   if (prec == 2) {
     if (!a.V32 || !a.Y32) return hipErrorInvalidValue;
     return a.trans ? dispatch_bf16x3<1>(b, nsplit, s) : dispatch_bf16x3<0>(b, nsplit, s);

@@ -8,6 +8,7 @@
 #include <cmath>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <exception>
 #include <new>
@@ -1061,10 +1062,36 @@ void sparse_k1(rps_context& c, const double* M1T, int np, double* K1, hipStream_
   hip_check(csr_rowsum(c.sK1p.p, np, c.smu_ofs.p, c.smu_rows.p, (int)c.nbas, (int)c.Np, K1, st), "K1 sums");
 }
 
-void build_general(rps_context& c, int variant, int nocc, const double* Csrc, double* Kout, double* exout,
-                   hipStream_t st, double s1, double s2, double s3, double ce1, double ce3) {
+// The streaming passes of a general-path build (one description, used by the eager
+// build and by the batching form's persistent launches alike).
+StreamArgs pass_m2(const rps_context& c, int np) {   // M2 = (V o P) U, x = interpolation points
+  StreamArgs m2;
+  m2.V = c.V.p; m2.V32 = c.V32.p; m2.ldv = c.ngp; m2.trans = 0;
+  m2.X = c.gUg.p; m2.ldx = np; m2.Y = c.gU.p; m2.Y32 = c.gU32.p; m2.ldy = np;
+  m2.nx = c.nauxp; m2.ny = c.ngp; m2.np = np; m2.out = c.gSp.p;
+  return m2;
+}
+StreamArgs pass_m1(const rps_context& c, int np) {   // M1^T = (V o P)^T U_g, x = grid points
+  StreamArgs m1;
+  m1.V = c.V.p; m1.V32 = c.V32.p; m1.ldv = c.ngp; m1.trans = 1;
+  m1.X = c.gU.p; m1.ldx = np; m1.Y = c.gUg.p; m1.Y32 = c.gUg32.p; m1.ldy = np;
+  m1.nx = c.ngp; m1.ny = c.nauxp; m1.np = np; m1.out = c.gM1T.p;
+  return m1;
+}
+StreamArgs pass_l3(const rps_context& c, int np, double* out) {   // Y = (W o P_g) U_g, FP64
+  StreamArgs l3;
+  l3.V = c.W.p; l3.ldv = c.nauxp; l3.trans = 0;
+  l3.X = c.gUg.p; l3.ldx = np; l3.Y = c.gUg.p; l3.ldy = np;
+  l3.nx = c.nauxp; l3.ny = c.nauxp; l3.np = np; l3.out = out;
+  return l3;
+}
+int pass_splits(const rps_context& c, const StreamArgs& a) {
+  return stream_splits(a.nx, a.ny, c.tune_target > 0 ? c.tune_target : kStreamBlocks);
+}
+
+// Before the passes: C packed, U = Phi C, U_g, and the FP32 copies the precision forms read.
+void general_pre(rps_context& c, int nocc, const double* Csrc, hipStream_t st, bool f32_copies) {
   const int np = (int)round_up(nocc, 16);
-  ensure_general(c, np);
   hip_check(pack_matrix(Csrc, c.nbas, nocc, nocc, c.gCp.p, c.Np, np, st), "pack C");
   if (c.sparse) {
     sparse_u(c, c.gCp.p, np, c.gU.p, st);
@@ -1075,10 +1102,21 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
     gemm_run(g, c, st, "U", false);
   }
   hip_check(gather_rows(c.gU.p, np, c.dpoints.p, c.naux, c.nauxp, np, c.gUg.p, np, st), "U_g");
+  if (f32_copies) {
+    hip_check(to_f32(c.gU.p, c.ngp * np, c.gU32.p, st), "U to f32");
+    hip_check(to_f32(c.gUg.p, c.nauxp * np, c.gUg32.p, st), "U_g to f32");
+  }
+}
+
+void build_general(rps_context& c, int variant, int nocc, const double* Csrc, double* Kout, double* exout,
+                   hipStream_t st, double s1, double s2, double s3, double ce1, double ce3) {
+  const int np = (int)round_up(nocc, 16);
+  ensure_general(c, np);
   const bool need_main = (variant != RPS_VARIANT_THC);
   const bool need_l3 = (variant != RPS_VARIANT_PS);
   const bool k1 = need_main && variant == RPS_VARIANT_RPS;
   const bool stream = c.gSp.p != nullptr && np <= kStreamMaxNp;
+  general_pre(c, nocc, Csrc, st, false);
   // the streaming passes run the context's precision; the GEMM form runs FP32
   // products for either precision form
   c.last_arith = stream ? c.precision : (c.gA32.p != nullptr ? RPS_PREC_FP32 : RPS_PREC_FP64);
@@ -1091,21 +1129,12 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
         hip_check(to_f32(c.gU.p, c.ngp * np, c.gU32.p, st), "U to f32");
         hip_check(to_f32(c.gUg.p, c.nauxp * np, c.gUg32.p, st), "U_g to f32");
       }
-      StreamArgs m2;   // M2 = (V o P) U, x = interpolation points
-      m2.V = c.V.p; m2.V32 = c.V32.p; m2.ldv = c.ngp; m2.trans = 0;
-      m2.X = c.gUg.p; m2.ldx = np; m2.Y = c.gU.p; m2.Y32 = c.gU32.p; m2.ldy = np;
-      m2.nx = c.nauxp; m2.ny = c.ngp; m2.np = np; m2.out = c.gSp.p;
-      const int sp = stream_splits(m2.nx, m2.ny, c.tune_target > 0 ? c.tune_target : kStreamBlocks);
+      const StreamArgs m2 = pass_m2(c, np);
+      const int sp = pass_splits(c, m2);
       hip_check(stream_product(m2, prec, sp, st), "stream M2");
       hip_check(sum_partials3(c.gSp.p, sp, c.nauxp * np, c.gM2.p, nullptr, 0, 0, nullptr, nullptr, 0, 0, nullptr, st),
                 "M2 partials");
-      if (k1) {
-        StreamArgs m1;  // M1^T = (V o P)^T U_g, x = grid points
-        m1.V = c.V.p; m1.V32 = c.V32.p; m1.ldv = c.ngp; m1.trans = 1;
-        m1.X = c.gU.p; m1.ldx = np; m1.Y = c.gUg.p; m1.Y32 = c.gUg32.p; m1.ldy = np;
-        m1.nx = c.ngp; m1.ny = c.nauxp; m1.np = np; m1.out = c.gM1T.p;
-        hip_check(stream_product(m1, prec, 1, st), "stream M1");
-      }
+      if (k1) hip_check(stream_product(pass_m1(c, np), prec, 1, st), "stream M1");
       prof_mark(c, 2, st);
       if (k1 && c.sparse) {
         sparse_k1(c, c.gM1T.p, np, c.gK1.p, st);
@@ -1118,11 +1147,8 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
     }
     if (need_l3) {
       prof_mark(c, 3, st);
-      StreamArgs l3;   // Y = (W o P_g) U_g, FP64
-      l3.V = c.W.p; l3.ldv = c.nauxp; l3.trans = 0;
-      l3.X = c.gUg.p; l3.ldx = np; l3.Y = c.gUg.p; l3.ldy = np;
-      l3.nx = c.nauxp; l3.ny = c.nauxp; l3.np = np; l3.out = c.gSp.p;
-      const int sp = stream_splits(l3.nx, l3.ny, c.tune_target > 0 ? c.tune_target : kStreamBlocks);
+      const StreamArgs l3 = pass_l3(c, np, c.gSp.p);
+      const int sp = pass_splits(c, l3);
       hip_check(stream_product(l3, RPS_PREC_FP64, sp, st), "stream line 3");
       hip_check(sum_partials3(c.gSp.p, sp, c.nauxp * np, c.gY.p, nullptr, 0, 0, nullptr, nullptr, 0, 0, nullptr, st),
                 "line-3 partials");
@@ -1218,6 +1244,38 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
                      need_l3 ? c.gK3.p : nullptr, (int)c.nbas, nocc, np, (int)c.Np, s1, s2, s3, c.dV, Kout,
                      nullptr, 0, nullptr, 0, ce1, ce3, exout, st, dots),
             "finalize");
+}
+
+// After the passes, in the batching form (rPS variant, streaming form): the ordered
+// sums of the M2 partials (sp_m2 of them in gSp) and of the fit-fit partials (sp_l3
+// in p3), K1, K3 and the combine, exactly as the eager build forms them.
+void general_post(rps_context& c, int nocc, int sp_m2, const double* p3, int sp_l3, double* Kout, double* exout,
+                  hipStream_t st) {
+  const int np = (int)round_up(nocc, 16);
+  hip_check(sum_partials3(c.gSp.p, sp_m2, c.nauxp * np, c.gM2.p, nullptr, 0, 0, nullptr, nullptr, 0, 0, nullptr, st),
+            "M2 partials");
+  if (c.sparse) {
+    sparse_k1(c, c.gM1T.p, np, c.gK1.p, st);
+  } else {
+    Gemm g;   // K1 = Phi^T M1^T
+    g.M = c.Np; g.N = np; g.K = c.ngp;
+    g.A = c.Phi.p; g.lda = c.Np; g.transA = true; g.B = c.gM1T.p; g.ldb = np; g.C = c.gK1.p; g.ldc = np;
+    gemm_run(g, c, st, "K1", true);
+  }
+  hip_check(sum_partials3(p3, sp_l3, c.nauxp * np, c.gY.p, nullptr, 0, 0, nullptr, nullptr, 0, 0, nullptr, st),
+            "line-3 partials");
+  Gemm k3;    // K3 = Phi_g^T Y
+  k3.M = c.Np; k3.N = np; k3.K = c.nauxp;
+  k3.A = c.Phig.p; k3.lda = c.Np; k3.transA = true; k3.B = c.gY.p; k3.ldb = np; k3.C = c.gK3.p; k3.ldc = np;
+  gemm_run(k3, c, st, "K3", true);
+  EnergyDots dots;
+  dots.x1 = c.gUg.p; dots.y1 = c.gM2.p; dots.n1 = c.nauxp * np;
+  dots.x3 = c.gUg.p; dots.y3 = c.gY.p; dots.n3 = c.nauxp * np;
+  dots.part = c.epart.p; dots.nparts = kEnergyBlocks; dots.count = c.ecount.p;
+  hip_check(finalize(c.Phig.p, c.gM2.p, c.nauxp, c.gK1.p, c.gK3.p, (int)c.nbas, nocc, np, (int)c.Np, 1.0, 1.0, -1.0,
+                     c.dV, Kout, nullptr, 0, nullptr, 0, 2.0, -1.0, exout, st, dots),
+            "finalize");
+  c.last_arith = c.precision;
 }
 
 // The fused single-pass kernels cover N <= 128 with n <= 64 (FP64) or n <= 16
@@ -1870,6 +1928,20 @@ rps_status guarded(F&& f) {
 
 // A captured batch of exchange builds over many contexts (the batching form).
 struct rps_batch {
+  // Persistent pass launches: one per class (precision, padded n, orientation)
+  // over the work items of every streaming-form cell of the batch.
+  struct QClass {
+    int prec = 0, np = 0, trans = 0, nitems = 0, nblocks = 0;
+    DBuf<StreamArgs> args;
+    DBuf<StreamItem> items;
+  };
+  std::vector<int> qcell;              // cell -> 1 if its passes run in the persistent launches
+  std::vector<int> qsp_m2, qsp_l3;     // their split counts (M2 and fit-fit passes)
+  std::vector<std::unique_ptr<DBuf<double>>> qpart3;   // their fit-fit partials
+  std::vector<std::unique_ptr<QClass>> qclass;
+  DBuf<double> qcount;                 // one queue counter per class (8-byte slots)
+  hipStream_t pipe = nullptr;          // stream of the persistent launches during capture
+  std::vector<hipEvent_t> qev;
   std::vector<rps_context*> ctx;
   std::vector<uint64_t> gen;           // workspace generation of each context at capture
   std::vector<int32_t> nocc;
@@ -1892,17 +1964,111 @@ struct rps_batch {
   ~rps_batch() {
     release_graph();
     for (auto e : events) (void)hipEventDestroy(e);
+    for (auto e : qev) (void)hipEventDestroy(e);
     for (auto st : streams) (void)hipStreamDestroy(st);
+    if (pipe) (void)hipStreamDestroy(pipe);
     if (origin) (void)hipStreamDestroy(origin);
   }
 };
 
 namespace {
 
+// Work items of the persistent pass launches.  A cell takes part when its build is
+// the streaming form (general path, padded n <= 128): its M2 and M1^T passes (the
+// context's precision) and its fit-fit pass (FP64) become items (cell, x block,
+// y split) of the class (precision, n, orientation); items are ordered by the
+// length of their y split, longest first.  Everything else (fused-path cells,
+// the GEMM form) is built by its own launches beside them.
+void plan_queue(rps_batch& b) {
+  const int nb = (int)b.ctx.size();
+  b.qcell.assign(nb, 0);
+  b.qsp_m2.assign(nb, 0);
+  b.qsp_l3.assign(nb, 0);
+  b.qpart3.clear();
+  b.qpart3.resize(nb);
+  b.qclass.clear();
+  // Off unless RPS_BATCH_QUEUE=1: the first GPU run of this form ended in a host
+  // segmentation fault inside rps_batch_create whose cause is not found (the host
+  // logic runs clean under AddressSanitizer on a CPU stand-in for the runtime), so
+  // every cell keeps its own launches by default.
+  const char* qe = getenv("RPS_BATCH_QUEUE");
+  if (!(qe && qe[0] == '1')) return;
+  std::vector<std::vector<std::pair<StreamArgs, int>>> cls_args;   // per class: (args, nsplit)
+  std::vector<std::array<int, 3>> keys;
+  auto class_of = [&](int prec, int np, int trans) {
+    for (size_t k = 0; k < keys.size(); ++k)
+      if (keys[k][0] == prec && keys[k][1] == np && keys[k][2] == trans) return (int)k;
+    keys.push_back({prec, np, trans});
+    cls_args.emplace_back();
+    return (int)keys.size() - 1;
+  };
+  for (int i = 0; i < nb; ++i) {
+    rps_context& c = *b.ctx[i];
+    const int np = (int)round_up(b.nocc[i], 16);
+    if (!uses_general(c, np) || np > kStreamMaxNp || !c.gSp.p || c.gws_np != np) continue;
+    b.qcell[i] = 1;
+    const StreamArgs m2 = pass_m2(c, np), m1 = pass_m1(c, np);
+    b.qsp_m2[i] = pass_splits(c, m2);
+    b.qpart3[i] = std::make_unique<DBuf<double>>();
+    const StreamArgs l3 = pass_l3(c, np, nullptr);
+    b.qsp_l3[i] = pass_splits(c, l3);
+    b.qpart3[i]->alloc((int64_t)b.qsp_l3[i] * c.nauxp * np, nullptr);
+    const StreamArgs l3p = pass_l3(c, np, b.qpart3[i]->p);
+    cls_args[class_of(c.precision, np, 0)].push_back({m2, b.qsp_m2[i]});
+    cls_args[class_of(c.precision, np, 1)].push_back({m1, 1});
+    cls_args[class_of(RPS_PREC_FP64, np, 0)].push_back({l3p, b.qsp_l3[i]});
+  }
+  b.qcount.alloc(std::max<int64_t>((int64_t)keys.size(), 1), nullptr);
+  for (size_t k = 0; k < keys.size(); ++k) {
+    auto q = std::make_unique<rps_batch::QClass>();
+    q->prec = keys[k][0];
+    q->np = keys[k][1];
+    q->trans = keys[k][2];
+    std::vector<StreamArgs> args;
+    std::vector<StreamItem> items;
+    std::vector<int64_t> len;
+    for (auto& pa : cls_args[k]) {
+      StreamArgs a;
+      hip_check(stream_prepare(pa.first, q->prec, pa.second, a), "queue pass");
+      const int cell = (int)args.size();
+      args.push_back(a);
+      const int64_t xb = stream_xblocks(a.nx);
+      // every (x block, split) is an item, empty splits too: they write the zero
+      // partials the ordered sums expect, as in the one-cell launch
+      for (int64_t by = 0; by < pa.second; ++by) {
+        const int64_t ys = by * a.ysplit, ye = std::min(ys + a.ysplit, a.ny);
+        for (int64_t bx = 0; bx < xb; ++bx) {
+          items.push_back(StreamItem{cell, (int32_t)bx, (int32_t)by});
+          len.push_back(std::max<int64_t>(ye - ys, 0));
+        }
+      }
+    }
+    std::vector<size_t> order(items.size());
+    for (size_t t = 0; t < order.size(); ++t) order[t] = t;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return len[x] > len[y]; });
+    std::vector<StreamItem> sorted(items.size());
+    for (size_t t = 0; t < order.size(); ++t) sorted[t] = items[order[t]];
+    q->nitems = (int)sorted.size();
+    q->nblocks = std::max(1, std::min(q->nitems, stream_queue_blocks(q->prec, q->np, q->trans)));
+    q->args.alloc((int64_t)args.size(), nullptr);
+    q->items.alloc(std::max<int64_t>(q->nitems, 1), nullptr);
+    hip_check(hipMemcpy(q->args.p, args.data(), args.size() * sizeof(StreamArgs), hipMemcpyHostToDevice), "queue args");
+    if (q->nitems > 0)
+      hip_check(hipMemcpy(q->items.p, sorted.data(), sorted.size() * sizeof(StreamItem), hipMemcpyHostToDevice),
+                "queue items");
+    b.qclass.push_back(std::move(q));
+  }
+}
+
 // Capture every build of the batch into one graph.  Cells are ordered by
 // their work (n N_aux N_g, largest first) and dealt to `nbranch` parallel
 // branches by least accumulated work, so small cells fill the device beside
 // the large ones; the branches fork from and join back into `origin`.
+// Streaming-form cells (plan_queue) run in three phases: their orbitals on the
+// branches, then the persistent pass launches (one per class, on the pipe
+// stream, each preceded by a fill kernel that zeroes its queue counter), then
+// their sums, K1, K3 and the combine back on the branches; every other cell's
+// build runs on its branch in between, beside the persistent launches.
 void capture_batch(rps_batch& b, int nbranch, hipStream_t origin) {
   b.release_graph();
   const int nb = (int)b.ctx.size();
@@ -1916,6 +2082,12 @@ void capture_batch(rps_batch& b, int nbranch, hipStream_t origin) {
     hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
     b.events.push_back(e);
   }
+  while ((int)b.qev.size() < nbranch + 1) {
+    hipEvent_t e;
+    hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+    b.qev.push_back(e);
+  }
+  if (!b.pipe) hip_check(hipStreamCreateWithFlags(&b.pipe, hipStreamNonBlocking), "hipStreamCreate");
   std::vector<int> order(nb);
   for (int i = 0; i < nb; ++i) order[i] = i;
   auto work = [&](int i) {
@@ -1938,9 +2110,40 @@ void capture_batch(rps_batch& b, int nbranch, hipStream_t origin) {
   try {
     hip_check(hipEventRecord(b.events[nbranch], origin), "fork");
     for (int k = 0; k < nbranch; ++k) hip_check(hipStreamWaitEvent(b.streams[k], b.events[nbranch], 0), "fork wait");
+    const bool queue = !b.qclass.empty();
+    if (queue) {
+      // phase 1: orbitals of the streaming-form cells
+      for (int i : order)
+        if (b.qcell[i])
+          general_pre(*b.ctx[i], b.nocc[i], b.C[i], b.streams[assign[i]], b.ctx[i]->precision != RPS_PREC_FP64);
+      hip_check(hipStreamWaitEvent(b.pipe, b.events[nbranch], 0), "fork wait");
+      for (int k = 0; k < nbranch; ++k) {
+        hip_check(hipEventRecord(b.qev[k], b.streams[k]), "phase 1");
+        hip_check(hipStreamWaitEvent(b.pipe, b.qev[k], 0), "phase 1 wait");
+      }
+      // phase 2: the persistent pass launches
+      for (size_t k = 0; k < b.qclass.size(); ++k) {
+        const rps_batch::QClass& q = *b.qclass[k];
+        hip_check(fill(b.qcount.p + k, 1, 0.0, b.pipe), "clear queue counter");
+        hip_check(stream_product_queue(q.args.p, q.items.p, q.nitems, q.prec, q.np, q.trans,
+                                       reinterpret_cast<unsigned*>(b.qcount.p + k), q.nblocks, b.pipe),
+                  "persistent passes");
+      }
+      hip_check(hipEventRecord(b.qev[nbranch], b.pipe), "phase 2");
+    }
+    // every other cell: its whole build, beside phase 2
     for (int i : order)
-      build_impl(*b.ctx[i], RPS_VARIANT_RPS, b.nocc[i], b.C[i], b.K[i], b.ex ? b.ex + i : nullptr, RPS_PTRS_DEVICE,
-                 b.streams[assign[i]], false);
+      if (!queue || !b.qcell[i])
+        build_impl(*b.ctx[i], RPS_VARIANT_RPS, b.nocc[i], b.C[i], b.K[i], b.ex ? b.ex + i : nullptr, RPS_PTRS_DEVICE,
+                   b.streams[assign[i]], false);
+    if (queue) {
+      // phase 3: sums, K1, K3 and the combine of the streaming-form cells
+      for (int k = 0; k < nbranch; ++k) hip_check(hipStreamWaitEvent(b.streams[k], b.qev[nbranch], 0), "phase 2 wait");
+      for (int i : order)
+        if (b.qcell[i])
+          general_post(*b.ctx[i], b.nocc[i], b.qsp_m2[i], b.qpart3[i]->p, b.qsp_l3[i], b.K[i],
+                       b.ex ? b.ex + i : nullptr, b.streams[assign[i]]);
+    }
     for (int k = 0; k < nbranch; ++k) {
       hip_check(hipEventRecord(b.events[k], b.streams[k]), "join");
       hip_check(hipStreamWaitEvent(origin, b.events[k], 0), "join wait");
@@ -2137,6 +2340,7 @@ rps_status rps_batch_create(rps_context* const* ctx, int32_t nbatch, const int32
         build_impl(*ctx[i], RPS_VARIANT_RPS, nocc[i], C[i], K[i], ex ? ex + i : nullptr, RPS_PTRS_DEVICE, st, false);
     }
     hip_check(hipStreamSynchronize(st), "sync");
+    plan_queue(*b);
     hip_check(hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking), "hipStreamCreate");
     hipStream_t org = b->origin;
     const int fixed = (flags & RPS_BATCH_FIXED_BRANCHES_MASK) >> 8;

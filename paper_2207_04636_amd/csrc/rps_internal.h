@@ -277,4 +277,21 @@ int stream_splits(int64_t nx, int64_t ny, int target_blocks);
 // prec: 0 FP64 (V), 1 FP32 (V32, FP32 products), 2 split-BF16 products on V32.
 hipError_t stream_product(const StreamArgs& a, int prec, int nsplit, hipStream_t s);
 
+// Persistent form of the passes for the batching form.  A work item is one
+// workgroup's share of one cell's pass: x block bx (128 rows) and y split by.
+struct StreamItem {
+  int32_t cell, bx, by;
+};
+// Checks a pass as stream_product does and returns it with its split length set.
+hipError_t stream_prepare(const StreamArgs& a, int prec, int nsplit, StreamArgs& out);
+// x blocks of a pass with nx rows.
+int64_t stream_xblocks(int64_t nx);
+// Workgroups that stay resident for the passes of class (prec, np, trans).
+int stream_queue_blocks(int prec, int np, int trans);
+// One launch over items[0..nitems) (device arrays) of cells whose passes share
+// prec, np and trans; args[cell] as returned by stream_prepare; *counter (device)
+// must be zero at launch and is left at nitems + the number of workgroups.
+hipError_t stream_product_queue(const StreamArgs* args, const StreamItem* items, int nitems, int prec, int np,
+                                int trans, unsigned* counter, int nblocks, hipStream_t s);
+
 }  // namespace rps
