@@ -490,11 +490,17 @@ __global__ __launch_bounds__(256, 2) void gemm32v_kernel(Gemm32 g) {
       if (full) {
         ra[i] = *reinterpret_cast<const f4_t*>(src);
       } else {
-        // rows: m (TA = false) or k (TA = true); columns: the other
+        // rows: m (TA = false) or k (TA = true); columns: the other.  A piece wholly
+        // inside is one 16-byte load, one wholly outside is zero; only a piece that
+        // straddles the edge is read element by element.
         const int64_t rm = TA ? k0 + r : m0 + r, rlim = TA ? kend : g.M;
         const int64_t cm = TA ? m0 + c : k0 + c, clim = TA ? g.M : kend;
+        if (rm < rlim && cm + 4 <= clim) {
+          ra[i] = *reinterpret_cast<const f4_t*>(src);
+        } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) ra[i][j] = (rm < rlim && cm + j < clim) ? src[j] : 0.f;
+          for (int j = 0; j < 4; ++j) ra[i][j] = (rm < rlim && cm + j < clim) ? src[j] : 0.f;
+        }
       }
     }
 #pragma unroll
@@ -508,8 +514,12 @@ __global__ __launch_bounds__(256, 2) void gemm32v_kernel(Gemm32 g) {
       } else {
         const int64_t rn = TB ? n0 + r : k0 + r, rlim = TB ? g.N : kend;
         const int64_t cn = TB ? k0 + c : n0 + c, clim = TB ? kend : g.N;
+        if (rn < rlim && cn + 4 <= clim) {
+          rb[i] = *reinterpret_cast<const f4_t*>(src);
+        } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) rb[i][j] = (rn < rlim && cn + j < clim) ? src[j] : 0.f;
+          for (int j = 0; j < 4; ++j) rb[i][j] = (rn < rlim && cn + j < clim) ? src[j] : 0.f;
+        }
       }
     }
   };
