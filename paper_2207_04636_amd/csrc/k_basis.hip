@@ -185,6 +185,14 @@ __global__ void to_f32_kernel(const double* __restrict__ X, int64_t count, float
   if (i < count) Y[i] = (float)X[i];
 }
 
+__global__ void to_f32_pad_kernel(const double* __restrict__ X, int64_t rows, int64_t n, float* __restrict__ Y,
+                                  int64_t ldy) {
+  const int64_t i = flat_id();
+  if (i >= rows * ldy) return;
+  const int64_t r = i / ldy, c = i % ldy;
+  Y[i] = (c < n) ? (float)X[r * n + c] : 0.f;
+}
+
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -205,6 +213,12 @@ hipError_t gather_cols(const double* X, int64_t ldx, const int64_t* idx, int64_t
 hipError_t to_f32(const double* X, int64_t count, float* Y, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(to_f32_kernel, flat_grid(count), dim3(256), 0, s, X, count, Y);
+  return hipGetLastError();
+}
+
+hipError_t to_f32_pad(const double* X, int64_t rows, int64_t n, float* Y, int64_t ldy, hipStream_t s) {
+  if (rows <= 0 || ldy < n) return rows <= 0 ? hipSuccess : hipErrorInvalidValue;
+  hipLaunchKernelGGL(to_f32_pad_kernel, flat_grid(rows * ldy), dim3(256), 0, s, X, rows, n, Y, ldy);
   return hipGetLastError();
 }
 

@@ -470,7 +470,8 @@ __global__ __launch_bounds__(256, 2) void gemm32v_kernel(Gemm32 g) {
     kend = (kbeg + kper < g.K) ? kbeg + kper : g.K;
   }
   const int64_t nk = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
-  const bool interior = (m0 + BM <= g.M) && (n0 + BN <= g.N);
+  const int64_t nread = (g.Nread > g.N) ? g.Nread : g.N;   // readable columns of B
+  const bool interior = (m0 + BM <= g.M) && (n0 + BN <= nread);
   const int lda = (int)g.lda, ldb = (int)g.ldb;
 
   f4_t ra[NA4], rb[NB4];
@@ -512,8 +513,8 @@ __global__ __launch_bounds__(256, 2) void gemm32v_kernel(Gemm32 g) {
       if (full) {
         rb[i] = *reinterpret_cast<const f4_t*>(src);
       } else {
-        const int64_t rn = TB ? n0 + r : k0 + r, rlim = TB ? g.N : kend;
-        const int64_t cn = TB ? k0 + c : n0 + c, clim = TB ? kend : g.N;
+        const int64_t rn = TB ? n0 + r : k0 + r, rlim = TB ? nread : kend;
+        const int64_t cn = TB ? k0 + c : n0 + c, clim = TB ? kend : nread;
         if (rn < rlim && cn + 4 <= clim) {
           rb[i] = *reinterpret_cast<const f4_t*>(src);
         } else {

@@ -1002,10 +1002,11 @@ void ensure_general(rps_context& c, int np) {
   if (np > kStreamMaxNp || getenv("RPS_GENERAL_GEMM")) {
     c.gSp.release(cnt);
     if (f32) {
+      const int64_t npg = round_up(np, 64);      // FP32 copies padded to whole 64-column tiles
       c.gA.alloc(c.nauxp * c.nauxp, cnt);      // B of the fit-fit line (FP64)
       c.gA32.alloc(c.nauxp * rc, cnt);
-      c.gU32.alloc(c.ngp * np, cnt);
-      c.gUg32.alloc(c.nauxp * np, cnt);
+      c.gU32.alloc(c.ngp * npg, cnt);
+      c.gUg32.alloc(c.nauxp * npg, cnt);
     } else {
       c.gA.alloc(std::max(c.nauxp * rc, c.nauxp * c.nauxp), cnt);
     }
@@ -1160,31 +1161,34 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
     }
   } else if (need_main) {
     const bool f32 = c.gA32.p != nullptr;
+    // FP32 copies of U and U_g with npg >= np columns, zero beyond np: every tile of
+    // the n dimension then loads whole 16-byte pieces
+    const int64_t npg = round_up(np, 64);
     if (f32) {
-      hip_check(to_f32(c.gU.p, c.ngp * np, c.gU32.p, st), "U to f32");
-      hip_check(to_f32(c.gUg.p, c.nauxp * np, c.gUg32.p, st), "U_g to f32");
+      hip_check(to_f32_pad(c.gU.p, c.ngp, np, c.gU32.p, npg, st), "U to f32");
+      hip_check(to_f32_pad(c.gUg.p, c.nauxp, np, c.gUg32.p, npg, st), "U_g to f32");
     }
     prof_mark(c, 1, st);     // the profiled main phase: the chunk products only
     constexpr int64_t kF32Terms = 1ll << 40;   // split for parallelism only (FP32 sums are short)
     for (int64_t r0 = 0; r0 < c.ngp; r0 += c.gchunk) {
       const int64_t rc = std::min(c.gchunk, c.ngp - r0);
       if (f32) {
-        Gemm32 a;   // A_c = V[:, c] o (U_g U[c]^T), FP32
-        a.M = c.nauxp; a.N = rc; a.K = np;
-        a.A = c.gUg32.p; a.lda = np; a.B = c.gU32.p + r0 * np; a.ldb = np; a.transB = true;
+        Gemm32 a;   // A_c = V[:, c] o (U_g U[c]^T), FP32 (the zero columns add nothing)
+        a.M = c.nauxp; a.N = rc; a.K = npg;
+        a.A = c.gUg32.p; a.lda = npg; a.B = c.gU32.p + r0 * npg; a.ldb = npg; a.transB = true;
         a.C32 = c.gA32.p; a.ldc = rc; a.D32 = c.V32.p + r0; a.ldd = c.ngp;
         hip_check(gemm_f32(a, st), "A chunk");
         if (k1) {
           Gemm32 m1;   // M1^T[c] = A_c^T U_g
-          m1.M = rc; m1.N = np; m1.K = c.nauxp;
-          m1.A = c.gA32.p; m1.lda = rc; m1.transA = true; m1.B = c.gUg32.p; m1.ldb = np;
+          m1.M = rc; m1.N = np; m1.Nread = npg; m1.K = c.nauxp;
+          m1.A = c.gA32.p; m1.lda = rc; m1.transA = true; m1.B = c.gUg32.p; m1.ldb = npg;
           m1.C = c.gM1T.p + r0 * np; m1.ldc = np;
           m1.splitk = gemm32_splitk_for(m1.M, m1.N, m1.K, kF32Terms, kSplitWork); m1.work = c.gwork.p;
           hip_check(gemm_f32(m1, st), "M1");
         }
         Gemm32 m2;     // M2 += A_c U[c]
-        m2.M = c.nauxp; m2.N = np; m2.K = rc;
-        m2.A = c.gA32.p; m2.lda = rc; m2.B = c.gU32.p + r0 * np; m2.ldb = np;
+        m2.M = c.nauxp; m2.N = np; m2.Nread = npg; m2.K = rc;
+        m2.A = c.gA32.p; m2.lda = rc; m2.B = c.gU32.p + r0 * npg; m2.ldb = npg;
         m2.C = c.gM2.p; m2.ldc = np; m2.beta = (r0 == 0) ? 0.0 : 1.0;
         m2.splitk = gemm32_splitk_for(m2.M, m2.N, m2.K, kF32Terms, kSplitWork); m2.work = c.gwork.p;
         hip_check(gemm_f32(m2, st), "M2");

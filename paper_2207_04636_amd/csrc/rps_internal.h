@@ -63,6 +63,9 @@ struct Gemm32 {
   const float* D32 = nullptr; int64_t ldd = 0;
   int splitk = 1;
   double* work = nullptr;
+  // B holds Nread >= N columns (zero beyond N) that may be read: tiles reaching
+  // past N but not past Nread load B whole; outputs stay within N (0: Nread = N)
+  int64_t Nread = 0;
 };
 hipError_t gemm_f32(const Gemm32& g, hipStream_t s);
 // Split count with at most kmax of K per split and enough workgroups, within work_cap doubles
@@ -113,6 +116,8 @@ hipError_t set_unit_rows(double* X, int64_t ld, const int64_t* idx, int64_t n, h
 hipError_t gather_cols(const double* X, int64_t ldx, const int64_t* idx, int64_t n, double* Y,
                        int64_t ldy, hipStream_t s);
 hipError_t to_f32(const double* X, int64_t count, float* Y, hipStream_t s);
+// Y[r][c] = X[r][c] for c < n, 0 for n <= c < ldy (X rows x n contiguous, Y pitch ldy >= n)
+hipError_t to_f32_pad(const double* X, int64_t rows, int64_t n, float* Y, int64_t ldy, hipStream_t s);
 // x[i*ld + i] += v for i in [i0, i1)
 hipError_t add_diag(double* X, int64_t ld, int64_t i0, int64_t i1, double v, hipStream_t s);
 hipError_t fill(double* X, int64_t count, double v, hipStream_t s);
