@@ -637,8 +637,9 @@ __global__ __launch_bounds__(256, 2) void gemm32v_kernel(Gemm32 g) {
       }
 }
 
+// 128 x 64 tiles without the row scale fit three waves per SIMD (168 registers)
 template <int TM, int TN, bool TA, bool TB, bool KS = false>
-__global__ __launch_bounds__(256, 2) void gemm_big_kernel(Gemm g) {
+__global__ __launch_bounds__(256, (TN == 2 && !KS) ? 3 : 2) void gemm_big_kernel(Gemm g) {
   gemm_big_body<TM, TN, TA, TB, KS>(g, (int64_t)blockIdx.y * 32 * TM, (int64_t)blockIdx.x * 32 * TN, blockIdx.z);
 }
 
