@@ -287,9 +287,15 @@ struct Bf16Layout {
   static constexpr int NKC = (NP + 31) / 32;   // K chunks of the P^T product
   static constexpr int NPP = NKC * 32;         // n padded to whole chunks (zero tail)
   static constexpr int LR = NPP + 8;           // row-major plane pitch (bf16), 16-byte rows
-  static constexpr int LT = BY + 8;            // transposed plane pitch (bf16)
+  static constexpr int LT = BY + 4;            // transposed plane pitch (bf16): 18 dwords, so the
+                                               // 8-byte reads of 16 consecutive columns hit 32 banks
   static constexpr int SZR = BY * LR, SZT = NP * LT;
   static constexpr int BUF = 3 * SZR + 3 * SZT;   // bf16 per buffer: Y h/m/l, Y^T h/m/l
+  // Two staging buffers (one barrier per tile), 108 KB at n = 128: one workgroup of
+  // eight waves per CU.  One buffer (two barriers, two workgroups per CU) measured
+  // the same at n = 128.
+  static constexpr int NBUF = 2;
+  static constexpr size_t LDS_BYTES = (size_t)NBUF * BUF * 2;
 };
 
 template <int NC, int TRANS, int NW>
@@ -325,10 +331,10 @@ __device__ __forceinline__ void bf16x3_body(const StreamArgs& a, int64_t bx, int
       xl[j][e] = l;
     }
 
-  // zero tail columns [NP, NPP) of the row-major planes of both buffers (never staged)
+  // zero tail columns [NP, NPP) of the row-major planes of every buffer (never staged)
   if constexpr (NPP > NP) {
     constexpr int TAIL = BY * (NPP - NP);
-    for (int e = tid; e < 2 * 3 * TAIL; e += NW * 64) {
+    for (int e = tid; e < L::NBUF * 3 * TAIL; e += NW * 64) {
       const int plane = e / TAIL, rem = e % TAIL;
       const int r = rem / (NPP - NP), c = NP + rem % (NPP - NP);
       sm[(plane / 3) * L::BUF + (plane % 3) * SZR + r * LR + c] = (__bf16)0.f;
@@ -344,18 +350,36 @@ __device__ __forceinline__ void bf16x3_body(const StreamArgs& a, int64_t bx, int
     for (int r = 0; r < 4; ++r) od[cb][r] = 0.0;
   }
 
+  // Staging order: element k of a wave is one 8 x 8 block of the tile (rows
+  // 8 (b % 4) + lane / 8, columns 8 (b / 4) + lane % 8, b = w + NW k).  With row
+  // pitch LR/2 = 4 or 20 (mod 32) dwords such a block puts its 64 two-byte stores
+  // on 32 distinct banks of the row-major planes (two lanes per dword) and, with
+  // column pitch LT/2 = 18 dwords, on at most two dwords per bank of the
+  // transposed planes; a row of 64 consecutive columns hit each bank of the
+  // transposed planes from up to eight dwords.
+  static_assert(NW == 8 && PER == NC, "8 x 8 staging blocks: one per wave per element");
   float ystage[PER];   // from the FP32 copy of Y (the split keeps 24 bits anyway)
+  const int sr = lane >> 3, sc = lane & 7;
+  auto stage_rc = [&](int k, int& r, int& c) {
+    const int b = w + NW * k;
+    r = 8 * (b & 3) + sr;
+    c = 8 * (b >> 2) + sc;
+  };
   auto stage_load = [&](int64_t t) {
     const float* src = a.Y32 + (ys + t * BY) * a.ldy;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) ystage[k] = src[tid + k * NW * 64];
+    for (int k = 0; k < PER; ++k) {
+      int r, c;
+      stage_rc(k, r, c);
+      ystage[k] = src[r * NP + c];
+    }
   };
   auto stage_store = [&](int buf) {
     __bf16* b = sm + buf * L::BUF;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int e = tid + k * NW * 64;
-      const int r = e / NP, c = e % NP;
+      int r, c;
+      stage_rc(k, r, c);
       __bf16 h, m, l;
       split3_bf16(ystage[k], h, m, l);
       b[r * LR + c] = h;
@@ -396,7 +420,7 @@ __device__ __forceinline__ void bf16x3_body(const StreamArgs& a, int64_t bx, int
   for (int64_t t = 0; t < ntile; ++t) {
     stage_load(t + 1 < ntile ? t + 1 : t);
     load_s(t + 1, vn);    // the next tile's S values, a tile ahead
-    const __bf16* b = sm + (t & 1) * L::BUF;
+    const __bf16* b = sm + ((L::NBUF == 2) ? (int)(t & 1) : 0) * L::BUF;
     if (xvalid) {
       // P^T tiles of the two 16-row halves: reg r <-> y = 16 sb + 4 lq + r, x = l16
       f4_t sp[2];
@@ -478,7 +502,12 @@ __device__ __forceinline__ void bf16x3_body(const StreamArgs& a, int64_t bx, int
     }
 #pragma unroll
     for (int e = 0; e < 8; ++e) vv[e] = vn[e];
-    stage_store((t + 1) & 1);
+    if constexpr (L::NBUF == 2) {
+      stage_store((t + 1) & 1);
+    } else {
+      __syncthreads();     // every wave has read tile t
+      stage_store(0);
+    }
     __syncthreads();
   }
 
@@ -519,7 +548,7 @@ __global__ __launch_bounds__(NW * 64) void bf16x3_queue_kernel(const StreamArgs*
 template <int NC, int TRANS>
 hipError_t launch_bf16x3(const StreamArgs& a, int nsplit, hipStream_t s) {
   constexpr int NW = 8;
-  const size_t lds = (size_t)2 * Bf16Layout<NC>::BUF * 2;
+  const size_t lds = Bf16Layout<NC>::LDS_BYTES;
   auto kern = stream_bf16x3_kernel<NC, TRANS, NW>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -628,7 +657,7 @@ template <int NC, int TRANS>
 hipError_t queue_bf16x3(const StreamArgs* args, const StreamItem* items, int nitems, unsigned* counter, int nblocks,
                         hipStream_t s, int* resident) {
   constexpr int NW = 8;
-  const size_t lds = (size_t)2 * Bf16Layout<NC>::BUF * 2;
+  const size_t lds = Bf16Layout<NC>::LDS_BYTES;
   auto kern = bf16x3_queue_kernel<NC, TRANS, NW>;
   if (resident) { *resident = resident_blocks(kern, lds); return hipSuccess; }
   if (lds > 65536) {
