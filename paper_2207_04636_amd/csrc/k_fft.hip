@@ -9,7 +9,7 @@
 //
 // The 3-D transform is separable: one pass per axis, each pass moving 16
 // pencils of one axis into LDS and applying the length-L DFT by direct
-// summation with twiddles from sincospi in FP64 (axes up to 128 points).  Passes:
+// summation with twiddles from sincospi in FP64 (axes up to 256 points).  Passes:
 // forward along axis 2, forward along axis 1, [forward along axis 0, multiply
 // by k/N_g, inverse along axis 0] in one kernel, inverse along axis 1, inverse
 // along axis 2.  This is a set-up step (once per geometry), so the direct
@@ -22,17 +22,19 @@
 namespace rps {
 namespace {
 
-constexpr int LMAX = 128;    // longest supported axis
+constexpr int LMAX = 256;    // longest supported axis
 
 // Pencil p (of outer*inner) starts at o*L*inner + i with o = p / inner, i = p % inner;
 // element j of it is at start + j*inner.  PEN pencils per workgroup: 16 for the
-// set-up's many rows, 4 when a single row pair would leave most CUs idle.
-template <int MODE, int PEN>   // 0: forward, 1: inverse, 2: forward, multiply by kern, inverse
+// set-up's many rows, 4 when a single row pair would leave most CUs idle.  LM is
+// the longest axis the LDS arrays hold: 128 (68 KB at PEN = 16), or 256 for longer
+// axes with at most 8 pencils (70 KB).
+template <int MODE, int PEN, int LM>   // 0: forward, 1: inverse, 2: forward, multiply by kern, inverse
 __global__ __launch_bounds__(256) void dft_axis_kernel(double* __restrict__ V, int64_t ld, int L,
                                                       int64_t inner, int64_t npencil,
                                                       const double* __restrict__ kern) {
-  __shared__ double br[2][PEN][LMAX + 1], bi[2][PEN][LMAX + 1];
-  __shared__ double wr[LMAX], wi[LMAX];
+  __shared__ double br[2][PEN][LM + 1], bi[2][PEN][LM + 1];
+  __shared__ double wr[LM], wi[LM];
   const int tid = threadIdx.x;
   double* re = V + (int64_t)(2 * blockIdx.y) * ld;
   double* im = re + ld;
@@ -106,6 +108,18 @@ __global__ __launch_bounds__(256) void dft_axis_kernel(double* __restrict__ V, i
   }
 }
 
+template <int PEN, int LM>
+void go(double* V, int64_t ld, int L, int64_t inner, int64_t np, const double* kern, int64_t npairs, int mode,
+        hipStream_t s) {
+  dim3 grid((unsigned)((np + PEN - 1) / PEN), (unsigned)npairs);
+  if (mode == 0)
+    hipLaunchKernelGGL((dft_axis_kernel<0, PEN, LM>), grid, dim3(256), 0, s, V, ld, L, inner, np, kern);
+  else if (mode == 1)
+    hipLaunchKernelGGL((dft_axis_kernel<1, PEN, LM>), grid, dim3(256), 0, s, V, ld, L, inner, np, kern);
+  else
+    hipLaunchKernelGGL((dft_axis_kernel<2, PEN, LM>), grid, dim3(256), 0, s, V, ld, L, inner, np, kern);
+}
+
 }  // namespace
 
 hipError_t poisson_rows(double* V, int64_t nrows, int64_t ld, const int mesh[3],
@@ -123,24 +137,12 @@ hipError_t poisson_rows(double* V, int64_t nrows, int64_t ld, const int mesh[3],
     auto launch = [&](int axis, int mode) {
       const int L = mesh[axis];
       const int64_t np = ng / L;
-      if ((np + 15) / 16 * cn >= 1024) {
-        constexpr int PEN = 16;
-        dim3 grid((unsigned)((np + PEN - 1) / PEN), (unsigned)cn);
-        if (mode == 0)
-          hipLaunchKernelGGL((dft_axis_kernel<0, PEN>), grid, dim3(256), 0, s, Vc, ld, L, inner[axis], np, kern);
-        else if (mode == 1)
-          hipLaunchKernelGGL((dft_axis_kernel<1, PEN>), grid, dim3(256), 0, s, Vc, ld, L, inner[axis], np, kern);
-        else
-          hipLaunchKernelGGL((dft_axis_kernel<2, PEN>), grid, dim3(256), 0, s, Vc, ld, L, inner[axis], np, kern);
+      if (L > 128) {
+        go<8, 256>(Vc, ld, L, inner[axis], np, kern, cn, mode, s);
+      } else if ((np + 15) / 16 * cn >= 1024) {
+        go<16, 128>(Vc, ld, L, inner[axis], np, kern, cn, mode, s);
       } else {
-        constexpr int PEN = 4;
-        dim3 grid((unsigned)((np + PEN - 1) / PEN), (unsigned)cn);
-        if (mode == 0)
-          hipLaunchKernelGGL((dft_axis_kernel<0, PEN>), grid, dim3(256), 0, s, Vc, ld, L, inner[axis], np, kern);
-        else if (mode == 1)
-          hipLaunchKernelGGL((dft_axis_kernel<1, PEN>), grid, dim3(256), 0, s, Vc, ld, L, inner[axis], np, kern);
-        else
-          hipLaunchKernelGGL((dft_axis_kernel<2, PEN>), grid, dim3(256), 0, s, Vc, ld, L, inner[axis], np, kern);
+        go<4, 128>(Vc, ld, L, inner[axis], np, kern, cn, mode, s);
       }
     };
     launch(2, 0);

@@ -524,7 +524,7 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
   if (!(vol > 1e-10) || !inv3(c.lat, c.ainv)) fail(RPS_ERR_ARG, "lattice is singular");
   for (int k = 0; k < 3; ++k) {
     c.mesh[k] = cell->mesh[k];
-    if (c.mesh[k] < 2 || c.mesh[k] > 128) fail(RPS_ERR_SHAPE, "mesh sizes must be in [2, 128]");
+    if (c.mesh[k] < 2 || c.mesh[k] > 256) fail(RPS_ERR_SHAPE, "mesh sizes must be in [2, 256]");
   }
   c.natom = b->natom;
   int64_t nb = 0;

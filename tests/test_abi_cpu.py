@@ -82,7 +82,7 @@ def _setup_status(**over):
 @pytest.mark.parametrize("over,status", [
     (dict(lattice=np.zeros((3, 3))), B.RPS_ERR_ARG),
     (dict(mesh=[8, 1, 8]), B.RPS_ERR_SHAPE),
-    (dict(mesh=[8, 8, 200]), B.RPS_ERR_SHAPE),
+    (dict(mesh=[8, 8, 257]), B.RPS_ERR_SHAPE),
     (dict(sl=[0, 3]), B.RPS_ERR_ARG),
     (dict(se=[1.0, -1.0]), B.RPS_ERR_ARG),
     (dict(sa=[0, 5]), B.RPS_ERR_ARG),

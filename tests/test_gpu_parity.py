@@ -76,6 +76,38 @@ def test_setup_products_config1(lib, cfg1):
     np.testing.assert_array_equal(W, W.T)
 
 
+def _long_axis_cell(mesh):
+    """Orthorhombic cell, 0.17 bohr per grid step, with one axis longer than 128
+    points: four s and four p shells at seeded positions, 32 fitting functions."""
+    rng = np.random.default_rng(97)
+    L = 0.17 * np.asarray(mesh, dtype=np.float64)
+    pos = rng.uniform(0.0, 1.0, size=(8, 3)) * L
+    exps = np.exp(rng.uniform(np.log(0.5), np.log(3.0), 8))
+    return ri.Workload("long-axis-" + "x".join(map(str, mesh)), np.diag(L), np.asarray(mesh, dtype=np.int64),
+                       pos, np.arange(8), np.arange(8) % 2, exps, 2, 32, 97)
+
+
+@pytest.mark.parametrize("mesh", [(144, 16, 16), (16, 200, 16), (16, 16, 256)])
+def test_setup_products_long_axis(lib, mesh):
+    """V = Vc chi through the per-axis DFT on axes of 144-256 points (the
+    longer-axis kernel), against the oracle's FFT Poisson solve."""
+    _say(f"case: V and W on a {mesh} mesh with oracle points")
+    w = _long_axis_cell(mesh)
+    Phi = basis.eval_basis(w)
+    st = isdf.setup(w, Phi, mode="global")
+    dV = grid.dvol(w.lattice, w.mesh)
+    C = ri.lowdin(ri.random_coefficients(w), basis.overlap(Phi, dV))
+    Kref, Eref, _ = rps.build_occ(Phi, st["points"], st["V"], st["W"], C, dV)
+    with _ctx(lib, w, points=st["points"]) as ctx:
+        V = ctx.array(1)
+        W = ctx.array(2)
+        K, E = ctx.build(C)
+    assert np.abs(V - st["V"]).max() < 1e-8 * np.abs(st["V"]).max()
+    assert np.abs(W - st["W"]).max() < 1e-8 * np.abs(st["W"]).max()
+    assert abs(E - Eref) < 1e-8, (E, Eref)
+    assert _kerr(K, Kref) < 1e-7
+
+
 # ------------------------------------------------------------------ builds, config 1
 def test_build_config1_shared_points(lib, cfg1):
     _say("case: config-1 rPS build, shared points")
