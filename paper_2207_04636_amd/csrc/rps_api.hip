@@ -111,6 +111,7 @@ struct rps_context {
   int64_t gchunk = 0;
   DBuf<double> gCp, gU, gUg, gA, gSp, gM2, gM1T, gK1, gK3, gY, gwork, epart;
   DBuf<float> gU32, gUg32, gA32;   // precision form of the GEMM form: FP32 operands and A chunk
+  DBuf<float> gPhi32, gM1T32;      // and the FP32 operands of K1 = Phi^T M1^T (basis, padded M1^T)
   DBuf<unsigned> ecount;   // last-block counter of the finalize kernel's energy sum (zero between builds)
   int64_t rblocks_main = 0, blocks_main = 0, blocks_l3 = 0;
   int rtiles = 4, gblocks = 1, nwaves = 4;
@@ -167,6 +168,8 @@ struct rps_context {
     for (auto* b : gen) b->release(nullptr);
     gU32.release(nullptr);
     gUg32.release(nullptr);
+    gPhi32.release(nullptr);
+    gM1T32.release(nullptr);
     gA32.release(nullptr);
     ecount.release(nullptr);
     DBuf<double>* jb[] = {&kern, &jCp, &jCin, &jU, &jrho, &jwork, &jpart, &jJ, &Sdev, &mCp, &mSC, &mpart};
@@ -952,9 +955,10 @@ FusedWs context_ws(rps_context& c, int np) {
 // then K1 = Phi^T M1^T, K2 = Phi_g^T M2, B = W o (U_g U_g^T), Y = B U_g,
 // K3 = Phi_g^T Y, e1 = tr(U_g^T M2), e3 = tr(U_g^T Y)  (Eq. 16).  In the
 // precision form the three chunk products run on the FP32 matrix cores with V,
-// U and U_g in FP32 and A_c stored in FP32; the products into M1^T and M2 sum 64
-// terms at a time in FP32 and everything beyond (longer sums, splits, chunks, K)
-// in FP64.
+// U and U_g in FP32 and A_c stored in FP32, and so does K1 (dense basis) from FP32
+// copies of Phi and M1^T; the products into M1^T, M2 and K1 sum 64 terms at a
+// time in FP32 and everything beyond (longer sums, splits, chunks, K) in FP64.
+// U = Phi C stays FP64 (its rounding enters every product of the build).
 
 // workspace of the products with the screened basis's atom blocks
 void ensure_sparse_ws(rps_context& c, int np) {
@@ -999,6 +1003,7 @@ void ensure_general(rps_context& c, int np) {
   c.gU32.release(cnt);
   c.gUg32.release(cnt);
   c.gA32.release(cnt);
+  c.gM1T32.release(cnt);
   if (np > kStreamMaxNp || getenv("RPS_GENERAL_GEMM")) {
     c.gSp.release(cnt);
     if (f32) {
@@ -1007,6 +1012,14 @@ void ensure_general(rps_context& c, int np) {
       c.gA32.alloc(c.nauxp * rc, cnt);
       c.gU32.alloc(c.ngp * npg, cnt);
       c.gUg32.alloc(c.nauxp * npg, cnt);
+      if (!c.sparse) {
+        c.gM1T32.alloc(c.ngp * npg, cnt);
+        if (!c.gPhi32.p) {    // the basis does not change after set-up: converted once, here (no capture)
+          c.gPhi32.alloc(c.ngp * c.Np, cnt);
+          hip_check(to_f32(c.Phi.p, c.ngp * c.Np, c.gPhi32.p, nullptr), "Phi to f32");
+          hip_check(hipStreamSynchronize(nullptr), "sync");
+        }
+      }
     } else {
       c.gA.alloc(std::max(c.nauxp * rc, c.nauxp * c.nauxp), cnt);
     }
@@ -1215,6 +1228,17 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
     prof_mark(c, 2, st);
     if (k1 && c.sparse) {
       sparse_k1(c, c.gM1T.p, np, c.gK1.p, st);
+    } else if (k1 && f32) {
+      // K1 = Phi^T M1^T on the FP32 matrix cores: FP32 basis, M1^T rounded to FP32
+      // (padded to npg columns), FP32 sums over 64 terms and FP64 beyond
+      hip_check(to_f32_pad(c.gM1T.p, c.ngp, np, c.gM1T32.p, npg, st), "M1^T to f32");
+      Gemm32 g;
+      g.M = c.Np; g.N = np; g.Nread = npg; g.K = c.ngp;
+      g.A = c.gPhi32.p; g.lda = c.Np; g.transA = true; g.B = c.gM1T32.p; g.ldb = npg;
+      g.C = c.gK1.p; g.ldc = np;
+      // 22 x 7 output tiles at the 3x3x3 cell: the long K is split 32-39 ways for parallelism
+      g.splitk = gemm32_splitk_for(g.M, g.N, g.K, (g.K + 31) / 32, kSplitWork); g.work = c.gwork.p;
+      hip_check(gemm_f32(g, st), "K1");
     } else if (k1) {
       Gemm g;   // K1 = Phi^T M1^T
       g.M = c.Np; g.N = np; g.K = c.ngp;
