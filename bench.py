@@ -275,6 +275,11 @@ def scf_bench(args, w):
     achieved = flops / (main_ms * 1e-3) / 1e12
     dE = Em - E64
     F_all = 6.0 * n * naux * ng + 4.0 * n * ng * N + 4.0 * n * naux ** 2 + 4.0 * n * naux * N
+    # HBM bytes per build of the GEMM form's main phase (committed counter summary of the 3x3x3 cell)
+    traffic = (_traffic(f"gemm_form_{args.workload}", "k_gemm.hip")
+               if gemm_form and arith == P.PREC_FP32 and args.basis_eps == 0 else None)
+    if traffic is not None:
+        traffic = round(traffic)
     vbytes = (8.0 if arith == P.PREC_FP64 else 4.0) * naux * ng
     out = {
         "metric": "exchange builds/s (K_occ + E_x)",
@@ -303,12 +308,14 @@ def scf_bench(args, w):
         "step_ms": {"median": round(float(np.median(per)), 3), "min": round(float(per.min()), 3),
                     "max": round(float(per.max()), 3)},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
-                     "kernel": ("gemm32_kernel chunk products of the GEMM form (A_c = V o (U_g U_c^T), "
+                     "frac": round(achieved / peak, 4), "traffic": traffic,
+                     "kernel": ("gemm32v_kernel chunk products of the GEMM form (A_c = V o (U_g U_c^T), "
                                 "M1^T_c = A_c^T U_g, M2 += A_c U_c; Eq. 16 lines 1-2) with their split-K "
                                 "reductions, per build" if gemm_form else
                                 "stream_kernel passes (Eq. 16 lines 1-2), per build"),
                      "kernel_avg_us": round(main_ms * 1e3, 1),
+                     "traffic_source": (f"profiles/traffic_gemm_form_{args.workload}.txt (FETCH_SIZE + WRITE_SIZE per "
+                                        f"build, copy-calibrated)" if traffic is not None else None),
                      "algorithmic_flops_per_launch": flops,
                      "algorithmic_V_bytes_per_launch": vbytes,
                      "hbm_view_GBs": round(vbytes / (main_ms * 1e-3) / 1e9, 1)},
@@ -450,13 +457,13 @@ def synthetic_bench(args, w, mprec, run_steps, profile, nsets):
     print(json.dumps(out), flush=True)
 
 
-def _traffic(kernel_tag):
-    """HBM bytes per launch of the fused kernel from the committed rocprofv3
-    counter summary, or None when the kernel source changed since the counters
-    were taken (the summary records the source hash)."""
+def _traffic(kernel_tag, source="k_exchange.hip"):
+    """HBM bytes per launch (per build for the GEMM form's main phase) from the
+    committed rocprofv3 counter summary, or None when the kernel source changed
+    since the counters were taken (the summary records the source hash)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel_tag}.txt")
-    src = os.path.join(ROOT, "paper_2207_04636_amd", "csrc", "k_exchange.hip")
+    src = os.path.join(ROOT, "paper_2207_04636_amd", "csrc", source)
     if not os.path.exists(path):
         return None
     fields = {}
@@ -465,7 +472,7 @@ def _traffic(kernel_tag):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if fields.get("k_exchange.hip sha256") != sha or "traffic bytes per launch" not in fields:
+    if fields.get(f"{source} sha256") != sha or "traffic bytes per launch" not in fields:
         return None
     return float(fields["traffic bytes per launch"])
 
