@@ -298,7 +298,10 @@ def scf_bench(args, w):
         "config": {"workload": f"{w.name}: {ng} grid points, N={N}, n_occ={n}, N_aux={naux}, rPS occ-RI, "
                                + (f"screened basis eps1={args.basis_eps:g}, " if args.basis_eps > 0 else "")
                                + ("mixed: V, U, U_g and A in FP32, FP32 MFMA chunk products with FP32 sums over "
-                                  "64 terms and FP64 beyond; U = Phi C, K1, K2, K3, line 3 and E_x in FP64"
+                                  "64 terms and FP64 beyond, "
+                                  + ("K1 = Phi^T M1^T the same way on FP32 copies of Phi and M1^T; "
+                                     "U = Phi C, K2, K3, line 3 and E_x in FP64" if args.basis_eps == 0 else
+                                     "U = Phi C and K1 from the FP64 atom blocks; K2, K3, line 3 and E_x in FP64")
                                   if mixed and gemm_form and arith == P.PREC_FP32 else
                                   "mixed: V FP32, split-BF16 MFMA streaming products, FP32 in tile, FP64 across"
                                   if arith == P.PREC_BF16X3 else
