@@ -432,6 +432,220 @@ __device__ __forceinline__ int kmajor_row(int q) {
   return ((t >> 2) << 3) + (t & 3) + ((q & 1) << 2);
 }
 
+// The same products with the operands moved from global memory straight into LDS
+// (global_load_lds_dwordx4: lane L of a wave writes bytes [16 L, 16 L + 16) after a
+// wave-uniform LDS base), three LDS stages, loads issued two K steps ahead.  With
+// no staging registers and no LDS store instructions, each 16-deep step is: wait
+// for this step's loads (vmcnt, issue order), one barrier, issue the loads of step
+// t + 2 into the stage step t - 1 used, then the LDS reads and the matrix-core
+// instructions of step t.  The loads past the last step re-read the last step (in
+// bounds), so every step has the same number of loads in flight.  The loop is
+// unrolled over the three stages (one LDS array each), so the compiler can tell a
+// step's reads from the loads in flight to the other stages; it still waits for
+// all of them once per three steps, at the loop head.  Used for the FP64-output
+// products (128 x 64 tiles); unrolled, the 128 x 128 FP32-output tiles spill.
+//
+// LDS layouts are unpadded, with 16-byte chunks permuted within a row (the DMA
+// writes whole 1 KB runs): K-major rows (16 floats, 4 chunks) hold logical chunk q
+// at q ^ ((row >> 1) & 3); MN-major rows (tile width W floats) hold chunk c at
+// c ^ (k & 4).  The matrix-core operand reads of a wave then fall on distinct banks
+// (eight 16-byte reads at a time for K-major rows: 16 row + 4 chunk dwords cover
+// 32 banks; for MN-major rows lanes 0-31 read rows k and k + 4, whose chunk
+// groups the permutation puts 16 banks apart).
+// Requires K (and every K split) a multiple of 16; whole 16-byte pieces past M or
+// the readable N are read from the matrix's edge instead (their products only
+// reach outputs that are not stored).
+template <int TM, int TN, bool TA, bool TB, bool OUT32>
+__global__ __launch_bounds__(256, 2) void gemm32d_kernel(Gemm32 g) {
+  constexpr int BK = 16;
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  constexpr int ASZ = BM * BK, BSZ = BN * BK;                // floats per stage
+  constexpr int NA = ASZ / 4 / 256, NB = BSZ / 4 / 256;      // 16-byte pieces per thread per stage
+  constexpr int NPER = NA + NB;                              // loads per thread per stage
+  static_assert(NA >= 1 && NB >= 1 && NPER < 16, "stage split");
+  // one array per stage: the loop is unrolled by the three stages, so the compiler
+  // sees that a step's LDS reads and the loads it issues touch different arrays
+  __shared__ __attribute__((aligned(16))) float A0[ASZ], A1[ASZ], A2[ASZ];
+  __shared__ __attribute__((aligned(16))) float B0[BSZ], B1[BSZ], B2[BSZ];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int l16 = lane & 15, lq = lane >> 4;
+  // tile order: as gemm32v_kernel (XCD-contiguous ranges, K splits outermost, groups of 8 row panels)
+  const int64_t tiles_n = (g.N + BN - 1) / BN, tiles_m = (g.M + BM - 1) / BM;
+  const int64_t ntile = tiles_n * tiles_m * g.splitk;
+  const int64_t per = ((ntile + 7) / 8);
+  const int64_t T = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (T >= ntile) return;
+  constexpr int64_t GROUP = 8;
+  const int bz = (int)(T / (tiles_n * tiles_m));
+  const int64_t T2 = T % (tiles_n * tiles_m);
+  const int64_t grp = T2 / (GROUP * tiles_n), r2 = T2 % (GROUP * tiles_n);
+  const int64_t gh = (tiles_m - grp * GROUP < GROUP) ? tiles_m - grp * GROUP : GROUP;
+  const int64_t m0 = (grp * GROUP + r2 % gh) * BM, n0 = (r2 / gh) * BN;
+
+  int64_t kbeg = 0, kend = g.K;
+  if (g.splitk > 1) {
+    const int64_t kper = ((g.K + g.splitk - 1) / g.splitk + BK - 1) / BK * BK;
+    kbeg = (int64_t)bz * kper;
+    kend = (kbeg + kper < g.K) ? kbeg + kper : g.K;
+  }
+  const int64_t nk = (kend > kbeg) ? (kend - kbeg) / BK : 0;
+  const int64_t nread = (g.Nread > g.N) ? g.Nread : g.N;
+  const int64_t lda = g.lda, ldb = g.ldb;
+
+  // global source of piece P (0 <= P < 512 or < BSZ / 4) of a stage for K step k0
+  auto src_a = [&](int P, int64_t k0) -> const float* {
+    if constexpr (!TA) {                     // K-major: row P / 4, slot P % 4
+      const int r = P >> 2, q = (P & 3) ^ ((r >> 1) & 3);
+      int64_t gm = m0 + r;
+      if (gm >= g.M) gm = g.M - 1;
+      return g.A + gm * lda + k0 + 4 * q;
+    } else {                                 // MN-major: row k = P / (BM / 4), slot P % (BM / 4)
+      constexpr int CW = BM / 4;
+      const int k = P / CW, c = (P % CW) ^ (k & 4);
+      const int64_t gc = (m0 + 4 * c < g.M) ? m0 + 4 * c : m0;
+      return g.A + (k0 + k) * lda + gc;
+    }
+  };
+  auto src_b = [&](int P, int64_t k0) -> const float* {
+    if constexpr (TB) {                      // K-major: row n = P / 4
+      const int r = P >> 2, q = (P & 3) ^ ((r >> 1) & 3);
+      int64_t gn = n0 + r;
+      if (gn >= nread) gn = nread - 1;
+      return g.B + gn * ldb + k0 + 4 * q;
+    } else {                                 // MN-major: row k = P / (BN / 4)
+      constexpr int CW = BN / 4;
+      const int k = P / CW, c = (P % CW) ^ (k & 4);
+      const int64_t gc = (n0 + 4 * c < nread) ? n0 + 4 * c : n0;
+      return g.B + (k0 + k) * ldb + gc;
+    }
+  };
+  auto issue = [&](int64_t t, float* as, float* bs) {
+    const int64_t k0 = kbeg + ((t < nk) ? t : nk - 1) * BK;   // past the end: the last step again
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int run = i * 4 + wave;          // 1 KB run of this wave instruction
+      __builtin_amdgcn_global_load_lds((const void*)src_a(run * 64 + lane, k0),
+                                       (__attribute__((address_space(3))) void*)&as[run * 256], 16, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int run = i * 4 + wave;
+      __builtin_amdgcn_global_load_lds((const void*)src_b(run * 64 + lane, k0),
+                                       (__attribute__((address_space(3))) void*)&bs[run * 256], 16, 0, 0);
+    }
+  };
+
+  f4_t acc[TM][TN];
+  constexpr int FLUSH = OUT32 ? (1 << 30) : 64 / BK;   // FP64 output: FP32 sums over 64 terms of K
+  double acc64[OUT32 ? 1 : TM][OUT32 ? 1 : TN][4];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = zero_f4();
+  if constexpr (!OUT32) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
+  }
+
+  if (nk > 0) {
+    issue(0, A0, B0);
+    issue(1, A1, B1);
+  }
+  // step t: its stage (as, bs) and the stage of step t - 1, which receives step t + 2
+  auto step = [&](int64_t t, const float* as, const float* bs, float* an, float* bn) {
+    // this step's loads landed (the next step's NPER may still be in flight)
+    __builtin_amdgcn_s_waitcnt(0xF70 | NPER);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    issue(t + 2, an, bn);
+    f4_t a[TM], b[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int m = wm * 16 * TM + i * 16 + l16;
+      if constexpr (!TA) {
+        a[i] = *reinterpret_cast<const f4_t*>(&as[m * 16 + ((lq ^ ((m >> 1) & 3)) << 2)]);
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int k = 4 * lq + kk;
+          a[i][kk] = as[k * BM + (((m >> 2) ^ (k & 4)) << 2) + (m & 3)];
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int n = wn * 16 * TN + j * 16 + l16;
+      if constexpr (TB) {
+        b[j] = *reinterpret_cast<const f4_t*>(&bs[n * 16 + ((lq ^ ((n >> 1) & 3)) << 2)]);
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int k = 4 * lq + kk;
+          b[j][kk] = bs[k * BN + (((n >> 2) ^ (k & 4)) << 2) + (n & 3)];
+        }
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = mfma_f32(a[i][kk], b[j][kk], acc[i][j]);
+    if constexpr (!OUT32) {
+      if ((t + 1) % FLUSH == 0 || t + 1 == nk) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[i][j][r];
+            acc[i][j] = zero_f4();
+          }
+      }
+    }
+  };
+  for (int64_t t = 0; t < nk; t += 3) {
+    step(t, A0, B0, A2, B2);
+    if (t + 1 >= nk) break;
+    step(t + 1, A1, B1, A0, B0);
+    if (t + 2 >= nk) break;
+    step(t + 2, A2, B2, A1, B1);
+  }
+  // the two loads issued past the last step are still in flight: let them land
+  // before the workgroup's LDS can be reused
+  __builtin_amdgcn_s_waitcnt(0xF70);
+  asm volatile("" ::: "memory");
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = m0 + wm * 16 * TM + i * 16 + d32_row(lane, r);
+        const int64_t gn = n0 + wn * 16 * TN + j * 16 + l16;
+        if (gm < g.M && gn < g.N) {
+          if constexpr (OUT32) {
+            g.C32[gm * g.ldc + gn] = g.D32[gm * g.ldd + gn] * ((float)g.alpha * acc[i][j][r]);
+          } else {
+            const double v = g.alpha * acc64[i][j][r];
+            if (g.splitk > 1) {
+              g.work[((int64_t)bz * g.M + gm) * g.N + gn] = v;
+              continue;
+            }
+            double* c = g.C + gm * g.ldc + gn;
+            *c = (g.beta == 0.0) ? v : v + g.beta * *c;
+          }
+        }
+      }
+}
+
 template <int TM, int TN, bool TA, bool TB, bool OUT32, int BK>
 __global__ __launch_bounds__(256, 2) void gemm32v_kernel(Gemm32 g) {
   constexpr int BM = 32 * TM, BN = 32 * TN;
@@ -740,6 +954,14 @@ void launch32v_bk(const Gemm32& g, dim3 grid, hipStream_t s) {
 // K steps of 16: at the 3x3x3 cell's chunk shapes they measured 102-110 TF/s against
 // 98-106 TF/s with steps of 32 (twice the LDS and prefetch registers per workgroup)
 template <int TN, bool OUT32>
+void launch32d(const Gemm32& g, dim3 grid, hipStream_t s) {
+  if (!g.transA && !g.transB) hipLaunchKernelGGL((gemm32d_kernel<4, TN, false, false, OUT32>), grid, dim3(256), 0, s, g);
+  else if (g.transA && !g.transB) hipLaunchKernelGGL((gemm32d_kernel<4, TN, true, false, OUT32>), grid, dim3(256), 0, s, g);
+  else if (!g.transA && g.transB) hipLaunchKernelGGL((gemm32d_kernel<4, TN, false, true, OUT32>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((gemm32d_kernel<4, TN, true, true, OUT32>), grid, dim3(256), 0, s, g);
+}
+
+template <int TN, bool OUT32>
 void launch32v(const Gemm32& g, dim3 grid, hipStream_t s) {
   launch32v_bk<TN, OUT32, 16>(g, grid, s);
 }
@@ -778,11 +1000,17 @@ hipError_t gemm_f32(const Gemm32& g0, hipStream_t s) {
   const int64_t ntile = (int64_t)grid.x * grid.y * grid.z;
   const dim3 grid1((unsigned)((ntile + 7) / 8 * 8));
   if (vec && ntile > (int64_t)UINT32_MAX - 8) return hipErrorInvalidValue;
+  // operands straight into LDS when every K step is whole (K a multiple of 16)
+  const char* dv = getenv("RPS_GEMM32_DIRECT");    // "0": the register-staged kernel (comparison runs)
+  // (the FP64-output products; the 128 x 128 FP32-output tiles need more registers unrolled)
+  const bool direct = vec && !out32 && g.K % 16 == 0 && !(dv && dv[0] == '0');
   if (bn == 64) {
-    if (vec) { if (out32) launch32v<2, true>(g, grid1, s); else launch32v<2, false>(g, grid1, s); }
+    if (direct) launch32d<2, false>(g, grid1, s);
+    else if (vec) { if (out32) launch32v<2, true>(g, grid1, s); else launch32v<2, false>(g, grid1, s); }
     else { if (out32) launch32<2, true>(g, grid, s); else launch32<2, false>(g, grid, s); }
   } else {
-    if (vec) launch32v<4, true>(g, grid1, s); else launch32<4, true>(g, grid, s);
+    if (vec) launch32v<4, true>(g, grid1, s);
+    else launch32<4, true>(g, grid, s);
   }
   if (g.splitk > 1) {
     const int64_t cnt = g.M * g.N;
