@@ -442,8 +442,8 @@ __device__ __forceinline__ int kmajor_row(int q) {
 // bounds), so every step has the same number of loads in flight.  The loop is
 // unrolled over the three stages (one LDS array each), so the compiler can tell a
 // step's reads from the loads in flight to the other stages; it still waits for
-// all of them once per three steps, at the loop head.  Used for the FP64-output
-// products (128 x 64 tiles); unrolled, the 128 x 128 FP32-output tiles spill.
+// all of them once per three steps, at the loop head.  Used on 128 x 64 tiles
+// (unrolled, 128 x 128 tiles spill registers).
 //
 // LDS layouts are unpadded, with 16-byte chunks permuted within a row (the DMA
 // writes whole 1 KB runs): K-major rows (16 floats, 4 chunks) hold logical chunk q
@@ -991,21 +991,21 @@ hipError_t gemm_f32(const Gemm32& g0, hipStream_t s) {
   if (g.splitk < 1) g.splitk = 1;
   // 32-bit per-lane offsets inside a tile (at most 128 rows of either operand)
   if (g.lda > INT32_MAX / 128 || g.ldb > INT32_MAX / 128) return hipErrorInvalidValue;
-  const int bn = out32 ? gemm32_tile_n(g.N) : 64;
+  // operands straight into LDS when every K step is whole (K a multiple of 16), on
+  // 128 x 64 tiles; otherwise the register-staged kernel (128 x 128 tiles for FP32 output)
+  const char* dv = getenv("RPS_GEMM32_DIRECT");    // "0": the register-staged kernel (comparison runs)
+  const bool vec = vec4_ok(g);
+  const bool direct = vec && g.K % 16 == 0 && !(dv && dv[0] == '0');
+  const int bn = (out32 && !direct) ? gemm32_tile_n(g.N) : 64;
   dim3 grid((unsigned)((g.N + bn - 1) / bn), (unsigned)((g.M + 127) / 128), (unsigned)g.splitk);
   if (grid.y > 65535u) return hipErrorInvalidValue;
-  const bool vec = vec4_ok(g);
-  // the 16-byte kernel orders its tiles itself: one dimension, padded to whole rounds
+  // the 16-byte kernels order their tiles themselves: one dimension, padded to whole rounds
   // of the eight XCDs (the padding workgroups exit at once)
   const int64_t ntile = (int64_t)grid.x * grid.y * grid.z;
   const dim3 grid1((unsigned)((ntile + 7) / 8 * 8));
   if (vec && ntile > (int64_t)UINT32_MAX - 8) return hipErrorInvalidValue;
-  // operands straight into LDS when every K step is whole (K a multiple of 16)
-  const char* dv = getenv("RPS_GEMM32_DIRECT");    // "0": the register-staged kernel (comparison runs)
-  // (the FP64-output products; the 128 x 128 FP32-output tiles need more registers unrolled)
-  const bool direct = vec && !out32 && g.K % 16 == 0 && !(dv && dv[0] == '0');
   if (bn == 64) {
-    if (direct) launch32d<2, false>(g, grid1, s);
+    if (direct) { if (out32) launch32d<2, true>(g, grid1, s); else launch32d<2, false>(g, grid1, s); }
     else if (vec) { if (out32) launch32v<2, true>(g, grid1, s); else launch32v<2, false>(g, grid1, s); }
     else { if (out32) launch32<2, true>(g, grid, s); else launch32<2, false>(g, grid, s); }
   } else {
