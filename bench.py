@@ -312,7 +312,7 @@ def scf_bench(args, w):
                     "max": round(float(per.max()), 3)},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": traffic,
-                     "kernel": ("gemm32v_kernel chunk products of the GEMM form (A_c = V o (U_g U_c^T), "
+                     "kernel": ("gemm32d_kernel chunk products of the GEMM form (A_c = V o (U_g U_c^T), "
                                 "M1^T_c = A_c^T U_g, M2 += A_c U_c; Eq. 16 lines 1-2) with their split-K "
                                 "reductions, per build" if gemm_form else
                                 "stream_kernel passes (Eq. 16 lines 1-2), per build"),
