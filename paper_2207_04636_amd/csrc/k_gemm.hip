@@ -440,10 +440,10 @@ __device__ __forceinline__ int kmajor_row(int q) {
 // t + 2 into the stage step t - 1 used, then the LDS reads and the matrix-core
 // instructions of step t.  The loads past the last step re-read the last step (in
 // bounds), so every step has the same number of loads in flight.  The loop is
-// unrolled over the three stages (one LDS array each), so the compiler can tell a
-// step's reads from the loads in flight to the other stages; it still waits for
-// all of them once per three steps, at the loop head.  Used on 128 x 64 tiles
-// (unrolled, 128 x 128 tiles spill registers).
+// unrolled over the three stages (one LDS array each, passed to each step as
+// restrict pointers), so the compiler can tell a step's reads from the loads in
+// flight to the other stages and adds no wait of its own beyond the explicit one.
+// Used on 128 x 64 tiles (unrolled, 128 x 128 tiles spill registers).
 //
 // LDS layouts are unpadded, with 16-byte chunks permuted within a row (the DMA
 // writes whole 1 KB runs): K-major rows (16 floats, 4 chunks) hold logical chunk q
@@ -556,8 +556,12 @@ __global__ __launch_bounds__(256, 2) void gemm32d_kernel(Gemm32 g) {
     issue(0, A0, B0);
     issue(1, A1, B1);
   }
-  // step t: its stage (as, bs) and the stage of step t - 1, which receives step t + 2
-  auto step = [&](int64_t t, const float* as, const float* bs, float* an, float* bn) {
+  // step t: its stage (as, bs) and the stage of step t - 1, which receives step t + 2.
+  // The four are distinct arrays; saying so (restrict) lets the compiler's own wait
+  // for loads into LDS tell them apart across the loop's back edge too, where it
+  // otherwise waits for every load in flight once per three steps.
+  auto step = [&](int64_t t, const float* __restrict__ as, const float* __restrict__ bs,
+                  float* __restrict__ an, float* __restrict__ bn) {
     // this step's loads landed (the next step's NPER may still be in flight)
     __builtin_amdgcn_s_waitcnt(0xF70 | NPER);
     asm volatile("" ::: "memory");

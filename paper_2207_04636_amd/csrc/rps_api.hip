@@ -1186,8 +1186,8 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
     for (int64_t r0 = 0; r0 < c.ngp; r0 += c.gchunk) {
       const int64_t rc = std::min(c.gchunk, c.ngp - r0);
       if (f32) {
-        Gemm32 a;   // A_c = V[:, c] o (U_g U[c]^T), FP32 (the zero columns add nothing)
-        a.M = c.nauxp; a.N = rc; a.K = npg;
+        Gemm32 a;   // A_c = V[:, c] o (U_g U[c]^T), FP32; K = np rounded up to whole
+        a.M = c.nauxp; a.N = rc; a.K = round_up(np, 16);   // 16-deep steps (zero columns add nothing)
         a.A = c.gUg32.p; a.lda = npg; a.B = c.gU32.p + r0 * npg; a.ldb = npg; a.transB = true;
         a.C32 = c.gA32.p; a.ldc = rc; a.D32 = c.V32.p + r0; a.ldd = c.ngp;
         hip_check(gemm_f32(a, st), "A chunk");
