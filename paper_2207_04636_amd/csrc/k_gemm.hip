@@ -443,7 +443,8 @@ __device__ __forceinline__ int kmajor_row(int q) {
 // unrolled over the three stages (one LDS array each, passed to each step as
 // restrict pointers), so the compiler can tell a step's reads from the loads in
 // flight to the other stages and adds no wait of its own beyond the explicit one.
-// Used on 128 x 64 tiles (unrolled, 128 x 128 tiles spill registers).
+// FP64 output on 128 x 64 tiles (on 128 x 128 its accumulators spill registers);
+// FP32 output on 128 x 128 tiles, or 128 x 64 where those pad N less.
 //
 // LDS layouts are unpadded, with 16-byte chunks permuted within a row (the DMA
 // writes whole 1 KB runs): K-major rows (16 floats, 4 chunks) hold logical chunk q
@@ -614,12 +615,32 @@ __global__ __launch_bounds__(256, 2) void gemm32d_kernel(Gemm32 g) {
       }
     }
   };
-  for (int64_t t = 0; t < nk; t += 3) {
-    step(t, A0, B0, A2, B2);
-    if (t + 1 >= nk) break;
-    step(t + 1, A1, B1, A0, B0);
-    if (t + 2 >= nk) break;
-    step(t + 2, A2, B2, A1, B1);
+  // Loop form, measured per product at the 3x3x3 cell's shapes.  Whole triples of
+  // steps in the loop and the last one or two after it: no exits inside the loop,
+  // which keeps the FP32-output tiles at 102-113 registers on 128 x 64 (four waves
+  // per SIMD) and lets 128 x 128 fit without spilling, and ran the MN-major-A
+  // products 1.5% faster.  The K-major-A, FP64-output product (M2 += A_c U_c) ran 7%
+  // faster with an exit after each step, so it keeps that form.
+  constexpr bool kExitEachStep = !OUT32 && !TA;
+  if constexpr (kExitEachStep) {
+    for (int64_t t = 0; t < nk; t += 3) {
+      step(t, A0, B0, A2, B2);
+      if (t + 1 >= nk) break;
+      step(t + 1, A1, B1, A0, B0);
+      if (t + 2 >= nk) break;
+      step(t + 2, A2, B2, A1, B1);
+    }
+  } else {
+    int64_t t = 0;
+    for (; t + 3 <= nk; t += 3) {
+      step(t, A0, B0, A2, B2);
+      step(t + 1, A1, B1, A0, B0);
+      step(t + 2, A2, B2, A1, B1);
+    }
+    if (t < nk) {
+      step(t, A0, B0, A2, B2);
+      if (t + 1 < nk) step(t + 1, A1, B1, A0, B0);
+    }
   }
   // the two loads issued past the last step are still in flight: let them land
   // before the workgroup's LDS can be reused
@@ -995,12 +1016,13 @@ hipError_t gemm_f32(const Gemm32& g0, hipStream_t s) {
   if (g.splitk < 1) g.splitk = 1;
   // 32-bit per-lane offsets inside a tile (at most 128 rows of either operand)
   if (g.lda > INT32_MAX / 128 || g.ldb > INT32_MAX / 128) return hipErrorInvalidValue;
-  // operands straight into LDS when every K step is whole (K a multiple of 16), on
-  // 128 x 64 tiles; otherwise the register-staged kernel (128 x 128 tiles for FP32 output)
+  // operands straight into LDS when every K step is whole (K a multiple of 16),
+  // otherwise the register-staged kernel; FP64 output on 128 x 64 tiles, FP32 output
+  // on 128 x 128 unless 128 x 64 pads N less
   const char* dv = getenv("RPS_GEMM32_DIRECT");    // "0": the register-staged kernel (comparison runs)
   const bool vec = vec4_ok(g);
   const bool direct = vec && g.K % 16 == 0 && !(dv && dv[0] == '0');
-  const int bn = (out32 && !direct) ? gemm32_tile_n(g.N) : 64;
+  const int bn = out32 ? gemm32_tile_n(g.N) : 64;
   dim3 grid((unsigned)((g.N + bn - 1) / bn), (unsigned)((g.M + 127) / 128), (unsigned)g.splitk);
   if (grid.y > 65535u) return hipErrorInvalidValue;
   // the 16-byte kernels order their tiles themselves: one dimension, padded to whole rounds
@@ -1013,7 +1035,8 @@ hipError_t gemm_f32(const Gemm32& g0, hipStream_t s) {
     else if (vec) { if (out32) launch32v<2, true>(g, grid1, s); else launch32v<2, false>(g, grid1, s); }
     else { if (out32) launch32<2, true>(g, grid, s); else launch32<2, false>(g, grid, s); }
   } else {
-    if (vec) launch32v<4, true>(g, grid1, s);
+    if (direct) launch32d<4, true>(g, grid1, s);
+    else if (vec) launch32v<4, true>(g, grid1, s);
     else launch32<4, true>(g, grid, s);
   }
   if (g.splitk > 1) {
