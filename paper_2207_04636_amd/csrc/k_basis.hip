@@ -152,6 +152,13 @@ __global__ void symmetrize_kernel(double* A, int64_t n, int64_t ld) {
   A[j * ld + i] = v;
 }
 
+__global__ void mirror_upper_kernel(double* A, int64_t n, int64_t ld) {
+  const int64_t t = flat_id();
+  if (t >= n * n) return;
+  const int64_t i = t / n, j = t % n;
+  if (j < i) A[i * ld + j] = A[j * ld + i];
+}
+
 __global__ void transpose_kernel(const double* __restrict__ in, int64_t ldi, int64_t rows, int64_t cols,
                                  double* __restrict__ out, int64_t ldo) {
   __shared__ double tile[32][33];
@@ -258,6 +265,11 @@ hipError_t fill(double* X, int64_t count, double v, hipStream_t s) {
 
 hipError_t symmetrize(double* A, int64_t n, int64_t ld, hipStream_t s) {
   hipLaunchKernelGGL(symmetrize_kernel, flat_grid(n * n), dim3(256), 0, s, A, n, ld);
+  return hipGetLastError();
+}
+
+hipError_t mirror_upper(double* A, int64_t n, int64_t ld, hipStream_t s) {
+  hipLaunchKernelGGL(mirror_upper_kernel, flat_grid(n * n), dim3(256), 0, s, A, n, ld);
   return hipGetLastError();
 }
 

@@ -214,7 +214,7 @@ constexpr int64_t kSplitWork = 64ll << 20;   // doubles of split-K partials (512
 constexpr int kEnergyBlocks = 256;            // most blocks the energy dot products are split over
 constexpr int kStreamMaxNp = 128;             // largest padded n of the streaming form
 constexpr int64_t kChiPanel = 32768;          // grid columns per fitting-function panel (set-up)
-constexpr int64_t kWBlock = 8192;             // grid columns per block of the W product (set-up)
+constexpr int64_t kWPanel = 1024;             // rows per panel of the V and W stage (set-up)
 constexpr int kStreamBlocks = 512;            // workgroups aimed at per streaming launch (default)
 constexpr int kStreamMaxTarget = 1024;        // largest target the tuner tries
 constexpr int64_t kStreamPartRows = (int64_t)kStreamMaxTarget * 128;   // rows of split partials
@@ -569,8 +569,9 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
     const double vbytes = (given && prec != RPS_PREC_FP64) ? 0.0 : 8.0 * (double)c.nauxp * c.ngp;
     const double persist = 8.0 * ((double)c.ngp * c.Np + (double)c.nauxp * c.Np + (double)c.nauxp * c.nauxp) +
                            vbytes + ((prec != RPS_PREC_FP64) ? 4.0 * (double)c.nauxp * c.ngp : 0.0);
-    const double xgg = 8.0 * 3.0 * (double)c.nauxp * c.nauxp;   // L, T and its transpose
-    const double xblk = 8.0 * (double)c.nauxp * (double)kWBlock;
+    // the Cholesky factor for chi, then a panel of chi rows and the split partials for W
+    const double xgg = 8.0 * (double)c.nauxp * c.nauxp;
+    const double xblk = std::max(0.0, 8.0 * ((double)std::min(kWPanel, c.nauxp) * c.ngp + (double)kSplitWork) - xgg);
     double selb = 0.0;
     if (!points_in && !c.exact) {
       const double ncand = (mode == RPS_SELECT_GLOBAL) ? (double)c.ng : (double)c.naux + 10.0 * c.natom + 64;
@@ -711,39 +712,42 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
       hip_check(hipStreamSynchronize(st), "sync");
     }
     stage("fitting functions chi", st);
-    // ---- V = Vc chi (Sec. 3.2)
-    hip_check(poisson_rows(c.V.p, c.nauxp, c.ngp, c.mesh, dkern, st), "poisson");
-    stage("potentials V", st);
-    // ---- W = V chi^T = (V X_gR^T) X_gg^-1  (Eq. 14), X_gR recomputed in column blocks
-    {
-      const int64_t bc = kWBlock;
-      DBuf<double> T, Xb;
-      T.alloc(c.nauxp * c.nauxp, &tmpb);
-      Xb.alloc(c.nauxp * bc, &tmpb);
-      for (int64_t r0 = 0; r0 < c.ngp; r0 += bc) {
-        const int64_t nc = std::min(bc, c.ngp - r0);
-        Gemm g;
-        g.M = c.nauxp; g.N = nc; g.K = c.Np;
-        g.A = c.Phig.p; g.lda = c.Np; g.B = c.Phi.p + r0 * c.Np; g.ldb = c.Np; g.transB = true;
-        g.C = Xb.p; g.ldc = bc; g.epi = EPI_SQUARE;
-        hip_check(gemm_f64(g, st), "X_gR block");
-        Gemm t;
-        t.M = c.nauxp; t.N = c.nauxp; t.K = nc;
-        t.A = c.V.p + r0; t.lda = c.ngp; t.B = Xb.p; t.ldb = bc; t.transB = true;
-        t.C = T.p; t.ldc = c.nauxp; t.beta = (r0 == 0) ? 0.0 : 1.0;
-        hip_check(gemm_f64(t, st), "T");
-      }
-      // W^T = X_gg^-1 T^T
-      hip_check(transpose(T.p, c.nauxp, c.nauxp, c.nauxp, c.W.p, c.nauxp, st), "transpose");
-      hip_check(tri_solve_lower(L.p, c.nauxp, c.nauxp, c.W.p, c.nauxp, c.nauxp, false, st), "solve L");
-      hip_check(tri_solve_lower(L.p, c.nauxp, c.nauxp, c.W.p, c.nauxp, c.nauxp, true, st), "solve L^T");
-      hip_check(symmetrize(c.W.p, c.nauxp, c.nauxp, st), "symmetrize");
-      hip_check(hipStreamSynchronize(st), "sync");
-      T.release(nullptr);
-      Xb.release(nullptr);
-    }
+    hip_check(hipStreamSynchronize(st), "sync");
     L.release(nullptr);
-    stage("W", st);
+    // ---- V = Vc chi (Sec. 3.2) and W = V chi^T (Eq. 14) together, in row panels.  While
+    //      panel a turns from chi into V, the rows after it still hold chi, so the block
+    //      row W[a, a:] = V[a] chi[a:]^T is formed then (chi[a] itself from a copy kept for
+    //      the diagonal block).  W is symmetric: the upper triangle is formed, the lower one
+    //      copied from it.  Half the flops of the full product, and chi is not re-formed.
+    {
+      const int64_t P = std::min(kWPanel, c.nauxp);     // a multiple of 64 (rows in pairs)
+      DBuf<double> X, work;
+      X.alloc(P * c.ngp, &tmpb);
+      work.alloc(kSplitWork, &tmpb);
+      for (int64_t a0 = 0; a0 < c.nauxp; a0 += P) {
+        const int64_t pa = std::min(P, c.nauxp - a0);
+        double* Va = c.V.p + a0 * c.ngp;
+        hip_check(hipMemcpyAsync(X.p, Va, (size_t)(pa * c.ngp) * 8, hipMemcpyDeviceToDevice, st), "chi panel");
+        hip_check(poisson_rows(Va, pa, c.ngp, c.mesh, dkern, st), "poisson");
+        for (int part = 0; part < 2; ++part) {
+          Gemm g;   // part 0: W[a, a] = V[a] chi[a]^T; part 1: W[a, after a] = V[a] chi[after a]^T
+          g.M = pa; g.K = c.ngp;
+          g.N = (part == 0) ? pa : c.nauxp - a0 - pa;
+          if (g.N <= 0) continue;
+          g.A = Va; g.lda = c.ngp;
+          g.B = (part == 0) ? X.p : Va + pa * c.ngp; g.ldb = c.ngp; g.transB = true;
+          g.C = c.W.p + a0 * c.nauxp + a0 + ((part == 0) ? 0 : pa); g.ldc = c.nauxp;
+          gemm_plan(g, kSplitWork);
+          g.work = work.p;
+          hip_check(gemm_f64(g, st), "W block row");
+        }
+      }
+      hip_check(mirror_upper(c.W.p, c.nauxp, c.nauxp, st), "mirror");
+      hip_check(hipStreamSynchronize(st), "sync");
+      X.release(nullptr);
+      work.release(nullptr);
+    }
+    stage("potentials V and W", st);
   }
   hip_check(hipStreamSynchronize(st), "sync");
   if (prec != RPS_PREC_FP64) {

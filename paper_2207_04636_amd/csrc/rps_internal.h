@@ -123,6 +123,8 @@ hipError_t add_diag(double* X, int64_t ld, int64_t i0, int64_t i1, double v, hip
 hipError_t fill(double* X, int64_t count, double v, hipStream_t s);
 // B = (A + A^T)/2 in place for an n x n matrix (ld)
 hipError_t symmetrize(double* A, int64_t n, int64_t ld, hipStream_t s);
+// A[i][j] = A[j][i] for i > j: the lower triangle copied from the upper
+hipError_t mirror_upper(double* A, int64_t n, int64_t ld, hipStream_t s);
 // out[j*ldo + i] = in[i*ldi + j] (i < rows, j < cols)
 hipError_t transpose(const double* in, int64_t ldi, int64_t rows, int64_t cols, double* out,
                      int64_t ldo, hipStream_t s);
