@@ -720,7 +720,12 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
     //      the diagonal block).  W is symmetric: the upper triangle is formed, the lower one
     //      copied from it.  Half the flops of the full product, and chi is not re-formed.
     {
-      const int64_t P = std::min(kWPanel, c.nauxp);     // a multiple of 64 (rows in pairs)
+      int64_t P = kWPanel;
+      if (const char* wp = getenv("RPS_W_PANEL")) {      // smaller panels (tests of the panel path)
+        const int64_t v = atoll(wp);
+        if (v >= 64 && v <= kWPanel && v % 64 == 0) P = v;
+      }
+      P = std::min(P, c.nauxp);                          // a multiple of 64 (rows in pairs)
       DBuf<double> X, work;
       X.alloc(P * c.ngp, &tmpb);
       work.alloc(kSplitWork, &tmpb);

@@ -64,13 +64,27 @@ def test_basis_and_voronoi_config1(lib, cfg1):
     assert info["nbas"] == 40 and info["ngrid"] == 24 ** 3 and info["naux"] == 160
 
 
-def test_setup_products_config1(lib, cfg1):
-    _say("case: config-1 V and W with oracle points")
+@pytest.mark.parametrize("panel", [None, 64])
+def test_setup_products_config1(lib, cfg1, panel):
+    """V and W against the oracle.  With panel = 64 the set-up forms V and W in
+    three row panels of 64 (N_aux = 160, padded to 192): the block rows of W
+    after the first panel, the chi rows kept for each diagonal block and the
+    copied lower triangle all enter the comparison."""
+    _say(f"case: config-1 V and W with oracle points, W panel {panel or 'default'}")
     w, st = cfg1["w"], cfg1["st"]
-    with _ctx(lib, w, points=st["points"]) as ctx:
-        V = ctx.array(1)
-        W = ctx.array(2)
-        assert np.array_equal(ctx.points(), st["points"])
+    old = os.environ.get("RPS_W_PANEL")
+    if panel:
+        os.environ["RPS_W_PANEL"] = str(panel)
+    try:
+        with _ctx(lib, w, points=st["points"]) as ctx:
+            V = ctx.array(1)
+            W = ctx.array(2)
+            assert np.array_equal(ctx.points(), st["points"])
+    finally:
+        if old is None:
+            os.environ.pop("RPS_W_PANEL", None)
+        else:
+            os.environ["RPS_W_PANEL"] = old
     assert np.abs(V - st["V"]).max() < 1e-8 * np.abs(st["V"]).max()
     assert np.abs(W - st["W"]).max() < 1e-8 * np.abs(st["W"]).max()
     np.testing.assert_array_equal(W, W.T)
