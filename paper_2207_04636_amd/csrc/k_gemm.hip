@@ -876,6 +876,183 @@ __global__ __launch_bounds__(256, 2) void gemm32v_kernel(Gemm32 g) {
       }
 }
 
+// FP64 products with the operands moved from global memory straight into LDS, as
+// gemm32d_kernel does for FP32: global_load_lds_dwordx4 (two doubles per lane),
+// three LDS stages, loads issued two K steps ahead, one barrier per step, the loop
+// unrolled over the stages with restrict stage pointers and no exit inside it.  A
+// K step is 8 deep (two v_mfma_f64_16x16x4_f64 per output block); lane group q of
+// instruction kk takes k = 2 q + kk, so a lane reads its two K values of a K-major
+// row as one 16-byte LDS read.  K-major rows (8 doubles, four 16-byte chunks) hold
+// chunk q at q ^ ((row >> 1) & 3); MN-major rows are unpermuted (a 16-lane group of
+// an 8-byte read covers one 128-byte row segment).  Tiles follow the XCD-grouped
+// one-dimensional order of the FP32 kernels.  Requires K and every K split a
+// multiple of 8, even leading dimensions, 16-byte aligned bases and an even width
+// for an MN-major operand; whole 16-byte pieces past M or N are read from the
+// matrix's edge (their products reach only outputs that are not stored).
+template <int TM, int TN, bool TA, bool TB>
+__global__ __launch_bounds__(256, 2) void gemm64d_kernel(Gemm g) {
+  constexpr int BK8 = 8;
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  constexpr int ASZ = BM * BK8, BSZ = BN * BK8;              // doubles per stage
+  constexpr int NA = ASZ / 2 / 256, NB = BSZ / 2 / 256;      // 16-byte pieces per thread per stage
+  constexpr int NPER = NA + NB;
+  static_assert(NA >= 1 && NB >= 1 && NPER < 16, "stage split");
+  __shared__ __attribute__((aligned(16))) double A0[ASZ], A1[ASZ], A2[ASZ];
+  __shared__ __attribute__((aligned(16))) double B0[BSZ], B1[BSZ], B2[BSZ];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int64_t tiles_n = (g.N + BN - 1) / BN, tiles_m = (g.M + BM - 1) / BM;
+  const int64_t ntile = tiles_n * tiles_m * g.splitk;
+  const int64_t per = ((ntile + 7) / 8);
+  const int64_t T = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (T >= ntile) return;
+  constexpr int64_t GROUP = 8;
+  const int bz = (int)(T / (tiles_n * tiles_m));
+  const int64_t T2 = T % (tiles_n * tiles_m);
+  const int64_t grp = T2 / (GROUP * tiles_n), r2 = T2 % (GROUP * tiles_n);
+  const int64_t gh = (tiles_m - grp * GROUP < GROUP) ? tiles_m - grp * GROUP : GROUP;
+  const int64_t m0 = (grp * GROUP + r2 % gh) * BM, n0 = (r2 / gh) * BN;
+  if (g.lower_only && n0 > m0 + BM - 1) return;
+
+  int64_t kbeg = 0, kend = g.K;
+  if (g.splitk > 1) {
+    const int64_t kper = ((g.K + g.splitk - 1) / g.splitk + BK8 - 1) / BK8 * BK8;
+    kbeg = (int64_t)bz * kper;
+    kend = (kbeg + kper < g.K) ? kbeg + kper : g.K;
+  }
+  const int64_t nk = (kend > kbeg) ? (kend - kbeg) / BK8 : 0;
+  const int64_t lda = g.lda, ldb = g.ldb;
+
+  auto src_a = [&](int P, int64_t k0) -> const double* {
+    if constexpr (!TA) {                     // K-major: row P / 4, chunk P % 4
+      const int r = P >> 2, q = (P & 3) ^ ((r >> 1) & 3);
+      int64_t gm = m0 + r;
+      if (gm >= g.M) gm = g.M - 1;
+      return g.A + gm * lda + k0 + 2 * q;
+    } else {                                 // MN-major: row k = P / (BM / 2)
+      constexpr int CW = BM / 2;
+      const int k = P / CW, c = P % CW;
+      const int64_t gc = (m0 + 2 * c < g.M) ? m0 + 2 * c : m0;
+      return g.A + (k0 + k) * lda + gc;
+    }
+  };
+  auto src_b = [&](int P, int64_t k0) -> const double* {
+    if constexpr (TB) {                      // K-major: row n = P / 4
+      const int r = P >> 2, q = (P & 3) ^ ((r >> 1) & 3);
+      int64_t gn = n0 + r;
+      if (gn >= g.N) gn = g.N - 1;
+      return g.B + gn * ldb + k0 + 2 * q;
+    } else {                                 // MN-major: row k = P / (BN / 2)
+      constexpr int CW = BN / 2;
+      const int k = P / CW, c = P % CW;
+      const int64_t gc = (n0 + 2 * c < g.N) ? n0 + 2 * c : n0;
+      return g.B + (k0 + k) * ldb + gc;
+    }
+  };
+  auto issue = [&](int64_t t, double* as, double* bs) {
+    const int64_t k0 = kbeg + ((t < nk) ? t : nk - 1) * BK8;   // past the end: the last step again
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int run = i * 4 + wave;          // 1 KB run of this wave instruction
+      __builtin_amdgcn_global_load_lds((const void*)src_a(run * 64 + lane, k0),
+                                       (__attribute__((address_space(3))) void*)&as[run * 128], 16, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int run = i * 4 + wave;
+      __builtin_amdgcn_global_load_lds((const void*)src_b(run * 64 + lane, k0),
+                                       (__attribute__((address_space(3))) void*)&bs[run * 128], 16, 0, 0);
+    }
+  };
+
+  d4_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = zero_d4();
+
+  if (nk > 0) {
+    issue(0, A0, B0);
+    issue(1, A1, B1);
+  }
+  auto step = [&](int64_t t, const double* __restrict__ as, const double* __restrict__ bs,
+                  double* __restrict__ an, double* __restrict__ bn) {
+    __builtin_amdgcn_s_waitcnt(0xF70 | NPER);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    issue(t + 2, an, bn);
+    double a[TM][2], b[TN][2];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int m = wm * 16 * TM + i * 16 + l16;
+      if constexpr (!TA) {
+        const d2_t v = *reinterpret_cast<const d2_t*>(&as[m * 8 + ((lq ^ ((m >> 1) & 3)) << 1)]);
+        a[i][0] = v[0];
+        a[i][1] = v[1];
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) a[i][kk] = as[(2 * lq + kk) * BM + m];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int n = wn * 16 * TN + j * 16 + l16;
+      if constexpr (TB) {
+        const d2_t v = *reinterpret_cast<const d2_t*>(&bs[n * 8 + ((lq ^ ((n >> 1) & 3)) << 1)]);
+        b[j][0] = v[0];
+        b[j][1] = v[1];
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) b[j][kk] = bs[(2 * lq + kk) * BN + n];
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = mfma_f64(a[i][kk], b[j][kk], acc[i][j]);
+  };
+  int64_t t = 0;
+  for (; t + 3 <= nk; t += 3) {
+    step(t, A0, B0, A2, B2);
+    step(t + 1, A1, B1, A0, B0);
+    step(t + 2, A2, B2, A1, B1);
+  }
+  if (t < nk) {
+    step(t, A0, B0, A2, B2);
+    if (t + 1 < nk) step(t + 1, A1, B1, A0, B0);
+  }
+  // the two loads issued past the last step are still in flight: let them land
+  // before the workgroup's LDS can be reused
+  __builtin_amdgcn_s_waitcnt(0xF70);
+  asm volatile("" ::: "memory");
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = m0 + wm * 16 * TM + i * 16 + d64_row(lane, r);
+        const int64_t gn = n0 + wn * 16 * TN + j * 16 + l16;
+        if (gm < g.M && gn < g.N) {
+          const double v = g.alpha * acc[i][j][r];
+          if (g.splitk > 1) {
+            g.work[((int64_t)bz * g.M + gm) * g.N + gn] = v;
+            continue;
+          }
+          double* c = g.C + gm * g.ldc + gn;
+          if (g.epi == EPI_SQUARE) *c = v * v;
+          else if (g.epi == EPI_HADAMARD) *c = *c * v;
+          else if (g.epi == EPI_HADAMARD_SRC) *c = (g.D ? g.D[gm * g.ldd + gn] : (double)g.D32[gm * g.ldd + gn]) * v;
+          else *c = (g.beta == 0.0) ? v : v + g.beta * *c;
+        }
+      }
+}
+
 // 128 x 64 tiles without the row scale fit three waves per SIMD (168 registers)
 template <int TM, int TN, bool TA, bool TB, bool KS = false>
 __global__ __launch_bounds__(256, (TN == 2 && !KS) ? 3 : 2) void gemm_big_kernel(Gemm g) {
@@ -919,6 +1096,27 @@ void launch_big(const Gemm& g, dim3 grid, hipStream_t s) {
   else hipLaunchKernelGGL((gemm_big_kernel<TM, TN, true, true>), grid, dim3(256), 0, s, g);
 }
 
+template <int TN>
+void launch64d(const Gemm& g, dim3 grid, hipStream_t s) {
+  if (!g.transA && !g.transB) hipLaunchKernelGGL((gemm64d_kernel<4, TN, false, false>), grid, dim3(256), 0, s, g);
+  else if (g.transA && !g.transB) hipLaunchKernelGGL((gemm64d_kernel<4, TN, true, false>), grid, dim3(256), 0, s, g);
+  else if (!g.transA && g.transB) hipLaunchKernelGGL((gemm64d_kernel<4, TN, false, true>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((gemm64d_kernel<4, TN, true, true>), grid, dim3(256), 0, s, g);
+}
+
+// the LDS-direct FP64 kernel's requirements (see gemm64d_kernel)
+bool direct64_ok(const Gemm& g) {
+  auto al = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
+  if (g.kscale || g.K % 8 != 0 || g.lda % 2 || g.ldb % 2 || !al(g.A) || !al(g.B)) return false;
+  if ((g.transA && g.M % 2) || (!g.transB && g.N % 2)) return false;
+  // both operands K-major over a long K (W = V chi^T at set-up): each 8-deep step
+  // touches 64 bytes of every one of 192 rows megabytes apart, and the register-staged
+  // kernel's 16-deep steps ran faster there
+  if (!g.transA && g.transB && g.K > 16384) return false;
+  const char* v = getenv("RPS_GEMM64_DIRECT");    // "0": the register-staged kernel (comparison runs)
+  return !(v && v[0] == '0');
+}
+
 // Output tile width: 16 for skinny products, 64 when N <= 64, else 128 (all 128 rows high).
 int gemm_tile_n(int64_t M, int64_t N) {
   (void)M;
@@ -946,6 +1144,13 @@ hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
   if (bn == 16) {
     dim3 grid((unsigned)((g.N + 15) / 16), (unsigned)((g.M + 127) / 128), (unsigned)g.splitk);
     hipLaunchKernelGGL((gemm_kernel<4, 2, 1>), grid, dim3(256), 0, s, g);
+  } else if (direct64_ok(g)) {
+    // 128 x 64 tiles (three waves per SIMD; 128 x 128 holds two and ran slower on the
+    // set-up's updates), one-dimensional grid in XCD-grouped tile order, padded to
+    // whole rounds of eight
+    const int64_t ntile = ((g.N + 63) / 64) * ((g.M + 127) / 128) * g.splitk;
+    if (ntile > (int64_t)UINT32_MAX - 8) return hipErrorInvalidValue;
+    launch64d<2>(g, dim3((unsigned)((ntile + 7) / 8 * 8)), s);
   } else if (bn == 64) {
     dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 127) / 128), (unsigned)g.splitk);
     launch_big<4, 2>(g, grid, s);
