@@ -8,12 +8,14 @@
 // 2c + 1), which works because Vc is real: Vc(f + i h) = Vc f + i Vc h.
 //
 // The 3-D transform is separable: one pass per axis, each pass moving 16
-// pencils of one axis into LDS and applying the length-L DFT by direct
-// summation with twiddles from sincospi in FP64 (axes up to 256 points).  Passes:
+// pencils of one axis into LDS and applying the length-L transform there with
+// twiddles from sincospi in FP64 (axes up to 256 points): a self-sorting
+// mixed-radix FFT (radices 2, 3, 4, 5) when L has no other prime factor, else
+// the DFT by direct summation.  Passes:
 // forward along axis 2, forward along axis 1, [forward along axis 0, multiply
 // by k/N_g, inverse along axis 0] in one kernel, inverse along axis 1, inverse
-// along axis 2.  This is a set-up step (once per geometry), so the direct
-// O(L) sum per output is acceptable; the per-build path uses no transform.
+// along axis 2.  This is a set-up step (once per geometry); the per-build path
+// uses no transform.
 #include <math.h>
 
 #include "mfma.h"
@@ -66,10 +68,79 @@ __global__ __launch_bounds__(256) void dft_axis_kernel(double* __restrict__ V, i
   __syncthreads();
   constexpr int PASSES = (MODE == 2) ? 2 : 1;
   int cur = 0;
+  // lengths whose factors are all 2, 3 and 5 take the fast transform
+  int rest = L;
+  while (rest % 2 == 0) rest /= 2;
+  while (rest % 3 == 0) rest /= 3;
+  while (rest % 5 == 0) rest /= 5;
+  const bool fast = (rest == 1);
 #pragma unroll
   for (int pass = 0; pass < PASSES; ++pass) {
     // out[k] = sum_j x[j] exp(sg * 2 pi i j k / L), sg = -1 forward, +1 inverse
     const double sg = (MODE == 1 || pass == 1) ? 1.0 : -1.0;
+    if (fast) {
+      // Self-sorting (Stockham) mixed-radix transform, radices 4, 2, 3, 5: stage with
+      // radix R after sub-transforms of length ns: butterfly j (< L / R) takes the R
+      // points j + r L / R, turns them by exp(sg 2 pi i r (j mod ns) / (ns R)), applies
+      // the R-point transform and writes point r' to (j / ns) ns R + (j mod ns) + r' ns.
+      // Twiddles come from the table exp(2 pi i m / L) (ns R divides L).
+      int ns = 1, left = L;
+      while (left > 1) {
+        const int R = (left % 4 == 0) ? 4 : (left % 2 == 0) ? 2 : (left % 3 == 0) ? 3 : 5;
+        const int nb = L / R;
+        const int tstep = L / (ns * R);
+        for (int e = tid; e < PEN * nb; e += 256) {
+          const int q = e / nb, j = e % nb;
+          const int k = j % ns;
+          double vr[5], vi[5];
+#pragma unroll
+          for (int r = 0; r < 5; ++r) {
+            if (r < R) {
+              const double a = br[cur][q][j + r * nb], b = bi[cur][q][j + r * nb];
+              const int m = (r * k * tstep) % L;
+              const double c = wr[m], sn = sg * wi[m];
+              vr[r] = a * c - b * sn;
+              vi[r] = a * sn + b * c;
+            }
+          }
+          const int d0 = (j / ns) * ns * R + k;
+#pragma unroll
+          for (int o = 0; o < 5; ++o) {
+            if (o < R) {
+              double yr = 0.0, yi = 0.0;
+#pragma unroll
+              for (int r = 0; r < 5; ++r) {
+                if (r < R) {
+                  const int m = ((r * o) % R) * nb;
+                  const double c = wr[m], sn = sg * wi[m];
+                  yr += vr[r] * c - vi[r] * sn;
+                  yi += vr[r] * sn + vi[r] * c;
+                }
+              }
+              br[cur ^ 1][q][d0 + o * ns] = yr;
+              bi[cur ^ 1][q][d0 + o * ns] = yi;
+            }
+          }
+        }
+        __syncthreads();
+        cur ^= 1;
+        ns *= R;
+        left /= R;
+      }
+      if (MODE == 2 && pass == 0) {
+        for (int e = tid; e < PEN * L; e += 256) {
+          int q, k;
+          split(e, q, k);
+          const int64_t p = p0 + q;
+          double kv = 0.0;
+          if (p < npencil) kv = kern[(p / inner) * (int64_t)L * inner + (p % inner) + (int64_t)k * inner];
+          br[cur][q][k] *= kv;
+          bi[cur][q][k] *= kv;
+        }
+        __syncthreads();
+      }
+      continue;
+    }
     for (int e = tid; e < PEN * L; e += 256) {
       int q, k;
       split(e, q, k);
