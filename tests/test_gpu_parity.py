@@ -101,10 +101,12 @@ def _long_axis_cell(mesh):
                        pos, np.arange(8), np.arange(8) % 2, exps, 2, 32, 97)
 
 
-@pytest.mark.parametrize("mesh", [(144, 16, 16), (16, 200, 16), (16, 16, 256)])
+@pytest.mark.parametrize("mesh", [(144, 16, 16), (16, 200, 16), (16, 16, 256), (28, 16, 21), (14, 131, 16)])
 def test_setup_products_long_axis(lib, mesh):
-    """V = Vc chi through the per-axis DFT on axes of 144-256 points (the
-    longer-axis kernel), against the oracle's FFT Poisson solve."""
+    """V = Vc chi through the per-axis transform against the oracle's FFT
+    Poisson solve: axes of 144-256 points (the longer-axis kernel; 144, 200 and
+    256 take the mixed-radix FFT with radices 4, 2, 3 and 5), and axes with a
+    prime factor above 5 (14, 21 and 131 points), which take the direct sum."""
     _say(f"case: V and W on a {mesh} mesh with oracle points")
     w = _long_axis_cell(mesh)
     Phi = basis.eval_basis(w)
