@@ -99,7 +99,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(Gemm g) {
           if (g.epi == EPI_SQUARE) *c = v * v;
           else if (g.epi == EPI_HADAMARD) *c = *c * v;
           else if (g.epi == EPI_HADAMARD_SRC) *c = (g.D ? g.D[gm * g.ldd + gn] : (double)g.D32[gm * g.ldd + gn]) * v;
-          else *c = (g.beta == 0.0) ? v : v + g.beta * *c;
+          else {
+            *c = (g.beta == 0.0) ? v : v + g.beta * *c;
+            if (g.Cf) g.Cf[gm * g.ldcf + gn] = (float)*c;
+          }
         }
       }
 }
@@ -239,7 +242,10 @@ __device__ __forceinline__ void gemm_big_body(const Gemm& g, int64_t m0, int64_t
           if (g.epi == EPI_SQUARE) *c = v * v;
           else if (g.epi == EPI_HADAMARD) *c = *c * v;
           else if (g.epi == EPI_HADAMARD_SRC) *c = (g.D ? g.D[gm * g.ldd + gn] : (double)g.D32[gm * g.ldd + gn]) * v;
-          else *c = (g.beta == 0.0) ? v : v + g.beta * *c;
+          else {
+            *c = (g.beta == 0.0) ? v : v + g.beta * *c;
+            if (g.Cf) g.Cf[gm * g.ldcf + gn] = (float)*c;
+          }
         }
       }
 }
@@ -399,6 +405,7 @@ __global__ __launch_bounds__(256, 2) void gemm32_kernel(Gemm32 g) {
             }
             double* c = g.C + gm * g.ldc + gn;
             *c = (g.beta == 0.0) ? v : v + g.beta * *c;
+            if (g.Cf) g.Cf[gm * g.ldcf + gn] = (float)*c;
           }
         }
       }
@@ -666,6 +673,7 @@ __global__ __launch_bounds__(256, 2) void gemm32d_kernel(Gemm32 g) {
             }
             double* c = g.C + gm * g.ldc + gn;
             *c = (g.beta == 0.0) ? v : v + g.beta * *c;
+            if (g.Cf) g.Cf[gm * g.ldcf + gn] = (float)*c;
           }
         }
       }
@@ -871,6 +879,7 @@ __global__ __launch_bounds__(256, 2) void gemm32v_kernel(Gemm32 g) {
             }
             double* c = g.C + gm * g.ldc + gn;
             *c = (g.beta == 0.0) ? v : v + g.beta * *c;
+            if (g.Cf) g.Cf[gm * g.ldcf + gn] = (float)*c;
           }
         }
       }
@@ -1048,7 +1057,10 @@ __global__ __launch_bounds__(256, 2) void gemm64d_kernel(Gemm g) {
           if (g.epi == EPI_SQUARE) *c = v * v;
           else if (g.epi == EPI_HADAMARD) *c = *c * v;
           else if (g.epi == EPI_HADAMARD_SRC) *c = (g.D ? g.D[gm * g.ldd + gn] : (double)g.D32[gm * g.ldd + gn]) * v;
-          else *c = (g.beta == 0.0) ? v : v + g.beta * *c;
+          else {
+            *c = (g.beta == 0.0) ? v : v + g.beta * *c;
+            if (g.Cf) g.Cf[gm * g.ldcf + gn] = (float)*c;
+          }
         }
       }
 }
@@ -1077,7 +1089,8 @@ __global__ __launch_bounds__(256, 2) void gemm_grouped_kernel(Gemm base, const G
 
 // C = alpha * sum_z work[z] + beta * C (fixed order over z)
 __global__ void splitk_reduce_kernel(const double* __restrict__ work, int splitk, int64_t M, int64_t N,
-                                     double* __restrict__ C, int64_t ldc, double beta) {
+                                     double* __restrict__ C, int64_t ldc, double beta, float* __restrict__ Cf,
+                                     int64_t ldcf) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= M * N) return;
   double s = 0.0;
@@ -1085,6 +1098,7 @@ __global__ void splitk_reduce_kernel(const double* __restrict__ work, int splitk
   const int64_t m = t / N, n = t % N;
   double* c = C + m * ldc + n;
   *c = (beta == 0.0) ? s : s + beta * *c;
+  if (Cf) Cf[m * ldcf + n] = (float)*c;
 }
 
 template <int TM, int TN>
@@ -1134,6 +1148,7 @@ hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
   }
   if (g.splitk > 1 && (!g.work || g.epi != EPI_AXPBY)) return hipErrorInvalidValue;
   if (g.epi == EPI_HADAMARD_SRC && !g.D && !g.D32) return hipErrorInvalidValue;
+  if (g.Cf && (g.epi != EPI_AXPBY || g.keep_partials)) return hipErrorInvalidValue;
   if (g.splitk < 1) g.splitk = 1;
   int bn = gemm_tile_n(g.M, g.N);
   if (g.tile_n) {
@@ -1161,7 +1176,7 @@ hipError_t gemm_f64(const Gemm& g0, hipStream_t s) {
   if (g.splitk > 1 && !g.keep_partials) {
     const int64_t cnt = g.M * g.N;
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, g.work,
-                       g.splitk, g.M, g.N, g.C, g.ldc, g.beta);
+                       g.splitk, g.M, g.N, g.C, g.ldc, g.beta, g.Cf, g.ldcf);
   }
   return hipGetLastError();
 }
@@ -1215,7 +1230,7 @@ hipError_t gemm_f32(const Gemm32& g0, hipStream_t s) {
   Gemm32 g = g0;
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   const bool out32 = g.C32 != nullptr;
-  if (out32 && (!g.D32 || g.splitk > 1)) return hipErrorInvalidValue;
+  if (out32 && (!g.D32 || g.splitk > 1 || g.Cf)) return hipErrorInvalidValue;
   if (!out32 && !g.C) return hipErrorInvalidValue;
   if (g.splitk > 1 && !g.work) return hipErrorInvalidValue;
   if (g.splitk < 1) g.splitk = 1;
@@ -1247,7 +1262,7 @@ hipError_t gemm_f32(const Gemm32& g0, hipStream_t s) {
   if (g.splitk > 1) {
     const int64_t cnt = g.M * g.N;
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, g.work,
-                       g.splitk, g.M, g.N, g.C, g.ldc, g.beta);
+                       g.splitk, g.M, g.N, g.C, g.ldc, g.beta, g.Cf, g.ldcf);
   }
   return hipGetLastError();
 }
@@ -1258,7 +1273,8 @@ int gemm32_splitk_for(int64_t M, int64_t N, int64_t K, int64_t kmax, int64_t wor
   const int bn = 64;
   const int64_t tiles = ((M + 127) / 128) * ((N + bn - 1) / bn);
   // among the split counts that keep >= 1024 of K per split, the one whose workgroups
-  // fill the last round of 512 (two per CU) best, the smaller on a tie
+  // fill the last round of 768 (three per CU, as the FP64-output tiles run) best, the
+  // smaller on a tie
   int64_t z0 = 1;
   while ((K + z0 - 1) / z0 > kmax) ++z0;
   int64_t best = z0;
@@ -1266,8 +1282,8 @@ int gemm32_splitk_for(int64_t M, int64_t N, int64_t K, int64_t kmax, int64_t wor
   for (int64_t z = z0; z <= z0 + 7; ++z) {
     if (z > z0 && K / z < 1024) break;
     if (z > 1 && z * M * N > work_cap_doubles) break;
-    const int64_t wgs = tiles * z, rounds = (wgs + 511) / 512;
-    const double fill = (double)wgs / (double)(rounds * 512) + (rounds > 1 ? 0.0 : -0.5);
+    const int64_t wgs = tiles * z, rounds = (wgs + 767) / 768;
+    const double fill = (double)wgs / (double)(rounds * 768) + (rounds > 1 ? 0.0 : -0.5);
     if (fill > best_fill + 1e-9) { best_fill = fill; best = z; }
   }
   return (int)best;
@@ -1290,7 +1306,7 @@ void launch_grouped(const Gemm& g, const GemmItem* items, dim3 grid, hipStream_t
 hipError_t gemm_f64_grouped(const Gemm& base, const GemmItem* items, int nitems, int64_t maxM, int64_t maxN,
                             hipStream_t s) {
   if (nitems <= 0 || maxM <= 0 || maxN <= 0) return hipSuccess;
-  if (nitems > 65535 || base.splitk > 1 || base.epi != EPI_AXPBY) return hipErrorInvalidValue;
+  if (nitems > 65535 || base.splitk > 1 || base.epi != EPI_AXPBY || base.Cf) return hipErrorInvalidValue;
   if (base.kscale && !(base.transA && !base.transB)) return hipErrorInvalidValue;
   const int bn = (maxN <= 64) ? 64 : 128;
   dim3 grid((unsigned)((maxN + bn - 1) / bn), (unsigned)((maxM + 127) / 128), (unsigned)nitems);
@@ -1307,14 +1323,18 @@ void gemm_plan(Gemm& g, int64_t work_cap_doubles) {
     g.splitk = gemm_splitk_for(g.M, g.N, g.K, work_cap_doubles);
     return;
   }
+  // the LDS-direct kernel runs 128 x 64 tiles, three workgroups per CU; the
+  // register-staged one 128 x 64 or 128 x 128, two per CU
+  const bool direct = direct64_ok(g);
+  const int64_t slots = direct ? 768 : 512;
   double best = -1.0;
-  for (int bn = 128; bn >= 64; bn -= 64) {
+  for (int bn = direct ? 64 : 128; bn >= 64; bn -= 64) {
     const int64_t padn = (g.N + bn - 1) / bn * bn;
     const int64_t tiles = ((g.M + 127) / 128) * (padn / bn);
     for (int64_t z = 1; z <= 64; ++z) {
       if (z > 1 && (g.K / z < 256 || z * g.M * g.N > work_cap_doubles)) break;
-      const int64_t wgs = tiles * z, rounds = (wgs + 511) / 512;
-      const double score = (double)g.N / (double)padn * (double)wgs / (double)(rounds * 512);
+      const int64_t wgs = tiles * z, rounds = (wgs + slots - 1) / slots;
+      const double score = (double)g.N / (double)padn * (double)wgs / (double)(rounds * slots);
       if (score > best + 1e-9) {
         best = score;
         g.tile_n = bn;

@@ -1021,8 +1021,15 @@ void ensure_general(rps_context& c, int np) {
       c.gA32.alloc(c.nauxp * rc, cnt);
       c.gU32.alloc(c.ngp * npg, cnt);
       c.gUg32.alloc(c.nauxp * npg, cnt);
+      // the products write only the first np columns of these FP32 copies: the padding
+      // columns are cleared here, once (npg is even: cleared as pairs of floats)
+      hip_check(fill(reinterpret_cast<double*>(c.gU32.p), c.ngp * npg / 2, 0.0, nullptr), "clear U32");
       if (!c.sparse) {
         c.gM1T32.alloc(c.ngp * npg, cnt);
+        hip_check(fill(reinterpret_cast<double*>(c.gM1T32.p), c.ngp * npg / 2, 0.0, nullptr), "clear M1T32");
+      }
+      hip_check(hipStreamSynchronize(nullptr), "sync");    // before any build's stream writes them
+      if (!c.sparse) {
         if (!c.gPhi32.p) {    // the basis does not change after set-up: converted once, here (no capture)
           c.gPhi32.alloc(c.ngp * c.Np, cnt);
           hip_check(to_f32(c.Phi.p, c.ngp * c.Np, c.gPhi32.p, nullptr), "Phi to f32");
@@ -1113,8 +1120,12 @@ int pass_splits(const rps_context& c, const StreamArgs& a) {
 }
 
 // Before the passes: C packed, U = Phi C, U_g, and the FP32 copies the precision forms read.
-void general_pre(rps_context& c, int nocc, const double* Csrc, hipStream_t st, bool f32_copies) {
+// With uf set (dense basis), the U product also writes U rounded to FP32 there (pitch
+// lduf); the return value says whether it did.
+bool general_pre(rps_context& c, int nocc, const double* Csrc, hipStream_t st, bool f32_copies,
+                 float* uf = nullptr, int64_t lduf = 0) {
   const int np = (int)round_up(nocc, 16);
+  bool wrote_uf = false;
   hip_check(pack_matrix(Csrc, c.nbas, nocc, nocc, c.gCp.p, c.Np, np, st), "pack C");
   if (c.sparse) {
     sparse_u(c, c.gCp.p, np, c.gU.p, st);
@@ -1122,6 +1133,7 @@ void general_pre(rps_context& c, int nocc, const double* Csrc, hipStream_t st, b
     Gemm g;   // U = Phi C
     g.M = c.ngp; g.N = np; g.K = c.Np;
     g.A = c.Phi.p; g.lda = c.Np; g.B = c.gCp.p; g.ldb = np; g.C = c.gU.p; g.ldc = np;
+    if (uf) { g.Cf = uf; g.ldcf = lduf; wrote_uf = true; }
     gemm_run(g, c, st, "U", false);
   }
   hip_check(gather_rows(c.gU.p, np, c.dpoints.p, c.naux, c.nauxp, np, c.gUg.p, np, st), "U_g");
@@ -1129,6 +1141,7 @@ void general_pre(rps_context& c, int nocc, const double* Csrc, hipStream_t st, b
     hip_check(to_f32(c.gU.p, c.ngp * np, c.gU32.p, st), "U to f32");
     hip_check(to_f32(c.gUg.p, c.nauxp * np, c.gUg32.p, st), "U_g to f32");
   }
+  return wrote_uf;
 }
 
 void build_general(rps_context& c, int variant, int nocc, const double* Csrc, double* Kout, double* exout,
@@ -1139,7 +1152,10 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
   const bool need_l3 = (variant != RPS_VARIANT_PS);
   const bool k1 = need_main && variant == RPS_VARIANT_RPS;
   const bool stream = c.gSp.p != nullptr && np <= kStreamMaxNp;
-  general_pre(c, nocc, Csrc, st, false);
+  // GEMM form with FP32 products: U rounded to FP32 by the U product itself
+  const bool gemm_f32_form = !stream && need_main && c.gA32.p != nullptr;
+  const bool u32_done = general_pre(c, nocc, Csrc, st, false, gemm_f32_form ? c.gU32.p : nullptr,
+                                    round_up(np, 64));
   // the streaming passes run the context's precision; the GEMM form runs FP32
   // products for either precision form
   c.last_arith = stream ? c.precision : (c.gA32.p != nullptr ? RPS_PREC_FP32 : RPS_PREC_FP64);
@@ -1187,7 +1203,7 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
     // the n dimension then loads whole 16-byte pieces
     const int64_t npg = round_up(np, 64);
     if (f32) {
-      hip_check(to_f32_pad(c.gU.p, c.ngp, np, c.gU32.p, npg, st), "U to f32");
+      if (!u32_done) hip_check(to_f32_pad(c.gU.p, c.ngp, np, c.gU32.p, npg, st), "U to f32");
       hip_check(to_f32_pad(c.gUg.p, c.nauxp, np, c.gUg32.p, npg, st), "U_g to f32");
     }
     prof_mark(c, 1, st);     // the profiled main phase: the chunk products only
@@ -1205,6 +1221,7 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
           m1.M = rc; m1.N = np; m1.Nread = npg; m1.K = c.nauxp;
           m1.A = c.gA32.p; m1.lda = rc; m1.transA = true; m1.B = c.gUg32.p; m1.ldb = npg;
           m1.C = c.gM1T.p + r0 * np; m1.ldc = np;
+          if (c.gM1T32.p) { m1.Cf = c.gM1T32.p + r0 * npg; m1.ldcf = npg; }   // FP32 copy for K1
           m1.splitk = gemm32_splitk_for(m1.M, m1.N, m1.K, kF32Terms, kSplitWork); m1.work = c.gwork.p;
           hip_check(gemm_f32(m1, st), "M1");
         }
@@ -1240,7 +1257,7 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
     } else if (k1 && f32) {
       // K1 = Phi^T M1^T on the FP32 matrix cores: FP32 basis, M1^T rounded to FP32
       // (padded to npg columns), FP32 sums over 64 terms and FP64 beyond
-      hip_check(to_f32_pad(c.gM1T.p, c.ngp, np, c.gM1T32.p, npg, st), "M1^T to f32");
+      // (M1^T rounded to FP32 by its chunk products)
       Gemm32 g;
       g.M = c.Np; g.N = np; g.Nread = npg; g.K = c.ngp;
       g.A = c.gPhi32.p; g.lda = c.Np; g.transA = true; g.B = c.gM1T32.p; g.ldb = npg;

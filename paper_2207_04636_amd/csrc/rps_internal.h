@@ -30,6 +30,7 @@ struct Gemm {
   bool keep_partials = false;          // splitk > 1: leave the partials in work, no reduction
   const double* kscale = nullptr;      // op(B)[k][n] *= kscale[k] (transA && !transB, or N <= 16)
   int tile_n = 0;                      // output tile width 64 or 128 (0: chosen from N)
+  float* Cf = nullptr; int64_t ldcf = 0;   // also the final C rounded to FP32 here (EPI_AXPBY only)
 };
 hipError_t gemm_f64(const Gemm& g, hipStream_t s);
 // Split count and tile width of an AXPBY product together: the pair whose workgroups fill
@@ -66,6 +67,7 @@ struct Gemm32 {
   // B holds Nread >= N columns (zero beyond N) that may be read: tiles reaching
   // past N but not past Nread load B whole; outputs stay within N (0: Nread = N)
   int64_t Nread = 0;
+  float* Cf = nullptr; int64_t ldcf = 0;   // FP64 output: also the final C rounded to FP32 here
 };
 hipError_t gemm_f32(const Gemm32& g, hipStream_t s);
 // Split count with at most kmax of K per split and enough workgroups, within work_cap doubles
