@@ -299,10 +299,7 @@ __global__ __launch_bounds__(256) void presplit_bf16x3_kernel(const double* __re
     dst[e] = h;
     dst[BY * np + e] = m;
     dst[2 * BY * np + e] = l;
-    // transposed planes: eight rows of one column a piece, pieces ordered
-    // [row group][column] so that a wave's 8-byte LDS stores of consecutive pieces
-    // hit distinct banks (column pitch 36 values)
-    const int rr = e % 8, c2 = (e / 8) % np, r2 = (e / (8 * np)) * 8 + rr;
+    const int c2 = e / BY, r2 = e % BY;          // transposed planes: [c][r]
     split3_bf16(tile[r2][c2], h, m, l);
     dst[3 * BY * np + e] = h;
     dst[4 * BY * np + e] = m;
@@ -440,8 +437,8 @@ __device__ __forceinline__ void bf16x3_body(const StreamArgs& a, int64_t bx, int
   };
 
   // Pre-split Y: the tile's six planes as 16-byte pieces, row-major planes first
-  // ([plane][r][c], eight columns a piece) then the transposed ones ([plane][row
-  // group][c], eight rows of a column a piece), stored to LDS as whole pieces.
+  // ([plane][r][c], eight columns a piece) then the transposed ones ([plane][c][r],
+  // eight rows a piece), stored to LDS as whole pieces.
   constexpr int RPC = NP / 8, TPC = BY / 8;                  // pieces per row, per column
   constexpr int PROW = 3 * BY * RPC, PIECES = PROW + 3 * NP * TPC;
   constexpr int PPT = (PIECES + NW * 64 - 1) / (NW * 64);
@@ -467,7 +464,7 @@ __device__ __forceinline__ void bf16x3_body(const StreamArgs& a, int64_t bx, int
       } else if (e < PIECES) {
         const int e2 = e - PROW;
         const int pl = e2 / (NP * TPC), rem = e2 % (NP * TPC);
-        const int c = rem % NP, r0 = (rem / NP) * 8;
+        const int c = rem / TPC, r0 = (rem % TPC) * 8;
         uint2* d = reinterpret_cast<uint2*>(b + 3 * SZR + pl * SZT + c * LT + r0);
         d[0] = make_uint2(ysp[k].x, ysp[k].y);
         d[1] = make_uint2(ysp[k].z, ysp[k].w);

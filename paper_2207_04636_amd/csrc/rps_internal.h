@@ -285,8 +285,7 @@ struct StreamArgs {
 };
 // Y (ny x np FP64, ny a multiple of 32) rounded to FP32 and split into three BF16
 // terms, laid out per 32-row tile as the split-BF16 passes stage it: three row-major
-// planes [32][np], then three transposed planes [4][np][8] (row group, column, row in
-// the group; 6 * 32 * np values a tile).
+// planes [32][np], then three transposed planes [np][32] (6 * 32 * np values a tile).
 hipError_t presplit_bf16x3(const double* Y, int64_t ny, int np, uint16_t* out, hipStream_t s);
 // Split count along y giving about target_blocks workgroups.
 int stream_splits(int64_t nx, int64_t ny, int target_blocks);
