@@ -281,32 +281,6 @@ __device__ __forceinline__ void split3_bf16(float x, __bf16& h, __bf16& m, __bf1
   l = (__bf16)(r - (float)m);
 }
 
-// One workgroup per 32-row tile of Y: the tile in FP32 through LDS, then the three
-// row-major planes and the three transposed planes written with consecutive threads
-// on consecutive addresses.
-__global__ __launch_bounds__(256) void presplit_bf16x3_kernel(const double* __restrict__ Y, int np,
-                                                             __bf16* __restrict__ out) {
-  __shared__ float tile[BY][128 + 1];
-  const int64_t t = blockIdx.x;
-  const double* src = Y + t * BY * np;
-  for (int e = threadIdx.x; e < BY * np; e += 256) tile[e / np][e % np] = (float)src[e];
-  __syncthreads();
-  __bf16* dst = out + t * 6 * BY * np;
-  for (int e = threadIdx.x; e < BY * np; e += 256) {
-    __bf16 h, m, l;
-    const int r = e / np, c = e % np;            // row-major planes: [r][c]
-    split3_bf16(tile[r][c], h, m, l);
-    dst[e] = h;
-    dst[BY * np + e] = m;
-    dst[2 * BY * np + e] = l;
-    const int c2 = e / BY, r2 = e % BY;          // transposed planes: [c][r]
-    split3_bf16(tile[r2][c2], h, m, l);
-    dst[3 * BY * np + e] = h;
-    dst[4 * BY * np + e] = m;
-    dst[5 * BY * np + e] = l;
-  }
-}
-
 template <int NC>
 struct Bf16Layout {
   static constexpr int NP = 16 * NC;
@@ -324,7 +298,7 @@ struct Bf16Layout {
   static constexpr size_t LDS_BYTES = (size_t)NBUF * BUF * 2;
 };
 
-template <int NC, int TRANS, int NW, bool PRESPLIT = false>
+template <int NC, int TRANS, int NW>
 __device__ __forceinline__ void bf16x3_body(const StreamArgs& a, int64_t bx, int64_t by, unsigned char* smem_raw) {
   using L = Bf16Layout<NC>;
   constexpr int NP = L::NP, NKC = L::NKC, NPP = L::NPP, LR = L::LR, LT = L::LT;
@@ -436,57 +410,15 @@ __device__ __forceinline__ void bf16x3_body(const StreamArgs& a, int64_t bx, int
     }
   };
 
-  // Pre-split Y: the tile's six planes as 16-byte pieces, row-major planes first
-  // ([plane][r][c], eight columns a piece) then the transposed ones ([plane][c][r],
-  // eight rows a piece), stored to LDS as whole pieces.
-  constexpr int RPC = NP / 8, TPC = BY / 8;                  // pieces per row, per column
-  constexpr int PROW = 3 * BY * RPC, PIECES = PROW + 3 * NP * TPC;
-  constexpr int PPT = (PIECES + NW * 64 - 1) / (NW * 64);
-  constexpr bool presplit = PRESPLIT;
-  uint4 ysp[presplit ? PPT : 1];
-  auto stage_load_sp = [&](int64_t t) {
-    const uint4* src = reinterpret_cast<const uint4*>(a.Ysp) + ((ys + t * BY) / BY) * (PIECES);
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      const int e = tid + NW * 64 * k;
-      if (e < PIECES) ysp[k] = src[e];
-    }
-  };
-  auto stage_store_sp = [&](int buf) {
-    __bf16* b = sm + buf * L::BUF;
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      const int e = tid + NW * 64 * k;
-      if (e < PROW) {
-        const int pl = e / (BY * RPC), rem = e % (BY * RPC);
-        const int r = rem / RPC, c0 = (rem % RPC) * 8;
-        *reinterpret_cast<uint4*>(b + pl * SZR + r * LR + c0) = ysp[k];
-      } else if (e < PIECES) {
-        const int e2 = e - PROW;
-        const int pl = e2 / (NP * TPC), rem = e2 % (NP * TPC);
-        const int c = rem / TPC, r0 = (rem % TPC) * 8;
-        uint2* d = reinterpret_cast<uint2*>(b + 3 * SZR + pl * SZT + c * LT + r0);
-        d[0] = make_uint2(ysp[k].x, ysp[k].y);
-        d[1] = make_uint2(ysp[k].z, ysp[k].w);
-      }
-    }
-  };
-
   if (ntile > 0) {
-    if constexpr (presplit) {
-      stage_load_sp(0);
-      stage_store_sp(0);
-    } else {
-      stage_load(0);
-      stage_store(0);
-    }
+    stage_load(0);
+    stage_store(0);
     load_s(0, vv);
   }
   __syncthreads();
   // unconditional loads, as in the FP64/FP32 kernel
   for (int64_t t = 0; t < ntile; ++t) {
-    if constexpr (presplit) stage_load_sp(t + 1 < ntile ? t + 1 : t);
-    else stage_load(t + 1 < ntile ? t + 1 : t);
+    stage_load(t + 1 < ntile ? t + 1 : t);
     load_s(t + 1, vn);    // the next tile's S values, a tile ahead
     const __bf16* b = sm + ((L::NBUF == 2) ? (int)(t & 1) : 0) * L::BUF;
     if (xvalid) {
@@ -571,12 +503,10 @@ __device__ __forceinline__ void bf16x3_body(const StreamArgs& a, int64_t bx, int
 #pragma unroll
     for (int e = 0; e < 8; ++e) vv[e] = vn[e];
     if constexpr (L::NBUF == 2) {
-      if constexpr (presplit) stage_store_sp((t + 1) & 1);
-      else stage_store((t + 1) & 1);
+      stage_store((t + 1) & 1);
     } else {
       __syncthreads();     // every wave has read tile t
-      if constexpr (presplit) stage_store_sp(0);
-      else stage_store(0);
+      stage_store(0);
     }
     __syncthreads();
   }
@@ -589,10 +519,10 @@ __device__ __forceinline__ void bf16x3_body(const StreamArgs& a, int64_t bx, int
     for (int r = 0; r < 4; ++r) out[(x0 + 4 * lq + r) * a.np + 16 * cb + l16] = od[cb][r];
 }
 
-template <int NC, int TRANS, int NW, bool PRESPLIT>
+template <int NC, int TRANS, int NW>
 __global__ __launch_bounds__(NW * 64) void stream_bf16x3_kernel(StreamArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  bf16x3_body<NC, TRANS, NW, PRESPLIT>(a, blockIdx.x, blockIdx.y, smem_raw);
+  bf16x3_body<NC, TRANS, NW>(a, blockIdx.x, blockIdx.y, smem_raw);
 }
 
 // Persistent split-BF16 form (see stream_queue_kernel).
@@ -619,7 +549,7 @@ template <int NC, int TRANS>
 hipError_t launch_bf16x3(const StreamArgs& a, int nsplit, hipStream_t s) {
   constexpr int NW = 8;
   const size_t lds = Bf16Layout<NC>::LDS_BYTES;
-  auto kern = a.Ysp ? stream_bf16x3_kernel<NC, TRANS, NW, true> : stream_bf16x3_kernel<NC, TRANS, NW, false>;
+  auto kern = stream_bf16x3_kernel<NC, TRANS, NW>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -696,14 +626,6 @@ hipError_t stream_prepare(const StreamArgs& a, int prec, int nsplit, StreamArgs&
 }
 
 int64_t stream_xblocks(int64_t nx) { return (nx + 127) / 128; }
-
-hipError_t presplit_bf16x3(const double* Y, int64_t ny, int np, uint16_t* out, hipStream_t s) {
-  if (np < 16 || np > 128 || np % 16 || ny % BY) return hipErrorInvalidValue;
-  if (ny == 0) return hipSuccess;
-  hipLaunchKernelGGL(presplit_bf16x3_kernel, dim3((unsigned)(ny / BY)), dim3(256), 0, s, Y, np,
-                     reinterpret_cast<__bf16*>(out));
-  return hipGetLastError();
-}
 
 namespace {
 template <typename K>

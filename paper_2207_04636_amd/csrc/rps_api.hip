@@ -112,7 +112,6 @@ struct rps_context {
   DBuf<double> gCp, gU, gUg, gA, gSp, gM2, gM1T, gK1, gK3, gY, gwork, epart;
   DBuf<float> gU32, gUg32, gA32;   // precision form of the GEMM form: FP32 operands and A chunk
   DBuf<float> gPhi32, gM1T32;      // and the FP32 operands of K1 = Phi^T M1^T (basis, padded M1^T)
-  DBuf<uint16_t> gYsp;             // split-BF16 streaming form: U and U_g split once per build
   DBuf<unsigned> ecount;   // last-block counter of the finalize kernel's energy sum (zero between builds)
   int64_t rblocks_main = 0, blocks_main = 0, blocks_l3 = 0;
   int rtiles = 4, gblocks = 1, nwaves = 4;
@@ -172,7 +171,6 @@ struct rps_context {
     gPhi32.release(nullptr);
     gM1T32.release(nullptr);
     gA32.release(nullptr);
-    gYsp.release(nullptr);
     ecount.release(nullptr);
     DBuf<double>* jb[] = {&kern, &jCp, &jCin, &jU, &jrho, &jwork, &jpart, &jJ, &Sdev, &mCp, &mSC, &mpart};
     for (auto* b : jb) b->release(nullptr);
@@ -1015,7 +1013,6 @@ void ensure_general(rps_context& c, int np) {
   c.gUg32.release(cnt);
   c.gA32.release(cnt);
   c.gM1T32.release(cnt);
-  c.gYsp.release(cnt);
   if (np > kStreamMaxNp || getenv("RPS_GENERAL_GEMM")) {
     c.gSp.release(cnt);
     if (f32) {
@@ -1049,10 +1046,6 @@ void ensure_general(rps_context& c, int np) {
       c.gU32.alloc(c.ngp * np, cnt);
       c.gUg32.alloc(c.nauxp * np, cnt);
     }
-    // split-BF16: the Y operands split into their BF16 terms once per build, six planes
-    // per 32-row tile, instead of by every workgroup that stages the tile
-    const char* ps = getenv("RPS_BF16_PRESPLIT");    // "0": split while staging (comparison runs)
-    if (c.precision == RPS_PREC_BF16X3 && !(ps && ps[0] == '0')) c.gYsp.alloc((c.ngp + c.nauxp) * np * 6, cnt);
   }
   c.gM2.alloc(c.nauxp * np, cnt);
   c.gM1T.alloc(c.ngp * np, cnt);
@@ -1171,27 +1164,16 @@ void build_general(rps_context& c, int variant, int nocc, const double* Csrc, do
     const int prec = c.precision;
     if (need_main) {
       prof_mark(c, 1, st);
-      const bool presplit = prec == RPS_PREC_BF16X3 && c.gYsp.p != nullptr;
-      uint16_t* ysp_u = c.gYsp.p;                                // U, then U_g
-      uint16_t* ysp_g = presplit ? c.gYsp.p + c.ngp * np * 6 : nullptr;
-      if (presplit) {
-        hip_check(presplit_bf16x3(c.gU.p, c.ngp, np, ysp_u, st), "U split");
-        hip_check(presplit_bf16x3(c.gUg.p, c.nauxp, np, ysp_g, st), "U_g split");
-      } else if (prec != RPS_PREC_FP64) {
+      if (prec != RPS_PREC_FP64) {
         hip_check(to_f32(c.gU.p, c.ngp * np, c.gU32.p, st), "U to f32");
         hip_check(to_f32(c.gUg.p, c.nauxp * np, c.gUg32.p, st), "U_g to f32");
       }
-      StreamArgs m2 = pass_m2(c, np);
-      if (presplit) m2.Ysp = ysp_u;
+      const StreamArgs m2 = pass_m2(c, np);
       const int sp = pass_splits(c, m2);
       hip_check(stream_product(m2, prec, sp, st), "stream M2");
       hip_check(sum_partials3(c.gSp.p, sp, c.nauxp * np, c.gM2.p, nullptr, 0, 0, nullptr, nullptr, 0, 0, nullptr, st),
                 "M2 partials");
-      if (k1) {
-        StreamArgs m1 = pass_m1(c, np);
-        if (presplit) m1.Ysp = ysp_g;
-        hip_check(stream_product(m1, prec, 1, st), "stream M1");
-      }
+      if (k1) hip_check(stream_product(pass_m1(c, np), prec, 1, st), "stream M1");
       prof_mark(c, 2, st);
       if (k1 && c.sparse) {
         sparse_k1(c, c.gM1T.p, np, c.gK1.p, st);

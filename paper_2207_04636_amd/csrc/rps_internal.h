@@ -276,17 +276,11 @@ struct StreamArgs {
   const double* X = nullptr; int64_t ldx = 0;
   const double* Y = nullptr; int64_t ldy = 0;
   const float* Y32 = nullptr;  // FP32 copy of Y (same pitch), read by the FP32 and split-BF16 forms
-  // split-BF16 form: Y already split, per 32-row tile (presplit_bf16x3); used instead of Y32
-  const uint16_t* Ysp = nullptr;
   int64_t nx = 0, ny = 0;
   int64_t ysplit = 0;       // set by stream_product
   int np = 0;
   double* out = nullptr;
 };
-// Y (ny x np FP64, ny a multiple of 32) rounded to FP32 and split into three BF16
-// terms, laid out per 32-row tile as the split-BF16 passes stage it: three row-major
-// planes [32][np], then three transposed planes [np][32] (6 * 32 * np values a tile).
-hipError_t presplit_bf16x3(const double* Y, int64_t ny, int np, uint16_t* out, hipStream_t s);
 // Split count along y giving about target_blocks workgroups.
 int stream_splits(int64_t nx, int64_t ny, int target_blocks);
 // prec: 0 FP64 (V), 1 FP32 (V32, FP32 products), 2 split-BF16 products on V32.
