@@ -698,7 +698,12 @@ void setup_impl(rps_context& c, const rps_cell* cell, const rps_basis* b, int64_
     // ---- chi = X_gg^-1 X_gR in column panels, in place in V: X_gR = (Phi_g Phi^T)^2 for
     //      the panel, then the two triangular solves on it
     {
-      const int64_t pw = std::min(kChiPanel, c.ngp);
+      int64_t pw = kChiPanel;
+      if (const char* e = getenv("RPS_CHI_PANEL")) {     // tuning sweeps: columns per panel
+        const int64_t v = atoll(e);
+        if (v >= 64 && v % 64 == 0) pw = v;
+      }
+      pw = std::min(pw, c.ngp);
       for (int64_t r0 = 0; r0 < c.ngp; r0 += pw) {
         const int64_t nc = std::min(pw, c.ngp - r0);
         Gemm g;
