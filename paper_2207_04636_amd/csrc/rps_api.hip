@@ -972,7 +972,9 @@ FusedWs context_ws(rps_context& c, int np) {
 // U and U_g in FP32 and A_c stored in FP32, and so does K1 (dense basis) from FP32
 // copies of Phi and M1^T; the products into M1^T, M2 and K1 sum 64 terms at a
 // time in FP32 and everything beyond (longer sums, splits, chunks, K) in FP64.
-// U = Phi C stays FP64 (its rounding enters every product of the build).
+// U = Phi C stays FP64 (its rounding enters every product of the build); the U
+// product and the M1^T chunk products also write the FP32 copies the later
+// products read (rounded from their FP64 results).
 
 // workspace of the products with the screened basis's atom blocks
 void ensure_sparse_ws(rps_context& c, int np) {
