@@ -75,7 +75,8 @@ typedef enum {
 #define RPS_PTRS_HOST 0    /* C, K, ex are host pointers; the call is synchronous */
 #define RPS_PTRS_DEVICE 1  /* C, K, ex are device pointers; stream-ordered, asynchronous */
 
-/* Periodic cell and grid (Sec. 2.1): lattice rows a1, a2, a3 in bohr. */
+/* Periodic cell and grid (Sec. 2.1): lattice rows a1, a2, a3 in bohr; mesh points
+ * per axis, each in [2, 256] (RPS_ERR_SHAPE otherwise). */
 typedef struct {
     double lattice[9];
     int32_t mesh[3];
